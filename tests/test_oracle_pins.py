@@ -1,0 +1,496 @@
+"""Pins of the FP64 oracle against things other than itself: exact rational
+geometry, closed forms, invariances, rasterised area and finite differences.
+
+The IoU of convex polygons is the ratio of true areas (Sec. II-B listing), so
+its exact value on the (exactly representable) fp32 inputs is computable in
+rationals; the provenance flags (Sec. II-B, encoded as the oracle's header
+states) name exact points; the gradient is that of the IoU function, which
+central differences approximate.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import exact_geom as X
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.jsonl")
+
+
+def _filtered(orc, a, b, a_nv=None, b_nv=None):
+    return orc.filtered_mask(orc.pair_margins(a, b, a_nv, b_nv))
+
+
+def _exact_pair_check(orc, p, q):
+    """Oracle intersection of one generic pair against exact rationals."""
+    P, Q = X.fpoly(p), X.fpoly(q)
+    V = X.clip(P, Q)
+    verts, codes = orc.intersect(p, q)
+    assert len(codes) == len(V), (len(codes), len(V))
+    if not V:
+        return
+    assert int(codes[0]) == int(codes.min()), "sequence must start at the smallest code"
+    assert len(set(codes.tolist())) == len(codes)
+    ex = [X.vertex_from_code(P, Q, int(c)) for c in codes]
+    # every code names a vertex of the exact intersection, and only that code does
+    assert set(ex) == set(V)
+    for c, v in zip(codes, ex):
+        assert X.classify(P, Q, v) == {int(c)}
+    # the oracle's fp64 vertices are the exact ones
+    scale = max(1.0, float(np.abs(p).max()), float(np.abs(q).max()))
+    for k, v in enumerate(ex):
+        assert abs(verts[k, 0] - float(v[0])) <= 1e-13 * scale
+        assert abs(verts[k, 1] - float(v[1])) <= 1e-13 * scale
+    # counter-clockwise and the same cyclic sequence as the exact clip
+    m = len(ex)
+    for k in range(m):
+        assert X.orient(ex[k], ex[(k + 1) % m], ex[(k + 2) % m]) > 0
+    s = V.index(ex[0])
+    assert V[s:] + V[:s] == ex
+    # area
+    ai = X.area(V)
+    assert abs(orc.area(verts) - float(ai)) <= 1e-13 * max(1.0, float(ai))
+    a1, a2 = X.area(P), X.area(Q)
+    iou_exact = ai / (a1 + a2 - ai)
+    return iou_exact
+
+
+def _pair_sets():
+    sets = []
+    d = synth.c1_pairs(n=160, seed=11)
+    sets.append((d["a_xy"], d["b_xy"], None, None))
+    d = synth.c3_pairs(n=160, seed=12)
+    sets.append((d["a_xy"], d["b_xy"], None, None))
+    d = synth.c4_polygons(n=200, seed=13)
+    sets.append((d["a_xy"], d["b_xy"], d["a_nv"], d["b_nv"]))
+    return sets
+
+
+def test_exact_rational_intersections(orc):
+    checked = 0
+    for a, b, anv, bnv in _pair_sets():
+        keep = _filtered(orc, a, b, anv, bnv)
+        iou, nx, xf, bad = orc.iou_pairs(a, b, anv, bnv)
+        assert bad == 0
+        for i in np.nonzero(keep)[0]:
+            n1 = int(anv[i]) if anv is not None else a.shape[1]
+            n2 = int(bnv[i]) if bnv is not None else b.shape[1]
+            iou_ex = _exact_pair_check(orc, a[i, :n1].astype(np.float64),
+                                       b[i, :n2].astype(np.float64))
+            if iou_ex is None:
+                assert nx[i] == 0 and iou[i] == 0.0
+            else:
+                assert abs(iou[i] - float(iou_ex)) <= 1e-13
+            checked += 1
+    assert checked > 400
+
+
+def test_clip_crosscheck_all_inputs(orc):
+    """Sutherland-Hodgman (a different algorithm) agrees on every input,
+    degenerate ones included."""
+    sets = _pair_sets()
+    sa, sb, _ = synth.degenerate_stress()
+    sets.append((sa, sb, None, None))
+    for a, b, anv, bnv in sets:
+        iou, nx, xf, bad = orc.iou_pairs(a, b, anv, bnv)
+        for i in range(a.shape[0]):
+            n1 = int(anv[i]) if anv is not None else a.shape[1]
+            n2 = int(bnv[i]) if bnv is not None else b.shape[1]
+            p, q = a[i, :n1].astype(np.float64), b[i, :n2].astype(np.float64)
+            ci = orc.clip_area(p, q)
+            if nx[i] == 0:
+                assert abs(ci) <= 1e-12
+                continue
+            verts, _ = orc.intersect(p, q)
+            assert abs(orc.area(verts) - ci) <= 1e-12 * max(1.0, abs(ci))
+            a1, a2 = orc.area(p), orc.area(q)
+            assert abs(iou[i] - ci / (a1 + a2 - ci)) <= 1e-12
+
+
+def test_golden_closed_forms(orc):
+    for line in open(GOLDEN):
+        c = json.loads(line)
+        P = np.array(c["P"], np.float64)
+        Q = np.array(c["Q"], np.float64)
+        # the stored fractions agree with the stated closed form
+        I, A1, A2 = Fraction(c["I"]), Fraction(c["A1"]), Fraction(c["A2"])
+        exp = Fraction(0) if I == 0 else I / (A1 + A2 - I)
+        assert exp == Fraction(c["iou"]), c["name"]
+        assert X.area(X.fpoly(P)) == A1 and X.area(X.fpoly(Q)) == A2
+        # oracle
+        k = max(P.shape[0], Q.shape[0])
+        a = np.zeros((1, k, 2), np.float32)
+        b = np.zeros((1, k, 2), np.float32)
+        a[0, :P.shape[0]] = P
+        b[0, :Q.shape[0]] = Q
+        anv = np.array([P.shape[0]], np.uint8)
+        bnv = np.array([Q.shape[0]], np.uint8)
+        iou, nx, xf, bad = orc.iou_pairs(a, b, anv, bnv)
+        assert abs(iou[0] - float(exp)) <= 1e-15, c["name"]
+        if not c["degenerate"]:
+            assert int(nx[0]) == c["nx"], c["name"]
+            assert xf[0, :nx[0]].tolist() == c["flags"], c["name"]
+            assert np.all(xf[0, nx[0]:] == 0xFF)
+
+
+def _aabb(x0, y0, x1, y1):
+    return np.array([[x0, y0], [x1, y0], [x1, y1], [x0, y1]], np.float32)
+
+
+def test_closed_form_axis_aligned(orc):
+    rng = np.random.default_rng(5)
+    n = 400
+    lo = rng.integers(-32, 32, (n, 2, 2)) / 8.0          # dyadic: exact in fp32
+    size = rng.integers(1, 24, (n, 2, 2)) / 8.0
+    hi = lo + size
+    a = np.stack([_aabb(lo[i, 0, 0], lo[i, 0, 1], hi[i, 0, 0], hi[i, 0, 1]) for i in range(n)])
+    b = np.stack([_aabb(lo[i, 1, 0], lo[i, 1, 1], hi[i, 1, 0], hi[i, 1, 1]) for i in range(n)])
+    iou, nx, xf, bad = orc.iou_pairs(a, b)
+    for i in range(n):
+        wx = min(hi[i, 0, 0], hi[i, 1, 0]) - max(lo[i, 0, 0], lo[i, 1, 0])
+        wy = min(hi[i, 0, 1], hi[i, 1, 1]) - max(lo[i, 0, 1], lo[i, 1, 1])
+        inter = max(0.0, wx) * max(0.0, wy)
+        a1 = size[i, 0, 0] * size[i, 0, 1]
+        a2 = size[i, 1, 0] * size[i, 1, 1]
+        exp = inter / (a1 + a2 - inter)
+        assert abs(iou[i] - exp) <= 1e-14, (i, iou[i], exp)
+
+
+def _square(theta, half=1.0):
+    c, s = math.cos(theta), math.sin(theta)
+    base = [(half, -half), (half, half), (-half, half), (-half, -half)]
+    return np.array([[c * x - s * y, s * x + c * y] for x, y in base], np.float64)
+
+
+def _rot_squares_closed(theta):
+    """Concentric squares of half-size 1 at relative angle theta in (0, pi/2):
+    each of the 8 corners cut off is a right triangle with legs a, b below."""
+    a = 1.0 - math.tan(theta / 2)
+    b = 1.0 - math.tan(math.pi / 4 - theta / 2)
+    inter = 4.0 - 2.0 * a * b
+    da = -0.5 / math.cos(theta / 2) ** 2
+    db = 0.5 / math.cos(math.pi / 4 - theta / 2) ** 2
+    dinter = -2.0 * (da * b + a * db)
+    return inter, dinter
+
+
+def test_closed_form_rotated_squares(orc):
+    thetas = np.linspace(0.05, math.pi / 2 - 0.05, 23)
+    a = np.stack([_square(0.0)] * len(thetas))
+    b = np.stack([_square(t) for t in thetas])
+    iou, nx, xf = orc.iou_pairs_f64(a, b)
+    ga, gb, _, _ = orc.iou_pairs_grad_f64(a, b, np.ones(len(thetas)), nx, xf)
+    for k, t in enumerate(thetas):
+        inter, dinter = _rot_squares_closed(t)
+        assert nx[k] == 8
+        assert all(c >= 0x40 for c in xf[k])          # only crossings
+        assert abs(iou[k] - inter / (8.0 - inter)) <= 1e-13
+        # d IoU / d theta through the rotation field (-y, x) applied to Q
+        dq = np.stack([-b[k, :, 1], b[k, :, 0]], axis=-1)
+        dIoU = float((gb[k] * dq).sum())
+        exp = 8.0 / (8.0 - inter) ** 2 * dinter
+        assert abs(dIoU - exp) <= 1e-11, (t, dIoU, exp)
+    # at 45 degrees: 1/sqrt(2) and a stationary intersection area
+    iou45, nx45, xf45 = orc.iou_pairs_f64(_square(0.0)[None], _square(math.pi / 4)[None])
+    assert abs(iou45[0] - 1 / math.sqrt(2)) <= 1e-14 and nx45[0] == 8
+
+
+def test_identity_disjoint_nested(orc):
+    d = synth.c4_polygons(n=300, seed=21)
+    a, anv = d["a_xy"], d["a_nv"]
+    iou, nx, xf, bad = orc.iou_pairs(a, a, anv, anv)
+    # identical polygons resolve (tie rule) into crossings of adjacent edges at
+    # the shared vertices; their homogeneous meet loses ~1/sin(turn) ulps
+    assert np.all(np.abs(iou - 1.0) <= 1e-12)
+    # disjoint: shift far away
+    b = a.copy()
+    b[..., 0] += 100.0
+    iou, nx, xf, _ = orc.iou_pairs(a, b, anv, anv)
+    assert np.all(iou == 0) and np.all(nx == 0) and np.all(xf == 0xFF)
+    # nested: shrink about an interior point (the vertex mean) by 1/2 (exact)
+    c = np.zeros_like(a)
+    for i in range(a.shape[0]):
+        n = int(anv[i])
+        m = a[i, :n].astype(np.float64).mean(axis=0)
+        m = np.round(m * 64) / 64          # dyadic centre keeps the scaling exact-ish
+        c[i, :n] = (m + 0.5 * (a[i, :n] - m)).astype(np.float32)
+    iou, nx, xf, _ = orc.iou_pairs(a, c, anv, anv)
+    for i in range(a.shape[0]):
+        n = int(anv[i])
+        inside = all(orc.polygon_valid(c[i, :n]) for _ in [0])
+        if not inside:
+            continue
+        P, Q = X.fpoly(a[i], n), X.fpoly(c[i], n)
+        if not all(X.orient(P[j], P[(j + 1) % n], q) > 0 for q in Q for j in range(n)):
+            continue
+        assert nx[i] == n and xf[i, :n].tolist() == [0x10 | j for j in range(n)]
+        assert abs(iou[i] - float(X.area(Q) / X.area(P))) <= 1e-13
+
+
+def test_symmetry_and_rigid_motion(orc):
+    d = synth.c1_pairs(n=500, seed=31)
+    a, b = d["a_xy"], d["b_xy"]
+    iou, nx, xf, _ = orc.iou_pairs(a, b)
+    iou_t, nx_t, _, _ = orc.iou_pairs(b, a)
+    assert np.all(nx == nx_t)
+    assert np.max(np.abs(iou - iou_t)) <= 1e-14
+    a64, b64 = a.astype(np.float64), b.astype(np.float64)
+    th = 0.7
+    R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    t = np.array([13.25, -7.5])
+    iou_m, nx_m, _ = orc.iou_pairs_f64(a64 @ R.T + t, b64 @ R.T + t)
+    iou0, nx0, _ = orc.iou_pairs_f64(a64, b64)
+    assert np.max(np.abs(iou_m - iou0)) <= 1e-12
+    assert np.all(nx_m == nx0)
+
+
+def test_power_of_two_scaling_is_exact(orc):
+    d = synth.c4_polygons(n=400, seed=41)
+    a, b, anv, bnv, g = d["a_xy"], d["b_xy"], d["a_nv"], d["b_nv"], d["grad"]
+    iou, nx, xf, _ = orc.iou_pairs(a, b, anv, bnv)
+    ga, gb, _, _ = orc.iou_pairs_grad(a, b, g, nx, xf, anv, bnv)
+    for k in (-3, 5):
+        s = np.float32(2.0 ** k)
+        iou_s, nx_s, xf_s, _ = orc.iou_pairs(a * s, b * s, anv, bnv)
+        assert np.array_equal(iou_s, iou) and np.array_equal(nx_s, nx) and np.array_equal(xf_s, xf)
+        ga_s, gb_s, _, _ = orc.iou_pairs_grad(a * s, b * s, g, nx_s, xf_s, anv, bnv)
+        assert np.array_equal(ga_s, ga * 2.0 ** -k) and np.array_equal(gb_s, gb * 2.0 ** -k)
+
+
+def _inside(poly, pts):
+    n = poly.shape[0]
+    ok = np.ones(pts.shape[0], bool)
+    for k in range(n):
+        a, b = poly[k], poly[(k + 1) % n]
+        ok &= (b[0] - a[0]) * (pts[:, 1] - a[1]) - (b[1] - a[1]) * (pts[:, 0] - a[0]) >= 0
+    return ok
+
+
+def test_rasterised_area(orc):
+    d = synth.c1_pairs(n=12, seed=51)
+    a, b = d["a_xy"].astype(np.float64), d["b_xy"].astype(np.float64)
+    iou, nx, xf, _ = orc.iou_pairs(d["a_xy"], d["b_xy"])
+    h = 0.004
+    for i in range(a.shape[0]):
+        lo = np.minimum(a[i].min(0), b[i].min(0))
+        hi = np.maximum(a[i].max(0), b[i].max(0))
+        xs = np.arange(lo[0] + h / 2, hi[0], h)
+        ys = np.arange(lo[1] + h / 2, hi[1], h)
+        gx, gy = np.meshgrid(xs, ys)
+        pts = np.stack([gx.ravel(), gy.ravel()], -1)
+        est = np.count_nonzero(_inside(a[i], pts) & _inside(b[i], pts)) * h * h
+        verts, _ = orc.intersect(a[i], b[i])
+        ai = orc.area(verts) if len(verts) else 0.0
+        per = sum(np.hypot(*(p[(k + 1) % 4] - p[k])) for p in (a[i], b[i]) for k in range(4))
+        assert abs(ai - est) <= 2.0 * per * h, (i, ai, est)
+
+
+# ---------------------------------------------------------------- gradient
+
+def _fd_grads(orc, a, b, az, bz, h, nx, xf, keep):
+    n, ka = a.shape[:2]
+    kb = b.shape[1]
+    coords = [("a", k, c) for k in range(ka) for c in range(2)] + \
+             [("b", k, c) for k in range(kb) for c in range(2)]
+    if az is not None:
+        coords += [("az", 0, c) for c in range(2)] + [("bz", 0, c) for c in range(2)]
+    cols = []
+    for which, k, c in coords:
+        vals = []
+        for sgn in (1.0, -1.0):
+            aa, bb = a.copy(), b.copy()
+            zz1 = None if az is None else az.copy()
+            zz2 = None if bz is None else bz.copy()
+            if which == "a":
+                aa[:, k, c] += sgn * h
+            elif which == "b":
+                bb[:, k, c] += sgn * h
+            elif which == "az":
+                zz1[:, c] += sgn * h
+            else:
+                zz2[:, c] += sgn * h
+            v, nx_p, xf_p = orc.iou_pairs_f64(aa, bb, zz1, zz2)
+            keep &= (nx_p == nx) & np.all(xf_p == xf, axis=1)
+            vals.append(v)
+        cols.append((vals[0] - vals[1]) / (2 * h))
+    return np.stack(cols, 1)
+
+
+def _fd_check(orc, a, b, az=None, bz=None, h=1e-3):
+    """Central differences of IoU in fp64 (step h, and h/2 for a Richardson
+    step that cancels the O(h^2) truncation term) vs the analytic gradient, on
+    pairs whose nx and flags do not change at +-h, +-h/2 in any coordinate.
+    Returns per-pair relative errors (plain, extrapolated) and the mask."""
+    n = a.shape[0]
+    iou, nx, xf = orc.iou_pairs_f64(a, b, az, bz)
+    ga, gb, gaz, gbz = orc.iou_pairs_grad_f64(a, b, np.ones(n), nx, xf, az, bz)
+    keep = nx > 0
+    if az is not None:
+        # the z-overlap min(hi) - max(lo) has kinks where the extents' ends
+        # coincide or the overlap closes: keep pairs at least 2h away from them
+        hz = np.minimum(az[:, 1], bz[:, 1]) - np.maximum(az[:, 0], bz[:, 0])
+        keep &= (np.abs(az[:, 1] - bz[:, 1]) > 2 * h) & (np.abs(az[:, 0] - bz[:, 0]) > 2 * h)
+        keep &= hz > 2 * h
+    fd1 = _fd_grads(orc, a, b, az, bz, h, nx, xf, keep)
+    fd2 = _fd_grads(orc, a, b, az, bz, h / 2, nx, xf, keep)
+    fdr = (4.0 * fd2 - fd1) / 3.0
+    an = np.concatenate([ga.reshape(n, -1), gb.reshape(n, -1)], 1)
+    if az is not None:
+        an = np.concatenate([an, gaz, gbz], 1)
+    den = np.maximum(np.linalg.norm(an, axis=1), 1e-8)
+    e1 = np.linalg.norm(an - fd1, axis=1) / den
+    er = np.linalg.norm(an - fdr, axis=1) / den
+    return e1[keep], er[keep], keep
+
+
+def _check_fd(orc, a, b, az=None, bz=None, a_f32=None, b_f32=None):
+    e1, er, keep = _fd_check(orc, a, b, az, bz)
+    # extrapolated differences: truncation O(h^4), agreement to 1e-5 everywhere
+    assert er.max() <= 1e-5, np.sort(er)[-5:]
+    # plain h = 1e-3 differences: the truncation term grows like 1/sin^3 of the
+    # crossing angle and like 1/size of the intersection, so 1e-4 is asserted
+    # where every crossing has |sin| >= 0.1, every vertex is >= 1e-2 L from
+    # every edge line and the IoU is >= 1e-2 (the intersection is >> h)
+    if a_f32 is not None:
+        m = orc.pair_margins(a_f32, b_f32)[keep]
+        iou, _, _ = orc.iou_pairs_f64(a, b, az, bz)
+        good = (m[:, 1] >= 0.1) & (m[:, 0] >= 1e-2) & (iou[keep] >= 1e-2)
+        assert e1[good].max() <= 1e-4, np.sort(e1[good])[-5:]
+    return keep
+
+
+def test_gradient_vs_finite_differences_rectangles(orc):
+    d = synth.c3_pairs(n=4096, seed=61)
+    a, b = d["a_xy"].astype(np.float64), d["b_xy"].astype(np.float64)
+    keep = _check_fd(orc, a, b, a_f32=d["a_xy"], b_f32=d["b_xy"])
+    assert keep.sum() > 3000
+
+
+def test_gradient_vs_finite_differences_polygons(orc):
+    d = synth.c4_polygons(n=3000, seed=62)
+    checked = 0
+    for n1 in range(3, 9):
+        for n2 in (3, 5, 8):
+            sel = (d["a_nv"] == n1) & (d["b_nv"] == n2)
+            if sel.sum() == 0:
+                continue
+            a = d["a_xy"][sel, :n1].astype(np.float64)
+            b = d["b_xy"][sel, :n2].astype(np.float64)
+            keep = _check_fd(orc, a, b, a_f32=d["a_xy"][sel, :n1], b_f32=d["b_xy"][sel, :n2])
+            checked += keep.sum()
+    assert checked > 200
+
+
+def test_gradient_vs_finite_differences_3d(orc):
+    d = synth.c1_pairs(n=1500, seed=63)
+    rng = np.random.default_rng(64)
+    a, b = d["a_xy"].astype(np.float64), d["b_xy"].astype(np.float64)
+    z = rng.uniform(-2, 1, (a.shape[0], 2))
+    hgt = rng.uniform(1.4, 1.8, (a.shape[0], 2))
+    az = np.stack([z[:, 0] - hgt[:, 0] / 2, z[:, 0] + hgt[:, 0] / 2], 1)
+    bz = np.stack([z[:, 1] - hgt[:, 1] / 2, z[:, 1] + hgt[:, 1] / 2], 1)
+    keep = _check_fd(orc, a, b, az, bz, a_f32=d["a_xy"], b_f32=d["b_xy"])
+    assert keep.sum() > 300
+
+
+def test_gradient_invariants(orc):
+    """IoU is invariant under translation, rotation and scaling, so its
+    gradient field is orthogonal to those motions (summed over all vertices)."""
+    for d in (synth.c3_pairs(n=2000, seed=71), synth.c4_polygons(n=2000, seed=72)):
+        a, b = d["a_xy"], d["b_xy"]
+        anv, bnv = d.get("a_nv"), d.get("b_nv")
+        iou, nx, xf, _ = orc.iou_pairs(a, b, anv, bnv)
+        ga, gb, _, _ = orc.iou_pairs_grad(a, b, d["grad"], nx, xf, anv, bnv)
+        pts = np.concatenate([a, b], 1).astype(np.float64)
+        grd = np.concatenate([ga, gb], 1)
+        # padded slots carry zero gradient, so they drop out of the sums
+        scale = np.abs(grd).sum((1, 2)) * (1 + np.abs(pts).max((1, 2)))
+        tr = np.abs(grd.sum(1)).max(1)
+        rot = np.abs((pts[..., 0] * grd[..., 1] - pts[..., 1] * grd[..., 0]).sum(1))
+        sc = np.abs((pts[..., 0] * grd[..., 0] + pts[..., 1] * grd[..., 1]).sum(1))
+        assert np.all(tr <= 1e-13 * scale + 1e-300)
+        assert np.all(rot <= 1e-13 * scale + 1e-300)
+        assert np.all(sc <= 1e-13 * scale + 1e-300)
+
+
+def test_empty_pairs_have_zero_gradient(orc):
+    a, b, _ = synth.degenerate_stress()
+    iou, nx, xf, _ = orc.iou_pairs(a, b)
+    ga, gb, _, _ = orc.iou_pairs_grad(a, b, np.ones(a.shape[0]), nx, xf)
+    for i in range(a.shape[0]):
+        if nx[i] == 0:
+            assert not ga[i].any() and not gb[i].any()
+
+
+# ---------------------------------------------------------------- 3D
+
+def test_3d_closed_forms(orc):
+    d = synth.c1_pairs(n=300, seed=81)
+    a, b = d["a_xy"], d["b_xy"]
+    rng = np.random.default_rng(82)
+    lo = rng.uniform(-2, 1, 300).astype(np.float32)
+    hi = (lo + rng.uniform(1.4, 1.8, 300)).astype(np.float32)
+    iou2, _, _, _ = orc.iou_pairs(a, b)
+    iou3, _, _, _ = orc.iou_pairs(a, b, a_z=(lo, hi), b_z=(lo, hi))
+    assert np.max(np.abs(iou3 - iou2)) <= 1e-14     # equal z-extents reduce to 2D
+    # identical footprints: IoU3 = hz / (h1 + h2 - hz)
+    lo2 = (lo + rng.uniform(-1, 1, 300)).astype(np.float32)
+    hi2 = (lo2 + rng.uniform(1.4, 1.8, 300)).astype(np.float32)
+    iou3, _, _, _ = orc.iou_pairs(a, a, a_z=(lo, hi), b_z=(lo2, hi2))
+    l1, h1, l2, h2 = (x.astype(np.float64) for x in (lo, hi, lo2, hi2))
+    hz = np.maximum(0, np.minimum(h1, h2) - np.maximum(l1, l2))
+    exp = hz / ((h1 - l1) + (h2 - l2) - hz)
+    assert np.max(np.abs(iou3 - exp)) <= 1e-13
+
+
+# ---------------------------------------------------------------- matrices
+
+def test_matrix_matches_pairs_and_self_diagonal(orc):
+    d = synth.c5_scenes(scenes=3, nmin=20, nmax=40, seed=91)
+    xy, lo, hi, off = d["a_xy"], d["a_zlo"], d["a_zhi"], d["off"]
+    m, out_off = orc.iou_matrix(xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    assert np.array_equal(out_off, d["out_off"])
+    for s in range(3):
+        n = int(off[s + 1] - off[s])
+        blk = m[out_off[s]:out_off[s + 1]].reshape(n, n)
+        assert np.all(np.diag(blk) == 1.0)
+        r, c = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        ia, ib = (r.ravel() + off[s]), (c.ravel() + off[s])
+        v, _, _ = orc.iou_index_pairs(ia, ib, xy, xy, a_z=(lo, hi), b_z=(lo, hi))
+        v = v.reshape(n, n)
+        np.fill_diagonal(v, 1.0)
+        assert np.array_equal(v, blk)
+        assert np.max(np.abs(blk - blk.T)) <= 1e-14
+
+
+def test_matrix_grad_is_sum_of_pair_grads(orc):
+    d = synth.c5_scenes(scenes=2, nmin=15, nmax=25, seed=92)
+    xy, lo, hi, off = d["a_xy"], d["a_zlo"], d["a_zhi"], d["off"]
+    # crowd the boxes so that many pairs overlap
+    c = xy.astype(np.float64).mean(1, keepdims=True)
+    xy = (xy - c + 0.08 * c).astype(np.float32)
+    g = np.random.default_rng(93).uniform(-1, 1, int(d["out_off"][-1]))
+    ga, _, gaz, _ = orc.iou_matrix_grad(g, xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    ref = np.zeros_like(ga)
+    refz = np.zeros_like(gaz)
+    for s in range(2):
+        n = int(off[s + 1] - off[s])
+        r, c = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        sel = (r != c).ravel()
+        ia = (r.ravel() + off[s])[sel]
+        ib = (c.ravel() + off[s])[sel]
+        gs = g[d["out_off"][s]:d["out_off"][s + 1]][sel]
+        _, nx, xf = orc.iou_index_pairs(ia, ib, xy, xy, a_z=(lo, hi), b_z=(lo, hi))
+        pa, pb, pz1, pz2 = orc.iou_pairs_grad(xy[ia], xy[ib], gs, nx, xf,
+                                              a_z=(lo[ia], hi[ia]), b_z=(lo[ib], hi[ib]))
+        np.add.at(ref, ia, pa)
+        np.add.at(ref, ib, pb)
+        np.add.at(refz, ia, pz1)
+        np.add.at(refz, ib, pz2)
+    assert np.max(np.abs(ga - ref)) <= 1e-12
+    assert np.max(np.abs(gaz - refz)) <= 1e-12
+    assert np.abs(ga).max() > 0
