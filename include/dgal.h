@@ -1,0 +1,180 @@
+/*
+ * dgal.h -- C ABI of the MI355X (gfx950) library for batched, differentiable
+ * convex-polygon intersection-over-union.
+ *
+ * Paper: Y. Zhong, "Differentiable Computational Geometry for 2D and 3D machine
+ * learning", arXiv 2011.11134.  Its Sec. II-B listing defines the operation:
+ * the IoU of two convex polygons is the area of their intersection over
+ * area(p1) + area(p2) - area(intersection); the forward keeps the number of
+ * intersection vertices (nx) and one provenance flag per intersection vertex
+ * (xflags), and the gradient is computed from the two polygons, the upstream
+ * gradient, nx and xflags.  Sec. III fixes the data: polygons are convex,
+ * counter-clockwise, stored in fixed-capacity vertex arrays, and gradients are
+ * stored in the same polygon layout.  Sec. IV-A applies it to rotated 2D and
+ * 3D boxes.
+ *
+ * Conventions for every entry point:
+ *   - Every data pointer is CALLER-OWNED DEVICE memory on the context's device.
+ *     Nothing is retained after the call returns.
+ *   - Work is enqueued on `stream` (a hipStream_t, passed as void*; NULL is the
+ *     null stream) and runs asynchronously.  Outputs are OVERWRITTEN.
+ *   - The library allocates no memory per call; its only allocations are made
+ *     by dgal_create (a small workspace) and freed by dgal_destroy.
+ *   - Returns DGAL_OK (0) or a negative status.  Arguments are validated on the
+ *     host before anything is enqueued; on error nothing is enqueued.  No C++
+ *     exception crosses this interface.
+ *   - Per-element data (vertex counts outside [3, kmax], clockwise or
+ *     non-convex polygons) is not validated: results for such elements are
+ *     unspecified, but every memory access stays in bounds.  An intersection
+ *     that would overflow its capacity (possible only for invalid polygons)
+ *     sets a sticky device error that dgal_check reports as DGAL_ECAPACITY.
+ *   - A context may be used from one host thread at a time.
+ *
+ * Polygon layout (Sec. III): xy is [count][kmax][2] fp32 (x, y interleaved),
+ * vertices counter-clockwise and strictly convex, slots >= nv[i] ignored;
+ * the base pointer must be 8-byte aligned.  Intersections hold at most
+ * kmax_a + kmax_b vertices.
+ *
+ * Provenance codes (one uint8 per intersection vertex, listed counter-
+ * clockwise starting at the smallest code; unused slots hold 0xFF):
+ *   vertex i of polygon a             -> i               (0x00..0x07)
+ *   vertex j of polygon b             -> 0x10 | j        (0x10..0x17)
+ *   edge i of a crossing edge j of b  -> 0x40 | i<<3 | j (0x40..0x7F)
+ * Edge i runs from vertex i to vertex (i+1) mod n.
+ *
+ * Degenerate contacts (a vertex exactly on an edge line, collinear edges,
+ * identical polygons) are resolved as if polygon b were moved by
+ * (eps, eps^2), eps -> 0+; exact zeros of the orientation test take the sign
+ * of that motion.  Orientation signs are certified in fp32 and recomputed in
+ * fp64 (exactly, for fp32 inputs) when fp32 cannot certify them.
+ */
+#ifndef DGAL_H
+#define DGAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DGAL_OK = 0,
+  DGAL_EINVAL = -1,    /* invalid argument (see each entry point) */
+  DGAL_ECAPACITY = -2, /* deferred: an intersection or a saved-pair list overflowed */
+  DGAL_EHIP = -3       /* HIP runtime or launch error */
+};
+
+typedef struct dgal_ctx dgal_ctx;
+
+/* A set of polygons (Sec. III), optionally with a z-extent for 3D boxes. */
+typedef struct {
+  const float *xy;     /* [count][kmax][2] fp32, 8-byte aligned                  */
+  const uint8_t *nv;   /* [count] vertex counts in [3, kmax]; NULL => all kmax     */
+  const float *zlo;    /* [count] bottom of the z-extent, or NULL for 2D          */
+  const float *zhi;    /* [count] top of the z-extent, or NULL for 2D             */
+  int64_t count;       /* number of polygons, >= 0                                */
+  int32_t kmax;        /* vertex capacity, 3..8                                   */
+} dgal_polys;
+
+/* Creates a context on HIP device `hip_device` (allocates a small device
+ * workspace).  *out is set to NULL on failure.  Returns DGAL_OK, DGAL_EINVAL
+ * (out == NULL) or DGAL_EHIP. */
+int dgal_create(dgal_ctx **out, int hip_device);
+
+/* Frees the context and its workspace; NULL is a no-op.  The caller must make
+ * sure no work enqueued with the context is still running. */
+void dgal_destroy(dgal_ctx *ctx);
+
+/* Static string for a status code. */
+const char *dgal_status_string(int status);
+
+/* Synchronises `stream`, then returns (and clears) any sticky device-side
+ * error: DGAL_ECAPACITY (an overflow), DGAL_EINVAL (segment offsets the
+ * kernels rejected), DGAL_EHIP for a runtime error, else DGAL_OK. */
+int dgal_check(dgal_ctx *ctx, void *stream);
+
+/* Sec. II-B listing, batched: iou[i] = IoU(a[i], b[i]) for i < a.count.
+ * 3D (all four z pointers non-NULL): BEV intersection area times the
+ * z-overlap, over the union volume (Sec. IV-A "3D IoU").
+ *   iou    [count] fp32
+ *   nx     [count] uint8 intersection vertex counts        } saved for the
+ *   xflags [count][a.kmax + b.kmax] uint8 provenance codes } backward; both
+ *          NULL => forward only.
+ * DGAL_EINVAL: ctx/iou/a.xy/b.xy NULL with count > 0, count < 0, a.count !=
+ * b.count, kmax outside 3..8, exactly one of nx/xflags NULL, z pointers given
+ * for only one of a/b or only one of zlo/zhi, misaligned xy. */
+int dgal_iou_pairs(dgal_ctx *ctx, dgal_polys a, dgal_polys b, float *iou,
+                   uint8_t *nx, uint8_t *xflags, void *stream);
+
+/* Compact list of the matrix pairs whose intersection is non-empty, written
+ * by dgal_iou_matrix for the backward (every other pair has zero gradient).
+ * All pointers are device memory; *count is a device int64 that the forward
+ * overwrites.  Entries appear in no particular order. */
+typedef struct {
+  int64_t *pair_id;  /* [capacity] index into the flat iou output            */
+  uint8_t *nx;       /* [capacity]                                           */
+  uint8_t *xflags;   /* [capacity][a.kmax + b.kmax]                          */
+  int64_t capacity;  /* entries available; overflow => DGAL_ECAPACITY (deferred) */
+  int64_t *count;    /* device scalar: number of entries written (<= capacity) */
+} dgal_saved;
+
+/* Most segments one matrix call may hold. */
+#define DGAL_MAX_SEGMENTS 4096
+
+/* IoU matrices (Sec. IV-A case study at scale), segmented.  For segment s,
+ * rows a[a_off[s] .. a_off[s+1]) and columns b[b_off[s] .. b_off[s+1]) form a
+ * row-major block of iou starting at element out_off[s].  With a_off ==
+ * b_off == out_off == NULL (nseg ignored) there is one block a.count x b.count
+ * at iou[0].  self_pairs != 0 means b is a (same pointers and counts; each
+ * segment's block is square): the diagonal of each block is exactly 1.
+ *   a_off, b_off  DEVICE int64 [nseg+1], non-decreasing, within [0, count]
+ *   out_off       DEVICE int64 [nseg]
+ *   out_size      number of fp32 elements the caller allocated at iou
+ *   iou           flat fp32 output
+ *   saved         NULL => forward only; else filled for dgal_iou_backward.
+ * Offsets live on the device so that the call can be captured in a HIP graph;
+ * the kernels check them (a block outside [0, out_size) or rows/columns
+ * outside [0, count) is skipped and reported by dgal_check as DGAL_EINVAL).
+ * DGAL_EINVAL (immediate): as dgal_iou_pairs except a.count == b.count, plus
+ * some but not all offsets NULL, nseg outside [1, DGAL_MAX_SEGMENTS] with
+ * offsets, out_size < a.count * b.count without offsets, self_pairs with a and
+ * b differing, saved with a NULL field or capacity < 0. */
+int dgal_iou_matrix(dgal_ctx *ctx, dgal_polys a, dgal_polys b,
+                    const int64_t *a_off, const int64_t *b_off,
+                    const int64_t *out_off, int32_t nseg, int32_t self_pairs,
+                    float *iou, int64_t out_size, const dgal_saved *saved,
+                    void *stream);
+
+enum { DGAL_PAIRS = 0, DGAL_MATRIX = 1 };
+
+/* Sec. II-B `iou_grad`: gradient of sum(grad_iou * iou) with respect to the
+ * vertices (and z-extents) of a and b, from the saved state of the forward
+ * (no intersection is recomputed from predicates).
+ * mode DGAL_PAIRS:  grad_iou [count]; nx, xflags as written by dgal_iou_pairs;
+ *                   saved and offsets ignored.
+ * mode DGAL_MATRIX: grad_iou has the shape of the matrix output (out_size
+ *                   elements, ignored in pairs mode); `saved` as
+ *                   written by dgal_iou_matrix with the same a, b, offsets and
+ *                   self_pairs; nx / xflags ignored.  With self_pairs the
+ *                   gradient of both roles accumulates into grad_a_* and
+ *                   grad_b_* must be NULL; the diagonal contributes nothing.
+ * Outputs (overwritten; padded vertex slots are written 0):
+ *   grad_a_xy [a.count][a.kmax][2], grad_b_xy [b.count][b.kmax][2] fp32
+ *   grad_a_z, grad_b_z [count][2] fp32 = (d/dzlo, d/dzhi); NULL for 2D.
+ * The matrix mode sums contributions with fp32 atomics, so its low-order bits
+ * may vary from run to run.
+ * DGAL_EINVAL: as the forward, plus a NULL required output or saved state, an
+ * unknown mode, z outputs requested for 2D input. */
+int dgal_iou_backward(dgal_ctx *ctx, int32_t mode, dgal_polys a, dgal_polys b,
+                      const int64_t *a_off, const int64_t *b_off,
+                      const int64_t *out_off, int32_t nseg, int32_t self_pairs,
+                      const float *grad_iou, int64_t out_size, const uint8_t *nx,
+                      const uint8_t *xflags, const dgal_saved *saved,
+                      float *grad_a_xy, float *grad_b_xy, float *grad_a_z,
+                      float *grad_b_z, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGAL_H */

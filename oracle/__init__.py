@@ -210,11 +210,11 @@ def iou_matrix_grad(g, a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None
 
 
 def pair_margins(a_xy, b_xy, a_nv=None, b_nv=None, threads=1):
-    """Degeneracy margins [n, 4] (see oracle_pair_margins)."""
+    """Degeneracy margins [n, 5] (see oracle_pair_margins)."""
     ka_keep, ka_args = _poly_args(a_xy, a_nv)
     kb_keep, kb_args = _poly_args(b_xy, b_nv)
     n = ka_keep[0].shape[0]
-    out = np.zeros((n, 4), np.float64)
+    out = np.zeros((n, 5), np.float64)
     L = lib()
     _run(lambda lo, hi: L.oracle_pair_margins(lo, hi, ka_args[0], ka_args[1], ka_args[2],
                                               kb_args[0], kb_args[1], kb_args[2],
@@ -227,12 +227,13 @@ FILTER_DELTA = 1e-4      # vertex/edge margin
 FILTER_SIN = 1e-3        # crossing angle
 FILTER_TURN = 1e-3       # polygon strict convexity
 FILTER_GAP = 1e-4        # angular gap between ordered intersection vertices
+FILTER_SLIVER = 1e-4     # intersection area / smaller polygon area, if non-empty
 
 
 def filtered_mask(margins):
     m = np.asarray(margins)
     return ((m[:, 0] >= FILTER_DELTA) & (m[:, 1] >= FILTER_SIN) & (m[:, 2] >= FILTER_TURN)
-            & (m[:, 3] >= FILTER_GAP))
+            & (m[:, 3] >= FILTER_GAP) & (m[:, 4] >= FILTER_SLIVER))
 
 
 def polygon_valid(xy):

@@ -661,23 +661,25 @@ void oracle_iou_matrix_grad(int nseg, const int64_t *a_off, const int64_t *b_off
   }
 }
 
-/* Degeneracy margins of pairs [lo, hi), four per pair (used to select the
+/* Degeneracy margins of pairs [lo, hi), five per pair (used to select the
  * generator-filtered parity set):
  *   [0] min |orient(e_s, e_e, v)| / (|e_e - e_s| * L) over all vertex/edge
  *       tests, L = bounding-box diagonal of P u Q;
  *   [1] min |sin| of the angle between two crossing edges (1 if none);
  *   [2] min normalised turn orient/(|u||w|) over the vertices of P and Q;
  *   [3] min normalised cross product between consecutive ordered intersection
- *       vertices seen from the centroid (1 if empty). */
+ *       vertices seen from the centroid (1 if empty);
+ *   [4] intersection area over the smaller polygon area (1 if empty): a
+ *       sliver sits next to the change to an empty intersection. */
 void oracle_pair_margins(int64_t lo, int64_t hi, const float *a_xy,
                          const uint8_t *a_nv, int ka, const float *b_xy,
                          const uint8_t *b_nv, int kb, double *out) {
   for (int64_t i = lo; i < hi; ++i) {
     point P[ORC_MAXV], Q[ORC_MAXV];
-    double *o = out + 4 * i;
+    double *o = out + 5 * i;
     int n1 = load_poly(a_xy, a_nv, ka, i, P), n2 = load_poly(b_xy, b_nv, kb, i, Q);
     if (n1 < 0 || n2 < 0) {
-      o[0] = o[1] = o[2] = o[3] = 0.0;
+      o[0] = o[1] = o[2] = o[3] = o[4] = 0.0;
       continue;
     }
     double xmin = P[0].x, xmax = P[0].x, ymin = P[0].y, ymax = P[0].y;
@@ -730,10 +732,18 @@ void oracle_pair_margins(int64_t lo, int64_t hi, const float *a_xy,
     } else if (m > 0) {
       gmin = 0.0;
     }
+    double sliver = 1.0;
+    if (m >= 3) {
+      double a1 = area(P, n1), a2 = area(Q, n2);
+      sliver = area(X.v, m) / (a1 < a2 ? a1 : a2);
+    } else if (m > 0) {
+      sliver = 0.0;
+    }
     o[0] = dmin;
     o[1] = smin;
     o[2] = tmin;
     o[3] = gmin;
+    o[4] = sliver;
   }
 }
 

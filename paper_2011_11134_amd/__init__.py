@@ -1,0 +1,373 @@
+"""Batched, differentiable convex-polygon IoU on MI355X (gfx950).
+
+Thin ctypes binding over the C ABI in include/dgal.h (libdgal.so, built by
+paper_2011_11134_amd/build.py): argument marshalling only; every step of the
+computation runs in the library's HIP kernels on torch's current stream.
+There is no CPU fallback: without the built library the import fails.
+
+Paper: Y. Zhong, "Differentiable Computational Geometry for 2D and 3D machine
+learning", arXiv 2011.11134 (Sec. II-B listing: IoU with saved nx / xflags and
+its gradient; Sec. III: convex CCW polygons in fixed-capacity arrays; Sec.
+IV-A: rotated 2D/3D box IoU).
+"""
+import atexit
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgal.so")
+
+DGAL_OK, DGAL_EINVAL, DGAL_ECAPACITY, DGAL_EHIP = 0, -1, -2, -3
+DGAL_PAIRS, DGAL_MATRIX = 0, 1
+MAX_SEGMENTS = 4096
+
+_vp = ctypes.c_void_p
+
+
+class Polys(ctypes.Structure):
+    """dgal_polys"""
+    _fields_ = [("xy", _vp), ("nv", _vp), ("zlo", _vp), ("zhi", _vp),
+                ("count", ctypes.c_int64), ("kmax", ctypes.c_int32)]
+
+
+class Saved(ctypes.Structure):
+    """dgal_saved"""
+    _fields_ = [("pair_id", _vp), ("nx", _vp), ("xflags", _vp),
+                ("capacity", ctypes.c_int64), ("count", _vp)]
+
+
+EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
+           "dgal_iou_pairs", "dgal_iou_matrix", "dgal_iou_backward")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python {_HERE}/build.py` "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    L.dgal_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+    L.dgal_create.restype = ctypes.c_int
+    L.dgal_destroy.argtypes = [_vp]
+    L.dgal_destroy.restype = None
+    L.dgal_status_string.argtypes = [ctypes.c_int]
+    L.dgal_status_string.restype = ctypes.c_char_p
+    L.dgal_check.argtypes = [_vp, _vp]
+    L.dgal_check.restype = ctypes.c_int
+    L.dgal_iou_pairs.argtypes = [_vp, Polys, Polys, _vp, _vp, _vp, _vp]
+    L.dgal_iou_pairs.restype = ctypes.c_int
+    L.dgal_iou_matrix.argtypes = [_vp, Polys, Polys, _vp, _vp, _vp, i32, i32, _vp, i64,
+                                  ctypes.POINTER(Saved), _vp]
+    L.dgal_iou_matrix.restype = ctypes.c_int
+    L.dgal_iou_backward.argtypes = [_vp, i32, Polys, Polys, _vp, _vp, _vp, i32, i32, _vp, i64,
+                                    _vp, _vp, ctypes.POINTER(Saved), _vp, _vp, _vp, _vp, _vp]
+    L.dgal_iou_backward.restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+_ctx = {}
+
+
+def _destroy_all():
+    for c in _ctx.values():
+        lib.dgal_destroy(c)
+    _ctx.clear()
+
+
+atexit.register(_destroy_all)
+
+
+class DgalError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {lib.dgal_status_string(status).decode()}")
+        self.status = status
+
+
+def _ok(status, what):
+    if status != DGAL_OK:
+        raise DgalError(status, what)
+
+
+def context(device=None):
+    """The library context of a CUDA/HIP device (created once)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    c = _ctx.get(idx)
+    if c is None:
+        h = _vp()
+        _ok(lib.dgal_create(ctypes.byref(h), idx), "dgal_create")
+        c = h.value
+        _ctx[idx] = c
+    return c
+
+
+def _stream(t):
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _need(t, dtype, name, dev=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (the library has no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dev is not None and t.device != dev:
+        raise ValueError(f"{name} is on {t.device}, expected {dev}")
+    return t
+
+
+def polys(xy, nv=None, z=None):
+    """Describes [n, kmax, 2] fp32 polygons (+ optional [n] uint8 counts and a
+    (zlo, zhi) pair of [n] fp32 tensors) as a dgal_polys; returns (struct, keep)."""
+    _need(xy, torch.float32, "xy")
+    if xy.dim() != 3 or xy.shape[2] != 2:
+        raise ValueError("polygons must be [n, kmax, 2]")
+    n, k = xy.shape[0], xy.shape[1]
+    if nv is not None:
+        _need(nv, torch.uint8, "nv", xy.device)
+        if nv.shape != (n,):
+            raise ValueError("nv must be [n]")
+    zlo = zhi = None
+    if z is not None:
+        zlo, zhi = z
+        _need(zlo, torch.float32, "zlo", xy.device)
+        _need(zhi, torch.float32, "zhi", xy.device)
+        if zlo.shape != (n,) or zhi.shape != (n,):
+            raise ValueError("zlo / zhi must be [n]")
+    s = Polys(_ptr(xy), _ptr(nv), _ptr(zlo), _ptr(zhi), n, k)
+    return s, (xy, nv, zlo, zhi)
+
+
+# --------------------------------------------------------------------- pairs
+
+def iou_pairs(a_xy, b_xy, a_nv=None, b_nv=None, a_z=None, b_z=None, save=True):
+    """IoU of elementwise pairs (Sec. II-B listing, batched).
+
+    Returns (iou [n] fp32, nx [n] uint8, xflags [n, ka+kb] uint8); nx and
+    xflags are None when save is False."""
+    pa, ka = polys(a_xy, a_nv, a_z)
+    pb, kb = polys(b_xy, b_nv, b_z)
+    n = a_xy.shape[0]
+    dev = a_xy.device
+    iou = torch.empty(n, dtype=torch.float32, device=dev)
+    nx = xf = None
+    if save:
+        nx = torch.empty(n, dtype=torch.uint8, device=dev)
+        xf = torch.empty((n, a_xy.shape[1] + b_xy.shape[1]), dtype=torch.uint8, device=dev)
+    _ok(lib.dgal_iou_pairs(context(dev), pa, pb, _ptr(iou), _ptr(nx), _ptr(xf), _stream(a_xy)),
+        "dgal_iou_pairs")
+    return iou, nx, xf
+
+
+def iou_pairs_backward(a_xy, b_xy, grad, nx, xflags, a_nv=None, b_nv=None, a_z=None, b_z=None):
+    """Gradient of sum(grad * IoU) from the saved nx / xflags (Sec. II-B
+    `iou_grad`).  Returns (grad_a [n,ka,2], grad_b [n,kb,2], grad_a_z [n,2] or
+    None, grad_b_z [n,2] or None); z gradients are (d/dzlo, d/dzhi)."""
+    pa, ka = polys(a_xy, a_nv, a_z)
+    pb, kb = polys(b_xy, b_nv, b_z)
+    dev = a_xy.device
+    _need(grad, torch.float32, "grad", dev)
+    _need(nx, torch.uint8, "nx", dev)
+    _need(xflags, torch.uint8, "xflags", dev)
+    ga = torch.empty_like(a_xy)
+    gb = torch.empty_like(b_xy)
+    gaz = gbz = None
+    if a_z is not None:
+        gaz = torch.empty((a_xy.shape[0], 2), dtype=torch.float32, device=dev)
+        gbz = torch.empty((b_xy.shape[0], 2), dtype=torch.float32, device=dev)
+    _ok(lib.dgal_iou_backward(context(dev), DGAL_PAIRS, pa, pb, None, None, None, 0, 0, _ptr(grad),
+                              0, _ptr(nx), _ptr(xflags), None, _ptr(ga), _ptr(gb), _ptr(gaz),
+                              _ptr(gbz), _stream(a_xy)),
+        "dgal_iou_backward(pairs)")
+    return ga, gb, gaz, gbz
+
+
+# --------------------------------------------------------------------- matrix
+
+class SavedPairs:
+    """Device buffers of a dgal_saved list (non-empty pairs of a matrix)."""
+
+    def __init__(self, capacity, cap, device):
+        self.pair_id = torch.empty(capacity, dtype=torch.int64, device=device)
+        self.nx = torch.empty(capacity, dtype=torch.uint8, device=device)
+        self.xflags = torch.empty((capacity, cap), dtype=torch.uint8, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+        self.capacity = capacity
+
+    def struct(self):
+        return Saved(_ptr(self.pair_id), _ptr(self.nx), _ptr(self.xflags), self.capacity,
+                     _ptr(self.count))
+
+
+def _segments(n_a, n_b, a_off, b_off, self_pairs, dev):
+    """Device offsets (a_off, b_off, out_off) and total output size."""
+    if a_off is None:
+        return None, None, None, 0, n_a * n_b
+    a_off = torch.as_tensor(a_off, dtype=torch.int64)
+    b_off = a_off if (self_pairs or b_off is None) else torch.as_tensor(b_off, dtype=torch.int64)
+    a_cpu, b_cpu = a_off.cpu(), b_off.cpu()
+    sizes = (a_cpu[1:] - a_cpu[:-1]) * (b_cpu[1:] - b_cpu[:-1])
+    out_off = torch.cat([torch.zeros(1, dtype=torch.int64), torch.cumsum(sizes, 0)[:-1]])
+    total = int(sizes.sum())
+    nseg = int(a_cpu.numel() - 1)
+    if not 1 <= nseg <= MAX_SEGMENTS:
+        raise ValueError(f"1..{MAX_SEGMENTS} segments supported, got {nseg}")
+    return (a_off.to(dev).contiguous(), b_off.to(dev).contiguous(), out_off.to(dev).contiguous(),
+            nseg, total)
+
+
+def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=None, b_off=None,
+               self_pairs=False, save=False, capacity=None, check=True):
+    """IoU matrix (one a x b block, or segments such as per-scene self pairs).
+
+    Returns (iou, saved, seg): iou is [na, nb] for one block or flat
+    (blocks concatenated row-major) with segments; saved is a SavedPairs for
+    the backward when save=True; seg is the tuple of device offsets."""
+    if self_pairs:
+        b_xy, b_nv, b_z, b_off = a_xy, a_nv, a_z, a_off
+    pa, ka = polys(a_xy, a_nv, a_z)
+    pb, kb = polys(b_xy, b_nv, b_z)
+    dev = a_xy.device
+    d_a, d_b, d_o, nseg, total = _segments(a_xy.shape[0], b_xy.shape[0], a_off, b_off,
+                                           self_pairs, dev)
+    iou = torch.empty(total, dtype=torch.float32, device=dev)
+    saved = None
+    if save:
+        if capacity is None:
+            capacity = max(1 << 16, total // 16)
+        saved = SavedPairs(capacity, a_xy.shape[1] + b_xy.shape[1], dev)
+    st = saved.struct() if saved is not None else None
+    _ok(lib.dgal_iou_matrix(context(dev), pa, pb, _ptr(d_a), _ptr(d_b), _ptr(d_o), nseg,
+                            int(bool(self_pairs)), _ptr(iou), total,
+                            ctypes.byref(st) if st is not None else None, _stream(a_xy)),
+        "dgal_iou_matrix")
+    if check:
+        check_errors(dev)
+    if a_off is None:
+        iou = iou.view(a_xy.shape[0], b_xy.shape[0])
+    return iou, saved, (d_a, d_b, d_o, nseg)
+
+
+def iou_matrix_backward(grad, saved, seg, a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None,
+                        b_z=None, self_pairs=False):
+    """Gradient of sum(grad * IoU-matrix) from the saved list.  Returns
+    (grad_a, grad_b, grad_a_z, grad_b_z); with self_pairs everything is in
+    grad_a / grad_a_z and the b entries are None."""
+    if self_pairs:
+        b_xy, b_nv, b_z = a_xy, a_nv, a_z
+    pa, ka = polys(a_xy, a_nv, a_z)
+    pb, kb = polys(b_xy, b_nv, b_z)
+    dev = a_xy.device
+    grad = _need(grad.contiguous(), torch.float32, "grad", dev)
+    d_a, d_b, d_o, nseg = seg
+    ga = torch.empty_like(a_xy)
+    gb = None if self_pairs else torch.empty_like(b_xy)
+    gaz = gbz = None
+    if a_z is not None:
+        gaz = torch.empty((a_xy.shape[0], 2), dtype=torch.float32, device=dev)
+        gbz = None if self_pairs else torch.empty((b_xy.shape[0], 2), dtype=torch.float32,
+                                                  device=dev)
+    st = saved.struct()
+    _ok(lib.dgal_iou_backward(context(dev), DGAL_MATRIX, pa, pb, _ptr(d_a), _ptr(d_b), _ptr(d_o),
+                              nseg, int(bool(self_pairs)), _ptr(grad), grad.numel(), None, None,
+                              ctypes.byref(st), _ptr(ga), _ptr(gb), _ptr(gaz), _ptr(gbz),
+                              _stream(a_xy)),
+        "dgal_iou_backward(matrix)")
+    return ga, gb, gaz, gbz
+
+
+def check_errors(device=None):
+    """Synchronises torch's current stream and raises on a deferred device error."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    st = lib.dgal_check(context(dev), torch.cuda.current_stream(dev).cuda_stream)
+    _ok(st, "deferred device error")
+
+
+# --------------------------------------------------------------------- autograd
+
+class IoUPairs(torch.autograd.Function):
+    """IoU of elementwise polygon pairs; backward by the library's kernel from
+    the saved nx / xflags (no re-intersection)."""
+
+    @staticmethod
+    def forward(ctx, a_xy, b_xy, a_nv=None, b_nv=None):
+        iou, nx, xf = iou_pairs(a_xy, b_xy, a_nv, b_nv, save=True)
+        ctx.save_for_backward(a_xy, b_xy, nx, xf)
+        ctx.nvs = (a_nv, b_nv)
+        ctx.mark_non_differentiable(nx, xf)
+        return iou
+
+    @staticmethod
+    def backward(ctx, g):
+        a_xy, b_xy, nx, xf = ctx.saved_tensors
+        a_nv, b_nv = ctx.nvs
+        ga, gb, _, _ = iou_pairs_backward(a_xy, b_xy, g.contiguous().float(), nx, xf, a_nv, b_nv)
+        return ga, gb, None, None
+
+
+class IoU3DPairs(torch.autograd.Function):
+    """3D IoU (BEV polygon intersection x z-overlap) of elementwise pairs."""
+
+    @staticmethod
+    def forward(ctx, a_xy, a_zlo, a_zhi, b_xy, b_zlo, b_zhi):
+        iou, nx, xf = iou_pairs(a_xy, b_xy, a_z=(a_zlo, a_zhi), b_z=(b_zlo, b_zhi), save=True)
+        ctx.save_for_backward(a_xy, a_zlo, a_zhi, b_xy, b_zlo, b_zhi, nx, xf)
+        return iou
+
+    @staticmethod
+    def backward(ctx, g):
+        a_xy, a_zlo, a_zhi, b_xy, b_zlo, b_zhi, nx, xf = ctx.saved_tensors
+        ga, gb, gaz, gbz = iou_pairs_backward(a_xy, b_xy, g.contiguous().float(), nx, xf,
+                                              a_z=(a_zlo, a_zhi), b_z=(b_zlo, b_zhi))
+        return ga, gaz[:, 0], gaz[:, 1], gb, gbz[:, 0], gbz[:, 1]
+
+
+class IoUMatrix(torch.autograd.Function):
+    """IoU matrix of two polygon sets; backward from the saved non-empty pairs."""
+
+    @staticmethod
+    def forward(ctx, a_xy, b_xy, capacity=None):
+        iou, saved, seg = iou_matrix(a_xy, b_xy, save=True, capacity=capacity)
+        ctx.saved_list = saved
+        ctx.seg = seg
+        ctx.save_for_backward(a_xy, b_xy)
+        return iou
+
+    @staticmethod
+    def backward(ctx, g):
+        a_xy, b_xy = ctx.saved_tensors
+        ga, gb, _, _ = iou_matrix_backward(g.contiguous().float().reshape(-1), ctx.saved_list,
+                                           ctx.seg, a_xy, b_xy)
+        return ga, gb, None
+
+
+class IoU3DScenes(torch.autograd.Function):
+    """Per-scene self-pairwise 3D IoU of boxes (BEV polygons with z-extents);
+    scene s holds boxes off[s]..off[s+1] and owns an off-diagonal block of the
+    flat output (its diagonal is 1 with zero gradient)."""
+
+    @staticmethod
+    def forward(ctx, xy, zlo, zhi, off, capacity=None):
+        iou, saved, seg = iou_matrix(xy, a_z=(zlo, zhi), a_off=off, self_pairs=True, save=True,
+                                     capacity=capacity)
+        ctx.saved_list = saved
+        ctx.seg = seg
+        ctx.save_for_backward(xy, zlo, zhi)
+        return iou
+
+    @staticmethod
+    def backward(ctx, g):
+        xy, zlo, zhi = ctx.saved_tensors
+        ga, _, gaz, _ = iou_matrix_backward(g.contiguous().float(), ctx.saved_list, ctx.seg, xy,
+                                            a_z=(zlo, zhi), self_pairs=True)
+        return ga, gaz[:, 0], gaz[:, 1], None, None

@@ -1,0 +1,118 @@
+// internal.hpp -- declarations shared by the C ABI (api.hip) and the kernel
+// translation units.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dgal.h"
+
+namespace dgal {
+
+// Bits of the sticky device error word.
+enum : int { kErrCapacity = 1, kErrSegment = 2 };
+
+struct PolyArgs {
+  const float* xy;
+  const uint8_t* nv;
+  const float* zlo;
+  const float* zhi;
+  int64_t count;
+  int kmax;
+  bool vec4;  // rows of exactly K vertices, 16-byte aligned
+};
+
+struct PairsFwdArgs {
+  PolyArgs a, b;
+  float* iou;
+  uint8_t* nx;
+  uint8_t* xflags;
+  int cap;        // a.kmax + b.kmax: bytes per xflags row
+  bool flags_vec; // cap == 2K and rows aligned to cap bytes
+  int* err;
+};
+
+struct PairsBwdArgs {
+  PolyArgs a, b;
+  const float* grad;
+  const uint8_t* nx;
+  const uint8_t* xflags;
+  int cap;
+  bool flags_vec;
+  float* ga_xy;
+  float* gb_xy;
+  float* ga_z;
+  float* gb_z;
+};
+
+// What the kernels need from a context.
+struct CtxView {
+  int device;
+  int cus;          // compute units of the device
+  int* err;         // sticky device error word
+  int64_t* prefix;  // [DGAL_MAX_SEGMENTS + 1] tile prefix workspace
+};
+
+inline bool aligned(const void* p, uintptr_t a) {
+  return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0;
+}
+
+// Register capacity for polygons of up to kmax vertices.
+inline int reg_k(int kmax_a, int kmax_b) { return (kmax_a <= 4 && kmax_b <= 4) ? 4 : 8; }
+
+inline bool valid_polys(const dgal_polys& p) {
+  if (p.count < 0 || p.kmax < 3 || p.kmax > 8) return false;
+  if (p.count > 0 && (p.xy == nullptr || !aligned(p.xy, 8))) return false;
+  if ((p.zlo == nullptr) != (p.zhi == nullptr)) return false;
+  return true;
+}
+
+inline PolyArgs poly_args(const dgal_polys& p, int K) {
+  PolyArgs a;
+  a.xy = p.xy;
+  a.nv = p.nv;
+  a.zlo = p.zlo;
+  a.zhi = p.zhi;
+  a.count = p.count;
+  a.kmax = p.kmax;
+  a.vec4 = (p.kmax == K) && aligned(p.xy, 16);
+  return a;
+}
+
+inline bool same_polys(const dgal_polys& a, const dgal_polys& b) {
+  return a.xy == b.xy && a.nv == b.nv && a.zlo == b.zlo && a.zhi == b.zhi && a.count == b.count &&
+         a.kmax == b.kmax;
+}
+
+// Switches to a device for the duration of a call, restoring the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
+                   const int64_t* b_off, const int64_t* out_off, int nseg, int self_pairs,
+                   float* iou, int64_t out_size, const dgal_saved* saved, hipStream_t stream);
+int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
+                    const int64_t* b_off, const int64_t* out_off, int nseg, int self_pairs,
+                    const float* grad_iou, int64_t out_size, const dgal_saved* saved,
+                    float* grad_a_xy, float* grad_b_xy, float* grad_a_z, float* grad_b_z,
+                    hipStream_t stream);
+
+// Launchers (return a hipError_t from the launch).
+hipError_t launch_pairs_fwd(const PairsFwdArgs& args, int K, bool fixed, bool z3, bool save,
+                            hipStream_t stream);
+hipError_t launch_pairs_bwd(const PairsBwdArgs& args, int K, bool fixed, bool z3,
+                            hipStream_t stream);
+
+}  // namespace dgal

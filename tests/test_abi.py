@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every entry point include/dgal.h
+declares; host-side argument checks that need no device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dgal.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dgal_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def dgal():
+    import paper_2011_11134_amd as d
+    return d
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("dgal_iou_pairs", "dgal_iou_matrix", "dgal_iou_backward", "dgal_create",
+              "dgal_destroy", "dgal_check", "dgal_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(dgal):
+    L = ctypes.CDLL(dgal.LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert set(_declared()) == set(dgal.EXPORTS)
+
+
+def test_status_strings(dgal):
+    for st in (0, -1, -2, -3):
+        assert dgal.lib.dgal_status_string(st).startswith(b"DGAL_")
+    assert b"unknown" in dgal.lib.dgal_status_string(7)
+
+
+def test_null_context_is_rejected_before_any_device_call(dgal):
+    P = dgal.Polys(None, None, None, None, 0, 4)
+    assert dgal.lib.dgal_iou_pairs(None, P, P, None, None, None, None) == dgal.DGAL_EINVAL
+    assert dgal.lib.dgal_iou_matrix(None, P, P, None, None, None, 0, 0, None, 0, None,
+                                    None) == dgal.DGAL_EINVAL
+    assert dgal.lib.dgal_iou_backward(None, 0, P, P, None, None, None, 0, 0, None, 0, None, None,
+                                      None, None, None, None, None, None) == dgal.DGAL_EINVAL
+    assert dgal.lib.dgal_check(None, None) == dgal.DGAL_EINVAL
+    dgal.lib.dgal_destroy(None)  # no-op
+    assert dgal.lib.dgal_create(None, 0) == dgal.DGAL_EINVAL
+
+
+def test_binding_refuses_cpu_tensors(dgal):
+    import torch
+    a = torch.zeros((4, 4, 2), dtype=torch.float32)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        dgal.iou_pairs(a, a)
+
+
+def test_sorting_networks_sort_every_binary_input():
+    """0-1 principle: the comparator lists in geom.hpp sort all 2^n inputs."""
+    import itertools
+    src = open(os.path.join(ROOT, "paper_2011_11134_amd", "csrc", "geom.hpp")).read()
+    for name, n in (("DGAL_NET7", 7), ("DGAL_NET15", 15)):
+        # the macro body: its backslash-continued lines
+        body = re.search(r"#define %s\(X\)((?:.*\\\n)*.*)" % name, src).group(1)
+        pairs = [(int(a), int(b)) for a, b in re.findall(r"X\((\d+), (\d+)\)", body)]
+        assert all(a < b < n for a, b in pairs)
+        for bits in range(1 << n):
+            v = [(bits >> k) & 1 for k in range(n)]
+            for a, b in pairs:
+                if v[a] > v[b]:
+                    v[a], v[b] = v[b], v[a]
+            assert v == sorted(v), (name, bits)

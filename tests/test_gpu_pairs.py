@@ -1,0 +1,228 @@
+"""GPU parity of the elementwise-pair path (forward + backward kernels through
+the C ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import GRAD_TOL, IOU_TOL, compare_pairs, dev_t, grad_rel_err, run_pairs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import paper_2011_11134_amd as d
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return d
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_rectangles_c1(dg):
+    _say("case: c1 rectangles 1024 pairs")
+    d = synth.c1_pairs()
+    s = compare_pairs(dg, d["a_xy"], d["b_xy"], grad=d["grad"])
+    _say(str(s))
+    # the backward kernel, fed the oracle's state, matches on every pair
+    assert s["max_grad_err_oracle_state_all"] <= GRAD_TOL
+
+
+def test_rectangles_ragged_many_tiles(dg):
+    n = 65536 * 2 + 77          # many workgroups and a ragged tail
+    _say(f"case: c3 rectangles {n} pairs")
+    d = synth.c3_pairs(n=n, seed=7)
+    s = compare_pairs(dg, d["a_xy"], d["b_xy"], grad=d["grad"])
+    _say(str(s))
+
+
+def test_polygons_mixed_counts(dg):
+    n = 40000 + 13
+    _say(f"case: c4 polygons {n} pairs")
+    d = synth.c4_polygons(n=n, seed=8)
+    s = compare_pairs(dg, d["a_xy"], d["b_xy"], d["a_nv"], d["b_nv"], grad=d["grad"])
+    _say(str(s))
+
+
+def test_polygons_padding_is_ignored(dg):
+    """Slots past a polygon's count may hold anything (NaN here)."""
+    d = synth.c4_polygons(n=5000, seed=9)
+    a, b = d["a_xy"].copy(), d["b_xy"].copy()
+    for xy, nv in ((a, d["a_nv"]), (b, d["b_nv"])):
+        mask = np.arange(8)[None, :] >= nv[:, None]
+        xy[mask] = np.nan
+    r1 = run_pairs(dg, a, b, d["a_nv"], d["b_nv"], grad=d["grad"])
+    r0 = run_pairs(dg, d["a_xy"], d["b_xy"], d["a_nv"], d["b_nv"], grad=d["grad"])
+    assert np.array_equal(r1["iou"], r0["iou"])
+    assert np.array_equal(r1["xflags"], r0["xflags"])
+    assert np.array_equal(r1["ga"], r0["ga"]) and np.array_equal(r1["gb"], r0["gb"])
+    mask = np.arange(8)[None, :] >= d["a_nv"][:, None]
+    assert not r1["ga"][mask].any()
+
+
+@pytest.mark.parametrize("k", [3, 5, 6, 7])
+def test_polygon_capacities(dg, k):
+    """kmax other than 4 / 8: unaligned rows, scalar loads, byte-wise flags."""
+    d = synth.c4_polygons(n=3001, seed=20 + k)
+    nv_a = np.minimum(d["a_nv"], k).astype(np.uint8)
+    nv_b = np.minimum(d["b_nv"], k).astype(np.uint8)
+    # polygons with fewer vertices: re-draw so that the first nv points are a polygon
+    rng = np.random.default_rng(k)
+    a, nva = synth.workloads.random_convex(rng, 3001, kmin=3, kmax=k)
+    b, nvb = synth.workloads.random_convex(rng, 3001, kmin=3, kmax=k)
+    s = compare_pairs(dg, a, b, nva, nvb, grad=d["grad"])
+    _say(f"kmax={k}: {s}")
+
+
+def test_triangles_without_counts(dg):
+    rng = np.random.default_rng(31)
+    a, _ = synth.workloads.random_convex(rng, 4000, kmin=3, kmax=3)
+    b, _ = synth.workloads.random_convex(rng, 4000, kmin=3, kmax=3)
+    g = rng.uniform(-1, 1, 4000).astype(np.float32)
+    compare_pairs(dg, a, b, grad=g)
+
+
+def test_3d_pairs(dg):
+    d = synth.c1_pairs(n=20000, seed=41)
+    rng = np.random.default_rng(42)
+    z = rng.uniform(-2, 1, (20000, 2))
+    h = rng.uniform(1.4, 1.8, (20000, 2))
+    az = ((z[:, 0] - h[:, 0] / 2).astype(np.float32), (z[:, 0] + h[:, 0] / 2).astype(np.float32))
+    bz = ((z[:, 1] - h[:, 1] / 2).astype(np.float32), (z[:, 1] + h[:, 1] / 2).astype(np.float32))
+    s = compare_pairs(dg, d["a_xy"], d["b_xy"], a_z=az, b_z=bz, grad=d["grad"])
+    _say(str(s))
+
+
+def test_degenerate_stress(dg):
+    """Exactly degenerate contacts: the fp64 fallback and the tie rule give the
+    oracle's vertex count and IoU (only the IoU is required here)."""
+    a, b, names = synth.degenerate_stress()
+    g = np.ones(len(names), np.float32)
+    gpu = run_pairs(dg, a, b, grad=g)
+    ref, nx, xf, _ = oracle.iou_pairs(a, b)
+    d = np.abs(gpu["iou"] - ref)
+    assert d.max() <= IOU_TOL, [(names[i], gpu["iou"][i], ref[i]) for i in np.argsort(-d)[:3]]
+    assert np.array_equal(gpu["nx"], nx), [(names[i], gpu["nx"][i], nx[i]) for i in range(len(nx))]
+    # swapped roles and translated copies (exact: dyadic shifts)
+    for shift in (0.0, 1024.0, -3.5):
+        gpu2 = run_pairs(dg, b + np.float32(shift), a + np.float32(shift))
+        assert np.abs(gpu2["iou"] - ref).max() <= IOU_TOL
+
+
+def test_near_degenerate_fallback(dg):
+    """Pairs within fp32 rounding of a vertex/edge contact: signs are decided in
+    fp64, so nx matches the oracle exactly."""
+    d = synth.c1_pairs(n=4096, seed=51)
+    a = d["a_xy"].copy()
+    b = d["b_xy"].copy()
+    # move a vertex of b onto (or within one ulp of) an edge of a
+    t = np.float32(0.37)
+    p = a[:, 0] + t * (a[:, 1] - a[:, 0])
+    b[:, 2] = p.astype(np.float32)
+    b[1::2, 2] = np.nextafter(b[1::2, 2], np.float32(np.inf))
+    valid = np.array([oracle.polygon_valid(b[i].astype(np.float64)) for i in range(len(b))])
+    a, b = a[valid], b[valid]
+    gpu = run_pairs(dg, a, b)
+    ref, nx, xf, _ = oracle.iou_pairs(a, b)
+    assert np.abs(gpu["iou"] - ref).max() <= IOU_TOL
+    assert np.array_equal(gpu["nx"], nx)
+
+
+def test_empty_and_single(dg):
+    e = np.zeros((0, 4, 2), np.float32)
+    iou, nx, xf = dg.iou_pairs(dev_t(e), dev_t(e))
+    assert iou.numel() == 0 and xf.shape == (0, 8)
+    d = synth.c1_pairs(n=1, seed=3)
+    compare_pairs(dg, d["a_xy"], d["b_xy"], grad=d["grad"], require_filtered_frac=0.0)
+
+
+def test_full_size_rectangles_sampled(dg):
+    """1,048,576 pairs in the benchmark's launch configuration; sampled pairs
+    against the oracle, every pair against invariants."""
+    d = synth.c3_pairs()
+    n = len(d["a_xy"])
+    _say(f"case: c3 full {n} pairs")
+    gpu = run_pairs(dg, d["a_xy"], d["b_xy"], grad=d["grad"])
+    idx = np.random.default_rng(0).choice(n, 60000, replace=False)
+    idx = np.concatenate([idx, np.arange(n - 100, n)])
+    sub = {k: d[k][idx] for k in ("a_xy", "b_xy", "grad")}
+    ref, nx, xf, _ = oracle.iou_pairs(sub["a_xy"], sub["b_xy"], threads=8)
+    keep = oracle.filtered_mask(oracle.pair_margins(sub["a_xy"], sub["b_xy"], threads=8))
+    assert np.abs(gpu["iou"][idx] - ref).max() <= IOU_TOL
+    assert np.array_equal(gpu["nx"][idx][keep], nx[keep])
+    assert np.array_equal(gpu["xflags"][idx][keep], xf[keep])
+    ga, gb, _, _ = oracle.iou_pairs_grad(sub["a_xy"], sub["b_xy"], sub["grad"], nx, xf, threads=8)
+    err = grad_rel_err(np.concatenate([gpu["ga"][idx].reshape(len(idx), -1),
+                                       gpu["gb"][idx].reshape(len(idx), -1)], 1),
+                       np.concatenate([ga.reshape(len(idx), -1), gb.reshape(len(idx), -1)], 1))
+    assert err[keep].max() <= GRAD_TOL
+    # every pair: IoU in [0, 1], nx in {0} u [3, 8], translation invariance of the gradient
+    assert gpu["iou"].min() >= 0 and gpu["iou"].max() <= 1 + 1e-6
+    assert np.all((gpu["nx"] == 0) | ((gpu["nx"] >= 3) & (gpu["nx"] <= 8)))
+    tot = gpu["ga"].sum(1) + gpu["gb"].sum(1)
+    scale = np.abs(gpu["ga"]).sum((1, 2)) + np.abs(gpu["gb"]).sum((1, 2)) + 1e-30
+    assert np.max(np.abs(tot).max(1) / scale) <= 1e-4
+
+
+def test_full_size_polygons_sampled(dg):
+    d = synth.c4_polygons()
+    n = len(d["a_xy"])
+    _say(f"case: c4 full {n} pairs")
+    gpu = run_pairs(dg, d["a_xy"], d["b_xy"], d["a_nv"], d["b_nv"], grad=d["grad"])
+    idx = np.random.default_rng(1).choice(n, 30000, replace=False)
+    sub = {k: d[k][idx] for k in ("a_xy", "b_xy", "grad", "a_nv", "b_nv")}
+    ref, nx, xf, _ = oracle.iou_pairs(sub["a_xy"], sub["b_xy"], sub["a_nv"], sub["b_nv"], threads=8)
+    keep = oracle.filtered_mask(oracle.pair_margins(sub["a_xy"], sub["b_xy"], sub["a_nv"],
+                                                    sub["b_nv"], threads=8))
+    assert np.abs(gpu["iou"][idx] - ref).max() <= IOU_TOL
+    assert np.array_equal(gpu["nx"][idx][keep], nx[keep])
+    assert np.array_equal(gpu["xflags"][idx][keep], xf[keep])
+
+
+def test_deterministic(dg):
+    d = synth.c4_polygons(n=20000, seed=61)
+    r1 = run_pairs(dg, d["a_xy"], d["b_xy"], d["a_nv"], d["b_nv"], grad=d["grad"])
+    r2 = run_pairs(dg, d["a_xy"], d["b_xy"], d["a_nv"], d["b_nv"], grad=d["grad"])
+    for k in ("iou", "nx", "xflags", "ga", "gb"):
+        assert np.array_equal(r1[k], r2[k]), k
+
+
+def test_autograd_function(dg):
+    d = synth.c1_pairs(n=2048, seed=71)
+    a = dev_t(d["a_xy"]).requires_grad_(True)
+    b = dev_t(d["b_xy"]).requires_grad_(True)
+    iou = dg.IoUPairs.apply(a, b)
+    (iou * dev_t(d["grad"])).sum().backward()
+    ref, nx, xf, _ = oracle.iou_pairs(d["a_xy"], d["b_xy"])
+    ga, gb, _, _ = oracle.iou_pairs_grad(d["a_xy"], d["b_xy"], d["grad"], nx, xf)
+    keep = oracle.filtered_mask(oracle.pair_margins(d["a_xy"], d["b_xy"]))
+    err = grad_rel_err(np.concatenate([a.grad.cpu().numpy().reshape(2048, -1),
+                                       b.grad.cpu().numpy().reshape(2048, -1)], 1),
+                       np.concatenate([ga.reshape(2048, -1), gb.reshape(2048, -1)], 1))
+    assert err[keep].max() <= GRAD_TOL
+
+
+def test_invalid_arguments(dg):
+    ctx = dg.context()
+    ok = dg.Polys(0, None, None, None, 1, 4)  # pointer checked only when used
+    a = dev_t(np.zeros((2, 4, 2), np.float32))
+    pa, _ = dg.polys(a)
+    bad_k = dg.Polys(pa.xy, None, None, None, 2, 9)
+    out = torch.empty(2, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    assert dg.lib.dgal_iou_pairs(ctx, pa, bad_k, out.data_ptr(), None, None, s) == dg.DGAL_EINVAL
+    pb = dg.Polys(pa.xy, None, None, None, 3, 4)          # count mismatch
+    assert dg.lib.dgal_iou_pairs(ctx, pa, pb, out.data_ptr(), None, None, s) == dg.DGAL_EINVAL
+    mis = dg.Polys(pa.xy + 4, None, None, None, 1, 4)     # 4-byte aligned only
+    assert dg.lib.dgal_iou_pairs(ctx, mis, mis, out.data_ptr(), None, None, s) == dg.DGAL_EINVAL
+    nx = torch.empty(2, dtype=torch.uint8, device="cuda")
+    assert dg.lib.dgal_iou_pairs(ctx, pa, pa, out.data_ptr(), nx.data_ptr(), None, s) == dg.DGAL_EINVAL
+    zonly = dg.Polys(pa.xy, None, out.data_ptr(), None, 2, 4)
+    assert dg.lib.dgal_iou_pairs(ctx, zonly, zonly, out.data_ptr(), None, None, s) == dg.DGAL_EINVAL
+    assert dg.lib.dgal_iou_backward(ctx, 5, pa, pa, None, None, None, 0, 0, out.data_ptr(), 0,
+                                    None, None, None, None, None, None, None, s) == dg.DGAL_EINVAL
+    del ok
+    dg.check_errors()
