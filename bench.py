@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the batched differentiable convex-polygon IoU path
+on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic inputs that
+are resident in HBM before timing starts:
+  c3 (default): 1,048,576 rotated-rectangle pairs, forward (IoU + saved nx /
+                xflags) and backward (gradients for both boxes) kernels;
+  c1 / c4:      the same on 1,024 rectangle pairs / 262,144 mixed 3..8-gon pairs;
+  c2:           4096 x 4096 IoU matrix, forward;
+  c5:           64 scenes of 3D boxes, per-scene self-pair IoU, forward and
+                backward (saved non-empty pairs).
+Prints one JSON line (rank 0, one GPU).  Kernel durations come from HIP events
+recorded on the stream the kernels run on, around every launch of the timed
+steps.
+"""
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "IoU pairs/s fwd+bwd fp32 (≤1e-5 vs FP64 oracle), fused batched vs plain"
+HBM_PEAK_GBS = 8000.0
+# fp32 vector peak: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3
+
+# Algorithmic bytes per pair (inputs read + outputs written, nothing else):
+#   rectangles, forward:  2 x 32 B vertices + 4 B IoU + 1 B nx + 8 B flags  = 77
+#   rectangles, backward: 2 x 32 B vertices + 4 B grad + 1 B nx + 8 B flags
+#                         + 2 x 32 B gradients                                = 141
+#   8-slot polygons:      2 x (64 + 1) B vertices and counts; flags 16 B
+BYTES = {
+    ("rect", "fwd"): 77, ("rect", "bwd"): 141,
+    ("poly", "fwd"): 130 + 4 + 1 + 16, ("poly", "bwd"): 130 + 4 + 1 + 16 + 128,
+}
+# Algorithmic fp32 operations per rectangle pair (FMA = 2), counted from the
+# method's arithmetic (see the design notes): forward 320, backward 420.
+FLOPS = {("rect", "fwd"): 320, ("rect", "bwd"): 420}
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-calib-mib", type=int, default=0,
+                   help="also run a plain device copy of this size (HBM counter calibration)")
+    return p.parse_args()
+
+
+class PairsStep:
+    """Forward + backward of elementwise pairs with fixed device buffers."""
+
+    def __init__(self, dg, torch, d):
+        self.dg = dg
+        self.a = torch.from_numpy(d["a_xy"]).cuda()
+        self.b = torch.from_numpy(d["b_xy"]).cuda()
+        self.anv = None if d.get("a_nv") is None else torch.from_numpy(d["a_nv"]).cuda()
+        self.bnv = None if d.get("b_nv") is None else torch.from_numpy(d["b_nv"]).cuda()
+        self.g = torch.from_numpy(d["grad"]).cuda()
+        n, ka = self.a.shape[:2]
+        kb = self.b.shape[1]
+        self.n = n
+        self.iou = torch.empty(n, device="cuda")
+        self.nx = torch.empty(n, dtype=torch.uint8, device="cuda")
+        self.xf = torch.empty((n, ka + kb), dtype=torch.uint8, device="cuda")
+        self.ga = torch.empty_like(self.a)
+        self.gb = torch.empty_like(self.b)
+        self.pa, _ = dg.polys(self.a, self.anv)
+        self.pb, _ = dg.polys(self.b, self.bnv)
+        self.ctx = dg.context()
+        self.kind = "rect" if ka == 4 and self.anv is None else "poly"
+        self.pairs = n
+
+    def fwd(self, stream):
+        st = self.dg.lib.dgal_iou_pairs(self.ctx, self.pa, self.pb, self.iou.data_ptr(),
+                                        self.nx.data_ptr(), self.xf.data_ptr(), stream)
+        assert st == 0, st
+
+    def bwd(self, stream):
+        dg = self.dg
+        st = dg.lib.dgal_iou_backward(self.ctx, dg.DGAL_PAIRS, self.pa, self.pb, None, None, None, 0,
+                                      0, self.g.data_ptr(), 0, self.nx.data_ptr(),
+                                      self.xf.data_ptr(), None, self.ga.data_ptr(),
+                                      self.gb.data_ptr(), None, None, stream)
+        assert st == 0, st
+
+
+def cpu_baseline(d, kind):
+    """The FP64 oracle, as it stands, on the host cores: forward + analytic
+    backward of the whole workload, repeated for at least 1 s of wall time
+    (at least 3 runs), median run."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    a, b, g = d["a_xy"], d["b_xy"], d["grad"]
+    anv, bnv = d.get("a_nv"), d.get("b_nv")
+    times = []
+    start = time.perf_counter()
+    while len(times) < 3 or time.perf_counter() - start < 1.0:
+        t0 = time.perf_counter()
+        iou, nx, xf, _ = oracle.iou_pairs(a, b, anv, bnv, threads=threads)
+        oracle.iou_pairs_grad(a, b, g, nx, xf, anv, bnv, threads=threads)
+        times.append(time.perf_counter() - t0)
+    t = statistics.median(times)
+    return {"value": round(len(a) / t, 1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"whole workload ({len(a)} pairs, forward + backward) x {len(times)} runs, "
+                      f"median {t:.4f} s per run"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the path shards by independent pairs / scenes, see the design notes",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2011_11134_amd as dg
+    import synth
+
+    torch.cuda.set_device(0)
+    wl = args.workload
+    if wl not in ("c1", "c3", "c4"):
+        raise SystemExit(f"workload {wl} is not wired into bench.py yet")
+    d = synth.get(wl)
+    step = PairsStep(dg, torch, d)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    for _ in range(args.warmup):
+        step.fwd(stream)
+        step.bwd(stream)
+    torch.cuda.synchronize()
+    dg.check_errors()
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record()
+        step.fwd(stream)
+        ev[k][1].record()
+        step.bwd(stream)
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dg.check_errors()
+    fwd_ms = statistics.mean(ev[k][0].elapsed_time(ev[k][1]) for k in range(args.steps))
+    bwd_ms = statistics.mean(ev[k][1].elapsed_time(ev[k][2]) for k in range(args.steps))
+
+    kernels = {"fwd": fwd_ms, "bwd": bwd_ms}
+    dom = max(kernels, key=kernels.get)
+    dur_s = kernels[dom] * 1e-3
+    bytes_per = BYTES[(step.kind, dom)]
+    hbm_gbs = bytes_per * step.pairs / dur_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"k_pairs_{dom}", "kernel_ms": round(kernels[dom], 4),
+            "bytes_per_pair": bytes_per}
+    if (step.kind, dom) in FLOPS:
+        tf = FLOPS[(step.kind, dom)] * step.pairs / dur_s / 1e12
+        roof["alu"] = {"achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+                       "flops_per_pair": FLOPS[(step.kind, dom)]}
+
+    if args.copy_calib_mib:
+        src = torch.empty(args.copy_calib_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(d, step.kind)
+
+    value = step.pairs * args.steps / elapsed
+    names = {"c1": "c1: 1,024 rotated-rectangle pairs, forward + backward",
+             "c3": "c3: 1,048,576 rotated-rectangle pairs, forward + backward",
+             "c4": "c4: 262,144 convex 3..8-gon pairs, forward + backward"}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": names[wl], "pairs": step.pairs, "kmax": int(step.a.shape[1]),
+                   "parallelism": "single GPU"},
+        "kernels_ms": {k: round(v, 4) for k, v in kernels.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
