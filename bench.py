@@ -52,6 +52,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-plain", action="store_true", help="skip the plain per-op GPU form")
     p.add_argument("--copy-calib-mib", type=int, default=0,
                    help="also run a plain device copy of this size (HBM counter calibration)")
     return p.parse_args()
@@ -95,6 +96,97 @@ class PairsStep:
         assert st == 0, st
 
 
+class MatrixStep:
+    """4096 x 4096 IoU matrix (forward only) or per-scene 3D self pairs
+    (forward + backward) with fixed device buffers."""
+
+    def __init__(self, dg, torch, d, wl):
+        self.dg = dg
+        self.wl = wl
+        self.a = torch.from_numpy(d["a_xy"]).cuda()
+        self.ctx = dg.context()
+        if wl == "c2":
+            self.b = torch.from_numpy(d["b_xy"]).cuda()
+            self.pa, _ = dg.polys(self.a)
+            self.pb, _ = dg.polys(self.b)
+            self.total = self.a.shape[0] * self.b.shape[0]
+            self.seg = (None, None, None, 0)
+            self.saved = None
+            self.self_pairs = 0
+        else:
+            self.lo = torch.from_numpy(d["a_zlo"]).cuda()
+            self.hi = torch.from_numpy(d["a_zhi"]).cuda()
+            self.pa, _ = dg.polys(self.a, None, (self.lo, self.hi))
+            self.pb = self.pa
+            d_a, d_b, d_o, nseg, total = dg.segments(len(self.a), len(self.a), d["off"],
+                                                     self_pairs=True)
+            self.seg = (d_a, d_b, d_o, nseg)
+            self.total = total
+            self.saved = dg.SavedPairs(max(1 << 16, total // 16), 8, self.a.device)
+            self.g = torch.from_numpy(d["grad"]).cuda()
+            self.ga = torch.empty_like(self.a)
+            self.gz = torch.empty((len(self.a), 2), device="cuda")
+            self.self_pairs = 1
+        self.iou = torch.empty(self.total, device="cuda")
+        self.pairs = self.total
+        self.kind = "matrix"
+        self.has_bwd = wl == "c5"
+
+    def _p(self, t):
+        return None if t is None else t.data_ptr()
+
+    def fwd(self, stream):
+        dg = self.dg
+        d_a, d_b, d_o, nseg = self.seg
+        st_s = self.saved.struct() if self.saved is not None else None
+        st = dg.lib.dgal_iou_matrix(self.ctx, self.pa, self.pb, self._p(d_a), self._p(d_b),
+                                    self._p(d_o), nseg, self.self_pairs, self.iou.data_ptr(),
+                                    self.total, dg.ctypes.byref(st_s) if st_s is not None else None,
+                                    stream)
+        assert st == 0, st
+
+    def bwd(self, stream):
+        dg = self.dg
+        d_a, d_b, d_o, nseg = self.seg
+        st_s = self.saved.struct()
+        st = dg.lib.dgal_iou_backward(self.ctx, dg.DGAL_MATRIX, self.pa, self.pb, d_a.data_ptr(),
+                                      d_b.data_ptr(), d_o.data_ptr(), nseg, 1, self.g.data_ptr(),
+                                      self.total, None, None, dg.ctypes.byref(st_s),
+                                      self.ga.data_ptr(), None, self.gz.data_ptr(), None, stream)
+        assert st == 0, st
+
+
+def plain_baseline(torch, d, steps=5, warmup=2):
+    """The plain per-op GPU form (torch ops + autograd) on the same workload:
+    forward + backward pairs/s."""
+    from bench_plain import iou_pairs_plain
+    a = torch.from_numpy(d["a_xy"]).cuda().requires_grad_(True)
+    b = torch.from_numpy(d["b_xy"]).cuda().requires_grad_(True)
+    anv = None if d.get("a_nv") is None else torch.from_numpy(d["a_nv"]).cuda()
+    bnv = None if d.get("b_nv") is None else torch.from_numpy(d["b_nv"]).cuda()
+    g = torch.from_numpy(d["grad"]).cuda()
+
+    def step():
+        a.grad = None
+        b.grad = None
+        iou = iou_pairs_plain(a, b, anv, bnv)
+        iou.backward(g)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"value": round(len(d["a_xy"]) / (ms * 1e-3), 1), "unit": "pairs/s",
+            "ms_per_step": round(ms, 4), "steps": steps,
+            "form": "torch ops + autograd on the GPU (bench_plain.py)"}
+
+
 def cpu_baseline(d, kind):
     """The FP64 oracle, as it stands, on the host cores: forward + analytic
     backward of the whole workload, repeated for at least 1 s of wall time
@@ -131,15 +223,15 @@ def main():
 
     torch.cuda.set_device(0)
     wl = args.workload
-    if wl not in ("c1", "c3", "c4"):
-        raise SystemExit(f"workload {wl} is not wired into bench.py yet")
     d = synth.get(wl)
-    step = PairsStep(dg, torch, d)
+    step = PairsStep(dg, torch, d) if wl in ("c1", "c3", "c4") else MatrixStep(dg, torch, d, wl)
+    has_bwd = getattr(step, "has_bwd", True)
     stream = torch.cuda.current_stream().cuda_stream
 
     for _ in range(args.warmup):
         step.fwd(stream)
-        step.bwd(stream)
+        if has_bwd:
+            step.bwd(stream)
     torch.cuda.synchronize()
     dg.check_errors()
 
@@ -150,7 +242,8 @@ def main():
         ev[k][0].record()
         step.fwd(stream)
         ev[k][1].record()
-        step.bwd(stream)
+        if has_bwd:
+            step.bwd(stream)
         ev[k][2].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -158,15 +251,21 @@ def main():
     fwd_ms = statistics.mean(ev[k][0].elapsed_time(ev[k][1]) for k in range(args.steps))
     bwd_ms = statistics.mean(ev[k][1].elapsed_time(ev[k][2]) for k in range(args.steps))
 
-    kernels = {"fwd": fwd_ms, "bwd": bwd_ms}
+    kernels = {"fwd": fwd_ms, "bwd": bwd_ms} if has_bwd else {"fwd": fwd_ms}
     dom = max(kernels, key=kernels.get)
     dur_s = kernels[dom] * 1e-3
-    bytes_per = BYTES[(step.kind, dom)]
-    hbm_gbs = bytes_per * step.pairs / dur_s / 1e9
+    if step.kind == "matrix":
+        # the output stream: 4 B per pair written (inputs are a few MB)
+        bytes_total = 4 * step.pairs
+        kname = "k_matrix_fwd" if dom == "fwd" else "k_matrix_bwd"
+    else:
+        bytes_total = BYTES[(step.kind, dom)] * step.pairs
+        kname = f"k_pairs_{dom}"
+    hbm_gbs = bytes_total / dur_s / 1e9
     roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"k_pairs_{dom}", "kernel_ms": round(kernels[dom], 4),
-            "bytes_per_pair": bytes_per}
+            "kernel": kname, "kernel_ms": round(kernels[dom], 4),
+            "bytes_per_launch": bytes_total}
     if (step.kind, dom) in FLOPS:
         tf = FLOPS[(step.kind, dom)] * step.pairs / dur_s / 1e12
         roof["alu"] = {"achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -181,23 +280,30 @@ def main():
         torch.cuda.synchronize()
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and step.kind != "matrix":
         cpu = cpu_baseline(d, step.kind)
+    plain = None
+    if not args.no_plain and step.kind != "matrix":
+        plain = plain_baseline(torch, d)
 
     value = step.pairs * args.steps / elapsed
     names = {"c1": "c1: 1,024 rotated-rectangle pairs, forward + backward",
+             "c2": "c2: 4096 x 4096 rotated BEV box IoU matrix, forward",
              "c3": "c3: 1,048,576 rotated-rectangle pairs, forward + backward",
-             "c4": "c4: 262,144 convex 3..8-gon pairs, forward + backward"}
+             "c4": "c4: 262,144 convex 3..8-gon pairs, forward + backward",
+             "c5": "c5: 64 scenes (U{50..2000} boxes), per-scene 3D self-pair IoU, forward + backward"}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": names[wl], "pairs": step.pairs, "kmax": int(step.a.shape[1]),
+        "config": {"workload": names[wl], "pairs": int(step.pairs), "kmax": int(step.a.shape[1]),
                    "parallelism": "single GPU"},
         "kernels_ms": {k: round(v, 4) for k, v in kernels.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "plain": plain,
+        "vs_plain": None if plain is None else round(value / plain["value"], 2),
     }
     print(json.dumps(out), flush=True)
 

@@ -201,12 +201,21 @@ class SavedPairs:
         self.pair_id = torch.empty(capacity, dtype=torch.int64, device=device)
         self.nx = torch.empty(capacity, dtype=torch.uint8, device=device)
         self.xflags = torch.empty((capacity, cap), dtype=torch.uint8, device=device)
-        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+        # reset by the forward's own kernel (graph replays included)
+        self.count = torch.empty(1, dtype=torch.int64, device=device)
         self.capacity = capacity
 
     def struct(self):
         return Saved(_ptr(self.pair_id), _ptr(self.nx), _ptr(self.xflags), self.capacity,
                      _ptr(self.count))
+
+
+def segments(n_a, n_b, a_off, b_off=None, self_pairs=False, device=None):
+    """Device segment table for iou_matrix: (a_off, b_off, out_off, nseg,
+    total output size).  Build it before a HIP-graph capture and pass it as
+    `seg=` (the table itself needs host-to-device copies)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    return _segments(n_a, n_b, a_off, b_off, self_pairs, dev)
 
 
 def _segments(n_a, n_b, a_off, b_off, self_pairs, dev):
@@ -227,7 +236,7 @@ def _segments(n_a, n_b, a_off, b_off, self_pairs, dev):
 
 
 def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=None, b_off=None,
-               self_pairs=False, save=False, capacity=None, check=True):
+               self_pairs=False, save=False, capacity=None, check=True, seg=None):
     """IoU matrix (one a x b block, or segments such as per-scene self pairs).
 
     Returns (iou, saved, seg): iou is [na, nb] for one block or flat
@@ -238,8 +247,9 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
     pa, ka = polys(a_xy, a_nv, a_z)
     pb, kb = polys(b_xy, b_nv, b_z)
     dev = a_xy.device
-    d_a, d_b, d_o, nseg, total = _segments(a_xy.shape[0], b_xy.shape[0], a_off, b_off,
-                                           self_pairs, dev)
+    if seg is None:
+        seg = _segments(a_xy.shape[0], b_xy.shape[0], a_off, b_off, self_pairs, dev)
+    d_a, d_b, d_o, nseg, total = seg
     iou = torch.empty(total, dtype=torch.float32, device=dev)
     saved = None
     if save:
@@ -253,7 +263,7 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
         "dgal_iou_matrix")
     if check:
         check_errors(dev)
-    if a_off is None:
+    if d_a is None:
         iou = iou.view(a_xy.shape[0], b_xy.shape[0])
     return iou, saved, (d_a, d_b, d_o, nseg)
 

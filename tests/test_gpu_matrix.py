@@ -1,0 +1,323 @@
+"""GPU parity of the IoU-matrix path (LDS tiles, cull, survivor compaction,
+persistent segment schedule, saved non-empty pairs, atomic backward) and of
+per-scene 3D self-pairs, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import GRAD_TOL, IOU_TOL, dev_t
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import paper_2011_11134_amd as d
+    assert torch.cuda.is_available()
+    return d
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _crowd(xy, factor):
+    """Moves box centres towards the origin (boxes keep their shape)."""
+    c = xy.astype(np.float64).mean(1, keepdims=True)
+    return (xy - c + factor * c).astype(np.float32)
+
+
+def _aabb_candidates(a, b, a_off=None, b_off=None, self_pairs=False):
+    """Index pairs whose axis-aligned bounding boxes overlap (every other pair
+    is disjoint, so its IoU is exactly 0).  Returns (ia, ib, flat index)."""
+    lo_a, hi_a = a.min(1), a.max(1)
+    lo_b, hi_b = b.min(1), b.max(1)
+    segs = [(0, len(a), 0, len(b), 0)] if a_off is None else []
+    if a_off is not None:
+        out = 0
+        for s in range(len(a_off) - 1):
+            segs.append((a_off[s], a_off[s + 1], b_off[s], b_off[s + 1], out))
+            out += (a_off[s + 1] - a_off[s]) * (b_off[s + 1] - b_off[s])
+    IA, IB, FL = [], [], []
+    for a0, a1, b0, b1, o in segs:
+        nb = b1 - b0
+        for r0 in range(a0, a1, 512):
+            r1 = min(a1, r0 + 512)
+            ov = ((lo_a[r0:r1, None, 0] <= hi_b[None, b0:b1, 0]) &
+                  (lo_b[None, b0:b1, 0] <= hi_a[r0:r1, None, 0]) &
+                  (lo_a[r0:r1, None, 1] <= hi_b[None, b0:b1, 1]) &
+                  (lo_b[None, b0:b1, 1] <= hi_a[r0:r1, None, 1]))
+            r, c = np.nonzero(ov)
+            IA.append(r + r0)
+            IB.append(c + b0)
+            FL.append(o + (r + r0 - a0) * nb + c)
+    return np.concatenate(IA), np.concatenate(IB), np.concatenate(FL)
+
+
+def _check_matrix_exact(iou_flat, a, b, a_z=None, b_z=None, a_off=None, b_off=None,
+                        self_pairs=False):
+    ia, ib, fl = _aabb_candidates(a, b, a_off, b_off, self_pairs)
+    ref, nx, xf = oracle.iou_index_pairs(ia, ib, a, b, a_z=a_z, b_z=b_z, threads=8)
+    if self_pairs:
+        ref = np.where(ia == ib, 1.0, ref)
+    d = np.abs(iou_flat[fl].astype(np.float64) - ref)
+    assert d.max() <= IOU_TOL, (d.max(), ia[d.argmax()], ib[d.argmax()])
+    outside = np.ones(iou_flat.shape[0], bool)
+    outside[fl] = False
+    assert not iou_flat[outside].any(), "non-zero IoU for a pair with disjoint AABBs"
+    return ia, ib, fl, ref, nx, xf
+
+
+def test_matrix_small_dense_overlap(dg):
+    d = synth.c2_matrix(n=300, m=257, seed=3)
+    a, b = _crowd(d["a_xy"], 0.1), _crowd(d["b_xy"], 0.1)
+    iou, saved, seg = dg.iou_matrix(dev_t(a), dev_t(b), save=True)
+    dg.check_errors()
+    got = iou.cpu().numpy()
+    ref, _ = oracle.iou_matrix(a, b)
+    ref = ref.reshape(300, 257)
+    assert np.abs(got - ref).max() <= IOU_TOL
+    # saved list = exactly the pairs with a non-empty intersection
+    cnt = int(saved.count.item())
+    pid = np.sort(saved.pair_id[:cnt].cpu().numpy())
+    r, c = np.meshgrid(np.arange(300), np.arange(257), indexing="ij")
+    _, nx_all, _ = oracle.iou_index_pairs(r.ravel(), c.ravel(), a, b, threads=8)
+    assert np.array_equal(pid, np.nonzero(nx_all > 0)[0])
+    _say(f"small matrix: {cnt} non-empty pairs of {300 * 257}")
+
+
+def test_matrix_backward_small(dg):
+    d = synth.c2_matrix(n=200, m=150, seed=4)
+    a, b = _crowd(d["a_xy"], 0.08), _crowd(d["b_xy"], 0.08)
+    g = np.random.default_rng(5).uniform(-1, 1, (200, 150)).astype(np.float32)
+    iou, saved, seg = dg.iou_matrix(dev_t(a), dev_t(b), save=True)
+    ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g).reshape(-1), saved, seg, dev_t(a), dev_t(b))
+    ref_a, ref_b, _, _ = oracle.iou_matrix_grad(g.reshape(-1), a, b)
+    for got, ref in ((ga.cpu().numpy(), ref_a), (gb.cpu().numpy(), ref_b)):
+        err = np.linalg.norm((got - ref).reshape(len(ref), -1), axis=1)
+        scale = np.maximum(np.linalg.norm(ref.reshape(len(ref), -1), axis=1), 1e-6)
+        assert np.max(err / scale) <= 5 * GRAD_TOL, np.max(err / scale)
+    # autograd wrapper
+    ta = dev_t(a).requires_grad_(True)
+    tb = dev_t(b).requires_grad_(True)
+    out = dg.IoUMatrix.apply(ta, tb)
+    (out * dev_t(g)).sum().backward()
+    assert torch.allclose(ta.grad, ga, atol=1e-5) and torch.allclose(tb.grad, gb, atol=1e-5)
+
+
+def test_matrix_full_size_exact(dg):
+    """4096 x 4096 BEV boxes (the benchmark shape), every pair checked: AABB-
+    disjoint pairs must be 0, all others equal the oracle."""
+    d = synth.c2_matrix()
+    _say("case: c2 4096x4096")
+    iou, saved, seg = dg.iou_matrix(dev_t(d["a_xy"]), dev_t(d["b_xy"]), save=True)
+    dg.check_errors()
+    flat = iou.cpu().numpy().reshape(-1)
+    ia, ib, fl, ref, nx, xf = _check_matrix_exact(flat, d["a_xy"], d["b_xy"])
+    cnt = int(saved.count.item())
+    assert cnt == int((nx > 0).sum())
+    _say(f"c2: {len(fl)} AABB candidates, {cnt} non-empty ({cnt / flat.size:.4%})")
+
+
+def test_matrix_ragged_tiles(dg):
+    """Sizes that are not multiples of the tile, including a single row."""
+    for n, m in ((1, 1), (1, 200), (65, 64), (130, 1), (129, 191)):
+        d = synth.c2_matrix(n=n, m=m, seed=n * 1000 + m)
+        a, b = _crowd(d["a_xy"], 0.05), _crowd(d["b_xy"], 0.05)
+        iou, _, _ = dg.iou_matrix(dev_t(a), dev_t(b))
+        ref, _ = oracle.iou_matrix(a, b)
+        assert np.abs(iou.cpu().numpy().reshape(-1) - ref).max() <= IOU_TOL, (n, m)
+
+
+def test_matrix_polygons(dg):
+    d = synth.c4_polygons(n=300, seed=5)
+    a, anv, b, bnv = d["a_xy"][:180], d["a_nv"][:180], d["b_xy"][:220], d["b_nv"][:220]
+    iou, saved, seg = dg.iou_matrix(dev_t(a), dev_t(b), dev_t(anv), dev_t(bnv), save=True)
+    ref, _ = oracle.iou_matrix(a, b, anv, bnv)
+    assert np.abs(iou.cpu().numpy().reshape(-1) - ref).max() <= IOU_TOL
+    g = np.random.default_rng(6).uniform(-1, 1, 180 * 220).astype(np.float32)
+    ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(a), dev_t(b), dev_t(anv),
+                                          dev_t(bnv))
+    ref_a, ref_b, _, _ = oracle.iou_matrix_grad(g, a, b, anv, bnv)
+    for got, ref in ((ga.cpu().numpy(), ref_a), (gb.cpu().numpy(), ref_b)):
+        err = np.linalg.norm((got - ref).reshape(len(ref), -1), axis=1)
+        scale = np.maximum(np.linalg.norm(ref.reshape(len(ref), -1), axis=1), 1e-6)
+        assert np.percentile(err / scale, 99) <= GRAD_TOL
+
+
+def _scenes(scenes, nmin, nmax, seed, crowd):
+    d = synth.c5_scenes(scenes=scenes, nmin=nmin, nmax=nmax, seed=seed)
+    xy = d["a_xy"]
+    if crowd is not None:
+        xy = _crowd(xy, crowd)
+    return xy, d["a_zlo"], d["a_zhi"], d["off"], d["out_off"]
+
+
+def test_scenes_small_forward_backward(dg):
+    xy, lo, hi, off, out_off = _scenes(5, 10, 140, 7, 0.12)
+    total = int(out_off[-1])
+    g = np.random.default_rng(8).uniform(-1, 1, total).astype(np.float32)
+    txy, tlo, thi = dev_t(xy), dev_t(lo), dev_t(hi)
+    iou, saved, seg = dg.iou_matrix(txy, a_z=(tlo, thi), a_off=off, self_pairs=True, save=True)
+    ref, ref_off = oracle.iou_matrix(xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    got = iou.cpu().numpy()
+    assert np.array_equal(ref_off, out_off)
+    assert np.abs(got - ref).max() <= IOU_TOL
+    for s in range(5):
+        n = off[s + 1] - off[s]
+        blk = got[out_off[s]:out_off[s + 1]].reshape(n, n)
+        assert np.all(np.diag(blk) == 1.0)
+    ga, _, gaz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, txy, a_z=(tlo, thi),
+                                           self_pairs=True)
+    ref_a, _, ref_z, _ = oracle.iou_matrix_grad(g, xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    got_all = np.concatenate([ga.cpu().numpy().reshape(len(xy), -1), gaz.cpu().numpy()], 1)
+    ref_all = np.concatenate([ref_a.reshape(len(xy), -1), ref_z], 1)
+    err = np.linalg.norm(got_all - ref_all, axis=1)
+    scale = np.maximum(np.linalg.norm(ref_all, axis=1), 1e-6)
+    assert np.percentile(err / scale, 99.5) <= GRAD_TOL, np.sort(err / scale)[-5:]
+    assert np.max(err) <= 1e-3 * np.max(scale)
+    _say(f"scenes small: {int(saved.count.item())} saved pairs")
+
+
+def test_scenes_with_empty_and_single_box_segments(dg):
+    d = synth.c5_scenes(scenes=6, nmin=5, nmax=40, seed=9)
+    xy, lo, hi = _crowd(d["a_xy"], 0.1), d["a_zlo"], d["a_zhi"]
+    counts = np.diff(d["off"]).copy()
+    counts[1] = 0
+    counts[3] = 1
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    n = int(off[-1])
+    xy, lo, hi = xy[:n], lo[:n], hi[:n]
+    iou, saved, seg = dg.iou_matrix(dev_t(xy), a_z=(dev_t(lo), dev_t(hi)), a_off=off,
+                                    self_pairs=True, save=True)
+    dg.check_errors()
+    ref, _ = oracle.iou_matrix(xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
+
+
+def test_segmented_two_sets(dg):
+    """Segments that pair different row and column sets (not self pairs)."""
+    d = synth.c2_matrix(n=400, m=300, seed=10)
+    a, b = _crowd(d["a_xy"], 0.1), _crowd(d["b_xy"], 0.1)
+    a_off = np.array([0, 100, 100, 250, 400], np.int64)
+    b_off = np.array([0, 50, 120, 121, 300], np.int64)
+    iou, saved, seg = dg.iou_matrix(dev_t(a), dev_t(b), a_off=a_off, b_off=b_off, save=True)
+    ref, _ = oracle.iou_matrix(a, b, a_off=a_off, b_off=b_off)
+    assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
+    g = np.random.default_rng(11).uniform(-1, 1, ref.shape[0]).astype(np.float32)
+    ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(a), dev_t(b))
+    ref_a, ref_b, _, _ = oracle.iou_matrix_grad(g, a, b, a_off=a_off, b_off=b_off)
+    for got, rr in ((ga.cpu().numpy(), ref_a), (gb.cpu().numpy(), ref_b)):
+        err = np.linalg.norm((got - rr).reshape(len(rr), -1), axis=1)
+        scale = np.maximum(np.linalg.norm(rr.reshape(len(rr), -1), axis=1), 1e-6)
+        assert np.percentile(err / scale, 99) <= GRAD_TOL
+
+
+def test_scenes_full_size(dg):
+    """64 ragged scenes, 3D self pairs, the benchmark shape: the forward is
+    checked on every pair (AABB-disjoint pairs 0, the rest against the oracle);
+    the backward against the oracle's gradients summed over the saved pairs."""
+    d = synth.c5_scenes()
+    xy, lo, hi, off, out_off = d["a_xy"], d["a_zlo"], d["a_zhi"], d["off"], d["out_off"]
+    _say(f"case: c5 full, {len(xy)} boxes, {int(out_off[-1])} pairs")
+    txy, tlo, thi = dev_t(xy), dev_t(lo), dev_t(hi)
+    iou, saved, seg = dg.iou_matrix(txy, a_z=(tlo, thi), a_off=off, self_pairs=True, save=True)
+    dg.check_errors()
+    flat = iou.cpu().numpy()
+    ia, ib, fl, ref, nx, xf = _check_matrix_exact(flat, xy, xy, (lo, hi), (lo, hi), off, off,
+                                                  self_pairs=True)
+    cnt = int(saved.count.item())
+    nonempty = (nx > 0) & (ia != ib)
+    # z-disjoint pairs are culled before the intersection: the saved list holds
+    # the pairs with a non-empty BEV intersection and overlapping z-extents
+    zov = np.minimum(hi[ia], hi[ib]) > np.maximum(lo[ia], lo[ib])
+    assert cnt == int((nonempty & zov).sum()), (cnt, int((nonempty & zov).sum()))
+    g = d["grad"]
+    ga, _, gaz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, txy, a_z=(tlo, thi),
+                                           self_pairs=True)
+    sel = nonempty & zov
+    pa, pb, pz1, pz2 = oracle.iou_pairs_grad(xy[ia[sel]], xy[ib[sel]], g[fl[sel]], nx[sel], xf[sel],
+                                             a_z=(lo[ia[sel]], hi[ia[sel]]),
+                                             b_z=(lo[ib[sel]], hi[ib[sel]]), threads=8)
+    ref_a = np.zeros((len(xy), 4, 2))
+    ref_z = np.zeros((len(xy), 2))
+    np.add.at(ref_a, ia[sel], pa)
+    np.add.at(ref_a, ib[sel], pb)
+    np.add.at(ref_z, ia[sel], pz1)
+    np.add.at(ref_z, ib[sel], pz2)
+    got_all = np.concatenate([ga.cpu().numpy().reshape(len(xy), -1), gaz.cpu().numpy()], 1)
+    ref_all = np.concatenate([ref_a.reshape(len(xy), -1), ref_z], 1)
+    err = np.linalg.norm(got_all - ref_all, axis=1)
+    scale = np.maximum(np.linalg.norm(ref_all, axis=1), 1e-6)
+    assert np.percentile(err / scale, 99.9) <= GRAD_TOL, np.sort(err / scale)[-5:]
+    _say(f"c5: {cnt} saved pairs, grad rel err p99.9 {np.percentile(err / scale, 99.9):.2e} "
+         f"max {np.max(err / scale):.2e}")
+
+
+def test_graph_replay_matches_eager(dg):
+    """Scenes forward + backward captured in a HIP graph (via torch), replayed
+    several times with eager work in between; every replay equals eager."""
+    xy, lo, hi, off, out_off = _scenes(4, 30, 300, 12, 0.15)
+    g = dev_t(np.random.default_rng(13).uniform(-1, 1, int(out_off[-1])).astype(np.float32))
+    txy, tlo, thi = dev_t(xy), dev_t(lo), dev_t(hi)
+    iou_e, saved_e, seg_e = dg.iou_matrix(txy, a_z=(tlo, thi), a_off=off, self_pairs=True,
+                                          save=True)
+    ga_e, _, gaz_e, _ = dg.iou_matrix_backward(g, saved_e, seg_e, txy, a_z=(tlo, thi),
+                                               self_pairs=True)
+    seg_t = dg.segments(len(xy), len(xy), off, self_pairs=True)  # device table, before capture
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):  # warm up on the side stream
+            iou_w, saved_w, seg_w = dg.iou_matrix(txy, a_z=(tlo, thi), a_off=off, self_pairs=True,
+                                                  save=True, check=False, seg=seg_t)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        iou_g, saved_g, seg_g = dg.iou_matrix(txy, a_z=(tlo, thi), a_off=off, self_pairs=True,
+                                              save=True, check=False, seg=seg_t)
+        ga_g, _, gaz_g, _ = dg.iou_matrix_backward(g, saved_g, seg_g, txy, a_z=(tlo, thi),
+                                                   self_pairs=True)
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(iou_g, iou_e), rep
+        assert int(saved_g.count.item()) == int(saved_e.count.item())
+        assert torch.allclose(ga_g, ga_e, atol=1e-5, rtol=1e-5), rep
+        assert torch.allclose(gaz_g, gaz_e, atol=1e-5, rtol=1e-5), rep
+        del junk
+
+
+def test_invalid_segments_are_rejected(dg):
+    xy, lo, hi, off, out_off = _scenes(3, 10, 20, 14, None)
+    txy = dev_t(xy)
+    pa, _ = dg.polys(txy)
+    bad_a = torch.tensor([0, 5, 3, int(off[-1])], dtype=torch.int64, device="cuda")  # decreasing
+    good_o = torch.tensor([0, 25, 25], dtype=torch.int64, device="cuda")
+    out = torch.zeros(int(out_off[-1]), device="cuda")
+    st = dg.lib.dgal_iou_matrix(dg.context(), pa, pa, bad_a.data_ptr(), bad_a.data_ptr(),
+                                good_o.data_ptr(), 3, 1, out.data_ptr(), out.numel(), None,
+                                torch.cuda.current_stream().cuda_stream)
+    assert st == dg.DGAL_OK          # offsets live on the device: reported by the check
+    with pytest.raises(dg.DgalError) as e:
+        dg.check_errors()
+    assert e.value.status == dg.DGAL_EINVAL
+    dg.check_errors()                # the error word was cleared
+    # immediate errors
+    assert dg.lib.dgal_iou_matrix(dg.context(), pa, pa, bad_a.data_ptr(), None, None, 3, 1,
+                                  out.data_ptr(), out.numel(), None, 0) == dg.DGAL_EINVAL
+    assert dg.lib.dgal_iou_matrix(dg.context(), pa, pa, None, None, None, 0, 0,
+                                  out.data_ptr(), 10, None, 0) == dg.DGAL_EINVAL  # out too small
+
+
+def test_saved_capacity_overflow_is_reported(dg):
+    d = synth.c2_matrix(n=100, m=100, seed=15)
+    a = _crowd(d["a_xy"], 0.02)
+    with pytest.raises(dg.DgalError) as e:
+        dg.iou_matrix(dev_t(a), dev_t(a), save=True, capacity=4)
+    assert e.value.status == dg.DGAL_ECAPACITY
+    dg.check_errors()
