@@ -111,18 +111,20 @@ class MatrixStep:
             self.pb, _ = dg.polys(self.b)
             self.total = self.a.shape[0] * self.b.shape[0]
             self.seg = (None, None, None, 0)
-            self.saved = None
+            tiles = dg.segments(len(self.a), len(self.b), None)[5]
+            # the forward's work list (survivors of the cull)
+            self.saved = dg.SavedPairs(max(1 << 16, self.total // 16), 8, tiles, self.a.device)
             self.self_pairs = 0
         else:
             self.lo = torch.from_numpy(d["a_zlo"]).cuda()
             self.hi = torch.from_numpy(d["a_zhi"]).cuda()
             self.pa, _ = dg.polys(self.a, None, (self.lo, self.hi))
             self.pb = self.pa
-            d_a, d_b, d_o, nseg, total = dg.segments(len(self.a), len(self.a), d["off"],
-                                                     self_pairs=True)
+            d_a, d_b, d_o, nseg, total, tiles = dg.segments(len(self.a), len(self.a), d["off"],
+                                                            self_pairs=True)
             self.seg = (d_a, d_b, d_o, nseg)
             self.total = total
-            self.saved = dg.SavedPairs(max(1 << 16, total // 16), 8, self.a.device)
+            self.saved = dg.SavedPairs(max(1 << 16, total // 16), 8, tiles, self.a.device)
             self.g = torch.from_numpy(d["grad"]).cuda()
             self.ga = torch.empty_like(self.a)
             self.gz = torch.empty((len(self.a), 2), device="cuda")
@@ -138,11 +140,10 @@ class MatrixStep:
     def fwd(self, stream):
         dg = self.dg
         d_a, d_b, d_o, nseg = self.seg
-        st_s = self.saved.struct() if self.saved is not None else None
+        st_s = self.saved.struct()
         st = dg.lib.dgal_iou_matrix(self.ctx, self.pa, self.pb, self._p(d_a), self._p(d_b),
                                     self._p(d_o), nseg, self.self_pairs, self.iou.data_ptr(),
-                                    self.total, dg.ctypes.byref(st_s) if st_s is not None else None,
-                                    stream)
+                                    self.total, dg.ctypes.byref(st_s), stream)
         assert st == 0, st
 
     def bwd(self, stream):

@@ -106,16 +106,30 @@ int dgal_check(dgal_ctx *ctx, void *stream);
 int dgal_iou_pairs(dgal_ctx *ctx, dgal_polys a, dgal_polys b, float *iou,
                    uint8_t *nx, uint8_t *xflags, void *stream);
 
-/* Compact list of the matrix pairs whose intersection is non-empty, written
- * by dgal_iou_matrix for the backward (every other pair has zero gradient).
- * All pointers are device memory; *count is a device int64 that the forward
- * overwrites.  Entries appear in no particular order. */
+/* Tiles of DGAL_TILE_ROWS rows x DGAL_TILE_COLS columns are the unit of work
+ * of the matrix kernels. */
+#define DGAL_TILE_ROWS 8
+#define DGAL_TILE_COLS 256
+
+/* Work list and saved state of a matrix forward: one entry per pair that
+ * survived the conservative cull (every other pair is disjoint: its IoU is 0
+ * and its gradient zero), with the intersection's vertex count and provenance
+ * codes (nx == 0 for a survivor whose intersection is empty), and a table that
+ * gives each tile its contiguous range of entries.  Tiles are numbered segment
+ * by segment, row-major over the segment's tile grid (ceil(rows / 8) x
+ * ceil(cols / 256) tiles per segment with both sides non-empty).  All pointers
+ * are device memory; the forward overwrites everything, including *count.
+ * Entries are laid out tile by tile, in a fixed order. */
 typedef struct {
-  int64_t *pair_id;  /* [capacity] index into the flat iou output            */
-  uint8_t *nx;       /* [capacity]                                           */
-  uint8_t *xflags;   /* [capacity][a.kmax + b.kmax]                          */
-  int64_t capacity;  /* entries available; overflow => DGAL_ECAPACITY (deferred) */
-  int64_t *count;    /* device scalar: number of entries written (<= capacity) */
+  int64_t *pair_id;       /* [capacity] index into the flat iou output               */
+  uint8_t *nx;            /* [capacity]                                               */
+  uint8_t *xflags;        /* [capacity][a.kmax + b.kmax]                              */
+  int64_t capacity;       /* entries available; overflow => DGAL_ECAPACITY (deferred,
+                             and the overflowing pairs' IoU is not written)           */
+  int64_t *count;         /* device scalar: survivors found (may exceed capacity)    */
+  int64_t *tile_start;    /* [tile_capacity] first entry of each tile                 */
+  int32_t *tile_count;    /* [tile_capacity] entries of each tile                     */
+  int64_t tile_capacity;  /* >= number of tiles, else DGAL_ECAPACITY (deferred)       */
 } dgal_saved;
 
 /* Most segments one matrix call may hold. */
@@ -131,14 +145,16 @@ typedef struct {
  *   out_off       DEVICE int64 [nseg]
  *   out_size      number of fp32 elements the caller allocated at iou
  *   iou           flat fp32 output
- *   saved         NULL => forward only; else filled for dgal_iou_backward.
+ *   saved         REQUIRED: the forward's work list, also the state that
+ *                 dgal_iou_backward needs (a forward-only caller may discard it).
  * Offsets live on the device so that the call can be captured in a HIP graph;
  * the kernels check them (a block outside [0, out_size) or rows/columns
  * outside [0, count) is skipped and reported by dgal_check as DGAL_EINVAL).
  * DGAL_EINVAL (immediate): as dgal_iou_pairs except a.count == b.count, plus
  * some but not all offsets NULL, nseg outside [1, DGAL_MAX_SEGMENTS] with
- * offsets, out_size < a.count * b.count without offsets, self_pairs with a and
- * b differing, saved with a NULL field or capacity < 0. */
+ * offsets, out_size < a.count * b.count without offsets, a block with 2^24 or
+ * more columns, self_pairs with a and b differing, saved with a NULL field or
+ * a negative capacity, saved NULL. */
 int dgal_iou_matrix(dgal_ctx *ctx, dgal_polys a, dgal_polys b,
                     const int64_t *a_off, const int64_t *b_off,
                     const int64_t *out_off, int32_t nseg, int32_t self_pairs,
@@ -161,8 +177,10 @@ enum { DGAL_PAIRS = 0, DGAL_MATRIX = 1 };
  * Outputs (overwritten; padded vertex slots are written 0):
  *   grad_a_xy [a.count][a.kmax][2], grad_b_xy [b.count][b.kmax][2] fp32
  *   grad_a_z, grad_b_z [count][2] fp32 = (d/dzlo, d/dzhi); NULL for 2D.
- * The matrix mode sums contributions with fp32 atomics, so its low-order bits
- * may vary from run to run.
+ * The matrix mode sums each row's gradient over its tiles in LDS (their
+ * order, and so the low-order bits, may vary from run to run) and writes every
+ * row once; with two different sets the column gradients are added with fp32
+ * global atomics.
  * DGAL_EINVAL: as the forward, plus a NULL required output or saved state, an
  * unknown mode, z outputs requested for 2D input. */
 int dgal_iou_backward(dgal_ctx *ctx, int32_t mode, dgal_polys a, dgal_polys b,

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libdgal.so")
 DGAL_OK, DGAL_EINVAL, DGAL_ECAPACITY, DGAL_EHIP = 0, -1, -2, -3
 DGAL_PAIRS, DGAL_MATRIX = 0, 1
 MAX_SEGMENTS = 4096
+TILE_ROWS, TILE_COLS = 8, 256
 
 _vp = ctypes.c_void_p
 
@@ -35,7 +36,8 @@ class Polys(ctypes.Structure):
 class Saved(ctypes.Structure):
     """dgal_saved"""
     _fields_ = [("pair_id", _vp), ("nx", _vp), ("xflags", _vp),
-                ("capacity", ctypes.c_int64), ("count", _vp)]
+                ("capacity", ctypes.c_int64), ("count", _vp),
+                ("tile_start", _vp), ("tile_count", _vp), ("tile_capacity", ctypes.c_int64)]
 
 
 EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
@@ -195,24 +197,28 @@ def iou_pairs_backward(a_xy, b_xy, grad, nx, xflags, a_nv=None, b_nv=None, a_z=N
 # --------------------------------------------------------------------- matrix
 
 class SavedPairs:
-    """Device buffers of a dgal_saved list (non-empty pairs of a matrix)."""
+    """Device buffers of a dgal_saved work list (pairs that survived the cull
+    of a matrix forward, with their nx / xflags) and its per-tile table."""
 
-    def __init__(self, capacity, cap, device):
+    def __init__(self, capacity, cap, tiles, device):
         self.pair_id = torch.empty(capacity, dtype=torch.int64, device=device)
         self.nx = torch.empty(capacity, dtype=torch.uint8, device=device)
         self.xflags = torch.empty((capacity, cap), dtype=torch.uint8, device=device)
         # reset by the forward's own kernel (graph replays included)
         self.count = torch.empty(1, dtype=torch.int64, device=device)
+        self.tile_start = torch.empty(max(tiles, 1), dtype=torch.int64, device=device)
+        self.tile_count = torch.empty(max(tiles, 1), dtype=torch.int32, device=device)
         self.capacity = capacity
+        self.tiles = tiles
 
     def struct(self):
         return Saved(_ptr(self.pair_id), _ptr(self.nx), _ptr(self.xflags), self.capacity,
-                     _ptr(self.count))
+                     _ptr(self.count), _ptr(self.tile_start), _ptr(self.tile_count), self.tiles)
 
 
 def segments(n_a, n_b, a_off, b_off=None, self_pairs=False, device=None):
     """Device segment table for iou_matrix: (a_off, b_off, out_off, nseg,
-    total output size).  Build it before a HIP-graph capture and pass it as
+    total output size, tile count).  Build it before a HIP-graph capture and pass it as
     `seg=` (the table itself needs host-to-device copies)."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
     return _segments(n_a, n_b, a_off, b_off, self_pairs, dev)
@@ -221,7 +227,8 @@ def segments(n_a, n_b, a_off, b_off=None, self_pairs=False, device=None):
 def _segments(n_a, n_b, a_off, b_off, self_pairs, dev):
     """Device offsets (a_off, b_off, out_off) and total output size."""
     if a_off is None:
-        return None, None, None, 0, n_a * n_b
+        tiles = (-(-n_a // TILE_ROWS)) * (-(-n_b // TILE_COLS)) if n_a and n_b else 0
+        return None, None, None, 0, n_a * n_b, tiles
     a_off = torch.as_tensor(a_off, dtype=torch.int64)
     b_off = a_off if (self_pairs or b_off is None) else torch.as_tensor(b_off, dtype=torch.int64)
     a_cpu, b_cpu = a_off.cpu(), b_off.cpu()
@@ -231,8 +238,12 @@ def _segments(n_a, n_b, a_off, b_off, self_pairs, dev):
     nseg = int(a_cpu.numel() - 1)
     if not 1 <= nseg <= MAX_SEGMENTS:
         raise ValueError(f"1..{MAX_SEGMENTS} segments supported, got {nseg}")
+    na = a_cpu[1:] - a_cpu[:-1]
+    nb = b_cpu[1:] - b_cpu[:-1]
+    tiles = int(torch.where(sizes > 0, ((na + TILE_ROWS - 1) // TILE_ROWS) *
+                            ((nb + TILE_COLS - 1) // TILE_COLS), 0).sum())
     return (a_off.to(dev).contiguous(), b_off.to(dev).contiguous(), out_off.to(dev).contiguous(),
-            nseg, total)
+            nseg, total, tiles)
 
 
 def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=None, b_off=None,
@@ -240,8 +251,10 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
     """IoU matrix (one a x b block, or segments such as per-scene self pairs).
 
     Returns (iou, saved, seg): iou is [na, nb] for one block or flat
-    (blocks concatenated row-major) with segments; saved is a SavedPairs for
-    the backward when save=True; seg is the tuple of device offsets."""
+    (blocks concatenated row-major) with segments; saved is the SavedPairs
+    work list (the backward's state; None when save=False); seg is the tuple
+    of device offsets.  capacity bounds the survivors of the cull (default
+    max(65536, pairs / 16)); exceeding it raises (check=True)."""
     if self_pairs:
         b_xy, b_nv, b_z, b_off = a_xy, a_nv, a_z, a_off
     pa, ka = polys(a_xy, a_nv, a_z)
@@ -249,23 +262,21 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
     dev = a_xy.device
     if seg is None:
         seg = _segments(a_xy.shape[0], b_xy.shape[0], a_off, b_off, self_pairs, dev)
-    d_a, d_b, d_o, nseg, total = seg
+    d_a, d_b, d_o, nseg, total, tiles = seg
     iou = torch.empty(total, dtype=torch.float32, device=dev)
-    saved = None
-    if save:
-        if capacity is None:
-            capacity = max(1 << 16, total // 16)
-        saved = SavedPairs(capacity, a_xy.shape[1] + b_xy.shape[1], dev)
-    st = saved.struct() if saved is not None else None
+    if capacity is None:
+        capacity = max(1 << 16, total // 16)
+    saved = SavedPairs(capacity, a_xy.shape[1] + b_xy.shape[1], tiles, dev)
+    st = saved.struct()
     _ok(lib.dgal_iou_matrix(context(dev), pa, pb, _ptr(d_a), _ptr(d_b), _ptr(d_o), nseg,
-                            int(bool(self_pairs)), _ptr(iou), total,
-                            ctypes.byref(st) if st is not None else None, _stream(a_xy)),
+                            int(bool(self_pairs)), _ptr(iou), total, ctypes.byref(st),
+                            _stream(a_xy)),
         "dgal_iou_matrix")
     if check:
         check_errors(dev)
     if d_a is None:
         iou = iou.view(a_xy.shape[0], b_xy.shape[0])
-    return iou, saved, (d_a, d_b, d_o, nseg)
+    return iou, (saved if save else None), (d_a, d_b, d_o, nseg)
 
 
 def iou_matrix_backward(grad, saved, seg, a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None,

@@ -35,6 +35,7 @@ int dgal_create(dgal_ctx** out, int hip_device) {
   c->v.device = hip_device;
   c->v.err = nullptr;
   c->v.prefix = nullptr;
+  c->v.scan = nullptr;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
       cus <= 0)
@@ -42,11 +43,14 @@ int dgal_create(dgal_ctx** out, int hip_device) {
   c->v.cus = cus;
   if (hipMalloc(reinterpret_cast<void**>(&c->v.err), sizeof(int)) != hipSuccess ||
       hipMemset(c->v.err, 0, sizeof(int)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->v.prefix), sizeof(int64_t) * (DGAL_MAX_SEGMENTS + 1)) !=
+      hipMalloc(reinterpret_cast<void**>(&c->v.prefix), sizeof(int64_t) * 2 * (DGAL_MAX_SEGMENTS + 1)) !=
+          hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->v.scan), sizeof(int64_t) * dgal::kScanTotals) !=
           hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     if (c->v.err) (void)hipFree(c->v.err);
     if (c->v.prefix) (void)hipFree(c->v.prefix);
+    if (c->v.scan) (void)hipFree(c->v.scan);
     delete c;
     return DGAL_EHIP;
   }
@@ -59,6 +63,7 @@ void dgal_destroy(dgal_ctx* ctx) {
   DeviceGuard g(ctx->v.device);
   if (ctx->v.err) (void)hipFree(ctx->v.err);
   if (ctx->v.prefix) (void)hipFree(ctx->v.prefix);
+  if (ctx->v.scan) (void)hipFree(ctx->v.scan);
   delete ctx;
 }
 

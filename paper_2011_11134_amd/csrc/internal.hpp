@@ -49,8 +49,12 @@ struct CtxView {
   int device;
   int cus;          // compute units of the device
   int* err;         // sticky device error word
-  int64_t* prefix;  // [DGAL_MAX_SEGMENTS + 1] tile prefix workspace
+  int64_t* prefix;  // [2][DGAL_MAX_SEGMENTS + 1]: tile and row-group prefixes
+  int64_t* scan;    // [kScanTotals]: per-chunk totals of the tile scan
 };
+
+// Chunks of 4096 tiles the tile scan can combine (2^24 tiles per call).
+constexpr int64_t kScanTotals = 4096;
 
 inline bool aligned(const void* p, uintptr_t a) {
   return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0;

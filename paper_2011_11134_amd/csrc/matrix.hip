@@ -1,15 +1,30 @@
 // matrix.hip -- IoU matrices (one block a.count x b.count, or ragged segments
 // such as per-scene self-pairs of 3D boxes, Sec. IV-A case study at scale) and
-// their backward from the compact list of non-empty pairs.
+// their backward from the saved per-pair state (Sec. II-B: nx and xflags).
 //
-// Forward schedule: the output is cut into TILE x TILE tiles; a persistent
-// grid walks the tile space of all segments (a prefix sum of tiles per
-// segment, computed on the device so the call is graph-capturable).  For one
-// tile a workgroup stages the TILE row boxes and TILE column boxes in LDS with
-// a bounding circle each, culls every pair whose circles (or z-extents) are
-// apart, compacts the survivors into an LDS list and runs the exact pair
-// forward on them with all lanes busy; the finished tile leaves LDS as
-// coalesced row segments.
+// The forward is split by register pressure into lean cull kernels and one
+// dense exact kernel, with no shared counter anywhere:
+//   k_matrix_count -- one wavefront per tile of kTileRows rows x kTileCols
+//     columns of one segment.  The rows' axis-aligned bounds (and z-extents)
+//     sit in scalar registers; each lane bounds its column boxes 64 at a time,
+//     tests them against the rows, writes the 0 (or the self diagonal's 1) of
+//     every disjoint pair straight to the output row segments (coalesced) and
+//     counts the survivors into the tile table.
+//   k_tile_scan    -- one workgroup: exclusive prefix of the tile counts, so
+//     the work list is laid out tile by tile, deterministically.
+//   k_matrix_fill  -- the same cull again; survivors go to their tile's range.
+//   k_matrix_exact -- one lane per survivor with every lane busy: the exact
+//     pair forward, the IoU written to its place in the output, nx / xflags
+//     kept in the work list for the backward.
+// A persistent grid walks the tiles of all segments (a prefix sum of tiles per
+// segment computed on the device by k_seg_prep, so everything is
+// graph-capturable).  The backward (k_matrix_bwd) gives one wavefront a row
+// group: its tiles' entries are one contiguous range of the work list; the row
+// gradients are summed in LDS and every row is written once.  Self pairs need
+// nothing else (the column role of pair (k, i) equals the row role of pair
+// (i, k)); for two different sets the column gradients are added with global
+// atomics.
+#include <algorithm>
 #include <type_traits>
 
 #include "geom.hpp"
@@ -17,453 +32,693 @@
 
 namespace dgal {
 
-constexpr int kTile = 64;          // rows and columns per tile
-constexpr int kMatBlock = 256;     // threads per workgroup
+constexpr int kTileRows = DGAL_TILE_ROWS;
+constexpr int kTileCols = DGAL_TILE_COLS;
+constexpr int kCullBlock = 256;   // four independent wavefronts
+constexpr int kScanBlock = 1024;
+constexpr int kExactBlock = 256;
 constexpr int kMaxSeg = DGAL_MAX_SEGMENTS;
-
-struct MatArgs {
-  PolyArgs a, b;
-  const int64_t* a_off;  // NULL => one segment
-  const int64_t* b_off;
-  const int64_t* out_off;
-  const int64_t* tile_prefix;  // [nseg+1] (segmented) from k_seg_prep
-  int nseg;
-  int64_t single_tiles;  // tile count of the single segment
-  int self_pairs;
-  float* iou;
-  int64_t out_size;
-  // saved list (pair_id == nullptr => forward only)
-  int64_t* pair_id;
-  uint8_t* s_nx;
-  uint8_t* s_flags;
-  int64_t capacity;
-  int64_t* count;
-  int cap;
-  int* err;
-};
+static_assert(kTileCols % 64 == 0 && kTileCols <= 65536, "tile columns");
 
 struct Segment {
   int64_t a0, b0, na, nb, out0;
   bool ok;
 };
 
-__device__ __forceinline__ Segment load_segment(const MatArgs& m, int s) {
+struct SegArgs {
+  const int64_t* a_off;  // NULL => one segment
+  const int64_t* b_off;
+  const int64_t* out_off;
+  int nseg;
+  int64_t a_count, b_count, out_size;
+  int self_pairs;
+  const int64_t* tile_prefix;   // [nseg+1] (segmented), from k_seg_prep
+  const int64_t* group_prefix;  // [nseg+1] row groups (segmented), from k_seg_prep
+};
+
+__device__ __forceinline__ Segment load_segment(const SegArgs& a, int s) {
   Segment g;
-  if (m.a_off == nullptr) {
+  if (a.a_off == nullptr) {
     g.a0 = 0;
     g.b0 = 0;
-    g.na = m.a.count;
-    g.nb = m.b.count;
+    g.na = a.a_count;
+    g.nb = a.b_count;
     g.out0 = 0;
     g.ok = true;
     return g;
   }
-  const int64_t a0 = m.a_off[s], a1 = m.a_off[s + 1], b0 = m.b_off[s], b1 = m.b_off[s + 1];
-  const int64_t o0 = m.out_off[s];
+  const int64_t a0 = a.a_off[s], a1 = a.a_off[s + 1], b0 = a.b_off[s], b1 = a.b_off[s + 1];
+  const int64_t o0 = a.out_off[s];
   g.a0 = a0;
   g.b0 = b0;
   g.na = a1 - a0;
   g.nb = b1 - b0;
   g.out0 = o0;
-  g.ok = a0 >= 0 && a1 >= a0 && a1 <= m.a.count && b0 >= 0 && b1 >= b0 && b1 <= m.b.count &&
-         o0 >= 0 && o0 <= m.out_size && g.na * g.nb <= m.out_size - o0 &&
-         (!m.self_pairs || (a0 == b0 && a1 == b1));
+  g.ok = a0 >= 0 && a1 >= a0 && a1 <= a.a_count && b0 >= 0 && b1 >= b0 && b1 <= a.b_count &&
+         o0 >= 0 && o0 <= a.out_size && g.nb < (1 << 24) &&
+         (g.nb == 0 || g.na <= (a.out_size - o0) / g.nb) &&
+         (!a.self_pairs || (a0 == b0 && a1 == b1));
   if (s > 0) {  // blocks are laid out in segment order without overlap
-    const int64_t pna = m.a_off[s] - m.a_off[s - 1], pnb = m.b_off[s] - m.b_off[s - 1];
-    g.ok = g.ok && o0 >= m.out_off[s - 1] + pna * pnb;
+    const int64_t pna = a.a_off[s] - a.a_off[s - 1], pnb = a.b_off[s] - a.b_off[s - 1];
+    g.ok = g.ok && o0 >= a.out_off[s - 1] + pna * pnb;
   }
   return g;
 }
 
-// Tile prefix over segments (one workgroup): tile_prefix[s] = tiles of
-// segments < s.  Rejected segments get no tiles and raise kErrSegment.
-__global__ __launch_bounds__(256) void k_seg_prep(MatArgs m, int64_t* tile_prefix) {
-  __shared__ int64_t part[256];
+__device__ __forceinline__ int64_t groups_of(const Segment& g) {
+  return (g.na > 0 && g.nb > 0) ? (g.na + kTileRows - 1) / kTileRows : 0;
+}
+__device__ __forceinline__ int64_t col_tiles_of(const Segment& g) {
+  return (g.nb + kTileCols - 1) / kTileCols;
+}
+
+// Tile and row-group prefixes over segments (one workgroup).  Rejected
+// segments own nothing and raise kErrSegment.
+__global__ __launch_bounds__(256) void k_seg_prep(SegArgs a, int* err, int64_t* tile_prefix,
+                                                  int64_t* group_prefix) {
+  __shared__ int64_t part_t[256], part_g[256];
   const int tid = threadIdx.x;
-  const int per = (m.nseg + 255) / 256;
-  const int s0 = tid * per, s1 = min(m.nseg, s0 + per);
-  int64_t sum = 0;
+  const int per = (a.nseg + 255) / 256;
+  const int s0 = min(a.nseg, tid * per), s1 = min(a.nseg, s0 + per);
+  int64_t st = 0, sg = 0;
   for (int s = s0; s < s1; ++s) {
-    const Segment g = load_segment(m, s);
+    const Segment g = load_segment(a, s);
     if (!g.ok) {
-      atomicOr(m.err, kErrSegment);
+      atomicOr(err, kErrSegment);
       continue;
     }
-    sum += ((g.na + kTile - 1) / kTile) * ((g.nb + kTile - 1) / kTile);
+    sg += groups_of(g);
+    st += groups_of(g) * col_tiles_of(g);
   }
-  part[tid] = sum;
+  part_t[tid] = st;
+  part_g[tid] = sg;
   __syncthreads();
-  for (int d = 1; d < 256; d <<= 1) {  // inclusive scan
-    const int64_t v = tid >= d ? part[tid - d] : 0;
+  for (int d = 1; d < 256; d <<= 1) {  // inclusive scans
+    const int64_t vt = tid >= d ? part_t[tid - d] : 0;
+    const int64_t vg = tid >= d ? part_g[tid - d] : 0;
     __syncthreads();
-    part[tid] += v;
+    part_t[tid] += vt;
+    part_g[tid] += vg;
     __syncthreads();
   }
-  int64_t run = tid > 0 ? part[tid - 1] : 0;
-  if (tid == 0) tile_prefix[0] = 0;
+  int64_t rt = tid > 0 ? part_t[tid - 1] : 0, rg = tid > 0 ? part_g[tid - 1] : 0;
+  if (tid == 0) {
+    tile_prefix[0] = 0;
+    group_prefix[0] = 0;
+  }
   for (int s = s0; s < s1; ++s) {
-    const Segment g = load_segment(m, s);
-    if (g.ok) run += ((g.na + kTile - 1) / kTile) * ((g.nb + kTile - 1) / kTile);
-    tile_prefix[s + 1] = run;
+    const Segment g = load_segment(a, s);
+    if (g.ok) {
+      rg += groups_of(g);
+      rt += groups_of(g) * col_tiles_of(g);
+    }
+    tile_prefix[s + 1] = rt;
+    group_prefix[s + 1] = rg;
   }
 }
 
-// Staged box: vertices (local K slots), count, bounding circle, z-extent.
-template <int K>
-struct BoxLds {
-  float x[K][kTile];
-  float y[K][kTile];
-  float cx[kTile], cy[kTile], r[kTile];
-  float lo[kTile], hi[kTile];
-  uint8_t n[kTile];
+// Last s with prefix[s] <= v (the segment that owns item v of a prefix).
+__device__ __forceinline__ int find_segment(const int64_t* prefix, int nseg, int64_t v) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Axis-aligned bounds and z-extent of one box (padded slots repeat vertex 0,
+// so the bounds over all K slots are the polygon's).
+struct Bounds {
+  float x0, y0, x1, y1, lo, hi;
 };
 
 template <int K, bool FIXED, bool Z3>
-__device__ __forceinline__ void stage_box(const PolyArgs& p, int64_t idx, bool valid, int t,
-                                          BoxLds<K>& s) {
+__device__ __forceinline__ Bounds box_bounds(const PolyArgs& p, int64_t idx) {
   Poly<K> P;
-  int n = K;
-  if (valid) {
-    n = FIXED ? K : poly_count(p.nv, idx, p.kmax);
-    load_poly<K, FIXED>(p.xy, idx, p.kmax, p.vec4, n, P);
-  } else {
+  const int n = FIXED ? K : poly_count(p.nv, idx, p.kmax);
+  load_poly<K, FIXED>(p.xy, idx, p.kmax, p.vec4, n, P);
+  Bounds b;
+  b.x0 = b.x1 = P.x[0];
+  b.y0 = b.y1 = P.y[0];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      P.x[k] = 0.f;
-      P.y[k] = 0.f;
+  for (int k = 1; k < K; ++k) {
+    b.x0 = fminf(b.x0, P.x[k]);
+    b.x1 = fmaxf(b.x1, P.x[k]);
+    b.y0 = fminf(b.y0, P.y[k]);
+    b.y1 = fmaxf(b.y1, P.y[k]);
+  }
+  b.lo = Z3 ? p.zlo[idx] : 0.f;
+  b.hi = Z3 ? p.zhi[idx] : 0.f;
+  return b;
+}
+
+__device__ __forceinline__ float lane_bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct CullArgs {
+  SegArgs seg;
+  PolyArgs a, b;
+  int64_t single_tiles;
+  float* iou;
+  int64_t* pair_id;
+  int64_t capacity;
+  int64_t* tile_start;
+  int32_t* tile_count;
+  int64_t tile_capacity;
+  int* err;
+};
+
+// FILL == false: write the culled pairs' values and count the survivors of
+// every tile; FILL == true: write the survivors' output indices into their
+// tile's range of the work list (the same decisions, in the same order).
+template <int K, bool FIXED, bool Z3, bool FILL>
+__global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
+  constexpr int WAVES = kCullBlock / 64;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const bool segmented = m.seg.a_off != nullptr;
+  const int64_t total = segmented ? m.seg.tile_prefix[m.seg.nseg] : m.single_tiles;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+  for (int64_t u = (int64_t)blockIdx.x * WAVES + wave; u < total; u += (int64_t)gridDim.x * WAVES) {
+    const int s = segmented ? find_segment(m.seg.tile_prefix, m.seg.nseg, u) : 0;
+    const int64_t lu = segmented ? u - m.seg.tile_prefix[s] : u;
+    const Segment g = load_segment(m.seg, s);
+    if (!g.ok) continue;  // unreachable: rejected segments own no tiles
+    const int64_t nct = col_tiles_of(g);
+    const int64_t tr = lu / nct, tc = lu - tr * nct;
+    const int64_t r0 = tr * kTileRows, cb = tc * kTileCols;
+    const int nr = (int)min((int64_t)kTileRows, g.na - r0);
+    const int64_t ce = min(g.nb, cb + kTileCols);
+    float* out_rows = m.iou + g.out0 + r0 * g.nb;
+    int64_t base = 0;
+    if (FILL) {
+      if (u >= m.tile_capacity) continue;
+      base = m.tile_start[u];
+    }
+
+    // row bounds: lane j < nr bounds row j, then every lane holds all of them
+    Bounds rl = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
+    if (lane < nr) rl = box_bounds<K, FIXED, Z3>(m.a, g.a0 + r0 + lane);
+    Bounds rb[kTileRows];
+#pragma unroll
+    for (int j = 0; j < kTileRows; ++j) {
+      rb[j].x0 = lane_bcast(rl.x0, j);
+      rb[j].y0 = lane_bcast(rl.y0, j);
+      rb[j].x1 = lane_bcast(rl.x1, j);
+      rb[j].y1 = lane_bcast(rl.y1, j);
+      rb[j].lo = lane_bcast(rl.lo, j);
+      rb[j].hi = lane_bcast(rl.hi, j);
+    }
+    int64_t n = 0;  // survivors so far (uniform)
+    // the next 64 column boxes are loaded while the current ones are tested
+    Bounds nxt = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
+    if (cb + lane < ce) nxt = box_bounds<K, FIXED, Z3>(m.b, g.b0 + cb + lane);
+    for (int64_t c0 = cb; c0 < ce; c0 += 64) {
+      const int64_t col = c0 + lane;
+      const bool valid = col < ce;
+      const Bounds cbx = nxt;
+      if (c0 + 64 + lane < ce) nxt = box_bounds<K, FIXED, Z3>(m.b, g.b0 + c0 + 64 + lane);
+#pragma unroll
+      for (int j = 0; j < kTileRows; ++j) {
+        bool keep = false;
+        if (valid && j < nr) {
+          // closed bounds overlap (touching pairs go to the exact test), z
+          // extents overlap, not the diagonal of a self block
+          keep = cbx.x0 <= rb[j].x1 && rb[j].x0 <= cbx.x1 && cbx.y0 <= rb[j].y1 &&
+                 rb[j].y0 <= cbx.y1;
+          if (Z3) keep &= fminf(cbx.hi, rb[j].hi) > fmaxf(cbx.lo, rb[j].lo);
+          const bool diag = m.seg.self_pairs && (r0 + j == col);
+          keep &= !diag;
+          if (!FILL && !keep) out_rows[(int64_t)j * g.nb + col] = diag ? 1.f : 0.f;
+        }
+        const uint64_t mk = __ballot(keep);
+        if (FILL && keep) {
+          const int64_t slot = base + n + __popcll(mk & below);
+          if (slot < m.capacity) m.pair_id[slot] = g.out0 + (r0 + j) * g.nb + col;
+        }
+        n += __popcll(mk);
+      }
+    }
+    if (!FILL && lane == 0) {
+      if (u < m.tile_capacity) m.tile_count[u] = (int32_t)n;
+      else atomicOr(m.err, kErrCapacity);
     }
   }
-  float cx = 0.f, cy = 0.f;
+}
+
+// Exclusive prefix of the tile counts in two parallel passes over chunks of
+// kScanChunk tiles: k_scan_totals sums every chunk; k_scan_apply rescans its
+// chunk in LDS, adds the totals of the chunks before it, writes tile_start,
+// clamps the counts to what the capacity holds and (last chunk) the total.
+constexpr int kScanChunk = kScanBlock * 4;
+
+__device__ __forceinline__ int64_t scan_tiles(const int64_t* tile_prefix, int nseg,
+                                              int64_t single_tiles, int64_t tile_capacity) {
+  const int64_t nt = tile_prefix != nullptr ? tile_prefix[nseg] : single_tiles;
+  return nt < tile_capacity ? nt : tile_capacity;
+}
+
+// Block-wide inclusive scan of one value per thread (wave scans + LDS).
+__device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* s_w) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    cx += P.x[k];
-    cy += P.y[k];
-    s.x[k][t] = P.x[k];
-    s.y[k][t] = P.y[k];
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t o = __shfl_up(v, d);
+    if (lane >= d) v += o;
   }
-  // padded slots repeat vertex 0, so the mean over K slots is inside the hull
-  cx *= 1.0f / K;
-  cy *= 1.0f / K;
-  float r2 = 0.f;
+  if (lane == 63) s_w[wave] = v;
+  __syncthreads();
+  int64_t add = 0;
+  for (int w = 0; w < wave; ++w) add += s_w[w];
+  __syncthreads();
+  return v + add;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_totals(const int64_t* tile_prefix, int nseg,
+                                                            int64_t single_tiles,
+                                                            int64_t tile_capacity,
+                                                            const int32_t* tile_count,
+                                                            int64_t* totals) {
+  __shared__ int64_t s_w[kScanBlock / 64];
+  const int64_t nt = scan_tiles(tile_prefix, nseg, single_tiles, tile_capacity);
+  const int64_t c0 = (int64_t)blockIdx.x * kScanChunk;
+  if (c0 >= nt) return;  // uniform
+  int64_t v = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const float dx = P.x[k] - cx, dy = P.y[k] - cy;
-    r2 = fmaxf(r2, dx * dx + dy * dy);
+  for (int k = 0; k < kScanChunk / kScanBlock; ++k) {
+    const int64_t t = c0 + k * kScanBlock + threadIdx.x;
+    if (t < nt) v += tile_count[t];
   }
-  s.cx[t] = cx;
-  s.cy[t] = cy;
-  // inflated by 1e-5 relative: covers the rounding of the centre, the
-  // distances and the square root, so the circle contains the polygon
-  s.r[t] = valid ? sqrtf(r2) * 1.00001f + 1e-30f : -1.f;
-  s.n[t] = (uint8_t)n;
-  if (Z3) {
-    s.lo[t] = valid ? p.zlo[idx] : 0.f;
-    s.hi[t] = valid ? p.zhi[idx] : 0.f;
+  v = block_inclusive_scan(v, s_w);
+  if (threadIdx.x == kScanBlock - 1) totals[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int64_t* tile_prefix, int nseg,
+                                                           int64_t single_tiles,
+                                                           int64_t tile_capacity,
+                                                           const int64_t* totals,
+                                                           int64_t* tile_start,
+                                                           int32_t* tile_count, int64_t* count,
+                                                           int64_t capacity, int* err) {
+  __shared__ int64_t s_w[kScanBlock / 64];
+  const int64_t nt = scan_tiles(tile_prefix, nseg, single_tiles, tile_capacity);
+  const int64_t nchunks = (nt + kScanChunk - 1) / kScanChunk;
+  const int64_t c0 = (int64_t)blockIdx.x * kScanChunk;
+  if (c0 >= nt) {  // uniform; an empty matrix still publishes its total
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = 0;
+    return;
   }
+  // base: totals of the chunks before this one
+  int64_t b = 0;
+  for (int64_t k = threadIdx.x; k < blockIdx.x; k += kScanBlock) b += totals[k];
+  b = block_inclusive_scan(b, s_w);
+  __shared__ int64_t s_base;
+  if (threadIdx.x == kScanBlock - 1) s_base = b;
+  __syncthreads();
+  int64_t run = s_base;
+  // this chunk: kScanChunk / kScanBlock consecutive tiles per thread
+  constexpr int PER = kScanChunk / kScanBlock;
+  int64_t c[PER];
+  int64_t v = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t t = c0 + (int64_t)threadIdx.x * PER + k;
+    c[k] = t < nt ? tile_count[t] : 0;
+    v += c[k];
+  }
+  const int64_t incl = block_inclusive_scan(v, s_w);
+  run += incl - v;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t t = c0 + (int64_t)threadIdx.x * PER + k;
+    if (t < nt) {
+      tile_start[t] = run;
+      int64_t room = capacity - run;
+      room = room < 0 ? 0 : (room > c[k] ? c[k] : room);
+      tile_count[t] = (int32_t)room;
+    }
+    run += c[k];
+  }
+  if (blockIdx.x == nchunks - 1 && threadIdx.x == kScanBlock - 1) {
+    *count = run;
+    if (run > capacity) atomicOr(err, kErrCapacity);
+  }
+}
+
+struct ExactArgs {
+  SegArgs seg;
+  PolyArgs a, b;
+  float* iou;
+  const int64_t* pair_id;
+  uint8_t* s_nx;
+  uint8_t* s_flags;
+  int64_t capacity;
+  const int64_t* count;
+  int cap;
+  int* err;
+};
+
+// Segment, row and column (within the segment) of a flat output index.
+__device__ __forceinline__ bool locate(const SegArgs& sa, int64_t pid, Segment& g, int64_t& r,
+                                       int64_t& c) {
+  const int s = sa.a_off != nullptr ? find_segment(sa.out_off, sa.nseg, pid) : 0;
+  g = load_segment(sa, s);
+  const int64_t local = pid - g.out0;
+  if (!g.ok || g.nb <= 0 || local < 0) return false;
+  r = local / g.nb;
+  c = local - r * g.nb;
+  return r < g.na;
 }
 
 template <int K, bool FIXED, bool Z3>
-__global__ __launch_bounds__(kMatBlock) void k_matrix_fwd(MatArgs m) {
+__global__ __launch_bounds__(kExactBlock) void k_matrix_exact(ExactArgs m) {
   constexpr int CAP = 2 * K;
-  __shared__ BoxLds<K> sa, sb;
-  __shared__ float s_out[kTile][kTile + 1];
-  __shared__ uint16_t s_surv[kTile * kTile];
-  __shared__ int s_nsurv;
-  __shared__ float2 s_pt[CAP * kMatBlock];
-  __shared__ uint8_t s_cd[CAP * kMatBlock];
+  __shared__ float2 s_pt[CAP * kExactBlock];
+  __shared__ uint8_t s_cd[CAP * kExactBlock];
   const int tid = threadIdx.x;
-  const bool segmented = m.a_off != nullptr;
-  const int64_t total = segmented ? m.tile_prefix[m.nseg] : m.single_tiles;
-
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    // locate the tile's segment
-    int s = 0;
-    int64_t lt = t;
-    if (segmented) {
-      int lo = 0, hi = m.nseg - 1;  // last s with prefix[s] <= t
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (m.tile_prefix[mid] <= t) lo = mid; else hi = mid - 1;
-      }
-      s = lo;
-      lt = t - m.tile_prefix[s];
+  int64_t n = *m.count;
+  n = n < m.capacity ? n : m.capacity;
+  for (int64_t e = (int64_t)blockIdx.x * kExactBlock + tid; e < n;
+       e += (int64_t)gridDim.x * kExactBlock) {
+    const int64_t pid = m.pair_id[e];
+    Segment g;
+    int64_t r = 0, c = 0;
+    if (!locate(m.seg, pid, g, r, c)) continue;  // not written by the cull on these shapes
+    const int64_t ia = g.a0 + r, ib = g.b0 + c;
+    const int n1 = FIXED ? K : poly_count(m.a.nv, ia, m.a.kmax);
+    const int n2 = FIXED ? K : poly_count(m.b.nv, ib, m.b.kmax);
+    Poly<K> P, Q;
+    load_poly<K, FIXED>(m.a.xy, ia, m.a.kmax, m.a.vec4, n1, P);
+    load_poly<K, FIXED>(m.b.xy, ib, m.b.kmax, m.b.vec4, n2, Q);
+    PairResult<K> res;
+    pair_forward<K, FIXED, kExactBlock>(P, n1, Q, n2, s_pt + tid, s_cd + tid, res);
+    float v;
+    if (Z3) {
+      v = iou_3d(res.inter, res.a1, res.a2, res.m, m.a.zlo[ia], m.a.zhi[ia], m.b.zlo[ib],
+                 m.b.zhi[ib]);
+    } else {
+      v = iou_2d(res.inter, res.a1, res.a2, res.m);
     }
-    const Segment g = load_segment(m, s);
-    if (!g.ok) continue;  // unreachable: rejected segments own no tiles
-    const int64_t tcols = (g.nb + kTile - 1) / kTile;
-    const int64_t r0 = (lt / tcols) * kTile, c0 = (lt % tcols) * kTile;
-    const int nr = (int)min((int64_t)kTile, g.na - r0), nc = (int)min((int64_t)kTile, g.nb - c0);
-
-    __syncthreads();  // previous tile done with LDS
-    if (tid < kTile) {
-      stage_box<K, FIXED, Z3>(m.a, g.a0 + r0 + tid, tid < nr, tid, sa);
-    } else if (tid < 2 * kTile) {
-      stage_box<K, FIXED, Z3>(m.b, g.b0 + c0 + (tid - kTile), tid - kTile < nc, tid - kTile, sb);
-    }
-    if (tid == 0) s_nsurv = 0;
-    __syncthreads();
-
-    // cull: 16 pairs per thread, rows tid/16*... (row-major over the tile)
-#pragma unroll 4
-    for (int q = tid; q < kTile * kTile; q += kMatBlock) {
-      const int r = q / kTile, c = q % kTile;
-      float v = 0.f;
-      bool surv = false;
-      if (r < nr && c < nc) {
-        const float dx = sa.cx[r] - sb.cx[c], dy = sa.cy[r] - sb.cy[c];
-        const float rr = sa.r[r] + sb.r[c];
-        surv = dx * dx + dy * dy <= rr * rr * 1.00001f;
-        if (Z3) surv &= fminf(sa.hi[r], sb.hi[c]) > fmaxf(sa.lo[r], sb.lo[c]);
-        if (m.self_pairs && g.a0 + r0 + r == g.b0 + c0 + c) {
-          surv = false;
-          v = 1.f;
-        }
-      }
-      s_out[r][c] = v;
-      if (surv) {
-        const int slot = atomicAdd(&s_nsurv, 1);
-        s_surv[slot] = (uint16_t)q;
-      }
-    }
-    __syncthreads();
-
-    // exact forward on the survivors, all lanes busy
-    const int ns = s_nsurv;
-    for (int k = tid; k < ns; k += kMatBlock) {
-      const int q = s_surv[k];
-      const int r = q / kTile, c = q % kTile;
-      Poly<K> P, Q;
+    m.iou[pid] = v;
+    if (res.overflow) atomicOr(m.err, kErrCapacity);
+    m.s_nx[e] = (uint8_t)res.m;
+    uint8_t* row = m.s_flags + e * (int64_t)m.cap;
 #pragma unroll
-      for (int v = 0; v < K; ++v) {
-        P.x[v] = sa.x[v][r];
-        P.y[v] = sa.y[v][r];
-        Q.x[v] = sb.x[v][c];
-        Q.y[v] = sb.y[v][c];
-      }
-      const int n1 = sa.n[r], n2 = sb.n[c];
-      PairResult<K> res;
-      pair_forward<K, FIXED, kMatBlock>(P, n1, Q, n2, s_pt + tid, s_cd + tid, res);
-      float v;
-      if (Z3) {
-        v = iou_3d(res.inter, res.a1, res.a2, res.m, sa.lo[r], sa.hi[r], sb.lo[c], sb.hi[c]);
-      } else {
-        v = iou_2d(res.inter, res.a1, res.a2, res.m);
-      }
-      s_out[r][c] = v;
-      if (res.overflow) atomicOr(m.err, kErrCapacity);
-      if (m.pair_id != nullptr && res.m > 0) {
-        const unsigned long long e = atomicAdd(reinterpret_cast<unsigned long long*>(m.count), 1ull);
-        if ((int64_t)e < m.capacity) {
-          m.pair_id[e] = g.out0 + (r0 + r) * g.nb + (c0 + c);
-          m.s_nx[e] = (uint8_t)res.m;
-          uint8_t* row = m.s_flags + (int64_t)e * m.cap;
-#pragma unroll
-          for (int b = 0; b < CAP; ++b)
-            if (b < m.cap) row[b] = (uint8_t)(res.codes[b >> 2] >> ((b & 3) * 8));
-        } else {
-          atomicOr(m.err, kErrCapacity);
-        }
-      }
-    }
-    __syncthreads();
-
-    // write the tile: each row segment is contiguous in the output
-    float* base = m.iou + g.out0 + r0 * g.nb + c0;
-    for (int q = tid; q < kTile * kTile; q += kMatBlock) {
-      const int r = q / kTile, c = q % kTile;
-      if (r < nr && c < nc) base[(int64_t)r * g.nb + c] = s_out[r][c];
-    }
+    for (int b = 0; b < CAP; ++b)
+      if (b < m.cap) row[b] = (uint8_t)(res.codes[b >> 2] >> ((b & 3) * 8));
   }
 }
 
-// Zero-fills n floats (gradient outputs before atomic accumulation).
+// Zero-fills n floats.
 __global__ void k_fill_zero(float* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0.f;
 }
 
-// Resets the saved-list counter (a kernel, not a memset, so that graph
-// replays see the reset).
-__global__ void k_reset_count(int64_t* count) { *count = 0; }
-
-struct MatBwdArgs {
+struct BwdArgs {
+  SegArgs seg;
   PolyArgs a, b;
-  const int64_t* a_off;
-  const int64_t* b_off;
-  const int64_t* out_off;
-  int nseg;
-  int self_pairs;
+  int64_t single_groups;
   const float* grad;
-  int64_t out_size;  // elements of grad
   const int64_t* pair_id;
   const uint8_t* s_nx;
   const uint8_t* s_flags;
   int64_t capacity;
-  const int64_t* count;
+  const int64_t* tile_start;
+  const int32_t* tile_count;
+  int64_t tile_capacity;
   int cap;
   float* ga_xy;
-  float* gb_xy;  // == ga_xy when self_pairs
+  float* gb_xy;  // unused when self_pairs
   float* ga_z;
   float* gb_z;
 };
 
+template <int K>
+constexpr int bwd_block() {
+  return K == 8 ? 128 : 256;
+}
+
 template <int K, bool FIXED, bool Z3>
-__global__ __launch_bounds__(128) void k_matrix_bwd(MatBwdArgs m) {
-  constexpr int BLOCK = 128;
+__global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
+  constexpr int BLOCK = bwd_block<K>();
+  constexpr int WAVES = BLOCK / 64;
   constexpr int CAP = 2 * K;
+  constexpr int ROW = 2 * K + 2;  // accumulated floats per row: xy slots, then (zlo, zhi)
+  __shared__ float s_acc[WAVES][kTileRows * ROW];
   __shared__ float2 s_v[CAP * BLOCK];
   __shared__ float2 s_g[CAP * BLOCK];
   const int tid = threadIdx.x;
-  int64_t n = *m.count;
-  n = n < m.capacity ? n : m.capacity;
-  for (int64_t e = (int64_t)blockIdx.x * BLOCK + tid; e < n; e += (int64_t)gridDim.x * BLOCK) {
-    const int64_t pid = m.pair_id[e];
-    if (pid < 0 || pid >= m.out_size) continue;  // not written by a forward on these shapes
-    int64_t a0 = 0, b0 = 0, nb = m.b.count, local = pid;
-    if (m.a_off != nullptr) {
-      int lo = 0, hi = m.nseg - 1;  // last s with out_off[s] <= pid and a non-empty block
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (m.out_off[mid] <= pid) lo = mid; else hi = mid - 1;
-      }
-      // empty segments share their out_off with the next one: step back to
-      // the last segment whose block holds pid
-      int s = lo;
-      while (s > 0 && (m.b_off[s + 1] - m.b_off[s]) * (m.a_off[s + 1] - m.a_off[s]) == 0) --s;
-      a0 = m.a_off[s];
-      b0 = m.b_off[s];
-      nb = m.b_off[s + 1] - b0;
-      local = pid - m.out_off[s];
-    }
-    if (nb <= 0) continue;
-    const int64_t ia = a0 + local / nb, ib = b0 + local % nb;
-    if (ia < 0 || ia >= m.a.count || ib < 0 || ib >= m.b.count) continue;
-    const int n1 = FIXED ? K : poly_count(m.a.nv, ia, m.a.kmax);
-    const int n2 = FIXED ? K : poly_count(m.b.nv, ib, m.b.kmax);
-    Poly<K> P, Q;
-    load_poly<K, FIXED>(m.a.xy, ia, m.a.kmax, m.a.vec4, n1, P);
-    load_poly<K, FIXED>(m.b.xy, ib, m.b.kmax, m.b.vec4, n2, Q);
-    uint32_t codes[K / 2];
+  const int lane = tid & 63, wave = tid >> 6;
+  float* acc_w = s_acc[wave];
+  const bool segmented = m.seg.a_off != nullptr;
+  const int64_t total = segmented ? m.seg.group_prefix[m.seg.nseg] : m.single_groups;
+
+  for (int64_t u = (int64_t)blockIdx.x * WAVES + wave; u < total; u += (int64_t)gridDim.x * WAVES) {
+    const int s = segmented ? find_segment(m.seg.group_prefix, m.seg.nseg, u) : 0;
+    const int64_t tr = segmented ? u - m.seg.group_prefix[s] : u;  // row group in the segment
+    const Segment g = load_segment(m.seg, s);
+    if (!g.ok) continue;
+    const int64_t r0 = tr * kTileRows;
+    const int nr = (int)min((int64_t)kTileRows, g.na - r0);
+    const int64_t nct = col_tiles_of(g);
+    const int64_t t0 = (segmented ? m.seg.tile_prefix[s] : 0) + tr * nct;
+    for (int i = lane; i < kTileRows * ROW; i += 64) acc_w[i] = 0.f;
+    wave_sync();
+    // the row group's tiles are consecutive, so are their entries
+    const int64_t t1 = t0 + nct - 1;
+    const bool have = t1 < m.tile_capacity;
+    const int64_t e_begin = have ? m.tile_start[t0] : 0;
+    const int64_t e_end = have ? m.tile_start[t1] + m.tile_count[t1] : 0;
+    {
+      for (int64_t e = e_begin + lane; e < e_end; e += 64) {
+        if (e < 0 || e >= m.capacity) continue;
+        const int nx = m.s_nx[e];
+        if (nx == 0) continue;  // empty intersection: zero gradient
+        const int64_t pid = m.pair_id[e];
+        const int64_t local = pid - g.out0;
+        if (local < 0 || g.nb <= 0) continue;
+        const int64_t rg = local / g.nb, col = local - rg * g.nb;  // row within the segment
+        const int rl = (int)(rg - r0);
+        if (rl < 0 || rl >= nr) continue;
+        const int64_t ia = g.a0 + rg, ib = g.b0 + col;
+        const int n1 = FIXED ? K : poly_count(m.a.nv, ia, m.a.kmax);
+        const int n2 = FIXED ? K : poly_count(m.b.nv, ib, m.b.kmax);
+        Poly<K> P, Q;
+        load_poly<K, FIXED>(m.a.xy, ia, m.a.kmax, m.a.vec4, n1, P);
+        load_poly<K, FIXED>(m.b.xy, ib, m.b.kmax, m.b.vec4, n2, Q);
+        uint32_t codes[K / 2];
 #pragma unroll
-    for (int w = 0; w < K / 2; ++w) codes[w] = 0xffffffffu;
-    const uint8_t* row = m.s_flags + e * (int64_t)m.cap;
+        for (int w = 0; w < K / 2; ++w) codes[w] = 0xffffffffu;
+        const uint8_t* row = m.s_flags + e * (int64_t)m.cap;
 #pragma unroll
-    for (int k = 0; k < CAP; ++k) {
-      if (k < m.cap) {
-        const uint32_t c = row[k];
-        codes[k >> 2] = (codes[k >> 2] & ~(0xffu << ((k & 3) * 8))) | (c << ((k & 3) * 8));
-      }
-    }
-    float lo1 = 0.f, hi1 = 0.f, lo2 = 0.f, hi2 = 0.f;
-    if (Z3) {
-      lo1 = m.a.zlo[ia];
-      hi1 = m.a.zhi[ia];
-      lo2 = m.b.zlo[ib];
-      hi2 = m.b.zhi[ib];
-    }
-    float2 gP[K], gQ[K], gz1, gz2;
-    pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, m.grad[pid], (int)m.s_nx[e], codes, lo1, hi1,
-                                       lo2, hi2, s_v + tid, s_g + tid, gP, gQ, gz1, gz2);
-    float* oa = m.ga_xy + ia * (int64_t)m.a.kmax * 2;
-    float* ob = m.gb_xy + ib * (int64_t)m.b.kmax * 2;
+        for (int k = 0; k < CAP; ++k) {
+          if (k < m.cap) {
+            const uint32_t cc = row[k];
+            codes[k >> 2] = (codes[k >> 2] & ~(0xffu << ((k & 3) * 8))) | (cc << ((k & 3) * 8));
+          }
+        }
+        // self pairs: pair (k, i) gives box i the column-role gradient of an
+        // IoU that equals IoU(i, k); by symmetry it is the row-role gradient
+        // of (i, k)
+        float gw = m.grad[pid];
+        if (m.seg.self_pairs) gw += m.grad[g.out0 + col * g.nb + rg];
+        float lo1 = 0.f, hi1 = 0.f, lo2 = 0.f, hi2 = 0.f;
+        if (Z3) {
+          lo1 = m.a.zlo[ia];
+          hi1 = m.a.zhi[ia];
+          lo2 = m.b.zlo[ib];
+          hi2 = m.b.zhi[ib];
+        }
+        float2 gP[K], gQ[K], gz1, gz2;
+        pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
+                                           s_v + tid, s_g + tid, gP, gQ, gz1, gz2);
+        float* acc = acc_w + rl * ROW;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (k < n1 && k < m.a.kmax) {
-        unsafeAtomicAdd(oa + 2 * k, gP[k].x);
-        unsafeAtomicAdd(oa + 2 * k + 1, gP[k].y);
-      }
-      if (k < n2 && k < m.b.kmax) {
-        unsafeAtomicAdd(ob + 2 * k, gQ[k].x);
-        unsafeAtomicAdd(ob + 2 * k + 1, gQ[k].y);
+        for (int k = 0; k < K; ++k) {
+          if (FIXED || k < n1) {
+            atomicAdd(acc + 2 * k, gP[k].x);
+            atomicAdd(acc + 2 * k + 1, gP[k].y);
+          }
+        }
+        if (Z3) {
+          atomicAdd(acc + 2 * K, gz1.x);
+          atomicAdd(acc + 2 * K + 1, gz1.y);
+        }
+        if (!m.seg.self_pairs) {
+          float* ob = m.gb_xy + ib * (int64_t)m.b.kmax * 2;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            if ((FIXED || k < n2) && k < m.b.kmax) {
+              unsafeAtomicAdd(ob + 2 * k, gQ[k].x);
+              unsafeAtomicAdd(ob + 2 * k + 1, gQ[k].y);
+            }
+          }
+          if (Z3) {
+            unsafeAtomicAdd(m.gb_z + 2 * ib, gz2.x);
+            unsafeAtomicAdd(m.gb_z + 2 * ib + 1, gz2.y);
+          }
+        }
       }
     }
-    if (Z3) {
-      unsafeAtomicAdd(m.ga_z + 2 * ia, gz1.x);
-      unsafeAtomicAdd(m.ga_z + 2 * ia + 1, gz1.y);
-      unsafeAtomicAdd(m.gb_z + 2 * ib, gz2.x);
-      unsafeAtomicAdd(m.gb_z + 2 * ib + 1, gz2.y);
+    wave_sync();
+    // each row of a belongs to exactly one row group: plain stores
+    for (int i = lane; i < nr * ROW; i += 64) {
+      const int rl = i / ROW, k = i - rl * ROW;
+      const int64_t ia = g.a0 + r0 + rl;
+      const float v = acc_w[i];
+      if (k < 2 * K) {
+        if (k < 2 * m.a.kmax) m.ga_xy[ia * (int64_t)m.a.kmax * 2 + k] = v;
+      } else if (Z3) {
+        m.ga_z[ia * 2 + (k - 2 * K)] = v;
+      }
     }
+    wave_sync();
   }
 }
 
 namespace {
 
-template <int K, bool FIXED, bool Z3>
-void launch_fwd(const MatArgs& m, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_matrix_fwd<K, FIXED, Z3>), dim3(grid), dim3(kMatBlock), 0, s, m);
+template <bool B>
+using Bool = std::integral_constant<bool, B>;
+
+// Calls f(K, FIXED, Z3) with compile-time constants.
+template <typename F>
+void dispatch(int K, bool fixed, bool z3, F&& f) {
+  auto go = [&](auto k, auto fx) {
+    if (z3) f(k, fx, Bool<true>{}); else f(k, fx, Bool<false>{});
+  };
+  if (K == 4) {
+    if (fixed) go(std::integral_constant<int, 4>{}, Bool<true>{});
+    else go(std::integral_constant<int, 4>{}, Bool<false>{});
+  } else {
+    if (fixed) go(std::integral_constant<int, 8>{}, Bool<true>{});
+    else go(std::integral_constant<int, 8>{}, Bool<false>{});
+  }
 }
 
-template <int K, bool FIXED, bool Z3>
-void launch_bwd(const MatBwdArgs& m, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_matrix_bwd<K, FIXED, Z3>), dim3(grid), dim3(128), 0, s, m);
+bool valid_saved(const dgal_saved* s) {
+  return s != nullptr && s->pair_id && s->nx && s->xflags && s->count && s->capacity >= 0 &&
+         s->tile_start && s->tile_count && s->tile_capacity >= 0;
 }
+
+void zero(float* p, int64_t n, hipStream_t stream) {
+  if (p != nullptr && n > 0) {
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)(blocks > 4096 ? 4096 : blocks)), dim3(256), 0,
+                       stream, p, n);
+  }
+}
+
+// Common validation of the matrix shapes; fills the segment arguments.
+int check_shapes(dgal_polys a, dgal_polys b, const int64_t* a_off, const int64_t* b_off,
+                 const int64_t* out_off, int nseg, int self_pairs, int64_t out_size,
+                 const dgal_saved* saved, SegArgs& sa) {
+  if (!valid_polys(a) || !valid_polys(b) || out_size < 0) return DGAL_EINVAL;
+  if ((a.zlo == nullptr) != (b.zlo == nullptr)) return DGAL_EINVAL;
+  const bool segmented = a_off != nullptr;
+  if (segmented != (b_off != nullptr) || segmented != (out_off != nullptr)) return DGAL_EINVAL;
+  if (segmented && (nseg < 1 || nseg > kMaxSeg)) return DGAL_EINVAL;
+  if (self_pairs && !same_polys(a, b)) return DGAL_EINVAL;
+  if (!segmented && (b.count >= (1 << 24) ||
+                     (a.count > 0 && b.count > 0 && out_size / a.count < b.count)))
+    return DGAL_EINVAL;
+  if (!valid_saved(saved)) return DGAL_EINVAL;
+  if (saved->tile_capacity > kScanTotals * (int64_t)kScanChunk) return DGAL_EINVAL;
+  sa.a_off = a_off;
+  sa.b_off = b_off;
+  sa.out_off = out_off;
+  sa.nseg = segmented ? nseg : 1;
+  sa.a_count = a.count;
+  sa.b_count = b.count;
+  sa.out_size = out_size;
+  sa.self_pairs = self_pairs;
+  sa.tile_prefix = nullptr;
+  sa.group_prefix = nullptr;
+  return DGAL_OK;
+}
+
+int64_t ceil_div(int64_t x, int64_t y) { return (x + y - 1) / y; }
 
 }  // namespace
 
 int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
                    const int64_t* b_off, const int64_t* out_off, int nseg, int self_pairs,
                    float* iou, int64_t out_size, const dgal_saved* saved, hipStream_t stream) {
-  if (!valid_polys(a) || !valid_polys(b)) return DGAL_EINVAL;
-  if ((a.zlo == nullptr) != (b.zlo == nullptr)) return DGAL_EINVAL;
-  const bool segmented = a_off != nullptr;
-  if (segmented != (b_off != nullptr) || segmented != (out_off != nullptr)) return DGAL_EINVAL;
-  if (segmented && (nseg < 1 || nseg > kMaxSeg)) return DGAL_EINVAL;
-  if (self_pairs && !same_polys(a, b)) return DGAL_EINVAL;
-  if (out_size < 0) return DGAL_EINVAL;
-  if (!segmented && (a.count > 0 && b.count > 0) && out_size / (a.count > 0 ? a.count : 1) < b.count)
-    return DGAL_EINVAL;
-  if (out_size > 0 && (iou == nullptr || !aligned(iou, 4))) return DGAL_EINVAL;
-  if (saved != nullptr) {
-    if (saved->pair_id == nullptr || saved->nx == nullptr || saved->xflags == nullptr ||
-        saved->count == nullptr || saved->capacity < 0)
-      return DGAL_EINVAL;
-  }
-  if (a.count == 0 && b.count == 0 && !segmented) return DGAL_OK;
+  SegArgs sa;
+  const int st = check_shapes(a, b, a_off, b_off, out_off, nseg, self_pairs, out_size, saved, sa);
+  if (st != DGAL_OK) return st;
+  if (out_size > 0 && iou == nullptr) return DGAL_EINVAL;
   DeviceGuard dg(ctx.device);
   if (!dg.ok) return DGAL_EHIP;
-  const int K = (a.kmax <= 4 && b.kmax <= 4) ? 4 : 8;
-  MatArgs m;
-  m.a = poly_args(a, K);
-  m.b = poly_args(b, K);
-  m.a_off = a_off;
-  m.b_off = b_off;
-  m.out_off = out_off;
-  m.nseg = segmented ? nseg : 1;
-  m.self_pairs = self_pairs;
-  m.iou = iou;
-  m.out_size = out_size;
-  m.pair_id = saved ? saved->pair_id : nullptr;
-  m.s_nx = saved ? saved->nx : nullptr;
-  m.s_flags = saved ? saved->xflags : nullptr;
-  m.capacity = saved ? saved->capacity : 0;
-  m.count = saved ? saved->count : nullptr;
-  m.cap = a.kmax + b.kmax;
-  m.err = ctx.err;
-  m.single_tiles = segmented ? 0 : ((a.count + kTile - 1) / kTile) * ((b.count + kTile - 1) / kTile);
-  m.tile_prefix = nullptr;
-  if (saved) hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, stream, saved->count);
+  const int K = reg_k(a.kmax, b.kmax);
+  const bool segmented = a_off != nullptr;
+  int64_t single_tiles = 0;
   if (segmented) {
-    m.tile_prefix = ctx.prefix;
-    hipLaunchKernelGGL(k_seg_prep, dim3(1), dim3(256), 0, stream, m, ctx.prefix);
-  }
-  const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K;
-  const bool z3 = a.zlo != nullptr;
-  int grid = ctx.cus * 4;
-  if (!segmented && m.single_tiles < grid) grid = (int)(m.single_tiles > 0 ? m.single_tiles : 1);
-  if (K == 4) {
-    if (fixed) {
-      z3 ? launch_fwd<4, true, true>(m, grid, stream) : launch_fwd<4, true, false>(m, grid, stream);
-    } else {
-      z3 ? launch_fwd<4, false, true>(m, grid, stream) : launch_fwd<4, false, false>(m, grid, stream);
-    }
+    sa.tile_prefix = ctx.prefix;
+    sa.group_prefix = ctx.prefix + (kMaxSeg + 1);
+    hipLaunchKernelGGL(k_seg_prep, dim3(1), dim3(256), 0, stream, sa, ctx.err, ctx.prefix,
+                       ctx.prefix + (kMaxSeg + 1));
   } else {
-    if (fixed) {
-      z3 ? launch_fwd<8, true, true>(m, grid, stream) : launch_fwd<8, true, false>(m, grid, stream);
-    } else {
-      z3 ? launch_fwd<8, false, true>(m, grid, stream) : launch_fwd<8, false, false>(m, grid, stream);
-    }
+    if (a.count == 0 || b.count == 0) return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
+    single_tiles = ceil_div(a.count, kTileRows) * ceil_div(b.count, kTileCols);
   }
+  CullArgs c;
+  c.seg = sa;
+  c.a = poly_args(a, K);
+  c.b = poly_args(b, K);
+  c.single_tiles = single_tiles;
+  c.iou = iou;
+  c.pair_id = saved->pair_id;
+  c.capacity = saved->capacity;
+  c.tile_start = saved->tile_start;
+  c.tile_count = saved->tile_count;
+  c.tile_capacity = saved->tile_capacity;
+  c.err = ctx.err;
+  ExactArgs x;
+  x.seg = sa;
+  x.a = c.a;
+  x.b = c.b;
+  x.iou = iou;
+  x.pair_id = saved->pair_id;
+  x.s_nx = saved->nx;
+  x.s_flags = saved->xflags;
+  x.capacity = saved->capacity;
+  x.count = saved->count;
+  x.cap = a.kmax + b.kmax;
+  x.err = ctx.err;
+  int64_t cull_grid = (int64_t)ctx.cus * 16;
+  if (!segmented) cull_grid = std::min(cull_grid, ceil_div(single_tiles, kCullBlock / 64));
+  const int exact_grid = ctx.cus * 8;
+  const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K;
+  dispatch(K, fixed, a.zlo != nullptr, [&](auto k, auto fx, auto z) {
+    constexpr int KK = decltype(k)::value;
+    constexpr bool FX = decltype(fx)::value, ZZ = decltype(z)::value;
+    hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ, false>), dim3((unsigned)cull_grid),
+                       dim3(kCullBlock), 0, stream, c);
+    const int64_t chunks = std::max<int64_t>(1, ceil_div(saved->tile_capacity, kScanChunk));
+    hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)chunks), dim3(kScanBlock), 0, stream,
+                       sa.tile_prefix, sa.nseg, single_tiles, saved->tile_capacity,
+                       saved->tile_count, ctx.scan);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)chunks), dim3(kScanBlock), 0, stream,
+                       sa.tile_prefix, sa.nseg, single_tiles, saved->tile_capacity, ctx.scan,
+                       saved->tile_start, saved->tile_count, saved->count, saved->capacity,
+                       ctx.err);
+    hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ, true>), dim3((unsigned)cull_grid),
+                       dim3(kCullBlock), 0, stream, c);
+    hipLaunchKernelGGL((k_matrix_exact<KK, FX, ZZ>), dim3(exact_grid), dim3(kExactBlock), 0,
+                       stream, x);
+  });
   return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
 }
 
@@ -472,16 +727,10 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
                     const float* grad_iou, int64_t out_size, const dgal_saved* saved,
                     float* grad_a_xy, float* grad_b_xy, float* grad_a_z, float* grad_b_z,
                     hipStream_t stream) {
-  if (!valid_polys(a) || !valid_polys(b) || out_size < 0) return DGAL_EINVAL;
+  SegArgs sa;
+  const int st = check_shapes(a, b, a_off, b_off, out_off, nseg, self_pairs, out_size, saved, sa);
+  if (st != DGAL_OK) return st;
   const bool z3 = a.zlo != nullptr;
-  if ((a.zlo == nullptr) != (b.zlo == nullptr)) return DGAL_EINVAL;
-  const bool segmented = a_off != nullptr;
-  if (segmented != (b_off != nullptr) || segmented != (out_off != nullptr)) return DGAL_EINVAL;
-  if (segmented && (nseg < 1 || nseg > kMaxSeg)) return DGAL_EINVAL;
-  if (self_pairs && !same_polys(a, b)) return DGAL_EINVAL;
-  if (saved == nullptr || saved->pair_id == nullptr || saved->nx == nullptr ||
-      saved->xflags == nullptr || saved->count == nullptr || saved->capacity < 0)
-    return DGAL_EINVAL;
   if (grad_iou == nullptr || grad_a_xy == nullptr) return DGAL_EINVAL;
   if (self_pairs ? (grad_b_xy != nullptr || grad_b_z != nullptr) : (grad_b_xy == nullptr))
     return DGAL_EINVAL;
@@ -489,58 +738,53 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
   if (!self_pairs && z3 != (grad_b_z != nullptr)) return DGAL_EINVAL;
   DeviceGuard dg(ctx.device);
   if (!dg.ok) return DGAL_EHIP;
-  const int K = (a.kmax <= 4 && b.kmax <= 4) ? 4 : 8;
-  float* gbx = self_pairs ? grad_a_xy : grad_b_xy;
-  float* gbz = self_pairs ? grad_a_z : grad_b_z;
-  const int zb = 256;
-  auto zero = [&](float* p, int64_t n) {
-    if (p != nullptr && n > 0) {
-      int64_t blocks = (n + zb - 1) / zb;
-      hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)(blocks > 4096 ? 4096 : blocks)), dim3(zb), 0,
-                         stream, p, n);
-    }
-  };
-  zero(grad_a_xy, a.count * a.kmax * 2);
-  if (!self_pairs) zero(grad_b_xy, b.count * b.kmax * 2);
-  if (z3) {
-    zero(grad_a_z, a.count * 2);
-    if (!self_pairs) zero(grad_b_z, b.count * 2);
+  const int K = reg_k(a.kmax, b.kmax);
+  const bool segmented = a_off != nullptr;
+  // rows outside every row group keep zeros; row groups overwrite their rows
+  zero(grad_a_xy, a.count * a.kmax * 2, stream);
+  if (z3) zero(grad_a_z, a.count * 2, stream);
+  if (!self_pairs) {
+    zero(grad_b_xy, b.count * b.kmax * 2, stream);
+    if (z3) zero(grad_b_z, b.count * 2, stream);
   }
-  MatBwdArgs m;
+  int64_t single_groups = 0;
+  if (segmented) {
+    // recomputed: another matrix call may have used the workspace since the forward
+    sa.tile_prefix = ctx.prefix;
+    sa.group_prefix = ctx.prefix + (kMaxSeg + 1);
+    hipLaunchKernelGGL(k_seg_prep, dim3(1), dim3(256), 0, stream, sa, ctx.err, ctx.prefix,
+                       ctx.prefix + (kMaxSeg + 1));
+  } else {
+    if (a.count == 0 || b.count == 0) return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
+    single_groups = ceil_div(a.count, kTileRows);
+  }
+  BwdArgs m;
+  m.seg = sa;
   m.a = poly_args(a, K);
   m.b = poly_args(b, K);
-  m.a_off = a_off;
-  m.b_off = b_off;
-  m.out_off = out_off;
-  m.nseg = segmented ? nseg : 1;
-  m.self_pairs = self_pairs;
+  m.single_groups = single_groups;
   m.grad = grad_iou;
-  m.out_size = out_size;
   m.pair_id = saved->pair_id;
   m.s_nx = saved->nx;
   m.s_flags = saved->xflags;
   m.capacity = saved->capacity;
-  m.count = saved->count;
+  m.tile_start = saved->tile_start;
+  m.tile_count = saved->tile_count;
+  m.tile_capacity = saved->tile_capacity;
   m.cap = a.kmax + b.kmax;
   m.ga_xy = grad_a_xy;
-  m.gb_xy = gbx;
+  m.gb_xy = grad_b_xy;
   m.ga_z = grad_a_z;
-  m.gb_z = gbz;
+  m.gb_z = grad_b_z;
   const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K;
-  const int grid = ctx.cus * 4;
-  if (K == 4) {
-    if (fixed) {
-      z3 ? launch_bwd<4, true, true>(m, grid, stream) : launch_bwd<4, true, false>(m, grid, stream);
-    } else {
-      z3 ? launch_bwd<4, false, true>(m, grid, stream) : launch_bwd<4, false, false>(m, grid, stream);
-    }
-  } else {
-    if (fixed) {
-      z3 ? launch_bwd<8, true, true>(m, grid, stream) : launch_bwd<8, true, false>(m, grid, stream);
-    } else {
-      z3 ? launch_bwd<8, false, true>(m, grid, stream) : launch_bwd<8, false, false>(m, grid, stream);
-    }
-  }
+  dispatch(K, fixed, z3, [&](auto k, auto fx, auto z) {
+    constexpr int KK = decltype(k)::value;
+    constexpr bool FX = decltype(fx)::value, ZZ = decltype(z)::value;
+    int64_t grid = (int64_t)ctx.cus * 8;
+    if (!segmented) grid = std::min(grid, ceil_div(single_groups, bwd_block<KK>() / 64));
+    hipLaunchKernelGGL((k_matrix_bwd<KK, FX, ZZ>), dim3((unsigned)grid), dim3(bwd_block<KK>()), 0,
+                       stream, m);
+  });
   return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
 }
 

@@ -29,6 +29,17 @@ def _crowd(xy, factor):
     return (xy - c + factor * c).astype(np.float32)
 
 
+def _saved_entries(saved):
+    """(pair_id, nx) of the work-list entries, tile by tile, and the table."""
+    nt = saved.tiles
+    st = saved.tile_start[:nt].cpu().numpy()
+    sc = saved.tile_count[:nt].cpu().numpy()
+    pid_all = saved.pair_id.cpu().numpy()
+    nx_all = saved.nx.cpu().numpy()
+    idx = np.concatenate([np.arange(a, a + c) for a, c in zip(st, sc)]) if nt else np.zeros(0, int)
+    return pid_all[idx], nx_all[idx], st, sc
+
+
 def _aabb_candidates(a, b, a_off=None, b_off=None, self_pairs=False):
     """Index pairs whose axis-aligned bounding boxes overlap (every other pair
     is disjoint, so its IoU is exactly 0).  Returns (ia, ib, flat index)."""
@@ -79,13 +90,24 @@ def test_matrix_small_dense_overlap(dg):
     ref, _ = oracle.iou_matrix(a, b)
     ref = ref.reshape(300, 257)
     assert np.abs(got - ref).max() <= IOU_TOL
-    # saved list = exactly the pairs with a non-empty intersection
-    cnt = int(saved.count.item())
-    pid = np.sort(saved.pair_id[:cnt].cpu().numpy())
+    # work list: every cull survivor once, with the oracle's vertex counts; the
+    # entries with nx > 0 are exactly the pairs with a non-empty intersection;
+    # tile t covers rows 8 (t // ct) .. +7 and columns 256 (t % ct) .. +255
+    pid, snx, st, sc = _saved_entries(saved)
+    cnt = int((snx > 0).sum())
+    assert len(np.unique(pid)) == len(pid) == int(saved.count.item())
     r, c = np.meshgrid(np.arange(300), np.arange(257), indexing="ij")
     _, nx_all, _ = oracle.iou_index_pairs(r.ravel(), c.ravel(), a, b, threads=8)
-    assert np.array_equal(pid, np.nonzero(nx_all > 0)[0])
-    _say(f"small matrix: {cnt} non-empty pairs of {300 * 257}")
+    assert np.array_equal(np.sort(pid[snx > 0]), np.nonzero(nx_all > 0)[0])
+    assert np.array_equal(snx, nx_all[pid])
+    ct = (257 + 255) // 256
+    assert saved.tiles == ((300 + 7) // 8) * ct
+    for t in range(saved.tiles):
+        ent = saved.pair_id[st[t]:st[t] + sc[t]].cpu().numpy()
+        rows, cols = ent // 257, ent % 257
+        assert np.all((rows >= 8 * (t // ct)) & (rows < 8 * (t // ct) + 8))
+        assert np.all((cols >= 256 * (t % ct)) & (cols < 256 * (t % ct) + 256))
+    _say(f"small matrix: {cnt} non-empty of {300 * 257}")
 
 
 def test_matrix_backward_small(dg):
@@ -117,8 +139,11 @@ def test_matrix_full_size_exact(dg):
     flat = iou.cpu().numpy().reshape(-1)
     ia, ib, fl, ref, nx, xf = _check_matrix_exact(flat, d["a_xy"], d["b_xy"])
     cnt = int(saved.count.item())
-    assert cnt == int((nx > 0).sum())
-    _say(f"c2: {len(fl)} AABB candidates, {cnt} non-empty ({cnt / flat.size:.4%})")
+    pid, snx, _, _ = _saved_entries(saved)
+    assert cnt == len(fl)          # survivors are exactly the AABB-overlapping pairs
+    assert np.array_equal(np.sort(pid[snx > 0]), np.sort(fl[nx > 0]))
+    _say(f"c2: {len(fl)} AABB candidates, {cnt} survivors, {int((snx > 0).sum())} non-empty "
+         f"({(snx > 0).sum() / flat.size:.4%})")
 
 
 def test_matrix_ragged_tiles(dg):
@@ -230,10 +255,12 @@ def test_scenes_full_size(dg):
                                                   self_pairs=True)
     cnt = int(saved.count.item())
     nonempty = (nx > 0) & (ia != ib)
-    # z-disjoint pairs are culled before the intersection: the saved list holds
-    # the pairs with a non-empty BEV intersection and overlapping z-extents
+    # z-disjoint pairs are culled before the intersection: the saved entries
+    # with nx > 0 are the pairs with a non-empty BEV intersection and
+    # overlapping z-extents
     zov = np.minimum(hi[ia], hi[ib]) > np.maximum(lo[ia], lo[ib])
-    assert cnt == int((nonempty & zov).sum()), (cnt, int((nonempty & zov).sum()))
+    pid, snx, _, _ = _saved_entries(saved)
+    assert np.array_equal(np.sort(pid[snx > 0]), np.sort(fl[nonempty & zov]))
     g = d["grad"]
     ga, _, gaz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, txy, a_z=(tlo, thi),
                                            self_pairs=True)
@@ -252,7 +279,7 @@ def test_scenes_full_size(dg):
     err = np.linalg.norm(got_all - ref_all, axis=1)
     scale = np.maximum(np.linalg.norm(ref_all, axis=1), 1e-6)
     assert np.percentile(err / scale, 99.9) <= GRAD_TOL, np.sort(err / scale)[-5:]
-    _say(f"c5: {cnt} saved pairs, grad rel err p99.9 {np.percentile(err / scale, 99.9):.2e} "
+    _say(f"c5: {cnt} survivors, {int((snx > 0).sum())} non-empty, grad rel err p99.9 {np.percentile(err / scale, 99.9):.2e} "
          f"max {np.max(err / scale):.2e}")
 
 
@@ -287,6 +314,7 @@ def test_graph_replay_matches_eager(dg):
         torch.cuda.synchronize()
         assert torch.equal(iou_g, iou_e), rep
         assert int(saved_g.count.item()) == int(saved_e.count.item())
+        assert torch.equal(saved_g.tile_count, saved_e.tile_count)
         assert torch.allclose(ga_g, ga_e, atol=1e-5, rtol=1e-5), rep
         assert torch.allclose(gaz_g, gaz_e, atol=1e-5, rtol=1e-5), rep
         del junk
@@ -299,9 +327,14 @@ def test_invalid_segments_are_rejected(dg):
     bad_a = torch.tensor([0, 5, 3, int(off[-1])], dtype=torch.int64, device="cuda")  # decreasing
     good_o = torch.tensor([0, 25, 25], dtype=torch.int64, device="cuda")
     out = torch.zeros(int(out_off[-1]), device="cuda")
+    work = dg.SavedPairs(1 << 12, 8, 64, torch.device("cuda"))
+    ws = work.struct()
+    # a work list is required
+    assert dg.lib.dgal_iou_matrix(dg.context(), pa, pa, None, None, None, 0, 0, out.data_ptr(),
+                                  out.numel(), None, 0) == dg.DGAL_EINVAL
     st = dg.lib.dgal_iou_matrix(dg.context(), pa, pa, bad_a.data_ptr(), bad_a.data_ptr(),
-                                good_o.data_ptr(), 3, 1, out.data_ptr(), out.numel(), None,
-                                torch.cuda.current_stream().cuda_stream)
+                                good_o.data_ptr(), 3, 1, out.data_ptr(), out.numel(),
+                                dg.ctypes.byref(ws), torch.cuda.current_stream().cuda_stream)
     assert st == dg.DGAL_OK          # offsets live on the device: reported by the check
     with pytest.raises(dg.DgalError) as e:
         dg.check_errors()
@@ -309,9 +342,11 @@ def test_invalid_segments_are_rejected(dg):
     dg.check_errors()                # the error word was cleared
     # immediate errors
     assert dg.lib.dgal_iou_matrix(dg.context(), pa, pa, bad_a.data_ptr(), None, None, 3, 1,
-                                  out.data_ptr(), out.numel(), None, 0) == dg.DGAL_EINVAL
+                                  out.data_ptr(), out.numel(), dg.ctypes.byref(ws),
+                                  0) == dg.DGAL_EINVAL
     assert dg.lib.dgal_iou_matrix(dg.context(), pa, pa, None, None, None, 0, 0,
-                                  out.data_ptr(), 10, None, 0) == dg.DGAL_EINVAL  # out too small
+                                  out.data_ptr(), 10, dg.ctypes.byref(ws),
+                                  0) == dg.DGAL_EINVAL  # out too small
 
 
 def test_saved_capacity_overflow_is_reported(dg):
