@@ -113,7 +113,9 @@ int dgal_iou_pairs(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* iou, uint8_
   args.cap = a.kmax + b.kmax;
   args.flags_vec = args.cap == 2 * K && aligned(xflags, (uintptr_t)(2 * K));
   args.err = ctx->v.err;
-  const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K;
+  // the fixed-size kernels also assume vector-aligned rows of coordinates and codes
+  const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
+                     args.a.vec4 && args.b.vec4 && (nx == nullptr || args.flags_vec);
   return status_of(dgal::launch_pairs_fwd(args, K, fixed, a.zlo != nullptr, nx != nullptr,
                                           static_cast<hipStream_t>(stream)));
 }
@@ -161,7 +163,8 @@ int dgal_iou_backward(dgal_ctx* ctx, int32_t mode, dgal_polys a, dgal_polys b,
     args.gb_xy = grad_b_xy;
     args.ga_z = grad_a_z;
     args.gb_z = grad_b_z;
-    const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K;
+    const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
+                       args.a.vec4 && args.b.vec4 && args.flags_vec;
     return status_of(dgal::launch_pairs_bwd(args, K, fixed, z3, static_cast<hipStream_t>(stream)));
   }
   if (mode == DGAL_MATRIX) {

@@ -16,10 +16,11 @@
 //   2. inside vertices (all signs positive) and edge crossings (both edges
 //      straddle each other's line) are appended, in ascending provenance code,
 //      to the lane's column of an LDS buffer (dynamic slot index);
-//   3. the points are ordered counter-clockwise by a pseudo-angle about their
-//      centroid, measured from the first (smallest-code) point; keys carry the
-//      slot index in their low bits, so a min/max network sorts plain words
-//      and the points are gathered back from LDS by slot;
+//   3. the points are ordered counter-clockwise by a rational monotone angle
+//      about their centroid (one reciprocal, no arctangent), measured as a
+//      fraction of a turn from the first (smallest-code) point; keys carry
+//      the slot index in their low bits, so a min/max network sorts plain
+//      words and the points are gathered back from LDS by slot;
 //   4. shoelace areas in a frame centred on P's first vertex, then IoU.
 // Backward, per pair: the intersection vertices are rebuilt from the codes
 // (no orientation test, no sort), the shoelace gradient is routed to the
@@ -35,11 +36,12 @@ constexpr uint32_t kCodeQ = 0x10u;
 constexpr uint32_t kCodeX = 0x40u;
 
 // 16 * 2^-24: a sign of an fp32 orientation value whose magnitude exceeds
-// kCertify * E * D (E: largest edge component, D: largest coordinate spread of
-// the pair) is exact.  Derivation: the two differences and two products each
-// carry relative error 2^-24, the final (possibly fused) subtraction one more,
-// so |error| <= 4 * 2^-24 * (|ex*dy| + |ey*dx|) <= 8 * 2^-24 * E * D; the
-// factor 2 on top covers the rounding of E and D themselves.
+// kCertify * E * D (E: largest edge component of the pair, D: largest
+// component of the vertex differences P_i - Q_j) is exact.  Derivation: the
+// two differences and two products each carry relative error 2^-24, the
+// final (possibly fused) subtraction one more, so |error| <= 4 * 2^-24 *
+// (|ex*dy| + |ey*dx|) <= 8 * 2^-24 * E * D; the factor 2 on top covers the
+// rounding of E, D and of the bound itself.
 constexpr float kCertify = 16.0f * 5.9604644775390625e-08f;
 
 template <int K>
@@ -59,12 +61,13 @@ __device__ __forceinline__ int poly_count(const uint8_t* nv, int64_t i, int kmax
 
 // Loads polygon i of a [count][kmax][2] array into K register slots.  Slots at
 // or past n hold a copy of vertex 0, so every later computation on them stays
-// finite (their results are masked out).
+// finite (their results are masked out).  FIXED callers guarantee kmax == K
+// and 16-byte aligned rows, so they always take the vector path.
 template <int K, bool FIXED>
 __device__ __forceinline__ void load_poly(const float* __restrict__ xy, int64_t i, int kmax,
                                           bool vec4, int n, Poly<K>& p) {
   const float* base = xy + i * (int64_t)kmax * 2;
-  if (vec4) {  // kmax == K, 16-byte aligned rows
+  if (FIXED || vec4) {  // kmax == K, 16-byte aligned rows
 #pragma unroll
     for (int k = 0; k < K; k += 2) {
       float4 v = *reinterpret_cast<const float4*>(base + 2 * k);
@@ -121,15 +124,6 @@ __device__ __forceinline__ double orient64(float ax, float ay, float bx, float b
   return ux * vy - uy * vx;
 }
 
-// Pseudo-angle of (dx, dy) in [0, 4): monotone in the polar angle in [0, 2pi)
-// (one reciprocal instead of an arctangent).
-__device__ __forceinline__ float pseudo_angle(float dx, float dy) {
-  float ax = fabsf(dx), ay = fabsf(dy);
-  float den = ax + ay;
-  float r = den > 0.f ? dy * fast_rcp(den) : 0.f;
-  return dx >= 0.f ? (dy >= 0.f ? r : 4.f + r) : 2.f - r;
-}
-
 // Sorting networks (Batcher odd-even merge) on positions 1..7 and 1..15 of
 // the key array; position 0 always holds the smallest-code vertex.
 #define DGAL_NET7(X)                                                                       \
@@ -177,65 +171,68 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
                                              float2* __restrict__ s_pt,
                                              uint8_t* __restrict__ s_cd, PairResult<K>& res) {
   constexpr int CAP = 2 * K;
+  constexpr int NW = (K * K + 31) / 32;  // 32-bit words of a K x K sign table
+  constexpr uint32_t KM = (1u << K) - 1u;
   if (FIXED) {
     n1 = K;
     n2 = K;
   }
-  // ---- edges and the certification scale -------------------------------
+  // ---- edges -------------------------------------------------------------
+  // padded slots repeat vertex 0, so their edges are zero or real edges
   float epx[K], epy[K], eqx[K], eqy[K];
+  float E = 0.f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     epx[k] = next_of<K, FIXED>(P.x, k, n1) - P.x[k];
     epy[k] = next_of<K, FIXED>(P.y, k, n1) - P.y[k];
     eqx[k] = next_of<K, FIXED>(Q.x, k, n2) - Q.x[k];
     eqy[k] = next_of<K, FIXED>(Q.y, k, n2) - Q.y[k];
-  }
-  // padded slots repeat vertex 0, so their edges are zero or real edges and
-  // every min/max below may include them without widening the bound
-  float E = 0.f;
-  float xmin = P.x[0], xmax = P.x[0], ymin = P.y[0], ymax = P.y[0];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
     E = fmaxf(E, fmaxf(fmaxf(fabsf(epx[k]), fabsf(epy[k])), fmaxf(fabsf(eqx[k]), fabsf(eqy[k]))));
-    xmin = fminf(xmin, fminf(P.x[k], Q.x[k]));
-    xmax = fmaxf(xmax, fmaxf(P.x[k], Q.x[k]));
-    ymin = fminf(ymin, fminf(P.y[k], Q.y[k]));
-    ymax = fmaxf(ymax, fmaxf(P.y[k], Q.y[k]));
   }
-  const float eb = kCertify * E * fmaxf(xmax - xmin, ymax - ymin);
 
   // ---- 1. orientation table --------------------------------------------
-  // sp bit i*K+j: P_i strictly left of Q edge j; sq bit j*K+i: Q_j strictly
-  // left of P edge i.  oP[i][j] = orient(Q_j, Q_j+1, P_i).
-  using Mask = typename std::conditional<(K * K > 32), uint64_t, uint32_t>::type;
-  Mask sp = 0, sq = 0;
+  // oP[i][j] = orient(Q_j, Q_j+1, P_i); oq(i, j) = orient(P_i, P_i+1, Q_j).
+  // Their sign bits are shifted, highest table index first, into words whose
+  // bit i*K+j is set when the value is negative (or -0); D is the largest
+  // component of the vertex differences, omin the smallest magnitude.
   float oP[K][K];
-  bool certain = true;
+  uint32_t negp[NW], negq[NW];
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
+  for (int w = 0; w < NW; ++w) {
+    negp[w] = 0u;
+    negq[w] = 0u;
+  }
+  float D = 0.f, omin = __builtin_inff();
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+  for (int i = K - 1; i >= 0; --i) {
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j) {
       const float dx = P.x[i] - Q.x[j], dy = P.y[i] - Q.y[j];
       const float op = eqx[j] * dy - eqy[j] * dx;
       const float oq = epy[i] * dx - epx[i] * dy;
       oP[i][j] = op;
-      const bool valid = FIXED || (i < n1 && j < n2);
-      certain &= !valid || (fabsf(op) > eb && fabsf(oq) > eb);
-      sp |= (Mask)(op > 0.f) << (i * K + j);
-      sq |= (Mask)(oq > 0.f) << (j * K + i);
+      const int w = (i * K + j) >> 5;
+      negp[w] = __builtin_amdgcn_alignbit(negp[w], __float_as_uint(op), 31);
+      negq[w] = __builtin_amdgcn_alignbit(negq[w], __float_as_uint(oq), 31);
+      D = fmaxf(D, fmaxf(fabsf(dx), fabsf(dy)));
+      const float mo = fminf(fabsf(op), fabsf(oq));
+      omin = fminf(omin, (FIXED || (i < n1 && j < n2)) ? mo : __builtin_inff());
     }
   }
-  if (!certain) {
+  if (!(omin > kCertify * E * D)) {
     // exact signs in fp64; exact zeros take the sign of Q moved by (eps, eps^2)
-    sp = 0;
-    sq = 0;
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
+    for (int w = 0; w < NW; ++w) {
+      negp[w] = 0u;
+      negq[w] = 0u;
+    }
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
       const float pnx = next_of<K, FIXED>(P.x, i, n1), pny = next_of<K, FIXED>(P.y, i, n1);
       // orient(P_i, P_i1, Q_j + d) = o - e.y*eps + e.x*eps^2
       const bool tie_p = (P.y[i] != pny) ? (P.y[i] > pny) : (pnx > P.x[i]);
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
+      for (int j = K - 1; j >= 0; --j) {
         const float qnx = next_of<K, FIXED>(Q.x, j, n2), qny = next_of<K, FIXED>(Q.y, j, n2);
         // orient(Q_j + d, Q_j1 + d, P_i) = o + f.y*eps - f.x*eps^2
         const bool tie_q = (qny != Q.y[j]) ? (qny > Q.y[j]) : (Q.x[j] > qnx);
@@ -244,63 +241,73 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
         const bool bp = op > 0.0 || (op == 0.0 && tie_q);
         const bool bq = oq > 0.0 || (oq == 0.0 && tie_p);
         oP[i][j] = (float)op;
-        sp |= (Mask)bp << (i * K + j);
-        sq |= (Mask)bq << (j * K + i);
+        const int w = (i * K + j) >> 5;
+        negp[w] = (negp[w] << 1) | (uint32_t)!bp;
+        negq[w] = (negq[w] << 1) | (uint32_t)!bq;
       }
     }
   }
 
   // ---- 2. inside vertices and crossings, in ascending code -------------
-  const uint32_t row_mask = FIXED ? ((1u << K) - 1u) : ((1u << n2) - 1u);
-  const uint32_t col_mask = FIXED ? ((1u << K) - 1u) : ((1u << n1) - 1u);
-  uint32_t rowd[K], cold[K];  // straddle bits per edge
+  // row i of sp: bit j set when P_i is strictly left of Q edge j; row i of
+  // sq: bit j set when Q_j is strictly left of P edge i.
+  const uint32_t jmask = FIXED ? KM : ((1u << n2) - 1u);
+  uint32_t spr[K], sqr[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    const uint32_t r = (uint32_t)(sp >> (i * K)) & ((1u << K) - 1u);
-    const uint32_t rn = (uint32_t)(sp >> (next_idx<K, FIXED>(i, n1) * K)) & ((1u << K) - 1u);
-    rowd[i] = r ^ rn;
-    const uint32_t c = (uint32_t)(sq >> (i * K)) & ((1u << K) - 1u);
-    const uint32_t cn = (uint32_t)(sq >> (next_idx<K, FIXED>(i, n2) * K)) & ((1u << K) - 1u);
-    cold[i] = c ^ cn;
+    const int w = (i * K) >> 5, sh = (i * K) & 31;
+    spr[i] = ~(negp[w] >> sh) & KM;
+    sqr[i] = ~(negq[w] >> sh) & KM;
+    if (!FIXED && i >= n1) sqr[i] = KM;  // padded P edges constrain nothing
   }
-  const float ox = P.x[0], oy = P.y[0];  // local frame origin
+  uint32_t qin = KM;  // bit j: Q_j left of every P edge
+#pragma unroll
+  for (int i = 0; i < K; ++i) qin &= sqr[i];
+
+  float lpx[K], lpy[K];  // P in the frame centred on P_0
+  lpx[0] = 0.f;
+  lpy[0] = 0.f;
+#pragma unroll
+  for (int k = 1; k < K; ++k) {
+    lpx[k] = P.x[k] - P.x[0];
+    lpy[k] = P.y[k] - P.y[0];
+  }
   int cnt = 0;
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const uint32_t r = (uint32_t)(sp >> (i * K)) & row_mask;
-    const bool in = (FIXED || i < n1) && r == row_mask;
-    if (in && cnt < CAP) {
-      s_pt[cnt * BLOCK] = make_float2(P.x[i] - ox, P.y[i] - oy);
-      s_cd[cnt * BLOCK] = (uint8_t)i;
+  // Appends a point; only invalid input can pass the capacity, and its
+  // extra points then overwrite the last slot (the overflow is reported).
+  auto put = [&](bool in, float px, float py, uint32_t code) {
+    const int s = min(cnt, CAP - 1);
+    if (in) {
+      s_pt[s * BLOCK] = make_float2(px, py);
+      s_cd[s * BLOCK] = (uint8_t)code;
     }
     cnt += in;
-  }
+  };
 #pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const uint32_t c = (uint32_t)(sq >> (j * K)) & col_mask;
-    const bool in = (FIXED || j < n2) && c == col_mask;
-    if (in && cnt < CAP) {
-      s_pt[cnt * BLOCK] = make_float2(Q.x[j] - ox, Q.y[j] - oy);
-      s_cd[cnt * BLOCK] = (uint8_t)(kCodeQ | j);
-    }
-    cnt += in;
-  }
+  for (int i = 0; i < K; ++i)
+    put((FIXED || i < n1) && (spr[i] & jmask) == jmask, lpx[i], lpy[i], (uint32_t)i);
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    put((FIXED || j < n2) && ((qin >> j) & 1u), Q.x[j] - P.x[0], Q.y[j] - P.y[0], kCodeQ | j);
 #pragma unroll
   for (int i = 0; i < K; ++i) {
+    // P edge i straddles the line of Q edge j (rows i and i+1 of sp differ)
+    // and Q edge j straddles the line of P edge i (bits j and j+1 of row i of
+    // sq differ)
+    const int inx = next_idx<K, FIXED>(i, n1);
+    const uint32_t r = sqr[i];
+    const uint32_t rn = FIXED ? ((r >> 1) | (r << (K - 1))) : ((r >> 1) | ((r & 1u) << (n2 - 1)));
+    const uint32_t xm = (spr[i] ^ spr[inx]) & (r ^ rn) & jmask;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      const bool x = (FIXED || (i < n1 && j < n2)) && ((rowd[i] >> j) & (cold[j] >> i) & 1u);
-      if (x) {
-        // P edge i meets Q edge j at P_i + t e_i, t = o_i / (o_i - o_i1)
+      if ((FIXED || i < n1) && ((xm >> j) & 1u)) {
+        // P edge i meets Q edge j at P_i + t e_i, t = o_i / (o_i - o_i1); the
+        // two values have opposite signs (or one is an exact zero that the
+        // tie rule signed), so the difference is never zero for coordinates
+        // whose products stay normal floats
         const float o0 = oP[i][j];
-        const float o1 = (FIXED || i + 1 < n1) ? oP[(i + 1) % K][j] : oP[0][j];
-        const float den = o0 - o1;
-        const float t = den != 0.f ? o0 * fast_rcp(den) : 0.f;
-        if (cnt < CAP) {
-          s_pt[cnt * BLOCK] = make_float2(fmaf(t, epx[i], P.x[i] - ox), fmaf(t, epy[i], P.y[i] - oy));
-          s_cd[cnt * BLOCK] = (uint8_t)(kCodeX | (i << 3) | j);
-        }
-        ++cnt;
+        const float t = o0 * fast_rcp(o0 - oP[inx][j]);
+        put(true, fmaf(t, epx[i], lpx[i]), fmaf(t, epy[i], lpy[i]), kCodeX | (i << 3) | j);
       }
     }
   }
@@ -313,25 +320,31 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
   float cx = 0.f, cy = 0.f;
 #pragma unroll
   for (int k = 0; k < CAP; ++k) {
-    float2 v = make_float2(0.f, 0.f);
-    if (k < m) v = s_pt[k * BLOCK];
-    x[k] = v.x;
-    y[k] = v.y;
-    cx += v.x;
-    cy += v.y;
+    const float2 v = s_pt[k * BLOCK];
+    x[k] = k < m ? v.x : 0.f;
+    y[k] = k < m ? v.y : 0.f;
+    cx += x[k];
+    cy += y[k];
   }
   const float inv_m = m > 0 ? fast_rcp((float)m) : 0.f;
   cx *= inv_m;
   cy *= inv_m;
+  // Turn of (dx, dy) about the centroid, in [0, 1) of a full turn measured
+  // from the first (smallest-code) point: 2 - sign(dy) (1 + dx / (|dx|+|dy|))
+  // is monotone in the polar angle over [0, 4); the scaled difference to the
+  // first point's value wraps with a fractional part.
+  auto quarter_turns = [](float dx, float dy) {
+    const float q = fmaf(dx, fast_rcp(fmaxf(fabsf(dx) + fabsf(dy), 1.17549435e-38f)), 1.f);
+    return copysignf(q, dy);  // 2 - this is the turn in quarters
+  };
+  const float c0 = -0.25f * quarter_turns(x[0] - cx, y[0] - cy);
   uint32_t key[CAP];
-  const float a0 = pseudo_angle(x[0] - cx, y[0] - cy);
   key[0] = 0u;
 #pragma unroll
   for (int k = 1; k < CAP; ++k) {
-    float r = pseudo_angle(x[k] - cx, y[k] - cy) - a0;
-    r = r < 0.f ? r + 4.f : r;
-    // r >= 0 or -0: clearing the sign bit makes the word order the float order
-    const uint32_t kb = k < m ? (__float_as_uint(r) & 0x7fffffffu) : 0x7f000000u;
+    // fract(((2 - s_k) - (2 - s_0)) / 4) = fract(s_0/4 - s_k/4)
+    const float r = __builtin_amdgcn_fractf(fmaf(-0.25f, quarter_turns(x[k] - cx, y[k] - cy), -c0));
+    const uint32_t kb = k < m ? (__float_as_uint(r) & 0x7fffffffu) : 0x7f800000u;
     key[k] = (kb & ~(uint32_t)(CAP - 1)) | (uint32_t)k;
   }
   sort_keys<CAP>(key);
@@ -363,15 +376,13 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
 
   // polygon areas in the same frame (P_0 at the origin)
   float s1 = 0.f, s2 = 0.f;
-  const float qx0 = Q.x[0] - ox, qy0 = Q.y[0] - oy;
+  const float qx0 = Q.x[0] - P.x[0], qy0 = Q.y[0] - P.y[0];
 #pragma unroll
   for (int k = 1; k + 1 < K; ++k) {
-    if (FIXED || k + 1 < n1) {
-      s1 += (P.x[k] - ox) * (P.y[k + 1] - oy) - (P.y[k] - oy) * (P.x[k + 1] - ox);
-    }
+    if (FIXED || k + 1 < n1) s1 += lpx[k] * lpy[k + 1] - lpy[k] * lpx[k + 1];
     if (FIXED || k + 1 < n2) {
-      const float ux = Q.x[k] - ox - qx0, uy = Q.y[k] - oy - qy0;
-      const float vx = Q.x[k + 1] - ox - qx0, vy = Q.y[k + 1] - oy - qy0;
+      const float ux = Q.x[k] - P.x[0] - qx0, uy = Q.y[k] - P.y[0] - qy0;
+      const float vx = Q.x[k + 1] - P.x[0] - qx0, vy = Q.y[k + 1] - P.y[0] - qy0;
       s2 += ux * vy - uy * vx;
     }
   }
@@ -380,10 +391,11 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
 }
 
 // IoU from the areas (2D), with the conventions: empty intersection or a
-// non-positive union gives 0.
+// non-positive union gives 0.  The quotient uses the hardware reciprocal
+// (1 ulp), well inside the IoU tolerance.
 __device__ __forceinline__ float iou_2d(float inter, float a1, float a2, int m) {
   const float u = a1 + a2 - inter;
-  return (m > 0 && u > 0.f) ? inter / u : 0.f;
+  return (m > 0 && u > 0.f) ? inter * fast_rcp(u) : 0.f;
 }
 
 // 3D IoU: BEV intersection times z-overlap over the union volume.
@@ -392,22 +404,95 @@ __device__ __forceinline__ float iou_3d(float inter, float a1, float a2, int m, 
   const float hz = fmaxf(0.f, fminf(hi1, hi2) - fmaxf(lo1, lo2));
   const float v = inter * hz;
   const float u = a1 * (hi1 - lo1) + a2 * (hi2 - lo2) - v;
-  return (m > 0 && u > 0.f) ? v / u : 0.f;
+  return (m > 0 && u > 0.f) ? v * fast_rcp(u) : 0.f;
 }
 
 // ---------------------------------------------------------------------------
 // Backward of one pair from its saved count and codes.
 //   s_v: lane column of a [2K][BLOCK] float2 LDS buffer (local vertices)
 //   s_g: lane column of a [2K][BLOCK] float2 LDS buffer (gradient accumulators)
+//   s_tab: the block's code table (fill_code_table)
 // Writes gP[k], gQ[k] for k < K (zero for padded slots) and, in 3D, the
 // derivatives with respect to (zlo, zhi) of each polygon.
+//
+// Every intersection vertex is handled by one code path: its code names the
+// LDS slots A, B (an edge) and C, D (the other polygon's edge) with
+// X = A + t (B - A), t = cross(C - A, D - C) / cross(B - A, D - C) for a
+// crossing; a polygon vertex names its own slot four times, so that every
+// difference and t vanish and X = A.
+template <int K, bool FIXED>
+__device__ __forceinline__ void code_slots(uint32_t c, int n1, int n2, int& ia, int& ib, int& ic,
+                                           int& id) {
+  const bool cross = c >= kCodeX;
+  const int i = (int)((c >> 3) & (K - 1)), j = (int)(c & (K - 1));
+  const int own = j + ((c & kCodeQ) ? K : 0);  // vertex slot of a P or Q vertex code
+  const int in = FIXED ? ((i + 1) & (K - 1)) : (i + 1 < n1 ? i + 1 : 0);
+  const int jn = FIXED ? ((j + 1) & (K - 1)) : (j + 1 < n2 ? j + 1 : 0);
+  ia = cross ? i : own;
+  ib = cross ? in : own;
+  ic = cross ? K + j : own;
+  id = cross ? K + jn : own;
+}
+
+// Byte offsets, within a lane's column of a [2K][BLOCK] float2 LDS buffer, of
+// the slots A, B, C, D that code c names, packed as 16-bit halves:
+// x = A | B << 16, y = C | D << 16.  A block fills a 256-entry table of these
+// once, so the backward decodes a code with one LDS read.  On fixed-size
+// polygons the edge ends wrap at K; otherwise a crossing's B and D are stored
+// unwrapped (slot i + 1 and K + j + 1) and wrapped per lane.
+template <int K, bool FIXED, int BLOCK>
+__device__ __forceinline__ uint2 code_offsets(uint32_t c) {
+  int ia, ib, ic, id;
+  if (FIXED) {
+    code_slots<K, true>(c, K, K, ia, ib, ic, id);
+  } else {
+    code_slots<K, false>(c, K + 1, K + 1, ia, ib, ic, id);  // no wrap below K + 1
+  }
+  constexpr uint32_t S = BLOCK * sizeof(float2);
+  static_assert(2 * K * S < 65536u, "offsets fit 16 bits");
+  return make_uint2((uint32_t)ia * S | ((uint32_t)ib * S) << 16,
+                    (uint32_t)ic * S | ((uint32_t)id * S) << 16);
+}
+
+template <int K, bool FIXED, int BLOCK>
+__device__ __forceinline__ void fill_code_table(uint2* s_tab) {
+  for (int c = threadIdx.x; c < 256; c += blockDim.x)
+    s_tab[c] = code_offsets<K, FIXED, BLOCK>((uint32_t)c);
+}
+
+// LDS byte offsets of the four slots of code c.  n1S = n1 * S and
+// nqS = (K + n2) * S, S the slot stride in bytes, locate the wrap of a
+// crossing's edge ends on polygons with fewer than K vertices; offsets are
+// clamped to the lane's column, so that codes which do not fit the pair
+// (invalid saved state) still address this lane's own slots.
+template <int K, bool FIXED, int BLOCK>
+__device__ __forceinline__ void slot_offsets(uint32_t c, uint32_t n1S, uint32_t nqS,
+                                             const uint2* __restrict__ s_tab, uint32_t& oa,
+                                             uint32_t& ob, uint32_t& oc, uint32_t& od) {
+  const uint2 o = s_tab[c];
+  oa = o.x & 0xffffu;
+  ob = o.x >> 16;
+  oc = o.y & 0xffffu;
+  od = o.y >> 16;
+  if constexpr (!FIXED) {
+    constexpr uint32_t S = BLOCK * sizeof(float2);
+    const bool cross = c >= kCodeX;
+    ob = (cross && ob == n1S) ? 0u : min(ob, (2 * K - 1) * S);
+    od = (cross && od == nqS) ? K * S : min(od, (2 * K - 1) * S);
+  }
+}
+
+__device__ __forceinline__ float2& at(float2* col, uint32_t off) {
+  return *reinterpret_cast<float2*>(reinterpret_cast<char*>(col) + off);
+}
+
 template <int K, bool FIXED, bool Z3, int BLOCK>
 __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Poly<K>& Q, int n2,
                                               float g, int nx, const uint32_t (&codes)[K / 2],
                                               float lo1, float hi1, float lo2, float hi2,
                                               float2* __restrict__ s_v, float2* __restrict__ s_g,
-                                              float2 (&gP)[K], float2 (&gQ)[K], float2& gz1,
-                                              float2& gz2) {
+                                              const uint2* __restrict__ s_tab, float2 (&gP)[K],
+                                              float2 (&gQ)[K], float2& gz1, float2& gz2) {
   constexpr int CAP = 2 * K;
   if (FIXED) {
     n1 = K;
@@ -434,40 +519,30 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   }
   const float a1 = 0.5f * s1, a2 = 0.5f * s2;
 
-  // rebuild the intersection from the codes
+  // rebuild the intersection from the codes (padding codes name valid slots;
+  // their vertices are never used)
   const int m = min(nx, CAP);
-  float X[CAP], Y[CAP];
-  uint32_t cd[CAP];
+  constexpr uint32_t S = BLOCK * sizeof(float2);
+  const uint32_t n1S = (uint32_t)n1 * S, nqS = (uint32_t)(K + n2) * S;
+  float X[CAP], Y[CAP], T[CAP], IDN[CAP];
 #pragma unroll
   for (int r = 0; r < CAP; ++r) {
-    cd[r] = (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu;
-    float vx = 0.f, vy = 0.f;
-    if (r < m) {
-      const uint32_t c = cd[r];
-      if (c < kCodeQ) {
-        const float2 v = s_v[(c & (K - 1)) * BLOCK];
-        vx = v.x;
-        vy = v.y;
-      } else if (c < kCodeX) {
-        const float2 v = s_v[(K + (c & (K - 1))) * BLOCK];
-        vx = v.x;
-        vy = v.y;
-      } else {
-        const int i = (c >> 3) & (K - 1), j = c & (K - 1);
-        const int i1 = (i + 1 < n1) ? i + 1 : 0, j1 = (j + 1 < n2) ? j + 1 : 0;
-        const float2 a = s_v[i * BLOCK], b = s_v[i1 * BLOCK];
-        const float2 cc = s_v[(K + j) * BLOCK], d = s_v[(K + j1) * BLOCK];
-        const float ex = b.x - a.x, ey = b.y - a.y, fx = d.x - cc.x, fy = d.y - cc.y;
-        const float wx = cc.x - a.x, wy = cc.y - a.y;
-        const float den = ex * fy - ey * fx;
-        const float t = den != 0.f ? (wx * fy - wy * fx) / den : 0.f;
-        vx = fmaf(t, ex, a.x);
-        vy = fmaf(t, ey, a.y);
-      }
-    }
-    X[r] = vx;
-    Y[r] = vy;
+    const uint32_t c = (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu;
+    uint32_t oa, ob, oc, od;
+    slot_offsets<K, FIXED, BLOCK>(c, n1S, nqS, s_tab, oa, ob, oc, od);
+    const float2 a = at(s_v, oa), b = at(s_v, ob), cc = at(s_v, oc), d = at(s_v, od);
+    const float ex = b.x - a.x, ey = b.y - a.y, fx = d.x - cc.x, fy = d.y - cc.y;
+    const float wx = cc.x - a.x, wy = cc.y - a.y;
+    const float den = ex * fy - ey * fx;
+    IDN[r] = den != 0.f ? fast_rcp(den) : 0.f;
+    T[r] = (wx * fy - wy * fx) * IDN[r];
+    X[r] = fmaf(T[r], ex, a.x);
+    Y[r] = fmaf(T[r], ey, a.y);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  // the routing pass decodes and reads the slots again rather than keeping
+  // every slot's offsets and edge vectors live across the passes
+  asm volatile("" ::: "memory");
   float acc = 0.f;
 #pragma unroll
   for (int r = 1; r + 1 < CAP; ++r) {
@@ -482,9 +557,10 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   if (!Z3) {
     const float u = a1 + a2 - inter;
     if (m >= 3 && u > 0.f) {
-      const float iu2 = 1.f / (u * u);
-      gI = g * (a1 + a2) * iu2;
-      gA1 = -g * inter * iu2;
+      const float iu = fast_rcp(u);
+      const float giu2 = g * iu * iu;
+      gI = giu2 * (a1 + a2);
+      gA1 = -giu2 * inter;
       gA2 = gA1;
     }
   } else {
@@ -492,9 +568,10 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
     const float hz = fminf(hi1, hi2) - fmaxf(lo1, lo2);
     const float v = inter * hz, v1 = a1 * h1, v2 = a2 * h2, u = v1 + v2 - v;
     if (m >= 3 && hz > 0.f && u > 0.f) {
-      const float iu2 = 1.f / (u * u);
-      const float gV = g * (v1 + v2) * iu2;
-      const float gV1 = -g * v * iu2;
+      const float iu = fast_rcp(u);
+      const float giu2 = g * iu * iu;
+      const float gV = giu2 * (v1 + v2);
+      const float gV1 = -giu2 * v;
       gI = gV * hz;
       const float ghz = gV * inter;
       gA1 = gV1 * h1;
@@ -508,22 +585,27 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   }
 
   // accumulators start with the polygon-area terms dA/dv = 0.5 (y+ - y-, x- - x+)
+  const float h1a = 0.5f * gA1, h2a = 0.5f * gA2;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
+    float2 pn, pp, qn, qp;
+    if (FIXED) {
+      pn = make_float2(lpx[(k + 1) % K], lpy[(k + 1) % K]);
+      pp = make_float2(lpx[(k + K - 1) % K], lpy[(k + K - 1) % K]);
+      qn = make_float2(lqx[(k + 1) % K], lqy[(k + 1) % K]);
+      qp = make_float2(lqx[(k + K - 1) % K], lqy[(k + K - 1) % K]);
+    } else {
+      const int kn1 = next_idx<K, FIXED>(k, n1), kp1 = k == 0 ? n1 - 1 : k - 1;
+      const int kn2 = next_idx<K, FIXED>(k, n2), kp2 = k == 0 ? n2 - 1 : k - 1;
+      pn = s_v[kn1 * BLOCK];
+      pp = s_v[kp1 * BLOCK];
+      qn = s_v[(K + kn2) * BLOCK];
+      qp = s_v[(K + kp2) * BLOCK];
+    }
     const bool v1 = FIXED || k < n1, v2 = FIXED || k < n2;
-    const int kn1 = next_idx<K, FIXED>(k, n1), kp1 = FIXED ? (k + K - 1) % K : (k == 0 ? n1 - 1 : k - 1);
-    const int kn2 = next_idx<K, FIXED>(k, n2), kp2 = FIXED ? (k + K - 1) % K : (k == 0 ? n2 - 1 : k - 1);
-    float2 gp = make_float2(0.f, 0.f), gq = make_float2(0.f, 0.f);
-    if (v1) {
-      const float2 pn = s_v[kn1 * BLOCK], pp = s_v[kp1 * BLOCK];
-      gp = make_float2(0.5f * gA1 * (pn.y - pp.y), 0.5f * gA1 * (pp.x - pn.x));
-    }
-    if (v2) {
-      const float2 qn = s_v[(K + kn2) * BLOCK], qp = s_v[(K + kp2) * BLOCK];
-      gq = make_float2(0.5f * gA2 * (qn.y - qp.y), 0.5f * gA2 * (qp.x - qn.x));
-    }
-    s_g[k * BLOCK] = gp;
-    s_g[(K + k) * BLOCK] = gq;
+    s_g[k * BLOCK] = v1 ? make_float2(h1a * (pn.y - pp.y), h1a * (pp.x - pn.x)) : make_float2(0.f, 0.f);
+    s_g[(K + k) * BLOCK] =
+        v2 ? make_float2(h2a * (qn.y - qp.y), h2a * (qp.x - qn.x)) : make_float2(0.f, 0.f);
   }
 
   // shoelace gradient of the intersection, edge by edge: the term
@@ -552,53 +634,44 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   }
   const float hI = 0.5f * gI;
 
-  // route every vertex's gradient to the polygon vertices it came from
+  // route every vertex's gradient to the slots it came from: with
+  // e = B - A, f = D - C, w = C - A and dL/dX = G,
+  //   dL/dt = G.e, dL/dcross(w,f) = dL/dt / den, dL/dden = -dL/dt t / den,
+  //   A gets G - dL/de - dL/dw, B gets dL/de, C gets dL/dw - dL/df, D gets dL/df.
+  // A polygon vertex adds G to A and zeros to its three aliases, so the
+  // aliases are written before A.
 #pragma unroll
   for (int r = 0; r < CAP; ++r) {
-    if (r < m && gI != 0.f) {
+    if (r < m) {
       const float Gx = hI * GX[r], Gy = hI * GY[r];
-      const uint32_t c = cd[r];
-      if (c < kCodeX) {
-        const int slot = (c < kCodeQ) ? (int)(c & (K - 1)) : K + (int)(c & (K - 1));
-        float2 t = s_g[slot * BLOCK];
-        t.x += Gx;
-        t.y += Gy;
-        s_g[slot * BLOCK] = t;
-      } else {
-        // X = a + t e with t = cross(w, f) / cross(e, f), e = b - a, f = d - c, w = c - a
-        const int i = (c >> 3) & (K - 1), j = c & (K - 1);
-        const int i1 = (i + 1 < n1) ? i + 1 : 0, j1 = (j + 1 < n2) ? j + 1 : 0;
-        const float2 a = s_v[i * BLOCK], b = s_v[i1 * BLOCK];
-        const float2 cc = s_v[(K + j) * BLOCK], d = s_v[(K + j1) * BLOCK];
-        const float ex = b.x - a.x, ey = b.y - a.y, fx = d.x - cc.x, fy = d.y - cc.y;
-        const float wx = cc.x - a.x, wy = cc.y - a.y;
-        const float den = ex * fy - ey * fx;
-        const float id = den != 0.f ? 1.f / den : 0.f;
-        const float t = (wx * fy - wy * fx) * id;
-        const float gt = Gx * ex + Gy * ey;
-        const float gN = gt * id;       // d/d cross(w, f)
-        const float gD = -gt * t * id;  // d/d cross(e, f)
-        const float gex = t * Gx + gD * fy, gey = t * Gy - gD * fx;
-        const float gfx = -gN * wy - gD * ey, gfy = gN * wx + gD * ex;
-        const float gwx = gN * fy, gwy = -gN * fx;
-        float2 ta = s_g[i * BLOCK];
-        ta.x += Gx - gex - gwx;
-        ta.y += Gy - gey - gwy;
-        s_g[i * BLOCK] = ta;
-        float2 tb = s_g[i1 * BLOCK];
-        tb.x += gex;
-        tb.y += gey;
-        s_g[i1 * BLOCK] = tb;
-        float2 tc = s_g[(K + j) * BLOCK];
-        tc.x += gwx - gfx;
-        tc.y += gwy - gfy;
-        s_g[(K + j) * BLOCK] = tc;
-        float2 td = s_g[(K + j1) * BLOCK];
-        td.x += gfx;
-        td.y += gfy;
-        s_g[(K + j1) * BLOCK] = td;
-      }
+      const uint32_t c = (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu;
+      uint32_t oa, ob, oc, od;
+      slot_offsets<K, FIXED, BLOCK>(c, n1S, nqS, s_tab, oa, ob, oc, od);
+      const float2 a = at(s_v, oa), b = at(s_v, ob), cc = at(s_v, oc), d = at(s_v, od);
+      float2 ta = at(s_g, oa), tb = at(s_g, ob), tc = at(s_g, oc), td = at(s_g, od);
+      const float ex = b.x - a.x, ey = b.y - a.y, fx = d.x - cc.x, fy = d.y - cc.y;
+      const float wx = cc.x - a.x, wy = cc.y - a.y;
+      const float idn = IDN[r], t = T[r];
+      const float gt = Gx * ex + Gy * ey;
+      const float gN = gt * idn;   // d/d cross(w, f)
+      const float gD = -gN * t;    // d/d cross(e, f)
+      const float gex = t * Gx + gD * fy, gey = t * Gy - gD * fx;
+      const float gfx = -gN * wy - gD * ey, gfy = gN * wx + gD * ex;
+      const float gwx = gN * fy, gwy = -gN * fx;
+      tb.x += gex;
+      tb.y += gey;
+      tc.x += gwx - gfx;
+      tc.y += gwy - gfy;
+      td.x += gfx;
+      td.y += gfy;
+      ta.x += Gx - gex - gwx;
+      ta.y += Gy - gey - gwy;
+      at(s_g, ob) = tb;
+      at(s_g, oc) = tc;
+      at(s_g, od) = td;
+      at(s_g, oa) = ta;
     }
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {

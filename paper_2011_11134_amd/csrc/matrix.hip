@@ -4,15 +4,17 @@
 //
 // The forward is split by register pressure into lean cull kernels and one
 // dense exact kernel, with no shared counter anywhere:
-//   k_matrix_count -- one wavefront per tile of kTileRows rows x kTileCols
-//     columns of one segment.  The rows' axis-aligned bounds (and z-extents)
-//     sit in scalar registers; each lane bounds its column boxes 64 at a time,
-//     tests them against the rows, writes the 0 (or the self diagonal's 1) of
-//     every disjoint pair straight to the output row segments (coalesced) and
-//     counts the survivors into the tile table.
-//   k_tile_scan    -- one workgroup: exclusive prefix of the tile counts, so
-//     the work list is laid out tile by tile, deterministically.
-//   k_matrix_fill  -- the same cull again; survivors go to their tile's range.
+//   k_matrix_cull<FILL = false> -- one wavefront per tile of kTileRows rows x
+//     kTileCols columns of one segment.  The rows' axis-aligned bounds (and
+//     z-extents) sit in scalar registers; each lane bounds its column boxes 64
+//     at a time, tests them against the rows, writes every pair's initial
+//     value (0, or the self diagonal's 1) straight to the output row segments
+//     (coalesced) and counts the survivors into the tile table.
+//   k_scan_totals, k_scan_apply -- exclusive prefix of the tile counts in two
+//     parallel passes, so the work list is laid out tile by tile,
+//     deterministically.
+//   k_matrix_cull<FILL = true> -- the same cull again; survivors go to their
+//     tile's range.
 //   k_matrix_exact -- one lane per survivor with every lane busy: the exact
 //     pair forward, the IoU written to its place in the output, nx / xflags
 //     kept in the work list for the backward.
@@ -196,14 +198,18 @@ struct CullArgs {
   int* err;
 };
 
-// FILL == false: write the culled pairs' values and count the survivors of
-// every tile; FILL == true: write the survivors' output indices into their
-// tile's range of the work list (the same decisions, in the same order).
+// FILL == false: write every pair of the tile (0 for the culled ones, which
+// stays, or 1 on the self diagonal; the exact kernel later overwrites the
+// survivors) and count the survivors of every tile; FILL == true: write the
+// survivors' output indices into their tile's range of the work list (the
+// same decisions, in the same order).  The tile walk is wave-uniform, so its
+// indices, the segment and the rows' bounds live in scalar registers and
+// every output row segment is addressed from a scalar base.
 template <int K, bool FIXED, bool Z3, bool FILL>
 __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
   constexpr int WAVES = kCullBlock / 64;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool segmented = m.seg.a_off != nullptr;
   const int64_t total = segmented ? m.seg.tile_prefix[m.seg.nseg] : m.single_tiles;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -214,7 +220,15 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
     const Segment g = load_segment(m.seg, s);
     if (!g.ok) continue;  // unreachable: rejected segments own no tiles
     const int64_t nct = col_tiles_of(g);
-    const int64_t tr = lu / nct, tc = lu - tr * nct;
+    int64_t tr, tc;
+    if (lu < (int64_t)0xffffffff) {
+      const uint32_t q = (uint32_t)lu / (uint32_t)nct;
+      tr = q;
+      tc = lu - (int64_t)q * nct;
+    } else {
+      tr = lu / nct;
+      tc = lu - tr * nct;
+    }
     const int64_t r0 = tr * kTileRows, cb = tc * kTileCols;
     const int nr = (int)min((int64_t)kTileRows, g.na - r0);
     const int64_t ce = min(g.nb, cb + kTileCols);
@@ -225,9 +239,11 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
       base = m.tile_start[u];
     }
 
-    // row bounds: lane j < nr bounds row j, then every lane holds all of them
+    // row bounds: lane j < nr bounds row j, then every lane holds all of
+    // them; a row whose z-extent is empty meets nothing
     Bounds rl = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
     if (lane < nr) rl = box_bounds<K, FIXED, Z3>(m.a, g.a0 + r0 + lane);
+    if (lane >= nr || (Z3 && !(rl.hi > rl.lo))) rl.x1 = -__builtin_inff();  // meets no column
     Bounds rb[kTileRows];
 #pragma unroll
     for (int j = 0; j < kTileRows; ++j) {
@@ -243,27 +259,28 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
     Bounds nxt = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
     if (cb + lane < ce) nxt = box_bounds<K, FIXED, Z3>(m.b, g.b0 + cb + lane);
     for (int64_t c0 = cb; c0 < ce; c0 += 64) {
-      const int64_t col = c0 + lane;
-      const bool valid = col < ce;
+      const bool valid = c0 + lane < ce;
       const Bounds cbx = nxt;
       if (c0 + 64 + lane < ce) nxt = box_bounds<K, FIXED, Z3>(m.b, g.b0 + c0 + 64 + lane);
+      const bool cok = valid && (!Z3 || cbx.hi > cbx.lo);
+      float* out_c = out_rows + c0;
+      // the self diagonal crosses this chunk at lane r0 + j - c0
+      const int64_t dd = r0 - c0;
+      const bool dchunk = m.seg.self_pairs && dd > -kTileRows && dd < 64;
+      const int d0 = (int)(dchunk ? dd : -kTileRows - 64);
 #pragma unroll
       for (int j = 0; j < kTileRows; ++j) {
-        bool keep = false;
-        if (valid && j < nr) {
-          // closed bounds overlap (touching pairs go to the exact test), z
-          // extents overlap, not the diagonal of a self block
-          keep = cbx.x0 <= rb[j].x1 && rb[j].x0 <= cbx.x1 && cbx.y0 <= rb[j].y1 &&
-                 rb[j].y0 <= cbx.y1;
-          if (Z3) keep &= fminf(cbx.hi, rb[j].hi) > fmaxf(cbx.lo, rb[j].lo);
-          const bool diag = m.seg.self_pairs && (r0 + j == col);
-          keep &= !diag;
-          if (!FILL && !keep) out_rows[(int64_t)j * g.nb + col] = diag ? 1.f : 0.f;
-        }
+        // closed bounds overlap (touching pairs go to the exact test), open z
+        // extents overlap, not the diagonal of a self block
+        const bool diag = lane == d0 + j;
+        bool keep = cok && cbx.x0 <= rb[j].x1 && rb[j].x0 <= cbx.x1 && cbx.y0 <= rb[j].y1 &&
+                    rb[j].y0 <= cbx.y1 && !diag;
+        if (Z3) keep = keep && cbx.lo < rb[j].hi && rb[j].lo < cbx.hi;
+        if (!FILL && valid && j < nr) out_c[(int64_t)j * g.nb + lane] = diag ? 1.f : 0.f;
         const uint64_t mk = __ballot(keep);
         if (FILL && keep) {
           const int64_t slot = base + n + __popcll(mk & below);
-          if (slot < m.capacity) m.pair_id[slot] = g.out0 + (r0 + j) * g.nb + col;
+          if (slot < m.capacity) m.pair_id[slot] = g.out0 + (r0 + j) * g.nb + c0 + lane;
         }
         n += __popcll(mk);
       }
@@ -387,15 +404,41 @@ struct ExactArgs {
   int* err;
 };
 
-// Segment, row and column (within the segment) of a flat output index.
+__device__ __forceinline__ int64_t wave_first(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Quotient and remainder of a non-negative index by a positive divisor below
+// 2^24 (32-bit division when the index allows it).
+__device__ __forceinline__ void divmod(int64_t v, int64_t d, int64_t& q, int64_t& r) {
+  if (v < (int64_t)0xffffffff) {
+    const uint32_t q32 = (uint32_t)v / (uint32_t)d;
+    q = q32;
+  } else {
+    q = v / d;
+  }
+  r = v - q * d;
+}
+
+// Segment, row and column (within the segment) of a flat output index.  The
+// work list is in output order, so the entries of one wavefront mostly share
+// a segment: it is searched once for the wavefront's first entry, and a lane
+// outside that segment searches for itself.
 __device__ __forceinline__ bool locate(const SegArgs& sa, int64_t pid, Segment& g, int64_t& r,
                                        int64_t& c) {
-  const int s = sa.a_off != nullptr ? find_segment(sa.out_off, sa.nseg, pid) : 0;
+  int s = 0;
+  if (sa.a_off != nullptr) {
+    const int64_t pid0 = wave_first(pid);
+    const int s0 = find_segment(sa.out_off, sa.nseg, pid0);
+    const bool inside = pid >= sa.out_off[s0] && pid < sa.out_off[s0 + 1];
+    s = inside ? s0 : find_segment(sa.out_off, sa.nseg, pid);
+  }
   g = load_segment(sa, s);
   const int64_t local = pid - g.out0;
   if (!g.ok || g.nb <= 0 || local < 0) return false;
-  r = local / g.nb;
-  c = local - r * g.nb;
+  divmod(local, g.nb, r, c);
   return r < g.na;
 }
 
@@ -478,9 +521,13 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
   __shared__ float s_acc[WAVES][kTileRows * ROW];
   __shared__ float2 s_v[CAP * BLOCK];
   __shared__ float2 s_g[CAP * BLOCK];
+  __shared__ uint2 s_tab[256];
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the row-group walk is scalar
   float* acc_w = s_acc[wave];
+  fill_code_table<K, FIXED, BLOCK>(s_tab);
+  __syncthreads();
   const bool segmented = m.seg.a_off != nullptr;
   const int64_t total = segmented ? m.seg.group_prefix[m.seg.nseg] : m.single_groups;
 
@@ -508,7 +555,8 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
         const int64_t pid = m.pair_id[e];
         const int64_t local = pid - g.out0;
         if (local < 0 || g.nb <= 0) continue;
-        const int64_t rg = local / g.nb, col = local - rg * g.nb;  // row within the segment
+        int64_t rg, col;  // row and column within the segment
+        divmod(local, g.nb, rg, col);
         const int rl = (int)(rg - r0);
         if (rl < 0 || rl >= nr) continue;
         const int64_t ia = g.a0 + rg, ib = g.b0 + col;
@@ -542,7 +590,7 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
         }
         float2 gP[K], gQ[K], gz1, gz2;
         pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
-                                           s_v + tid, s_g + tid, gP, gQ, gz1, gz2);
+                                           s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2);
         float* acc = acc_w + rl * ROW;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -700,7 +748,8 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
   int64_t cull_grid = (int64_t)ctx.cus * 16;
   if (!segmented) cull_grid = std::min(cull_grid, ceil_div(single_tiles, kCullBlock / 64));
   const int exact_grid = ctx.cus * 8;
-  const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K;
+  const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
+                     aligned(a.xy, 16) && aligned(b.xy, 16);
   dispatch(K, fixed, a.zlo != nullptr, [&](auto k, auto fx, auto z) {
     constexpr int KK = decltype(k)::value;
     constexpr bool FX = decltype(fx)::value, ZZ = decltype(z)::value;
@@ -776,7 +825,8 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
   m.gb_xy = grad_b_xy;
   m.ga_z = grad_a_z;
   m.gb_z = grad_b_z;
-  const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K;
+  const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
+                     aligned(a.xy, 16) && aligned(b.xy, 16);
   dispatch(K, fixed, z3, [&](auto k, auto fx, auto z) {
     constexpr int KK = decltype(k)::value;
     constexpr bool FX = decltype(fx)::value, ZZ = decltype(z)::value;

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(pairs_block<K>()) void k_pairs_fwd(PairsFwdArgs arg
     if (SAVE) {
       args.nx[i] = (uint8_t)r.m;
       uint8_t* row = args.xflags + i * (int64_t)args.cap;
-      if (args.flags_vec) {
+      if (FIXED || args.flags_vec) {
         if constexpr (K == 4) {
           *reinterpret_cast<uint2*>(row) = make_uint2(r.codes[0], r.codes[1]);
         } else {
@@ -62,7 +62,10 @@ __global__ __launch_bounds__(pairs_block<K>()) void k_pairs_bwd(PairsBwdArgs arg
   constexpr int CAP = 2 * K;
   __shared__ float2 s_v[CAP * BLOCK];
   __shared__ float2 s_g[CAP * BLOCK];
+  __shared__ uint2 s_tab[256];
   const int tid = threadIdx.x;
+  fill_code_table<K, FIXED, BLOCK>(s_tab);
+  __syncthreads();
   const int64_t n = args.a.count;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + tid; i < n; i += (int64_t)gridDim.x * BLOCK) {
     const int n1 = FIXED ? K : poly_count(args.a.nv, i, args.a.kmax);
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(pairs_block<K>()) void k_pairs_bwd(PairsBwdArgs arg
     load_poly<K, FIXED>(args.b.xy, i, args.b.kmax, args.b.vec4, n2, Q);
     uint32_t codes[K / 2];
     const uint8_t* row = args.xflags + i * (int64_t)args.cap;
-    if (args.flags_vec) {
+    if (FIXED || args.flags_vec) {
       if constexpr (K == 4) {
         const uint2 w = *reinterpret_cast<const uint2*>(row);
         codes[0] = w.x;
@@ -104,10 +107,10 @@ __global__ __launch_bounds__(pairs_block<K>()) void k_pairs_bwd(PairsBwdArgs arg
     }
     float2 gP[K], gQ[K], gz1, gz2;
     pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, args.grad[i], (int)args.nx[i], codes, lo1, hi1,
-                                       lo2, hi2, s_v + tid, s_g + tid, gP, gQ, gz1, gz2);
+                                       lo2, hi2, s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2);
     float* oa = args.ga_xy + i * (int64_t)args.a.kmax * 2;
     float* ob = args.gb_xy + i * (int64_t)args.b.kmax * 2;
-    if (args.a.vec4) {
+    if (FIXED || args.a.vec4) {
 #pragma unroll
       for (int k = 0; k < K; k += 2)
         *reinterpret_cast<float4*>(oa + 2 * k) = make_float4(gP[k].x, gP[k].y, gP[k + 1].x, gP[k + 1].y);
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(pairs_block<K>()) void k_pairs_bwd(PairsBwdArgs arg
       for (int k = 0; k < K; ++k)
         if (k < args.a.kmax) *reinterpret_cast<float2*>(oa + 2 * k) = gP[k];
     }
-    if (args.b.vec4) {
+    if (FIXED || args.b.vec4) {
 #pragma unroll
       for (int k = 0; k < K; k += 2)
         *reinterpret_cast<float4*>(ob + 2 * k) = make_float4(gQ[k].x, gQ[k].y, gQ[k + 1].x, gQ[k + 1].y);
