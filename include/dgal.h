@@ -191,6 +191,74 @@ int dgal_iou_backward(dgal_ctx *ctx, int32_t mode, dgal_polys a, dgal_polys b,
                       float *grad_a_xy, float *grad_b_xy, float *grad_a_z,
                       float *grad_b_z, void *stream);
 
+/* The intersection primitive under the IoU (Sec. II-B: the convex polygon
+ * P n Q with its vertex count and one provenance flag per vertex; Sec. III:
+ * fixed-capacity storage), batched: for i < a.count,
+ *   out_xy [count][a.kmax + b.kmax][2] fp32: the intersection's vertices,
+ *          counter-clockwise from the smallest code, absolute coordinates;
+ *          slots at and past nx[i] are written 0
+ *   nx     [count] uint8, xflags [count][a.kmax + b.kmax] uint8 (0xFF padded):
+ *          the same values dgal_iou_pairs saves.
+ * All three outputs are required.  DGAL_EINVAL: as dgal_iou_pairs (z pointers
+ * are ignored), plus a NULL output or out_xy not 8-byte aligned. */
+int dgal_intersect(dgal_ctx *ctx, dgal_polys a, dgal_polys b, float *out_xy,
+                   uint8_t *nx, uint8_t *xflags, void *stream);
+
+/* Backward of dgal_intersect: the gradient of sum <grad_xy, out_xy> with
+ * respect to the vertices of a and b, from the saved nx / xflags (each
+ * vertex rebuilt from its code: a polygon vertex passes its gradient
+ * through, a crossing takes the chain rule of the two edges' meeting point).
+ *   grad_xy [count][a.kmax + b.kmax][2] fp32 (slots past nx are ignored)
+ *   grad_a_xy [count][a.kmax][2], grad_b_xy [count][b.kmax][2] fp32,
+ *   overwritten, padded slots written 0.
+ * DGAL_EINVAL: as dgal_intersect, plus a NULL input or output. */
+int dgal_intersect_backward(dgal_ctx *ctx, dgal_polys a, dgal_polys b,
+                            const float *grad_xy, const uint8_t *nx,
+                            const uint8_t *xflags, float *grad_a_xy,
+                            float *grad_b_xy, void *stream);
+
+/* Sec. III polygon area (shoelace about the first vertex; positive for a
+ * counter-clockwise polygon), batched: area [p.count] fp32.  z ignored.
+ * DGAL_EINVAL: ctx NULL, invalid p, area NULL with count > 0. */
+int dgal_area(dgal_ctx *ctx, dgal_polys p, float *area, void *stream);
+
+/* Backward of dgal_area: grad_xy [count][kmax][2] = grad_area[i] *
+ * d area / d vertex, i.e. (y_next - y_prev, x_prev - x_next) / 2 times the
+ * upstream gradient (cyclic neighbours; padded slots written 0). */
+int dgal_area_backward(dgal_ctx *ctx, dgal_polys p, const float *grad_area,
+                       float *grad_xy, void *stream);
+
+/* Rotated boxes by their parameters (Sec. IV-A case study), the corners
+ * formed in-kernel: corner k = (cx, cy) + R(yaw) (+-l/2, +-w/2),
+ * counter-clockwise from (+l/2, -w/2), i.e. the length along the heading.
+ *   p      [count][dim] fp32 rows: dim 5 = (cx, cy, w, l, yaw) for 2D,
+ *          dim 7 = (cx, cy, w, l, yaw, z, h) for 3D (z the centre: the
+ *          extent is [z - h/2, z + h/2]); rows 4-byte aligned. */
+typedef struct {
+  const float *p;
+  int64_t count;
+  int32_t dim;
+} dgal_boxes;
+
+/* IoU of box pairs (2D or 3D as the boxes' dim), batched like
+ * dgal_iou_pairs: iou [count] fp32; nx [count] uint8 and xflags [count][8]
+ * uint8 (8-byte aligned) saved for the backward, both NULL => forward only.
+ * DGAL_EINVAL: ctx or p NULL with count > 0, count < 0, a.count != b.count,
+ * dim not 5 / 7 or differing, iou NULL, exactly one of nx / xflags NULL,
+ * misaligned xflags. */
+int dgal_iou_boxes(dgal_ctx *ctx, dgal_boxes a, dgal_boxes b, float *iou,
+                   uint8_t *nx, uint8_t *xflags, void *stream);
+
+/* Gradient of sum(grad_iou * iou) with respect to the box parameters, from
+ * the saved nx / xflags: the corner gradient of dgal_iou_backward carried
+ * through the corner formula (and zlo = z - h/2, zhi = z + h/2).
+ *   grad_a, grad_b [count][dim] fp32, overwritten.
+ * DGAL_EINVAL: as dgal_iou_boxes, plus a NULL input or output. */
+int dgal_iou_boxes_backward(dgal_ctx *ctx, dgal_boxes a, dgal_boxes b,
+                            const float *grad_iou, const uint8_t *nx,
+                            const uint8_t *xflags, float *grad_a, float *grad_b,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

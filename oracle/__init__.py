@@ -56,6 +56,21 @@ def lib():
         L.oracle_iou_matrix_grad.restype = None
         L.oracle_pair_margins.argtypes = [i64, i64, _f32p, _u8p, i32, _f32p, _u8p, i32, _f64p]
         L.oracle_pair_margins.restype = None
+        p2 = [_f32p, _u8p, i32]
+        L.oracle_intersect_pairs.argtypes = [i64, i64] + p2 + p2 + [_f64p, _u8p, _u8p]
+        L.oracle_intersect_pairs.restype = i64
+        L.oracle_intersect_pairs_grad.argtypes = ([i64, i64] + p2 + p2 +
+                                                  [_f64p, _u8p, _u8p, _f64p, _f64p])
+        L.oracle_intersect_pairs_grad.restype = None
+        L.oracle_areas.argtypes = [i64, i64] + p2 + [_f64p]
+        L.oracle_areas.restype = None
+        L.oracle_areas_grad.argtypes = [i64, i64] + p2 + [_f64p, _f64p]
+        L.oracle_areas_grad.restype = None
+        L.oracle_iou_boxes.argtypes = [i64, i64, _f32p, _f32p, i32, _f64p, _u8p, _u8p]
+        L.oracle_iou_boxes.restype = i64
+        L.oracle_iou_boxes_grad.argtypes = [i64, i64, _f32p, _f32p, i32, _f64p, _u8p, _u8p,
+                                            _f64p, _f64p]
+        L.oracle_iou_boxes_grad.restype = None
         _lib = L
     return _lib
 
@@ -316,3 +331,104 @@ def iou_pairs_grad_f64(a_xy, b_xy, g, nx, xflags, a_z=None, b_z=None):
                                 _p(bz, _f64p), _p(g, _f64p), _p(nx, _u8p), _p(xflags, _u8p),
                                 _p(ga, _f64p), _p(gb, _f64p), _p(gaz, _f64p), _p(gbz, _f64p))
     return ga, gb, gaz, gbz
+
+
+def _poly2(xy, nv=None):
+    xy = np.ascontiguousarray(xy, dtype=np.float32)
+    assert xy.ndim == 3 and xy.shape[2] == 2
+    if nv is not None:
+        nv = np.ascontiguousarray(nv, dtype=np.uint8)
+    return (xy, nv), [_p(xy, _f32p), _p(nv, _u8p), xy.shape[1]]
+
+
+def intersect_pairs(a_xy, b_xy, a_nv=None, b_nv=None, threads=1):
+    """Intersection polygons of elementwise pairs (Sec. III), fixed capacity
+    ka + kb.  Returns (xy f64 [n, cap, 2] with slots >= nx zero, nx u8 [n],
+    xflags u8 [n, cap], n_invalid)."""
+    ka_keep, ka_args = _poly2(a_xy, a_nv)
+    kb_keep, kb_args = _poly2(b_xy, b_nv)
+    n = ka_keep[0].shape[0]
+    assert kb_keep[0].shape[0] == n
+    cap = ka_keep[0].shape[1] + kb_keep[0].shape[1]
+    xy = np.zeros((n, cap, 2), np.float64)
+    nx = np.zeros(n, np.uint8)
+    xf = np.full((n, cap), 0xFF, np.uint8)
+    L = lib()
+    bad = _run(lambda lo, hi: L.oracle_intersect_pairs(lo, hi, *ka_args, *kb_args, _p(xy, _f64p),
+                                                       _p(nx, _u8p), _p(xf, _u8p)), n, threads)
+    return xy, nx, xf, int(sum(bad))
+
+
+def intersect_pairs_grad(a_xy, b_xy, g_xy, nx, xflags, a_nv=None, b_nv=None, threads=1):
+    """Gradient of sum <g_xy, X> over the saved intersection vertices with
+    respect to both polygons.  Returns (ga [n,ka,2] f64, gb [n,kb,2] f64)."""
+    ka_keep, ka_args = _poly2(a_xy, a_nv)
+    kb_keep, kb_args = _poly2(b_xy, b_nv)
+    n, ka = ka_keep[0].shape[:2]
+    kb = kb_keep[0].shape[1]
+    g = np.ascontiguousarray(g_xy, np.float64)
+    assert g.shape == (n, ka + kb, 2)
+    nx = np.ascontiguousarray(nx, np.uint8)
+    xflags = np.ascontiguousarray(xflags, np.uint8)
+    ga = np.zeros((n, ka, 2), np.float64)
+    gb = np.zeros((n, kb, 2), np.float64)
+    L = lib()
+    _run(lambda lo, hi: L.oracle_intersect_pairs_grad(lo, hi, *ka_args, *kb_args, _p(g, _f64p),
+                                                      _p(nx, _u8p), _p(xflags, _u8p),
+                                                      _p(ga, _f64p), _p(gb, _f64p)), n, threads)
+    return ga, gb
+
+
+def areas(xy, nv=None):
+    """Shoelace areas of [n, k, 2] fp32 polygons (Sec. III), f64 [n]."""
+    keep, args = _poly2(xy, nv)
+    n = keep[0].shape[0]
+    out = np.zeros(n, np.float64)
+    lib().oracle_areas(0, n, *args, _p(out, _f64p))
+    return out
+
+
+def areas_grad(xy, g, nv=None):
+    """Gradient of sum(g * area) with respect to the vertices, f64 [n, k, 2]."""
+    keep, args = _poly2(xy, nv)
+    n, k = keep[0].shape[:2]
+    g = np.ascontiguousarray(g, np.float64)
+    out = np.zeros((n, k, 2), np.float64)
+    lib().oracle_areas_grad(0, n, *args, _p(g, _f64p), _p(out, _f64p))
+    return out
+
+
+def iou_boxes(a, b, threads=1):
+    """IoU of box pairs (Sec. IV-A): a, b are [n, 5] (cx, cy, w, l, yaw) or
+    [n, 7] (+ z centre, h) fp32; corners formed in fp64.  Returns
+    (iou f64 [n], nx u8 [n], xflags u8 [n, 8], n_invalid)."""
+    a = np.ascontiguousarray(a, np.float32)
+    b = np.ascontiguousarray(b, np.float32)
+    n, dim = a.shape
+    assert b.shape == (n, dim) and dim in (5, 7)
+    iou = np.zeros(n, np.float64)
+    nx = np.zeros(n, np.uint8)
+    xf = np.full((n, 8), 0xFF, np.uint8)
+    L = lib()
+    bad = _run(lambda lo, hi: L.oracle_iou_boxes(lo, hi, _p(a, _f32p), _p(b, _f32p), dim,
+                                                 _p(iou, _f64p), _p(nx, _u8p), _p(xf, _u8p)),
+               n, threads)
+    return iou, nx, xf, int(sum(bad))
+
+
+def iou_boxes_grad(a, b, g, nx, xflags, threads=1):
+    """Gradient of sum(g * IoU) with respect to the box parameters, f64
+    (ga [n, dim], gb [n, dim])."""
+    a = np.ascontiguousarray(a, np.float32)
+    b = np.ascontiguousarray(b, np.float32)
+    n, dim = a.shape
+    g = np.ascontiguousarray(g, np.float64)
+    nx = np.ascontiguousarray(nx, np.uint8)
+    xflags = np.ascontiguousarray(xflags, np.uint8)
+    ga = np.zeros((n, dim), np.float64)
+    gb = np.zeros((n, dim), np.float64)
+    L = lib()
+    _run(lambda lo, hi: L.oracle_iou_boxes_grad(lo, hi, _p(a, _f32p), _p(b, _f32p), dim,
+                                                _p(g, _f64p), _p(nx, _u8p), _p(xflags, _u8p),
+                                                _p(ga, _f64p), _p(gb, _f64p)), n, threads)
+    return ga, gb

@@ -315,6 +315,30 @@ static void line_meet_grad(point a, point b, point c, point d, point G,
   gd->y += t.v[1];
 }
 
+/* Adds the gradient with respect to P and Q of sum_k <gX[k], X_k>, X_k the
+ * intersection vertices named by their provenance codes: a polygon vertex
+ * passes its gradient through, a crossing takes the chain rule of the meeting
+ * point of two lines. */
+static void route_vertex_grads(const point *P, int n1, const point *Q, int n2, int nx,
+                               const uint8_t *flags, const point *gX, point *gP,
+                               point *gQ) {
+  for (int k = 0; k < nx; ++k) {
+    uint8_t code = flags[k];
+    if (code < 0x10) {
+      gP[code].x += gX[k].x;
+      gP[code].y += gX[k].y;
+    } else if (code < 0x40) {
+      gQ[code & 0x0F].x += gX[k].x;
+      gQ[code & 0x0F].y += gX[k].y;
+    } else {
+      int i = (code >> 3) & 7, j = code & 7;
+      int i1 = (i + 1) % n1, j1 = (j + 1) % n2;
+      line_meet_grad(P[i], P[i1], Q[j], Q[j1], gX[k], &gP[i], &gP[i1], &gQ[j],
+                     &gQ[j1]);
+    }
+  }
+}
+
 /* Sec. II-B `iou_grad`: gradient of one pair from the saved nx and flags.
  * Overwrites gP[0..n1-1], gQ[0..n2-1] (and gz1/gz2 = d/d(lo,hi) if 3D). */
 static void iou_grad_pair(const point *P, int n1, const point *Q, int n2,
@@ -358,21 +382,7 @@ static void iou_grad_pair(const point *P, int n1, const point *Q, int n2,
   point gX[ORC_CAP];
   for (int k = 0; k < nx; ++k) gX[k] = mkpt(0, 0);
   area_grad(X, nx, gI, gX);
-  for (int k = 0; k < nx; ++k) {
-    uint8_t code = flags[k];
-    if (code < 0x10) {
-      gP[code].x += gX[k].x;
-      gP[code].y += gX[k].y;
-    } else if (code < 0x40) {
-      gQ[code & 0x0F].x += gX[k].x;
-      gQ[code & 0x0F].y += gX[k].y;
-    } else {
-      int i = (code >> 3) & 7, j = code & 7;
-      int i1 = (i + 1) % n1, j1 = (j + 1) % n2;
-      line_meet_grad(P[i], P[i1], Q[j], Q[j1], gX[k], &gP[i], &gP[i1], &gQ[j],
-                     &gQ[j1]);
-    }
-  }
+  route_vertex_grads(P, n1, Q, n2, nx, flags, gX, gP, gQ);
   area_grad(P, n1, gA1, gP);
   area_grad(Q, n2, gA2, gQ);
 }
@@ -537,6 +547,196 @@ void oracle_iou_pairs_grad(int64_t lo, int64_t hi, const float *a_xy,
       ga_z[2 * i + 1] = gz1[1];
       gb_z[2 * i] = gz2[0];
       gb_z[2 * i + 1] = gz2[1];
+    }
+  }
+}
+
+/* Intersection polygons of pairs (a[i], b[i]) for i in [lo, hi) (Sec. III:
+ * the convex intersection in a fixed-capacity buffer, with the vertex count
+ * and provenance flags of Sec. II-B).  out_xy is [n][ka+kb][2] with slots at
+ * and past nx written 0; xflags is 0xFF padded.  Returns the number of pairs
+ * whose input was invalid or overflowed the capacity (written empty). */
+int64_t oracle_intersect_pairs(int64_t lo, int64_t hi, const float *a_xy,
+                               const uint8_t *a_nv, int ka, const float *b_xy,
+                               const uint8_t *b_nv, int kb, double *out_xy,
+                               uint8_t *nx, uint8_t *xflags) {
+  int64_t bad = 0;
+  int cap = ka + kb;
+  for (int64_t i = lo; i < hi; ++i) {
+    point P[ORC_MAXV], Q[ORC_MAXV];
+    polygon X;
+    double *row = out_xy + i * cap * 2;
+    for (int k = 0; k < 2 * cap; ++k) row[k] = 0.0;
+    memset(xflags + i * cap, 0xFF, (size_t)cap);
+    nx[i] = 0;
+    int n1 = load_poly(a_xy, a_nv, ka, i, P), n2 = load_poly(b_xy, b_nv, kb, i, Q);
+    int m = (n1 < 0 || n2 < 0) ? -1 : intersect(P, n1, Q, n2, &X);
+    if (m < 0 || m > cap) {
+      ++bad;
+      continue;
+    }
+    nx[i] = (uint8_t)m;
+    for (int k = 0; k < m; ++k) {
+      row[2 * k] = X.v[k].x;
+      row[2 * k + 1] = X.v[k].y;
+      xflags[i * cap + k] = X.code[k];
+    }
+  }
+  return bad;
+}
+
+/* Gradient, with respect to both polygons of every pair, of
+ * sum_i sum_k <g_xy[i][k], X_k(a[i], b[i])> for k < nx[i], the intersection
+ * vertices rebuilt from the saved flags.  ga_xy, gb_xy are [n][k][2]
+ * (padded slots written 0). */
+void oracle_intersect_pairs_grad(int64_t lo, int64_t hi, const float *a_xy,
+                                 const uint8_t *a_nv, int ka, const float *b_xy,
+                                 const uint8_t *b_nv, int kb, const double *g_xy,
+                                 const uint8_t *nx, const uint8_t *xflags,
+                                 double *ga_xy, double *gb_xy) {
+  int cap = ka + kb;
+  for (int64_t i = lo; i < hi; ++i) {
+    point P[ORC_MAXV], Q[ORC_MAXV], gP[ORC_MAXV], gQ[ORC_MAXV], gX[ORC_CAP];
+    for (int k = 0; k < ka * 2; ++k) ga_xy[i * ka * 2 + k] = 0.0;
+    for (int k = 0; k < kb * 2; ++k) gb_xy[i * kb * 2 + k] = 0.0;
+    int n1 = load_poly(a_xy, a_nv, ka, i, P), n2 = load_poly(b_xy, b_nv, kb, i, Q);
+    if (n1 < 0 || n2 < 0 || nx[i] > n1 + n2) continue;
+    for (int k = 0; k < n1; ++k) gP[k] = mkpt(0, 0);
+    for (int k = 0; k < n2; ++k) gQ[k] = mkpt(0, 0);
+    for (int k = 0; k < nx[i]; ++k)
+      gX[k] = mkpt(g_xy[(i * cap + k) * 2], g_xy[(i * cap + k) * 2 + 1]);
+    route_vertex_grads(P, n1, Q, n2, nx[i], xflags + i * cap, gX, gP, gQ);
+    for (int k = 0; k < n1; ++k) {
+      ga_xy[(i * ka + k) * 2] = gP[k].x;
+      ga_xy[(i * ka + k) * 2 + 1] = gP[k].y;
+    }
+    for (int k = 0; k < n2; ++k) {
+      gb_xy[(i * kb + k) * 2] = gQ[k].x;
+      gb_xy[(i * kb + k) * 2 + 1] = gQ[k].y;
+    }
+  }
+}
+
+/* Shoelace areas of polygons i in [lo, hi) (Sec. III), up to 16 vertices
+ * (an intersection polygon's capacity), 0 for an invalid vertex count. */
+void oracle_areas(int64_t lo, int64_t hi, const float *xy, const uint8_t *nv, int k,
+                  double *out) {
+  for (int64_t i = lo; i < hi; ++i) {
+    point V[ORC_CAP];
+    int n = k > ORC_CAP ? -1 : load_poly(xy, nv, k, i, V);
+    out[i] = n < 0 ? 0.0 : area(V, n);
+  }
+}
+
+/* Gradient of sum_i g[i] * area(p[i]); gxy is [n][k][2] (padded slots 0). */
+void oracle_areas_grad(int64_t lo, int64_t hi, const float *xy, const uint8_t *nv, int k,
+                       const double *g, double *gxy) {
+  for (int64_t i = lo; i < hi; ++i) {
+    point V[ORC_CAP], gV[ORC_CAP];
+    for (int t = 0; t < 2 * k; ++t) gxy[i * k * 2 + t] = 0.0;
+    int n = k > ORC_CAP ? -1 : load_poly(xy, nv, k, i, V);
+    if (n < 0) continue;
+    for (int t = 0; t < n; ++t) gV[t] = mkpt(0, 0);
+    area_grad(V, n, g[i], gV);
+    for (int t = 0; t < n; ++t) {
+      gxy[(i * k + t) * 2] = gV[t].x;
+      gxy[(i * k + t) * 2 + 1] = gV[t].y;
+    }
+  }
+}
+
+/* ---- rotated boxes (Sec. IV-A case study): box parameters -> corners ---- */
+
+/* R11: the corners of box (cx, cy, w, l, yaw) are c + R(yaw) (+-l/2, +-w/2),
+ * counter-clockwise from (+l/2, -w/2); the length runs along the heading. */
+static const double BOX_SL[4] = {1.0, 1.0, -1.0, -1.0};
+static const double BOX_SW[4] = {-1.0, 1.0, 1.0, -1.0};
+
+static void box_corners(const float *bx, point *out) {
+  double cx = bx[0], cy = bx[1], w = bx[2], l = bx[3], yaw = bx[4];
+  double c = cos(yaw), s = sin(yaw);
+  for (int k = 0; k < 4; ++k) {
+    double dx = 0.5 * BOX_SL[k] * l, dy = 0.5 * BOX_SW[k] * w;
+    out[k] = mkpt(cx + c * dx - s * dy, cy + s * dx + c * dy);
+  }
+}
+
+/* Gradient of L with respect to (cx, cy, w, l, yaw) given dL/dcorner_k. */
+static void box_param_grad(const float *bx, const point *gc, double *gp) {
+  double w = bx[2], l = bx[3], yaw = bx[4];
+  double c = cos(yaw), s = sin(yaw);
+  for (int t = 0; t < 5; ++t) gp[t] = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    double dx = 0.5 * BOX_SL[k] * l, dy = 0.5 * BOX_SW[k] * w;
+    gp[0] += gc[k].x;
+    gp[1] += gc[k].y;
+    /* corner = c + (c dx - s dy, s dx + c dy) */
+    gp[2] += 0.5 * BOX_SW[k] * (-s * gc[k].x + c * gc[k].y);
+    gp[3] += 0.5 * BOX_SL[k] * (c * gc[k].x + s * gc[k].y);
+    gp[4] += gc[k].x * (-s * dx - c * dy) + gc[k].y * (c * dx - s * dy);
+  }
+}
+
+/* IoU of box pairs for i in [lo, hi); boxes are [n][dim] fp32 with dim 5
+ * (cx, cy, w, l, yaw) for 2D or 7 (..., z, h; z the centre, R12) for 3D.
+ * The corners are formed in fp64 from the fp32 parameters. */
+int64_t oracle_iou_boxes(int64_t lo, int64_t hi, const float *a, const float *b, int dim,
+                         double *iou, uint8_t *nx, uint8_t *xflags) {
+  int64_t bad = 0;
+  for (int64_t i = lo; i < hi; ++i) {
+    point P[4], Q[4];
+    double z1[2], z2[2];
+    const float *ba = a + i * dim, *bb = b + i * dim;
+    box_corners(ba, P);
+    box_corners(bb, Q);
+    if (dim == 7) {
+      z1[0] = (double)ba[5] - 0.5 * ba[6];
+      z1[1] = (double)ba[5] + 0.5 * ba[6];
+      z2[0] = (double)bb[5] - 0.5 * bb[6];
+      z2[1] = (double)bb[5] + 0.5 * bb[6];
+    }
+    int err = 0;
+    iou[i] = iou_pair(P, 4, Q, 4, dim == 7 ? z1 : NULL, dim == 7 ? z2 : NULL,
+                      nx ? nx + i : NULL, xflags ? xflags + i * 8 : NULL, 8, &err);
+    bad += err;
+  }
+  return bad;
+}
+
+/* Gradient of sum_i g[i] * IoU(a[i], b[i]) with respect to the box
+ * parameters, from the saved nx / xflags: the corner gradient of the IoU
+ * backward, then the chain rule of the corner formula (and of
+ * zlo = z - h/2, zhi = z + h/2 in 3D). */
+void oracle_iou_boxes_grad(int64_t lo, int64_t hi, const float *a, const float *b, int dim,
+                           const double *g, const uint8_t *nx, const uint8_t *xflags,
+                           double *ga, double *gb) {
+  for (int64_t i = lo; i < hi; ++i) {
+    point P[4], Q[4], gP[4], gQ[4];
+    double z1[2], z2[2], gz1[2], gz2[2], gpa[5], gpb[5];
+    const float *ba = a + i * dim, *bb = b + i * dim;
+    box_corners(ba, P);
+    box_corners(bb, Q);
+    if (dim == 7) {
+      z1[0] = (double)ba[5] - 0.5 * ba[6];
+      z1[1] = (double)ba[5] + 0.5 * ba[6];
+      z2[0] = (double)bb[5] - 0.5 * bb[6];
+      z2[1] = (double)bb[5] + 0.5 * bb[6];
+    }
+    for (int t = 0; t < dim; ++t) ga[i * dim + t] = gb[i * dim + t] = 0.0;
+    if (nx[i] > 8) continue;
+    iou_grad_pair(P, 4, Q, 4, dim == 7 ? z1 : NULL, dim == 7 ? z2 : NULL, g[i], nx[i],
+                  xflags + i * 8, gP, gQ, gz1, gz2);
+    box_param_grad(ba, gP, gpa);
+    box_param_grad(bb, gQ, gpb);
+    for (int t = 0; t < 5; ++t) {
+      ga[i * dim + t] = gpa[t];
+      gb[i * dim + t] = gpb[t];
+    }
+    if (dim == 7) {
+      ga[i * dim + 5] = gz1[0] + gz1[1];
+      ga[i * dim + 6] = 0.5 * (gz1[1] - gz1[0]);
+      gb[i * dim + 5] = gz2[0] + gz2[1];
+      gb[i * dim + 6] = 0.5 * (gz2[1] - gz2[0]);
     }
   }
 }

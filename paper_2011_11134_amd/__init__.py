@@ -40,8 +40,15 @@ class Saved(ctypes.Structure):
                 ("tile_start", _vp), ("tile_count", _vp), ("tile_capacity", ctypes.c_int64)]
 
 
+class Boxes(ctypes.Structure):
+    """dgal_boxes"""
+    _fields_ = [("p", _vp), ("count", ctypes.c_int64), ("dim", ctypes.c_int32)]
+
+
 EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
-           "dgal_iou_pairs", "dgal_iou_matrix", "dgal_iou_backward")
+           "dgal_iou_pairs", "dgal_iou_matrix", "dgal_iou_backward",
+           "dgal_intersect", "dgal_intersect_backward", "dgal_area", "dgal_area_backward",
+           "dgal_iou_boxes", "dgal_iou_boxes_backward")
 
 
 def _load():
@@ -66,6 +73,18 @@ def _load():
     L.dgal_iou_backward.argtypes = [_vp, i32, Polys, Polys, _vp, _vp, _vp, i32, i32, _vp, i64,
                                     _vp, _vp, ctypes.POINTER(Saved), _vp, _vp, _vp, _vp, _vp]
     L.dgal_iou_backward.restype = ctypes.c_int
+    L.dgal_intersect.argtypes = [_vp, Polys, Polys, _vp, _vp, _vp, _vp]
+    L.dgal_intersect.restype = ctypes.c_int
+    L.dgal_intersect_backward.argtypes = [_vp, Polys, Polys, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.dgal_intersect_backward.restype = ctypes.c_int
+    L.dgal_area.argtypes = [_vp, Polys, _vp, _vp]
+    L.dgal_area.restype = ctypes.c_int
+    L.dgal_area_backward.argtypes = [_vp, Polys, _vp, _vp, _vp]
+    L.dgal_area_backward.restype = ctypes.c_int
+    L.dgal_iou_boxes.argtypes = [_vp, Boxes, Boxes, _vp, _vp, _vp, _vp]
+    L.dgal_iou_boxes.restype = ctypes.c_int
+    L.dgal_iou_boxes_backward.argtypes = [_vp, Boxes, Boxes, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.dgal_iou_boxes_backward.restype = ctypes.c_int
     return L
 
 
@@ -192,6 +211,103 @@ def iou_pairs_backward(a_xy, b_xy, grad, nx, xflags, a_nv=None, b_nv=None, a_z=N
                               _ptr(gbz), _stream(a_xy)),
         "dgal_iou_backward(pairs)")
     return ga, gb, gaz, gbz
+
+
+# ------------------------------------------------------------ primitives
+
+def intersect(a_xy, b_xy, a_nv=None, b_nv=None):
+    """Intersection polygons of elementwise pairs (Sec. II-B / III).
+
+    Returns (xy [n, ka+kb, 2] fp32 counter-clockwise from the smallest code,
+    0 past nx; nx [n] uint8; xflags [n, ka+kb] uint8)."""
+    pa, ka = polys(a_xy, a_nv)
+    pb, kb = polys(b_xy, b_nv)
+    n, cap = a_xy.shape[0], a_xy.shape[1] + b_xy.shape[1]
+    dev = a_xy.device
+    xy = torch.empty((n, cap, 2), dtype=torch.float32, device=dev)
+    nx = torch.empty(n, dtype=torch.uint8, device=dev)
+    xf = torch.empty((n, cap), dtype=torch.uint8, device=dev)
+    _ok(lib.dgal_intersect(context(dev), pa, pb, _ptr(xy), _ptr(nx), _ptr(xf), _stream(a_xy)),
+        "dgal_intersect")
+    return xy, nx, xf
+
+
+def intersect_backward(a_xy, b_xy, grad_xy, nx, xflags, a_nv=None, b_nv=None):
+    """Gradient of sum(grad_xy * xy) with respect to both polygons, from the
+    saved nx / xflags.  Returns (grad_a [n,ka,2], grad_b [n,kb,2])."""
+    pa, ka = polys(a_xy, a_nv)
+    pb, kb = polys(b_xy, b_nv)
+    dev = a_xy.device
+    _need(grad_xy, torch.float32, "grad_xy", dev)
+    _need(nx, torch.uint8, "nx", dev)
+    _need(xflags, torch.uint8, "xflags", dev)
+    if grad_xy.shape != (a_xy.shape[0], a_xy.shape[1] + b_xy.shape[1], 2):
+        raise ValueError("grad_xy must be [n, ka+kb, 2]")
+    ga = torch.empty_like(a_xy)
+    gb = torch.empty_like(b_xy)
+    _ok(lib.dgal_intersect_backward(context(dev), pa, pb, _ptr(grad_xy), _ptr(nx), _ptr(xflags),
+                                    _ptr(ga), _ptr(gb), _stream(a_xy)),
+        "dgal_intersect_backward")
+    return ga, gb
+
+
+def area(xy, nv=None):
+    """Shoelace areas (Sec. III) of [n, k, 2] fp32 polygons: [n] fp32."""
+    p, keep = polys(xy, nv)
+    out = torch.empty(xy.shape[0], dtype=torch.float32, device=xy.device)
+    _ok(lib.dgal_area(context(xy.device), p, _ptr(out), _stream(xy)), "dgal_area")
+    return out
+
+
+def area_backward(xy, grad, nv=None):
+    """Gradient of sum(grad * area) with respect to the vertices: [n, k, 2]."""
+    p, keep = polys(xy, nv)
+    _need(grad, torch.float32, "grad", xy.device)
+    out = torch.empty_like(xy)
+    _ok(lib.dgal_area_backward(context(xy.device), p, _ptr(grad), _ptr(out), _stream(xy)),
+        "dgal_area_backward")
+    return out
+
+
+# ------------------------------------------------------------- boxes
+
+def _boxes(p, name):
+    _need(p, torch.float32, name)
+    if p.dim() != 2 or p.shape[1] not in (5, 7):
+        raise ValueError(f"{name} must be [n, 5] (cx, cy, w, l, yaw) or [n, 7] (+ z, h)")
+    return Boxes(_ptr(p), p.shape[0], p.shape[1])
+
+
+def iou_boxes(a, b, save=True):
+    """IoU of box pairs given as parameter rows (Sec. IV-A), corners formed
+    in-kernel.  Returns (iou [n], nx [n] or None, xflags [n, 8] or None)."""
+    ba, bb = _boxes(a, "a"), _boxes(b, "b")
+    dev = a.device
+    n = a.shape[0]
+    iou = torch.empty(n, dtype=torch.float32, device=dev)
+    nx = xf = None
+    if save:
+        nx = torch.empty(n, dtype=torch.uint8, device=dev)
+        xf = torch.empty((n, 8), dtype=torch.uint8, device=dev)
+    _ok(lib.dgal_iou_boxes(context(dev), ba, bb, _ptr(iou), _ptr(nx), _ptr(xf), _stream(a)),
+        "dgal_iou_boxes")
+    return iou, nx, xf
+
+
+def iou_boxes_backward(a, b, grad, nx, xflags):
+    """Gradient of sum(grad * IoU) with respect to the box parameters:
+    (grad_a [n, dim], grad_b [n, dim])."""
+    ba, bb = _boxes(a, "a"), _boxes(b, "b")
+    dev = a.device
+    _need(grad, torch.float32, "grad", dev)
+    _need(nx, torch.uint8, "nx", dev)
+    _need(xflags, torch.uint8, "xflags", dev)
+    ga = torch.empty_like(a)
+    gb = torch.empty_like(b)
+    _ok(lib.dgal_iou_boxes_backward(context(dev), ba, bb, _ptr(grad), _ptr(nx), _ptr(xflags),
+                                    _ptr(ga), _ptr(gb), _stream(a)),
+        "dgal_iou_boxes_backward")
+    return ga, gb
 
 
 # --------------------------------------------------------------------- matrix
@@ -334,6 +450,58 @@ class IoUPairs(torch.autograd.Function):
         a_nv, b_nv = ctx.nvs
         ga, gb, _, _ = iou_pairs_backward(a_xy, b_xy, g.contiguous().float(), nx, xf, a_nv, b_nv)
         return ga, gb, None, None
+
+
+class Intersect(torch.autograd.Function):
+    """Intersection polygons of elementwise pairs; returns (xy, nx, xflags),
+    differentiable in xy (backward from the saved codes)."""
+
+    @staticmethod
+    def forward(ctx, a_xy, b_xy, a_nv=None, b_nv=None):
+        xy, nx, xf = intersect(a_xy, b_xy, a_nv, b_nv)
+        ctx.save_for_backward(a_xy, b_xy, nx, xf)
+        ctx.nvs = (a_nv, b_nv)
+        ctx.mark_non_differentiable(nx, xf)
+        return xy, nx, xf
+
+    @staticmethod
+    def backward(ctx, g, _gnx=None, _gxf=None):
+        a_xy, b_xy, nx, xf = ctx.saved_tensors
+        a_nv, b_nv = ctx.nvs
+        ga, gb = intersect_backward(a_xy, b_xy, g.contiguous().float(), nx, xf, a_nv, b_nv)
+        return ga, gb, None, None
+
+
+class Area(torch.autograd.Function):
+    """Polygon areas, differentiable in the vertices."""
+
+    @staticmethod
+    def forward(ctx, xy, nv=None):
+        ctx.save_for_backward(xy)
+        ctx.nv = nv
+        return area(xy, nv)
+
+    @staticmethod
+    def backward(ctx, g):
+        (xy,) = ctx.saved_tensors
+        return area_backward(xy, g.contiguous().float(), ctx.nv), None
+
+
+class IoUBoxes(torch.autograd.Function):
+    """IoU of box pairs from their parameters (2D [n, 5] or 3D [n, 7]);
+    backward down to the parameters."""
+
+    @staticmethod
+    def forward(ctx, a, b):
+        iou, nx, xf = iou_boxes(a, b, save=True)
+        ctx.save_for_backward(a, b, nx, xf)
+        return iou
+
+    @staticmethod
+    def backward(ctx, g):
+        a, b, nx, xf = ctx.saved_tensors
+        ga, gb = iou_boxes_backward(a, b, g.contiguous().float(), nx, xf)
+        return ga, gb
 
 
 class IoU3DPairs(torch.autograd.Function):

@@ -184,4 +184,140 @@ int dgal_iou_matrix(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const int64_t* a_
                               iou, out_size, saved, static_cast<hipStream_t>(stream));
 }
 
+int dgal_intersect(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* out_xy, uint8_t* nx,
+                   uint8_t* xflags, void* stream) {
+  if (ctx == nullptr || !valid_polys(a) || !valid_polys(b)) return DGAL_EINVAL;
+  if (a.count != b.count) return DGAL_EINVAL;
+  if (a.count == 0) return DGAL_OK;
+  if (out_xy == nullptr || nx == nullptr || xflags == nullptr || !aligned(out_xy, 8))
+    return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  const int K = reg_k(a.kmax, b.kmax);
+  dgal::IntersectArgs args;
+  args.a = poly_args(a, K);
+  args.b = poly_args(b, K);
+  args.out_xy = out_xy;
+  args.nx = nx;
+  args.xflags = xflags;
+  args.cap = a.kmax + b.kmax;
+  args.rows_vec = args.cap == 2 * K && aligned(out_xy, 16) && aligned(xflags, (uintptr_t)(2 * K));
+  args.err = ctx->v.err;
+  const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
+                     args.a.vec4 && args.b.vec4 && args.rows_vec;
+  return status_of(dgal::launch_intersect_fwd(args, K, fixed, static_cast<hipStream_t>(stream)));
+}
+
+int dgal_intersect_backward(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const float* grad_xy,
+                            const uint8_t* nx, const uint8_t* xflags, float* grad_a_xy,
+                            float* grad_b_xy, void* stream) {
+  if (ctx == nullptr || !valid_polys(a) || !valid_polys(b)) return DGAL_EINVAL;
+  if (a.count != b.count) return DGAL_EINVAL;
+  if (a.count == 0) return DGAL_OK;
+  if (grad_xy == nullptr || nx == nullptr || xflags == nullptr || grad_a_xy == nullptr ||
+      grad_b_xy == nullptr)
+    return DGAL_EINVAL;
+  if (!aligned(grad_xy, 8) || !aligned(grad_a_xy, 8) || !aligned(grad_b_xy, 8)) return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  const int K = reg_k(a.kmax, b.kmax);
+  dgal::IntersectBwdArgs args;
+  args.a = poly_args(a, K);
+  args.b = poly_args(b, K);
+  args.grad_xy = grad_xy;
+  args.nx = nx;
+  args.xflags = xflags;
+  args.cap = a.kmax + b.kmax;
+  args.ga_xy = grad_a_xy;
+  args.gb_xy = grad_b_xy;
+  const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
+                     args.a.vec4 && args.b.vec4;
+  return status_of(dgal::launch_intersect_bwd(args, K, fixed, static_cast<hipStream_t>(stream)));
+}
+
+int dgal_area(dgal_ctx* ctx, dgal_polys p, float* area, void* stream) {
+  if (ctx == nullptr || !valid_polys(p)) return DGAL_EINVAL;
+  if (p.count == 0) return DGAL_OK;
+  if (area == nullptr) return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  const int K = p.kmax <= 4 ? 4 : 8;
+  const dgal::PolyArgs pa = poly_args(p, K);
+  const bool fixed = p.nv == nullptr && p.kmax == K && pa.vec4;
+  return status_of(
+      dgal::launch_area(pa, nullptr, area, K, fixed, false, static_cast<hipStream_t>(stream)));
+}
+
+int dgal_area_backward(dgal_ctx* ctx, dgal_polys p, const float* grad_area, float* grad_xy,
+                       void* stream) {
+  if (ctx == nullptr || !valid_polys(p)) return DGAL_EINVAL;
+  if (p.count == 0) return DGAL_OK;
+  if (grad_area == nullptr || grad_xy == nullptr || !aligned(grad_xy, 8)) return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  const int K = p.kmax <= 4 ? 4 : 8;
+  const dgal::PolyArgs pa = poly_args(p, K);
+  const bool fixed = p.nv == nullptr && p.kmax == K && pa.vec4;
+  return status_of(dgal::launch_area(pa, grad_area, grad_xy, K, fixed, true,
+                                     static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"
+
+namespace {
+
+bool valid_boxes(const dgal_boxes& a, const dgal_boxes& b) {
+  if (a.count < 0 || a.count != b.count || a.dim != b.dim || (a.dim != 5 && a.dim != 7))
+    return false;
+  if (a.count > 0 && (a.p == nullptr || b.p == nullptr || !aligned(a.p, 4) || !aligned(b.p, 4)))
+    return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgal_iou_boxes(dgal_ctx* ctx, dgal_boxes a, dgal_boxes b, float* iou, uint8_t* nx,
+                   uint8_t* xflags, void* stream) {
+  if (ctx == nullptr || !valid_boxes(a, b)) return DGAL_EINVAL;
+  if ((nx == nullptr) != (xflags == nullptr)) return DGAL_EINVAL;
+  if (a.count == 0) return DGAL_OK;
+  if (iou == nullptr || (xflags != nullptr && !aligned(xflags, 8))) return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  dgal::BoxesFwdArgs args;
+  args.a = a.p;
+  args.b = b.p;
+  args.count = a.count;
+  args.iou = iou;
+  args.nx = nx;
+  args.xflags = xflags;
+  args.err = ctx->v.err;
+  return status_of(dgal::launch_boxes_fwd(args, a.dim == 7, nx != nullptr,
+                                          static_cast<hipStream_t>(stream)));
+}
+
+int dgal_iou_boxes_backward(dgal_ctx* ctx, dgal_boxes a, dgal_boxes b, const float* grad_iou,
+                            const uint8_t* nx, const uint8_t* xflags, float* grad_a,
+                            float* grad_b, void* stream) {
+  if (ctx == nullptr || !valid_boxes(a, b)) return DGAL_EINVAL;
+  if (a.count == 0) return DGAL_OK;
+  if (grad_iou == nullptr || nx == nullptr || xflags == nullptr || grad_a == nullptr ||
+      grad_b == nullptr || !aligned(xflags, 8) || !aligned(grad_a, 4) || !aligned(grad_b, 4))
+    return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  dgal::BoxesBwdArgs args;
+  args.a = a.p;
+  args.b = b.p;
+  args.count = a.count;
+  args.grad = grad_iou;
+  args.nx = nx;
+  args.xflags = xflags;
+  args.ga = grad_a;
+  args.gb = grad_b;
+  return status_of(dgal::launch_boxes_bwd(args, a.dim == 7, static_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

@@ -165,11 +165,14 @@ struct PairResult {
 };
 
 // Forward of one pair.  s_pt / s_cd address this lane's column of a
-// [2K][BLOCK] LDS buffer (element stride BLOCK).
-template <int K, bool FIXED, int BLOCK>
+// [2K][BLOCK] LDS buffer (element stride BLOCK).  EMIT: the ordered
+// intersection vertices are also returned in ov[0..2K) (absolute frame,
+// slots at and past the vertex count set to 0).
+template <int K, bool FIXED, int BLOCK, bool EMIT = false>
 __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Poly<K>& Q, int n2,
                                              float2* __restrict__ s_pt,
-                                             uint8_t* __restrict__ s_cd, PairResult<K>& res) {
+                                             uint8_t* __restrict__ s_cd, PairResult<K>& res,
+                                             float2* ov = nullptr) {
   constexpr int CAP = 2 * K;
   constexpr int NW = (K * K + 31) / 32;  // 32-bit words of a K x K sign table
   constexpr uint32_t KM = (1u << K) - 1u;
@@ -220,30 +223,38 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
     }
   }
   if (!(omin > kCertify * E * D)) {
-    // exact signs in fp64; exact zeros take the sign of Q moved by (eps, eps^2)
+    // Exact signs in fp64; exact zeros take the sign of Q moved by (eps,
+    // eps^2).  Rare, so it is written for few registers rather than speed:
+    // Q is staged in this lane's (still unused) LDS column and each row of
+    // the table is a runtime loop over Q's edges.
+#pragma unroll
+    for (int k = 0; k < K; ++k) s_pt[k * BLOCK] = make_float2(Q.x[k], Q.y[k]);
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
       negp[w] = 0u;
       negq[w] = 0u;
     }
 #pragma unroll
-    for (int i = K - 1; i >= 0; --i) {
+    for (int i = 0; i < K; ++i) {
       const float pnx = next_of<K, FIXED>(P.x, i, n1), pny = next_of<K, FIXED>(P.y, i, n1);
       // orient(P_i, P_i1, Q_j + d) = o - e.y*eps + e.x*eps^2
       const bool tie_p = (P.y[i] != pny) ? (P.y[i] > pny) : (pnx > P.x[i]);
-#pragma unroll
-      for (int j = K - 1; j >= 0; --j) {
-        const float qnx = next_of<K, FIXED>(Q.x, j, n2), qny = next_of<K, FIXED>(Q.y, j, n2);
+      const int w = (i * K) >> 5, sh = (i * K) & 31;
+#pragma unroll 1
+      for (int j = 0; j < K; ++j) {
+        const int jn = FIXED ? ((j + 1) & (K - 1)) : (j + 1 < n2 ? j + 1 : 0);
+        const float2 q = s_pt[j * BLOCK], qn = s_pt[jn * BLOCK];
         // orient(Q_j + d, Q_j1 + d, P_i) = o + f.y*eps - f.x*eps^2
-        const bool tie_q = (qny != Q.y[j]) ? (qny > Q.y[j]) : (Q.x[j] > qnx);
-        const double op = orient64(Q.x[j], Q.y[j], qnx, qny, P.x[i], P.y[i]);
-        const double oq = orient64(P.x[i], P.y[i], pnx, pny, Q.x[j], Q.y[j]);
+        const bool tie_q = (qn.y != q.y) ? (qn.y > q.y) : (q.x > qn.x);
+        const double op = orient64(q.x, q.y, qn.x, qn.y, P.x[i], P.y[i]);
+        const double oq = orient64(P.x[i], P.y[i], pnx, pny, q.x, q.y);
         const bool bp = op > 0.0 || (op == 0.0 && tie_q);
         const bool bq = oq > 0.0 || (oq == 0.0 && tie_p);
-        oP[i][j] = (float)op;
-        const int w = (i * K + j) >> 5;
-        negp[w] = (negp[w] << 1) | (uint32_t)!bp;
-        negq[w] = (negq[w] << 1) | (uint32_t)!bq;
+        negp[w] |= (uint32_t)!bp << (sh + j);
+        negq[w] |= (uint32_t)!bq << (sh + j);
+        const float o = (float)op;
+#pragma unroll
+        for (int t = 0; t < K; ++t) oP[i][t] = t == j ? o : oP[i][t];
       }
     }
   }
@@ -356,6 +367,11 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
 #pragma unroll
   for (int w = 0; w < K / 2; ++w) codes[w] = 0xffffffffu;
   if (m > 0) codes[0] = 0xffffff00u | (uint32_t)s_cd[0];
+  if (EMIT) {
+#pragma unroll
+    for (int r = 0; r < CAP; ++r) ov[r] = make_float2(0.f, 0.f);
+    if (m > 0) ov[0] = make_float2(x[0] + P.x[0], y[0] + P.y[0]);
+  }
 #pragma unroll
   for (int r = 1; r < CAP; ++r) {
     if (r < m) {
@@ -368,6 +384,7 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
       const uint32_t c = s_cd[slot * BLOCK];
       const int sh = (r & 3) * 8;
       codes[r >> 2] = (codes[r >> 2] & ~(0xffu << sh)) | (c << sh);
+      if (EMIT) ov[r] = make_float2(v.x + P.x[0], v.y + P.y[0]);
     }
   }
   res.inter = m >= 3 ? 0.5f * acc : 0.f;
@@ -485,8 +502,59 @@ __device__ __forceinline__ void slot_offsets(uint32_t c, uint32_t n1S, uint32_t 
 __device__ __forceinline__ float2& at(float2* col, uint32_t off) {
   return *reinterpret_cast<float2*>(reinterpret_cast<char*>(col) + off);
 }
+__device__ __forceinline__ const float2& at(const float2* col, uint32_t off) {
+  return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(col) + off);
+}
 
-template <int K, bool FIXED, bool Z3, int BLOCK>
+// Chain rule of one intersection vertex X = A + t (B - A) (see code_slots)
+// for dL/dX = G, added into the slots' gradient accumulators: with
+// e = B - A, f = D - C, w = C - A,
+//   dL/dt = G.e, dL/dcross(w,f) = dL/dt / den, dL/dden = -dL/dt t / den,
+//   A gets G - dL/de - dL/dw, B gets dL/de, C gets dL/dw - dL/df, D gets dL/df.
+// t and 1/den come from the caller (0 for a polygon vertex, whose slots are
+// all A: it adds G to A and zeros to the aliases, which are written first).
+__device__ __forceinline__ void route_slot(float Gx, float Gy, float t, float idn, uint32_t oa,
+                                           uint32_t ob, uint32_t oc, uint32_t od,
+                                           float2* __restrict__ s_v, float2* __restrict__ s_g) {
+  const float2 a = at(s_v, oa), b = at(s_v, ob), cc = at(s_v, oc), d = at(s_v, od);
+  float2 ta = at(s_g, oa), tb = at(s_g, ob), tc = at(s_g, oc), td = at(s_g, od);
+  const float ex = b.x - a.x, ey = b.y - a.y, fx = d.x - cc.x, fy = d.y - cc.y;
+  const float wx = cc.x - a.x, wy = cc.y - a.y;
+  const float gt = Gx * ex + Gy * ey;
+  const float gN = gt * idn;  // d/d cross(w, f)
+  const float gD = -gN * t;   // d/d cross(e, f)
+  const float gex = t * Gx + gD * fy, gey = t * Gy - gD * fx;
+  const float gfx = -gN * wy - gD * ey, gfy = gN * wx + gD * ex;
+  const float gwx = gN * fy, gwy = -gN * fx;
+  tb.x += gex;
+  tb.y += gey;
+  tc.x += gwx - gfx;
+  tc.y += gwy - gfy;
+  td.x += gfx;
+  td.y += gfy;
+  ta.x += Gx - gex - gwx;
+  ta.y += Gy - gey - gwy;
+  at(s_g, ob) = tb;
+  at(s_g, oc) = tc;
+  at(s_g, od) = td;
+  at(s_g, oa) = ta;
+}
+
+// t and 1/den of the vertex in slots (oa, ob, oc, od); its position is
+// A + t (B - A).
+__device__ __forceinline__ float2 slot_vertex(uint32_t oa, uint32_t ob, uint32_t oc, uint32_t od,
+                                              const float2* __restrict__ s_v, float& t,
+                                              float& idn) {
+  const float2 a = at(s_v, oa), b = at(s_v, ob), cc = at(s_v, oc), d = at(s_v, od);
+  const float ex = b.x - a.x, ey = b.y - a.y, fx = d.x - cc.x, fy = d.y - cc.y;
+  const float wx = cc.x - a.x, wy = cc.y - a.y;
+  const float den = ex * fy - ey * fx;
+  idn = den != 0.f ? fast_rcp(den) : 0.f;
+  t = (wx * fy - wy * fx) * idn;
+  return make_float2(fmaf(t, ex, a.x), fmaf(t, ey, a.y));
+}
+
+template <int K, bool FIXED, bool Z3, int BLOCK, bool KEEP_OFFSETS = FIXED && !Z3>
 __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Poly<K>& Q, int n2,
                                               float g, int nx, const uint32_t (&codes)[K / 2],
                                               float lo1, float hi1, float lo2, float hi2,
@@ -524,24 +592,27 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   const int m = min(nx, CAP);
   constexpr uint32_t S = BLOCK * sizeof(float2);
   const uint32_t n1S = (uint32_t)n1 * S, nqS = (uint32_t)(K + n2) * S;
+  // KEEP_OFFSETS: the caller has the registers to keep each slot's offsets
+  // (packed) for the routing pass (the 2D fixed-size pairs kernel does);
+  // otherwise the routing pass decodes the code again.
   float X[CAP], Y[CAP], T[CAP], IDN[CAP];
+  uint32_t OAB[CAP], OCD[CAP];
 #pragma unroll
   for (int r = 0; r < CAP; ++r) {
     const uint32_t c = (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu;
     uint32_t oa, ob, oc, od;
     slot_offsets<K, FIXED, BLOCK>(c, n1S, nqS, s_tab, oa, ob, oc, od);
-    const float2 a = at(s_v, oa), b = at(s_v, ob), cc = at(s_v, oc), d = at(s_v, od);
-    const float ex = b.x - a.x, ey = b.y - a.y, fx = d.x - cc.x, fy = d.y - cc.y;
-    const float wx = cc.x - a.x, wy = cc.y - a.y;
-    const float den = ex * fy - ey * fx;
-    IDN[r] = den != 0.f ? fast_rcp(den) : 0.f;
-    T[r] = (wx * fy - wy * fx) * IDN[r];
-    X[r] = fmaf(T[r], ex, a.x);
-    Y[r] = fmaf(T[r], ey, a.y);
+    if (KEEP_OFFSETS) {
+      OAB[r] = oa | (ob << 16);
+      OCD[r] = oc | (od << 16);
+    }
+    const float2 v = slot_vertex(oa, ob, oc, od, s_v, T[r], IDN[r]);
+    X[r] = v.x;
+    Y[r] = v.y;
     __builtin_amdgcn_sched_barrier(0);
   }
-  // the routing pass decodes and reads the slots again rather than keeping
-  // every slot's offsets and edge vectors live across the passes
+  // the routing pass reads the slots again rather than keeping every slot's
+  // edge vectors live across the passes
   asm volatile("" ::: "memory");
   float acc = 0.f;
 #pragma unroll
@@ -634,42 +705,22 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   }
   const float hI = 0.5f * gI;
 
-  // route every vertex's gradient to the slots it came from: with
-  // e = B - A, f = D - C, w = C - A and dL/dX = G,
-  //   dL/dt = G.e, dL/dcross(w,f) = dL/dt / den, dL/dden = -dL/dt t / den,
-  //   A gets G - dL/de - dL/dw, B gets dL/de, C gets dL/dw - dL/df, D gets dL/df.
-  // A polygon vertex adds G to A and zeros to its three aliases, so the
-  // aliases are written before A.
+  // route every vertex's gradient to the slots it came from (route_slot)
 #pragma unroll
   for (int r = 0; r < CAP; ++r) {
     if (r < m) {
       const float Gx = hI * GX[r], Gy = hI * GY[r];
-      const uint32_t c = (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu;
       uint32_t oa, ob, oc, od;
-      slot_offsets<K, FIXED, BLOCK>(c, n1S, nqS, s_tab, oa, ob, oc, od);
-      const float2 a = at(s_v, oa), b = at(s_v, ob), cc = at(s_v, oc), d = at(s_v, od);
-      float2 ta = at(s_g, oa), tb = at(s_g, ob), tc = at(s_g, oc), td = at(s_g, od);
-      const float ex = b.x - a.x, ey = b.y - a.y, fx = d.x - cc.x, fy = d.y - cc.y;
-      const float wx = cc.x - a.x, wy = cc.y - a.y;
-      const float idn = IDN[r], t = T[r];
-      const float gt = Gx * ex + Gy * ey;
-      const float gN = gt * idn;   // d/d cross(w, f)
-      const float gD = -gN * t;    // d/d cross(e, f)
-      const float gex = t * Gx + gD * fy, gey = t * Gy - gD * fx;
-      const float gfx = -gN * wy - gD * ey, gfy = gN * wx + gD * ex;
-      const float gwx = gN * fy, gwy = -gN * fx;
-      tb.x += gex;
-      tb.y += gey;
-      tc.x += gwx - gfx;
-      tc.y += gwy - gfy;
-      td.x += gfx;
-      td.y += gfy;
-      ta.x += Gx - gex - gwx;
-      ta.y += Gy - gey - gwy;
-      at(s_g, ob) = tb;
-      at(s_g, oc) = tc;
-      at(s_g, od) = td;
-      at(s_g, oa) = ta;
+      if (KEEP_OFFSETS) {
+        oa = OAB[r] & 0xffffu;
+        ob = OAB[r] >> 16;
+        oc = OCD[r] & 0xffffu;
+        od = OCD[r] >> 16;
+      } else {
+        const uint32_t c = (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu;
+        slot_offsets<K, FIXED, BLOCK>(c, n1S, nqS, s_tab, oa, ob, oc, od);
+      }
+      route_slot(Gx, Gy, T[r], IDN[r], oa, ob, oc, od, s_v, s_g);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -677,6 +728,95 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   for (int k = 0; k < K; ++k) {
     gP[k] = (FIXED || k < n1) ? s_g[k * BLOCK] : make_float2(0.f, 0.f);
     gQ[k] = (FIXED || k < n2) ? s_g[(K + k) * BLOCK] : make_float2(0.f, 0.f);
+  }
+}
+
+// Backward of one pair's intersection polygon: the gradient, with respect to
+// both polygons, of sum_r <G[r], X_r> over the nx saved vertices, each
+// rebuilt from its code and routed like the IoU backward's (no predicates,
+// no sort).  Buffers as in pair_backward.
+template <int K, bool FIXED, int BLOCK>
+__device__ __forceinline__ void pair_vertex_backward(const Poly<K>& P, int n1, const Poly<K>& Q,
+                                                     int n2, int nx,
+                                                     const uint32_t (&codes)[K / 2],
+                                                     const float2 (&G)[2 * K],
+                                                     float2* __restrict__ s_v,
+                                                     float2* __restrict__ s_g,
+                                                     const uint2* __restrict__ s_tab,
+                                                     float2 (&gP)[K], float2 (&gQ)[K]) {
+  constexpr int CAP = 2 * K;
+  if (FIXED) {
+    n1 = K;
+    n2 = K;
+  }
+  const float ox = P.x[0], oy = P.y[0];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s_v[k * BLOCK] = make_float2(P.x[k] - ox, P.y[k] - oy);
+    s_v[(K + k) * BLOCK] = make_float2(Q.x[k] - ox, Q.y[k] - oy);
+    s_g[k * BLOCK] = make_float2(0.f, 0.f);
+    s_g[(K + k) * BLOCK] = make_float2(0.f, 0.f);
+  }
+  const int m = min(nx, CAP);
+  constexpr uint32_t S = BLOCK * sizeof(float2);
+  const uint32_t n1S = (uint32_t)n1 * S, nqS = (uint32_t)(K + n2) * S;
+#pragma unroll
+  for (int r = 0; r < CAP; ++r) {
+    if (r < m) {
+      const uint32_t c = (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu;
+      uint32_t oa, ob, oc, od;
+      slot_offsets<K, FIXED, BLOCK>(c, n1S, nqS, s_tab, oa, ob, oc, od);
+      float t, idn;
+      (void)slot_vertex(oa, ob, oc, od, s_v, t, idn);
+      route_slot(G[r].x, G[r].y, t, idn, oa, ob, oc, od, s_v, s_g);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    gP[k] = (FIXED || k < n1) ? s_g[k * BLOCK] : make_float2(0.f, 0.f);
+    gQ[k] = (FIXED || k < n2) ? s_g[(K + k) * BLOCK] : make_float2(0.f, 0.f);
+  }
+}
+
+// Shoelace area of one polygon (Sec. III) about its first vertex, and its
+// gradient dA/dv_k = (y_k+1 - y_k-1, x_k-1 - x_k+1) / 2 (cyclic neighbours;
+// padded slots get 0).
+template <int K, bool FIXED>
+__device__ __forceinline__ float poly_area(const Poly<K>& P, int n) {
+  if (FIXED) n = K;
+  float s = 0.f;
+#pragma unroll
+  for (int k = 1; k + 1 < K; ++k) {
+    if (FIXED || k + 1 < n) {
+      const float ux = P.x[k] - P.x[0], uy = P.y[k] - P.y[0];
+      const float vx = P.x[k + 1] - P.x[0], vy = P.y[k + 1] - P.y[0];
+      s += ux * vy - uy * vx;
+    }
+  }
+  return 0.5f * s;
+}
+
+template <int K, bool FIXED>
+__device__ __forceinline__ void poly_area_grad(const Poly<K>& P, int n, float g, float2 (&gv)[K]) {
+  if (FIXED) n = K;
+  const float h = 0.5f * g;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int kn = FIXED ? (k + 1) % K : (k + 1 < n ? k + 1 : 0);
+    const int kp = FIXED ? (k + K - 1) % K : (k == 0 ? n - 1 : k - 1);
+    float pnx = P.x[0], pny = P.y[0], ppx = P.x[0], ppy = P.y[0];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {  // select the neighbours (static when FIXED)
+      if (t == kn) {
+        pnx = P.x[t];
+        pny = P.y[t];
+      }
+      if (t == kp) {
+        ppx = P.x[t];
+        ppy = P.y[t];
+      }
+    }
+    gv[k] = (FIXED || k < n) ? make_float2(h * (pny - ppy), h * (ppx - pnx)) : make_float2(0.f, 0.f);
   }
 }
 

@@ -44,6 +44,47 @@ struct PairsBwdArgs {
   float* gb_z;
 };
 
+struct IntersectArgs {
+  PolyArgs a, b;
+  float* out_xy;    // [count][cap][2]
+  uint8_t* nx;
+  uint8_t* xflags;  // [count][cap]
+  int cap;          // a.kmax + b.kmax
+  bool rows_vec;    // cap == 2K, vertex rows 16-byte and flag rows cap-byte aligned
+  int* err;
+};
+
+struct IntersectBwdArgs {
+  PolyArgs a, b;
+  const float* grad_xy;  // [count][cap][2]
+  const uint8_t* nx;
+  const uint8_t* xflags;
+  int cap;
+  float* ga_xy;
+  float* gb_xy;
+};
+
+struct BoxesFwdArgs {
+  const float* a;   // [count][5 or 7]
+  const float* b;
+  int64_t count;
+  float* iou;
+  uint8_t* nx;
+  uint8_t* xflags;  // [count][8], 8-byte aligned
+  int* err;
+};
+
+struct BoxesBwdArgs {
+  const float* a;
+  const float* b;
+  int64_t count;
+  const float* grad;
+  const uint8_t* nx;
+  const uint8_t* xflags;
+  float* ga;  // [count][5 or 7]
+  float* gb;
+};
+
 // What the kernels need from a context.
 struct CtxView {
   int device;
@@ -118,5 +159,12 @@ hipError_t launch_pairs_fwd(const PairsFwdArgs& args, int K, bool fixed, bool z3
                             hipStream_t stream);
 hipError_t launch_pairs_bwd(const PairsBwdArgs& args, int K, bool fixed, bool z3,
                             hipStream_t stream);
+hipError_t launch_intersect_fwd(const IntersectArgs& args, int K, bool fixed, hipStream_t stream);
+hipError_t launch_intersect_bwd(const IntersectBwdArgs& args, int K, bool fixed,
+                                hipStream_t stream);
+hipError_t launch_area(const PolyArgs& p, const float* grad, float* out, int K, bool fixed,
+                       bool backward, hipStream_t stream);
+hipError_t launch_boxes_fwd(const BoxesFwdArgs& args, bool z3, bool save, hipStream_t stream);
+hipError_t launch_boxes_bwd(const BoxesBwdArgs& args, bool z3, hipStream_t stream);
 
 }  // namespace dgal

@@ -62,7 +62,8 @@ def _draw_boxes(rng, n, center_lo, center_hi, wl_lo, wl_hi, w_range=None, l_rang
     return cx, cy, w, l, yaw
 
 
-def c1_pairs(n=1024, seed=None, center_sigma=0.5, yaw_sigma=0.3, size_sigma=None, cfg=0):
+def c1_pairs(n=1024, seed=None, center_sigma=0.5, yaw_sigma=0.3, size_sigma=None, cfg=0,
+             box_params=False):
     rng = _rng(cfg, seed)
     cx, cy, w, l, yaw = _draw_boxes(rng, n, (-2, -2), (2, 2), 1.0, 3.0)
     cx2 = cx + rng.normal(0.0, center_sigma, n)
@@ -81,11 +82,35 @@ def c1_pairs(n=1024, seed=None, center_sigma=0.5, yaw_sigma=0.3, size_sigma=None
     a = boxes_to_quads(cx, cy, w, l, yaw)
     b = boxes_to_quads(cx2, cy2, w2, l2, yaw2)
     g = rng.uniform(-1.0, 1.0, n).astype(np.float32)
-    return {"a_xy": a, "b_xy": b, "grad": g, "kind": "pairs"}
+    out = {"a_xy": a, "b_xy": b, "grad": g, "kind": "pairs"}
+    if box_params:
+        # the same boxes as parameter rows (cx, cy, w, l, yaw), rounded to fp32
+        out["a_box"] = np.stack([cx, cy, w, l, yaw], 1).astype(np.float32)
+        out["b_box"] = np.stack([cx2, cy2, w2, l2, yaw2], 1).astype(np.float32)
+    return out
 
 
-def c3_pairs(n=1 << 20, seed=None):
-    return c1_pairs(n=n, seed=seed, center_sigma=0.3, yaw_sigma=0.2, size_sigma=0.1, cfg=2)
+def c3_pairs(n=1 << 20, seed=None, box_params=False):
+    return c1_pairs(n=n, seed=seed, center_sigma=0.3, yaw_sigma=0.2, size_sigma=0.1, cfg=2,
+                    box_params=box_params)
+
+
+def c3_boxes(n=1 << 20, seed=None, three_d=False):
+    """c3's rectangle pairs as box-parameter rows for the fused box front end:
+    a_box, b_box [n, 5] fp32 (cx, cy, w, l, yaw), or [n, 7] with the c5 z
+    distribution appended (z centre U[-2, 1], h U[1.4, 1.8]; the second box's
+    z moved by N(0, 0.3^2)); grad U[-1, 1]."""
+    d = c3_pairs(n=n, seed=seed, box_params=True)
+    out = {"a_box": d["a_box"], "b_box": d["b_box"], "grad": d["grad"], "kind": "boxes"}
+    if three_d:
+        rng = _rng(5, None if seed is None else seed + 1)
+        z = rng.uniform(-2.0, 1.0, n)
+        h = rng.uniform(1.4, 1.8, n)
+        z2 = z + rng.normal(0.0, 0.3, n)
+        h2 = rng.uniform(1.4, 1.8, n)
+        out["a_box"] = np.concatenate([d["a_box"], np.stack([z, h], 1).astype(np.float32)], 1)
+        out["b_box"] = np.concatenate([d["b_box"], np.stack([z2, h2], 1).astype(np.float32)], 1)
+    return out
 
 
 def bev_boxes(rng, n):
@@ -203,6 +228,7 @@ WORKLOADS = {
     "c3": c3_pairs,
     "c4": c4_polygons,
     "c5": c5_scenes,
+    "c3b": c3_boxes,
 }
 
 

@@ -494,3 +494,218 @@ def test_matrix_grad_is_sum_of_pair_grads(orc):
     assert np.max(np.abs(ga - ref)) <= 1e-12
     assert np.max(np.abs(gaz - refz)) <= 1e-12
     assert np.abs(ga).max() > 0
+
+
+# ------------------------------------------------- intersection and area primitives
+
+def test_intersect_pairs_exact_rational(orc):
+    """Batched intersection polygons (fp64 vertices, nx, flags) against exact
+    rational clipping of the same fp32 inputs."""
+    checked = 0
+    for a, b, anv, bnv in _pair_sets():
+        keep = _filtered(orc, a, b, anv, bnv)
+        xy, nx, xf, bad = orc.intersect_pairs(a, b, anv, bnv)
+        assert bad == 0
+        cap = a.shape[1] + b.shape[1]
+        assert xy.shape == (len(a), cap, 2)
+        for i in np.nonzero(keep)[0][:120]:
+            n1 = int(anv[i]) if anv is not None else a.shape[1]
+            n2 = int(bnv[i]) if bnv is not None else b.shape[1]
+            P, Q = X.fpoly(a[i, :n1]), X.fpoly(b[i, :n2])
+            V = X.clip(P, Q)
+            m = int(nx[i])
+            assert m == len(V)
+            assert np.all(xy[i, m:] == 0.0) and np.all(xf[i, m:] == 0xFF)
+            if m == 0:
+                continue
+            s = V.index(X.vertex_from_code(P, Q, int(xf[i, 0])))
+            ex = V[s:] + V[:s]
+            scale = max(1.0, float(np.abs(a[i]).max()), float(np.abs(b[i]).max()))
+            for k in range(m):
+                assert X.classify(P, Q, ex[k]) == {int(xf[i, k])}
+                assert abs(xy[i, k, 0] - float(ex[k][0])) <= 1e-13 * scale
+                assert abs(xy[i, k, 1] - float(ex[k][1])) <= 1e-13 * scale
+            checked += 1
+    assert checked > 200
+
+
+def _perturbable(x, h):
+    """x + h and x - h are exact in fp32 (so differences see exactly +-h)."""
+    x = np.asarray(x, np.float32)
+    hp = (x + np.float32(h)).astype(np.float64) - x.astype(np.float64)
+    hm = x.astype(np.float64) - (x - np.float32(h)).astype(np.float64)
+    return (hp == h) & (hm == h)
+
+
+def test_intersect_grad_vs_finite_differences(orc):
+    """Gradient of sum <gX, X> over the intersection vertices (vertex codes
+    pass through, crossings through the homogeneous meet) against central
+    differences with a Richardson step, on pairs whose flags are unchanged."""
+    rng = np.random.default_rng(77)
+    for d in (synth.c3_pairs(n=512, seed=71), synth.c4_polygons(n=512, seed=72)):
+        a, b = d["a_xy"], d["b_xy"]
+        anv, bnv = d.get("a_nv"), d.get("b_nv")
+        n, ka = a.shape[:2]
+        kb = b.shape[1]
+        cap = ka + kb
+        xy, nx, xf, _ = orc.intersect_pairs(a, b, anv, bnv)
+        gX = rng.uniform(-1, 1, (n, cap, 2))
+        gX[np.arange(cap)[None, :] >= nx[:, None]] = 0.0
+        ga, gb = orc.intersect_pairs_grad(a, b, gX, nx, xf, anv, bnv)
+        keep = nx > 0
+        h = 2.0 ** -10
+        cols = {h: [], h / 2: []}
+        for which, k, c in [("a", k, c) for k in range(ka) for c in range(2)] + \
+                           [("b", k, c) for k in range(kb) for c in range(2)]:
+            src = a if which == "a" else b
+            keep &= _perturbable(src[:, k, c], h) & _perturbable(src[:, k, c], h / 2)
+            for step in (h, h / 2):
+                vals = []
+                for sgn in (1.0, -1.0):
+                    aa, bb = a.copy(), b.copy()
+                    (aa if which == "a" else bb)[:, k, c] += np.float32(sgn * step)
+                    xp, nxp, xfp, _ = orc.intersect_pairs(aa, bb, anv, bnv)
+                    keep &= (nxp == nx) & np.all(xfp == xf, axis=1)
+                    vals.append((gX * xp).sum(axis=(1, 2)))
+                cols[step].append((vals[0] - vals[1]) / (2 * step))
+        fd1, fd2 = np.stack(cols[h], 1), np.stack(cols[h / 2], 1)
+        fdr = (4.0 * fd2 - fd1) / 3.0
+        an = np.concatenate([ga.reshape(n, -1), gb.reshape(n, -1)], 1)
+        den = np.maximum(np.linalg.norm(an, axis=1), 1e-8)
+        err = (np.linalg.norm(an - fdr, axis=1) / den)[keep]
+        assert keep.sum() > 200, keep.sum()
+        # extrapolated differences: truncation O(h^4), the bound of the IoU test
+        assert err.max() <= 1e-5, np.sort(err)[-5:]
+        # padded slots of the polygons carry no gradient
+        if anv is not None:
+            pad_a = np.arange(ka)[None, :] >= anv[:, None]
+            assert np.all(ga[pad_a] == 0.0)
+
+
+def test_intersect_grad_vertex_codes_pass_through(orc):
+    """Nested polygons: every intersection vertex is a vertex of the inner
+    polygon, so the gradient is the upstream one, unchanged, on that polygon."""
+    outer = np.array([[[-4, -4], [4, -4], [4, 4], [-4, 4]]], np.float32)
+    inner = np.array([[[-1, -0.5], [1.5, -1], [1, 1], [-0.5, 1.25]]], np.float32)
+    xy, nx, xf, _ = orc.intersect_pairs(outer, inner)
+    assert nx[0] == 4 and set(xf[0, :4].tolist()) == {0x10, 0x11, 0x12, 0x13}
+    g = np.zeros((1, 8, 2))
+    g[0, :4] = np.arange(8).reshape(4, 2) + 1.0
+    ga, gb = orc.intersect_pairs_grad(outer, inner, g, nx, xf)
+    assert np.all(ga == 0.0)
+    for r in range(4):
+        assert np.array_equal(gb[0, xf[0, r] & 0x0F], g[0, r])
+
+
+def test_areas_closed_forms_and_gradient(orc):
+    sq = np.array([[[0, 0], [2, 0], [2, 2], [0, 2]]], np.float32)
+    tri = np.array([[[0, 0], [3, 0], [0, 4], [0, 0]]], np.float32)
+    assert orc.areas(sq)[0] == 4.0
+    assert orc.areas(tri, np.array([3], np.uint8))[0] == 6.0
+    # dA/dv_k = (y_k+1 - y_k-1, x_k-1 - x_k+1) / 2, written out for the square
+    g = orc.areas_grad(sq, np.ones(1))[0]
+    assert np.array_equal(g, np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], np.float64))
+    gt = orc.areas_grad(tri, np.ones(1), np.array([3], np.uint8))[0]
+    assert np.array_equal(gt, np.array([[-2, -1.5], [2, 0], [0, 1.5], [0, 0]], np.float64))
+    # random polygons: translation invariance of the gradient and central
+    # differences (the area is quadratic, so they are exact up to rounding)
+    d = synth.c4_polygons(n=256, seed=81)
+    xy, nv = d["a_xy"], d["a_nv"]
+    gg = orc.areas_grad(xy, np.ones(len(xy)), nv)
+    assert np.abs(gg.sum(axis=1)).max() <= 1e-12
+    h = 2.0 ** -8
+    for k in range(8):
+        for c in range(2):
+            ok = _perturbable(xy[:, k, c], h)
+            p, m = xy.copy(), xy.copy()
+            p[:, k, c] += np.float32(h)
+            m[:, k, c] -= np.float32(h)
+            fd = (orc.areas(p, nv) - orc.areas(m, nv)) / (2 * h)
+            assert np.abs(fd - gg[:, k, c])[ok].max() <= 1e-9
+
+
+# ------------------------------------------------------------ box front end
+
+def _corners_np(box):
+    """R11 written out in numpy fp64: c + R(yaw) (+-l/2, +-w/2), CCW from
+    (+l/2, -w/2)."""
+    b = np.asarray(box, np.float64)
+    cx, cy, w, l, yaw = b[:, 0], b[:, 1], b[:, 2], b[:, 3], b[:, 4]
+    sl = np.array([1, 1, -1, -1], np.float64) * 0.5
+    sw = np.array([-1, 1, 1, -1], np.float64) * 0.5
+    dx, dy = l[:, None] * sl, w[:, None] * sw
+    c, s = np.cos(yaw)[:, None], np.sin(yaw)[:, None]
+    return np.stack([cx[:, None] + c * dx - s * dy, cy[:, None] + s * dx + c * dy], -1)
+
+
+def test_boxes_match_corner_form(orc):
+    d = synth.c3_boxes(n=2048, seed=101, three_d=True)
+    for dim in (5, 7):
+        a, b = d["a_box"][:, :dim], d["b_box"][:, :dim]
+        iou, nx, xf, bad = orc.iou_boxes(a, b)
+        assert bad == 0
+        az = bz = None
+        if dim == 7:
+            az = np.stack([a[:, 5].astype(np.float64) - 0.5 * a[:, 6],
+                           a[:, 5].astype(np.float64) + 0.5 * a[:, 6]], 1)
+            bz = np.stack([b[:, 5].astype(np.float64) - 0.5 * b[:, 6],
+                           b[:, 5].astype(np.float64) + 0.5 * b[:, 6]], 1)
+        ref, rnx, rxf = orc.iou_pairs_f64(_corners_np(a), _corners_np(b), az, bz)
+        assert np.abs(iou - ref).max() <= 1e-13
+        assert np.array_equal(nx, rnx) and np.array_equal(xf, rxf)
+
+
+def test_boxes_axis_aligned_closed_form(orc):
+    """yaw 0: the boxes are [cx -+ l/2] x [cy -+ w/2]; yaw pi/2 swaps the
+    extents (dyadic values, exact in fp32; cos(pi/2) is ~6e-17 in fp64)."""
+    a = np.array([[0, 0, 2, 4, 0], [1, 1, 1, 3, 0], [0, 0, 2, 2, 0]], np.float32)
+    b = np.array([[1, 0.5, 2, 4, 0], [5, 5, 1, 1, 0], [0.5, 0.25, 2, 2, 0]], np.float32)
+    iou, nx, xf, _ = orc.iou_boxes(a, b)
+    # pair 0: x [-2,2] vs [-1,3] -> 3, y [-1,1] vs [-0.5,1.5] -> 1.5: I = 4.5, U = 16 - 4.5
+    # pair 1: disjoint; pair 2: x [-1,1] vs [-0.5,1.5] -> 1.5, y [-1,1] vs
+    # [-0.75,1.25] -> 1.75: I = 2.625, U = 8 - 2.625
+    assert abs(iou[0] - 4.5 / 11.5) <= 1e-15 and iou[1] == 0.0 and nx[1] == 0
+    assert abs(iou[2] - 2.625 / 5.375) <= 1e-15
+    a2 = a.copy()
+    a2[:, 4] = np.float32(np.pi / 2)
+    a2[:, [2, 3]] = a[:, [3, 2]]  # w <-> l with a quarter turn: the same footprint
+    iou2, _, _, _ = orc.iou_boxes(a2, b)
+    assert np.abs(iou2 - iou).max() <= 1e-6
+
+
+def test_boxes_grad_vs_finite_differences(orc):
+    d = synth.c3_boxes(n=1024, seed=102, three_d=True)
+    for dim in (5, 7):
+        a = np.ascontiguousarray(d["a_box"][:, :dim])
+        b = np.ascontiguousarray(d["b_box"][:, :dim])
+        n = len(a)
+        iou, nx, xf, _ = orc.iou_boxes(a, b)
+        ga, gb = orc.iou_boxes_grad(a, b, np.ones(n), nx, xf)
+        keep = nx > 0
+        if dim == 7:
+            zl1, zh1 = a[:, 5] - 0.5 * a[:, 6], a[:, 5] + 0.5 * a[:, 6]
+            zl2, zh2 = b[:, 5] - 0.5 * b[:, 6], b[:, 5] + 0.5 * b[:, 6]
+            hz = np.minimum(zh1, zh2) - np.maximum(zl1, zl2)
+            keep &= (np.abs(zh1 - zh2) > 0.05) & (np.abs(zl1 - zl2) > 0.05) & (hz > 0.05)
+        h = 2.0 ** -10
+        cols = {h: [], h / 2: []}
+        for which in ("a", "b"):
+            for t in range(dim):
+                src = a if which == "a" else b
+                keep &= _perturbable(src[:, t], h) & _perturbable(src[:, t], h / 2)
+                for step in (h, h / 2):
+                    vals = []
+                    for sgn in (1.0, -1.0):
+                        aa, bb = a.copy(), b.copy()
+                        (aa if which == "a" else bb)[:, t] += np.float32(sgn * step)
+                        v, nxp, xfp, _ = orc.iou_boxes(aa, bb)
+                        keep &= (nxp == nx) & np.all(xfp == xf, axis=1)
+                        vals.append(v)
+                    cols[step].append((vals[0] - vals[1]) / (2 * step))
+        fd1, fd2 = np.stack(cols[h], 1), np.stack(cols[h / 2], 1)
+        fdr = (4.0 * fd2 - fd1) / 3.0
+        an = np.concatenate([ga, gb], 1)
+        den = np.maximum(np.linalg.norm(an, axis=1), 1e-8)
+        err = (np.linalg.norm(an - fdr, axis=1) / den)[keep]
+        assert keep.sum() > 300, keep.sum()
+        assert err.max() <= 1e-5, np.sort(err)[-5:]
