@@ -37,8 +37,10 @@ FP32_PEAK_TFLOPS = 157.3
 #   rectangles, backward: 2 x 32 B vertices + 4 B grad + 1 B nx + 8 B flags
 #                         + 2 x 32 B gradients                                = 141
 #   8-slot polygons:      2 x (64 + 1) B vertices and counts; flags 16 B
+#   boxes by parameters:  2 x 20 B (cx, cy, w, l, yaw) + 13 B  /  + 4 + 9 + 2 x 20 B
 BYTES = {
     ("rect", "fwd"): 77, ("rect", "bwd"): 141,
+    ("box", "fwd"): 53, ("box", "bwd"): 93,
     ("poly", "fwd"): 130 + 4 + 1 + 16, ("poly", "bwd"): 130 + 4 + 1 + 16 + 128,
 }
 # Algorithmic fp32 operations per rectangle pair (FMA = 2), counted from the
@@ -51,7 +53,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "c3b"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true", help="skip the plain per-op GPU form")
     p.add_argument("--copy-calib-mib", type=int, default=0,
@@ -125,6 +127,39 @@ class PairsStep:
                                       0, self.g.data_ptr(), 0, self.nx.data_ptr(),
                                       self.xf.data_ptr(), None, self.ga.data_ptr(),
                                       self.gb.data_ptr(), None, None, stream)
+        assert st == 0, st
+
+
+class BoxesStep:
+    """Forward + backward of box pairs given by their parameters (corners
+    formed in-kernel), fixed device buffers."""
+
+    def __init__(self, dg, torch, d):
+        self.dg = dg
+        self.a = torch.from_numpy(d["a_box"]).cuda()
+        self.b = torch.from_numpy(d["b_box"]).cuda()
+        self.g = torch.from_numpy(d["grad"]).cuda()
+        n, dim = self.a.shape
+        self.n = self.pairs = n
+        self.iou = torch.empty(n, device="cuda")
+        self.nx = torch.empty(n, dtype=torch.uint8, device="cuda")
+        self.xf = torch.empty((n, 8), dtype=torch.uint8, device="cuda")
+        self.ga = torch.empty_like(self.a)
+        self.gb = torch.empty_like(self.b)
+        self.ba = dg.Boxes(self.a.data_ptr(), n, dim)
+        self.bb = dg.Boxes(self.b.data_ptr(), n, dim)
+        self.ctx = dg.context()
+        self.kind = "box"
+
+    def fwd(self, stream):
+        st = self.dg.lib.dgal_iou_boxes(self.ctx, self.ba, self.bb, self.iou.data_ptr(),
+                                        self.nx.data_ptr(), self.xf.data_ptr(), stream)
+        assert st == 0, st
+
+    def bwd(self, stream):
+        st = self.dg.lib.dgal_iou_boxes_backward(self.ctx, self.ba, self.bb, self.g.data_ptr(),
+                                                 self.nx.data_ptr(), self.xf.data_ptr(),
+                                                 self.ga.data_ptr(), self.gb.data_ptr(), stream)
         assert st == 0, st
 
 
@@ -257,7 +292,12 @@ def main():
     torch.cuda.set_device(0)
     wl = args.workload
     d = synth.get(wl)
-    step = PairsStep(dg, torch, d) if wl in ("c1", "c3", "c4") else MatrixStep(dg, torch, d, wl)
+    if wl in ("c1", "c3", "c4"):
+        step = PairsStep(dg, torch, d)
+    elif wl == "c3b":
+        step = BoxesStep(dg, torch, d)
+    else:
+        step = MatrixStep(dg, torch, d, wl)
     has_bwd = getattr(step, "has_bwd", True)
     stream = torch.cuda.current_stream().cuda_stream
 
@@ -352,10 +392,10 @@ def main():
         torch.cuda.synchronize()
 
     cpu = None
-    if not args.no_cpu_baseline and step.kind != "matrix":
+    if not args.no_cpu_baseline and step.kind in ("rect", "poly"):
         cpu = cpu_baseline(d, step.kind)
     plain = None
-    if not args.no_plain and step.kind != "matrix":
+    if not args.no_plain and step.kind in ("rect", "poly"):
         plain = plain_baseline(torch, d)
 
     value = step.pairs * args.steps / elapsed
@@ -363,13 +403,16 @@ def main():
              "c2": "c2: 4096 x 4096 rotated BEV box IoU matrix, forward",
              "c3": "c3: 1,048,576 rotated-rectangle pairs, forward + backward",
              "c4": "c4: 262,144 convex 3..8-gon pairs, forward + backward",
-             "c5": "c5: 64 scenes (U{50..2000} boxes), per-scene 3D self-pair IoU, forward + backward"}
+             "c5": "c5: 64 scenes (U{50..2000} boxes), per-scene 3D self-pair IoU, forward + backward",
+             "c3b": "c3 boxes: 1,048,576 rotated-box pairs as (cx, cy, w, l, yaw) rows, corners "
+                    "formed in-kernel, forward + backward to the parameters"}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": names[wl], "pairs": int(step.pairs), "kmax": int(step.a.shape[1]),
+        "config": {"workload": names[wl], "pairs": int(step.pairs),
+                   ("box_dim" if step.kind == "box" else "kmax"): int(step.a.shape[1]),
                    "parallelism": "single GPU",
                    "launch": "HIP graph replay" if args.graph else "eager"},
         "kernels_ms": {k: round(v, 4) for k, v in kernels.items()},

@@ -21,7 +21,9 @@ __device__ __forceinline__ BoxFrame box_frame(const float* b) {
   f.cx = b[0];
   f.cy = b[1];
   const float hw = 0.5f * b[2], hl = 0.5f * b[3];
-  sincosf(b[4], &f.s, &f.c);
+  // hardware sine / cosine (absolute error ~2^-21 on the yaw range of boxes,
+  // i.e. corner errors ~1e-6 of the box size, far inside the IoU tolerance)
+  __sincosf(b[4], &f.s, &f.c);
   const float sl[4] = {1.f, 1.f, -1.f, -1.f}, sw[4] = {-1.f, 1.f, 1.f, -1.f};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {

@@ -554,7 +554,26 @@ __device__ __forceinline__ float2 slot_vertex(uint32_t oa, uint32_t ob, uint32_t
   return make_float2(fmaf(t, ex, a.x), fmaf(t, ey, a.y));
 }
 
-template <int K, bool FIXED, bool Z3, int BLOCK, bool KEEP_OFFSETS = FIXED && !Z3>
+// The backward is one pass over the ordered vertices: vertex r + 1 is
+// rebuilt while vertex r, whose shoelace gradient needs both neighbours, is
+// routed; vertex 0 is routed last.  The routing is linear in the upstream
+// gradient, so it accumulates the unscaled shoelace gradient and the IoU's
+// factor (which needs the intersection area, known only at the end) scales
+// the accumulators when they are read back.
+struct SlotGeom {
+  uint32_t oa, ob, oc, od;
+  float t, idn;
+};
+
+template <int K, bool FIXED, int BLOCK>
+__device__ __forceinline__ float2 rebuild_slot(uint32_t c, uint32_t n1S, uint32_t nqS,
+                                               const uint2* __restrict__ s_tab,
+                                               const float2* __restrict__ s_v, SlotGeom& sg) {
+  slot_offsets<K, FIXED, BLOCK>(c, n1S, nqS, s_tab, sg.oa, sg.ob, sg.oc, sg.od);
+  return slot_vertex(sg.oa, sg.ob, sg.oc, sg.od, s_v, sg.t, sg.idn);
+}
+
+template <int K, bool FIXED, bool Z3, int BLOCK>
 __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Poly<K>& Q, int n2,
                                               float g, int nx, const uint32_t (&codes)[K / 2],
                                               float lo1, float hi1, float lo2, float hi2,
@@ -576,6 +595,8 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
     lqy[k] = Q.y[k] - oy;
     s_v[k * BLOCK] = make_float2(lpx[k], lpy[k]);
     s_v[(K + k) * BLOCK] = make_float2(lqx[k], lqy[k]);
+    s_g[k * BLOCK] = make_float2(0.f, 0.f);
+    s_g[(K + k) * BLOCK] = make_float2(0.f, 0.f);
   }
   // polygon areas (about vertex 0 of each)
   float s1 = 0.f, s2 = 0.f;
@@ -587,38 +608,37 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   }
   const float a1 = 0.5f * s1, a2 = 0.5f * s2;
 
-  // rebuild the intersection from the codes (padding codes name valid slots;
-  // their vertices are never used)
+  // ---- one pass: rebuild r + 1, route r (padding codes name valid slots;
+  // vertices past nx are never used)
   const int m = min(nx, CAP);
   constexpr uint32_t S = BLOCK * sizeof(float2);
   const uint32_t n1S = (uint32_t)n1 * S, nqS = (uint32_t)(K + n2) * S;
-  // KEEP_OFFSETS: the caller has the registers to keep each slot's offsets
-  // (packed) for the routing pass (the 2D fixed-size pairs kernel does);
-  // otherwise the routing pass decodes the code again.
-  float X[CAP], Y[CAP], T[CAP], IDN[CAP];
-  uint32_t OAB[CAP], OCD[CAP];
+  auto code_at = [&](int r) { return (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu; };
+  SlotGeom g0, gc, gn;
+  const float2 X0 = rebuild_slot<K, FIXED, BLOCK>(code_at(0), n1S, nqS, s_tab, s_v, g0);
+  const float2 X1 = rebuild_slot<K, FIXED, BLOCK>(code_at(1), n1S, nqS, s_tab, s_v, gc);
+  gn = gc;
+  float2 prev = X0, cur = X1, last = X0;
+  float acc = 0.f;  // twice the intersection area, about X0
 #pragma unroll
-  for (int r = 0; r < CAP; ++r) {
-    const uint32_t c = (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu;
-    uint32_t oa, ob, oc, od;
-    slot_offsets<K, FIXED, BLOCK>(c, n1S, nqS, s_tab, oa, ob, oc, od);
-    if (KEEP_OFFSETS) {
-      OAB[r] = oa | (ob << 16);
-      OCD[r] = oc | (od << 16);
+  for (int r = 1; r < CAP; ++r) {
+    if (r < m) {
+      float2 nxt = X0;
+      if (r + 1 < CAP && r + 1 < m) {
+        nxt = rebuild_slot<K, FIXED, BLOCK>(code_at(r + 1), n1S, nqS, s_tab, s_v, gn);
+        acc += (cur.x - X0.x) * (nxt.y - X0.y) - (cur.y - X0.y) * (nxt.x - X0.x);
+      }
+      // d(2I)/dX_r = (y_r+1 - y_r-1, x_r-1 - x_r+1)
+      route_slot(nxt.y - prev.y, prev.x - nxt.x, gc.t, gc.idn, gc.oa, gc.ob, gc.oc, gc.od, s_v,
+                 s_g);
+      last = cur;
+      prev = cur;
+      cur = nxt;
+      gc = gn;
     }
-    const float2 v = slot_vertex(oa, ob, oc, od, s_v, T[r], IDN[r]);
-    X[r] = v.x;
-    Y[r] = v.y;
-    __builtin_amdgcn_sched_barrier(0);
   }
-  // the routing pass reads the slots again rather than keeping every slot's
-  // edge vectors live across the passes
-  asm volatile("" ::: "memory");
-  float acc = 0.f;
-#pragma unroll
-  for (int r = 1; r + 1 < CAP; ++r) {
-    if (r + 1 < m) acc += (X[r] - X[0]) * (Y[r + 1] - Y[0]) - (Y[r] - Y[0]) * (X[r + 1] - X[0]);
-  }
+  if (m > 0) route_slot(X1.y - last.y, last.x - X1.x, g0.t, g0.idn, g0.oa, g0.ob, g0.oc, g0.od,
+                        s_v, s_g);
   const float inter = m >= 3 ? 0.5f * acc : 0.f;
 
   // scalar factors (zero where the IoU is constant: empty, non-positive union)
@@ -655,8 +675,9 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
     }
   }
 
-  // accumulators start with the polygon-area terms dA/dv = 0.5 (y+ - y-, x- - x+)
-  const float h1a = 0.5f * gA1, h2a = 0.5f * gA2;
+  // read back: dL/dv = gI / 2 * (routed shoelace terms) + gA * dA/dv, with
+  // dA/dv = (y+ - y-, x- - x+) / 2 over the polygon's own neighbours
+  const float hI = 0.5f * gI, h1a = 0.5f * gA1, h2a = 0.5f * gA2;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     float2 pn, pp, qn, qp;
@@ -673,61 +694,13 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
       qn = s_v[(K + kn2) * BLOCK];
       qp = s_v[(K + kp2) * BLOCK];
     }
-    const bool v1 = FIXED || k < n1, v2 = FIXED || k < n2;
-    s_g[k * BLOCK] = v1 ? make_float2(h1a * (pn.y - pp.y), h1a * (pp.x - pn.x)) : make_float2(0.f, 0.f);
-    s_g[(K + k) * BLOCK] =
-        v2 ? make_float2(h2a * (qn.y - qp.y), h2a * (qp.x - qn.x)) : make_float2(0.f, 0.f);
-  }
-
-  // shoelace gradient of the intersection, edge by edge: the term
-  // cross(X_r, X_r+1) gives (y_r+1, -x_r+1) to X_r and (-y_r, x_r) to X_r+1
-  float GX[CAP], GY[CAP];
-#pragma unroll
-  for (int r = 0; r < CAP; ++r) {
-    GX[r] = 0.f;
-    GY[r] = 0.f;
-  }
-#pragma unroll
-  for (int r = 0; r < CAP; ++r) {
-    if (r < m) {
-      const bool wrap = (r + 1 >= m);
-      const float xn = wrap ? X[0] : X[(r + 1) % CAP];
-      const float yn = wrap ? Y[0] : Y[(r + 1) % CAP];
-      GX[r] += yn;
-      GY[r] -= xn;
-      if (r + 1 < CAP) {
-        GX[r + 1] -= wrap ? 0.f : Y[r];
-        GY[r + 1] += wrap ? 0.f : X[r];
-      }
-      GX[0] -= wrap ? Y[r] : 0.f;
-      GY[0] += wrap ? X[r] : 0.f;
-    }
-  }
-  const float hI = 0.5f * gI;
-
-  // route every vertex's gradient to the slots it came from (route_slot)
-#pragma unroll
-  for (int r = 0; r < CAP; ++r) {
-    if (r < m) {
-      const float Gx = hI * GX[r], Gy = hI * GY[r];
-      uint32_t oa, ob, oc, od;
-      if (KEEP_OFFSETS) {
-        oa = OAB[r] & 0xffffu;
-        ob = OAB[r] >> 16;
-        oc = OCD[r] & 0xffffu;
-        od = OCD[r] >> 16;
-      } else {
-        const uint32_t c = (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu;
-        slot_offsets<K, FIXED, BLOCK>(c, n1S, nqS, s_tab, oa, ob, oc, od);
-      }
-      route_slot(Gx, Gy, T[r], IDN[r], oa, ob, oc, od, s_v, s_g);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    gP[k] = (FIXED || k < n1) ? s_g[k * BLOCK] : make_float2(0.f, 0.f);
-    gQ[k] = (FIXED || k < n2) ? s_g[(K + k) * BLOCK] : make_float2(0.f, 0.f);
+    const float2 tp = s_g[k * BLOCK], tq = s_g[(K + k) * BLOCK];
+    gP[k] = (FIXED || k < n1) ? make_float2(fmaf(hI, tp.x, h1a * (pn.y - pp.y)),
+                                            fmaf(hI, tp.y, h1a * (pp.x - pn.x)))
+                              : make_float2(0.f, 0.f);
+    gQ[k] = (FIXED || k < n2) ? make_float2(fmaf(hI, tq.x, h2a * (qn.y - qp.y)),
+                                            fmaf(hI, tq.y, h2a * (qp.x - qn.x)))
+                              : make_float2(0.f, 0.f);
   }
 }
 

@@ -589,7 +589,7 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
           hi2 = m.b.zhi[ib];
         }
         float2 gP[K], gQ[K], gz1, gz2;
-        pair_backward<K, FIXED, Z3, BLOCK, false>(P, n1, Q, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
+        pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
                                            s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2);
         float* acc = acc_w + rl * ROW;
 #pragma unroll
