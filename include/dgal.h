@@ -228,6 +228,24 @@ int dgal_area(dgal_ctx *ctx, dgal_polys p, float *area, void *stream);
 int dgal_area_backward(dgal_ctx *ctx, dgal_polys p, const float *grad_area,
                        float *grad_xy, void *stream);
 
+/* Launch-shape autotuning of the batched kernels (the grid of the pair
+ * kernels, the persistent grids of the matrix kernels).  While enabled, the
+ * first call of dgal_iou_pairs / dgal_iou_matrix / dgal_iou_backward on a new
+ * kind of input (entry point, vertex capacity 4 or 8, fixed-size or counted
+ * polygons, 2D or 3D, one block or segments) runs each candidate shape on
+ * the caller's own buffers (one warm-up and three timed runs, HIP events on
+ * the caller's stream) and keeps the fastest in the context for every later
+ * call of that kind, enabled or not.  That first call synchronises the stream
+ * (so it must not be captured in a graph) and creates two HIP events; its
+ * outputs are those of its last run, which every shape computes alike.
+ * Disabled by default: built-in shapes.  DGAL_EINVAL: ctx NULL. */
+int dgal_set_autotune(dgal_ctx *ctx, int32_t enable);
+
+/* Writes one line per tuned kind into buf (NUL-terminated, truncated to
+ * size) and returns the number of tuned kinds; DGAL_EINVAL for ctx NULL, a
+ * negative size, or buf NULL with size > 0. */
+int dgal_autotune_report(dgal_ctx *ctx, char *buf, int64_t size);
+
 /* Rotated boxes by their parameters (Sec. IV-A case study), the corners
  * formed in-kernel: corner k = (cx, cy) + R(yaw) (+-l/2, +-w/2),
  * counter-clockwise from (+l/2, -w/2), i.e. the length along the heading.

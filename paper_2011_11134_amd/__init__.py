@@ -48,7 +48,8 @@ class Boxes(ctypes.Structure):
 EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
            "dgal_iou_pairs", "dgal_iou_matrix", "dgal_iou_backward",
            "dgal_intersect", "dgal_intersect_backward", "dgal_area", "dgal_area_backward",
-           "dgal_iou_boxes", "dgal_iou_boxes_backward")
+           "dgal_iou_boxes", "dgal_iou_boxes_backward", "dgal_set_autotune",
+           "dgal_autotune_report")
 
 
 def _load():
@@ -85,6 +86,10 @@ def _load():
     L.dgal_iou_boxes.restype = ctypes.c_int
     L.dgal_iou_boxes_backward.argtypes = [_vp, Boxes, Boxes, _vp, _vp, _vp, _vp, _vp, _vp]
     L.dgal_iou_boxes_backward.restype = ctypes.c_int
+    L.dgal_set_autotune.argtypes = [_vp, i32]
+    L.dgal_set_autotune.restype = ctypes.c_int
+    L.dgal_autotune_report.argtypes = [_vp, ctypes.c_char_p, i64]
+    L.dgal_autotune_report.restype = ctypes.c_int
     return L
 
 
@@ -421,6 +426,22 @@ def iou_matrix_backward(grad, saved, seg, a_xy, b_xy=None, a_nv=None, b_nv=None,
                               _stream(a_xy)),
         "dgal_iou_backward(matrix)")
     return ga, gb, gaz, gbz
+
+
+def set_autotune(enable=True, device=None):
+    """Enables (or disables) launch-shape autotuning on a device's context:
+    the next call of each kind times its candidate grids once (synchronising)
+    and keeps the fastest."""
+    _ok(lib.dgal_set_autotune(context(device), int(bool(enable))), "dgal_set_autotune")
+
+
+def autotune_report(device=None):
+    """(number of tuned kinds, text with one line per kind)."""
+    buf = ctypes.create_string_buffer(8192)
+    n = lib.dgal_autotune_report(context(device), buf, len(buf))
+    if n < 0:
+        raise DgalError(n, "dgal_autotune_report")
+    return n, buf.value.decode()
 
 
 def check_errors(device=None):

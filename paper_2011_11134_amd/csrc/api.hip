@@ -1,11 +1,24 @@
 // api.hip -- the C ABI declared in include/dgal.h: argument validation on the
 // host, then kernel dispatch on the caller's stream.  No allocation per call.
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
 #include <new>
+#include <tuple>
+#include <vector>
 
 #include "internal.hpp"
 
+// A kind of call: (entry point, register capacity K, fixed size, 3D,
+// segmented) -> the launch shape the autotuner chose for it.
+using TuneKey = std::tuple<int, int, int, int, int>;
+enum { kTunePairsFwd, kTunePairsBwd, kTuneMatrixFwd, kTuneMatrixBwd };
+
 struct dgal_ctx {
   dgal::CtxView v;
+  bool tune = false;
+  std::map<TuneKey, dgal::LaunchShape> tuned;
 };
 
 namespace {
@@ -17,6 +30,76 @@ using dgal::reg_k;
 using dgal::valid_polys;
 
 int status_of(hipError_t e) { return e == hipSuccess ? DGAL_OK : DGAL_EHIP; }
+
+// Runs launch(shape) with the shape tuned for `key`; while tuning is enabled
+// and the kind is new, first times every candidate (one warm-up and three
+// timed runs each, HIP events on the caller's stream) and keeps the fastest.
+// The outputs are those of the last run: every shape computes the same values.
+template <class F>
+int run_tuned(dgal_ctx* ctx, const TuneKey& key, const std::vector<dgal::LaunchShape>& cands,
+              hipStream_t stream, F launch) {
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) return launch(it->second);
+  if (!ctx->tune) return launch(dgal::LaunchShape());
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return DGAL_EHIP;
+  }
+  int best = -1, st = DGAL_OK;
+  float best_ms = 0.f;
+  for (size_t c = 0; c < cands.size() && st == DGAL_OK; ++c) {
+    st = launch(cands[c]);
+    if (st != DGAL_OK) break;
+    if (hipEventRecord(e0, stream) != hipSuccess) st = DGAL_EHIP;
+    for (int r = 0; r < 3 && st == DGAL_OK; ++r) st = launch(cands[c]);
+    float ms = 0.f;
+    if (st == DGAL_OK && (hipEventRecord(e1, stream) != hipSuccess ||
+                          hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = DGAL_EHIP;
+    if (st == DGAL_OK && (best < 0 || ms < best_ms)) {
+      best = (int)c;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == DGAL_OK && best >= 0) ctx->tuned[key] = cands[best];
+  return st;
+}
+
+std::vector<dgal::LaunchShape> pair_grids(int cus) {
+  std::vector<dgal::LaunchShape> v;
+  for (int64_t m : {0, 2, 4, 8, 16}) {
+    dgal::LaunchShape s;
+    s.grid = (int64_t)cus * m;
+    v.push_back(s);
+  }
+  return v;
+}
+
+std::vector<dgal::LaunchShape> matrix_fwd_shapes() {
+  std::vector<dgal::LaunchShape> v;
+  for (int c : {8, 16, 32})
+    for (int e : {4, 8, 16}) {
+      dgal::LaunchShape s;
+      s.cull_mult = c;
+      s.exact_mult = e;
+      v.push_back(s);
+    }
+  return v;
+}
+
+std::vector<dgal::LaunchShape> matrix_bwd_shapes() {
+  std::vector<dgal::LaunchShape> v;
+  for (int b : {4, 8, 16}) {
+    dgal::LaunchShape s;
+    s.bwd_mult = b;
+    v.push_back(s);
+  }
+  return v;
+}
 
 }  // namespace
 
@@ -116,8 +199,12 @@ int dgal_iou_pairs(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* iou, uint8_
   // the fixed-size kernels also assume vector-aligned rows of coordinates and codes
   const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
                      args.a.vec4 && args.b.vec4 && (nx == nullptr || args.flags_vec);
-  return status_of(dgal::launch_pairs_fwd(args, K, fixed, a.zlo != nullptr, nx != nullptr,
-                                          static_cast<hipStream_t>(stream)));
+  const bool z3 = a.zlo != nullptr, save = nx != nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return run_tuned(ctx, TuneKey(kTunePairsFwd, K, fixed, z3, save), pair_grids(ctx->v.cus), s,
+                   [&](const dgal::LaunchShape& sh) {
+                     return status_of(dgal::launch_pairs_fwd(args, K, fixed, z3, save, s, sh));
+                   });
 }
 
 int dgal_iou_backward(dgal_ctx* ctx, int32_t mode, dgal_polys a, dgal_polys b,
@@ -165,12 +252,21 @@ int dgal_iou_backward(dgal_ctx* ctx, int32_t mode, dgal_polys a, dgal_polys b,
     args.gb_z = grad_b_z;
     const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
                        args.a.vec4 && args.b.vec4 && args.flags_vec;
-    return status_of(dgal::launch_pairs_bwd(args, K, fixed, z3, static_cast<hipStream_t>(stream)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return run_tuned(ctx, TuneKey(kTunePairsBwd, K, fixed, z3, 0), pair_grids(ctx->v.cus), s,
+                     [&](const dgal::LaunchShape& sh) {
+                       return status_of(dgal::launch_pairs_bwd(args, K, fixed, z3, s, sh));
+                     });
   }
   if (mode == DGAL_MATRIX) {
-    return dgal::matrix_backward(ctx->v, a, b, a_off, b_off, out_off, nseg,
-                                 self_pairs, grad_iou, out_size, saved, grad_a_xy, grad_b_xy,
-                                 grad_a_z, grad_b_z, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const TuneKey key(kTuneMatrixBwd, reg_k(a.kmax, b.kmax), a.nv == nullptr && b.nv == nullptr,
+                      z3, a_off != nullptr);
+    return run_tuned(ctx, key, matrix_bwd_shapes(), s, [&](const dgal::LaunchShape& sh) {
+      return dgal::matrix_backward(ctx->v, a, b, a_off, b_off, out_off, nseg, self_pairs,
+                                   grad_iou, out_size, saved, grad_a_xy, grad_b_xy, grad_a_z,
+                                   grad_b_z, s, sh);
+    });
   }
   return DGAL_EINVAL;
 }
@@ -180,8 +276,13 @@ int dgal_iou_matrix(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const int64_t* a_
                     int32_t self_pairs, float* iou, int64_t out_size, const dgal_saved* saved,
                     void* stream) {
   if (ctx == nullptr) return DGAL_EINVAL;
-  return dgal::matrix_forward(ctx->v, a, b, a_off, b_off, out_off, nseg, self_pairs,
-                              iou, out_size, saved, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const TuneKey key(kTuneMatrixFwd, reg_k(a.kmax, b.kmax), a.nv == nullptr && b.nv == nullptr,
+                    a.zlo != nullptr, a_off != nullptr);
+  return run_tuned(ctx, key, matrix_fwd_shapes(), s, [&](const dgal::LaunchShape& sh) {
+    return dgal::matrix_forward(ctx->v, a, b, a_off, b_off, out_off, nseg, self_pairs, iou,
+                                out_size, saved, s, sh);
+  });
 }
 
 int dgal_intersect(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* out_xy, uint8_t* nx,
@@ -277,6 +378,34 @@ bool valid_boxes(const dgal_boxes& a, const dgal_boxes& b) {
 }  // namespace
 
 extern "C" {
+
+int dgal_set_autotune(dgal_ctx* ctx, int32_t enable) {
+  if (ctx == nullptr) return DGAL_EINVAL;
+  ctx->tune = enable != 0;
+  return DGAL_OK;
+}
+
+int dgal_autotune_report(dgal_ctx* ctx, char* buf, int64_t size) {
+  if (ctx == nullptr || (buf == nullptr && size > 0) || size < 0) return DGAL_EINVAL;
+  static const char* names[] = {"pairs_fwd", "pairs_bwd", "matrix_fwd", "matrix_bwd"};
+  int64_t used = 0;
+  if (size > 0) buf[0] = '\0';
+  for (const auto& kv : ctx->tuned) {
+    const TuneKey& k = kv.first;
+    const dgal::LaunchShape& sh = kv.second;
+    char line[160];
+    const int n = snprintf(line, sizeof(line),
+                           "%s K=%d fixed=%d z3=%d seg/save=%d: grid=%lld cull=%d exact=%d bwd=%d\n",
+                           names[std::get<0>(k)], std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                           std::get<4>(k), (long long)sh.grid, sh.cull_mult, sh.exact_mult,
+                           sh.bwd_mult);
+    if (n > 0 && used + n < size) {
+      memcpy(buf + used, line, (size_t)n + 1);
+      used += n;
+    }
+  }
+  return (int)ctx->tuned.size();
+}
 
 int dgal_iou_boxes(dgal_ctx* ctx, dgal_boxes a, dgal_boxes b, float* iou, uint8_t* nx,
                    uint8_t* xflags, void* stream) {

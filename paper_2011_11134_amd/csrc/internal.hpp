@@ -85,6 +85,14 @@ struct BoxesBwdArgs {
   float* gb;
 };
 
+// Grid shapes of one call, chosen by the autotuner (0 = built-in default).
+// grid: workgroups of a grid-stride elementwise kernel (0 => one lane per
+// item); the matrix multipliers scale the persistent grids by the CU count.
+struct LaunchShape {
+  int64_t grid = 0;
+  int cull_mult = 0, exact_mult = 0, bwd_mult = 0;
+};
+
 // What the kernels need from a context.
 struct CtxView {
   int device;
@@ -147,18 +155,19 @@ struct DeviceGuard {
 
 int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
                    const int64_t* b_off, const int64_t* out_off, int nseg, int self_pairs,
-                   float* iou, int64_t out_size, const dgal_saved* saved, hipStream_t stream);
+                   float* iou, int64_t out_size, const dgal_saved* saved, hipStream_t stream,
+                   const LaunchShape& shape = LaunchShape());
 int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
                     const int64_t* b_off, const int64_t* out_off, int nseg, int self_pairs,
                     const float* grad_iou, int64_t out_size, const dgal_saved* saved,
                     float* grad_a_xy, float* grad_b_xy, float* grad_a_z, float* grad_b_z,
-                    hipStream_t stream);
+                    hipStream_t stream, const LaunchShape& shape = LaunchShape());
 
 // Launchers (return a hipError_t from the launch).
 hipError_t launch_pairs_fwd(const PairsFwdArgs& args, int K, bool fixed, bool z3, bool save,
-                            hipStream_t stream);
+                            hipStream_t stream, const LaunchShape& shape = LaunchShape());
 hipError_t launch_pairs_bwd(const PairsBwdArgs& args, int K, bool fixed, bool z3,
-                            hipStream_t stream);
+                            hipStream_t stream, const LaunchShape& shape = LaunchShape());
 hipError_t launch_intersect_fwd(const IntersectArgs& args, int K, bool fixed, hipStream_t stream);
 hipError_t launch_intersect_bwd(const IntersectBwdArgs& args, int K, bool fixed,
                                 hipStream_t stream);

@@ -702,7 +702,8 @@ int64_t ceil_div(int64_t x, int64_t y) { return (x + y - 1) / y; }
 
 int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
                    const int64_t* b_off, const int64_t* out_off, int nseg, int self_pairs,
-                   float* iou, int64_t out_size, const dgal_saved* saved, hipStream_t stream) {
+                   float* iou, int64_t out_size, const dgal_saved* saved, hipStream_t stream,
+                   const LaunchShape& shape) {
   SegArgs sa;
   const int st = check_shapes(a, b, a_off, b_off, out_off, nseg, self_pairs, out_size, saved, sa);
   if (st != DGAL_OK) return st;
@@ -745,9 +746,9 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
   x.count = saved->count;
   x.cap = a.kmax + b.kmax;
   x.err = ctx.err;
-  int64_t cull_grid = (int64_t)ctx.cus * 16;
+  int64_t cull_grid = (int64_t)ctx.cus * (shape.cull_mult > 0 ? shape.cull_mult : 16);
   if (!segmented) cull_grid = std::min(cull_grid, ceil_div(single_tiles, kCullBlock / 64));
-  const int exact_grid = ctx.cus * 8;
+  const int exact_grid = ctx.cus * (shape.exact_mult > 0 ? shape.exact_mult : 8);
   const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
                      aligned(a.xy, 16) && aligned(b.xy, 16);
   dispatch(K, fixed, a.zlo != nullptr, [&](auto k, auto fx, auto z) {
@@ -775,7 +776,7 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
                     const int64_t* b_off, const int64_t* out_off, int nseg, int self_pairs,
                     const float* grad_iou, int64_t out_size, const dgal_saved* saved,
                     float* grad_a_xy, float* grad_b_xy, float* grad_a_z, float* grad_b_z,
-                    hipStream_t stream) {
+                    hipStream_t stream, const LaunchShape& shape) {
   SegArgs sa;
   const int st = check_shapes(a, b, a_off, b_off, out_off, nseg, self_pairs, out_size, saved, sa);
   if (st != DGAL_OK) return st;
@@ -830,7 +831,7 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
   dispatch(K, fixed, z3, [&](auto k, auto fx, auto z) {
     constexpr int KK = decltype(k)::value;
     constexpr bool FX = decltype(fx)::value, ZZ = decltype(z)::value;
-    int64_t grid = (int64_t)ctx.cus * 8;
+    int64_t grid = (int64_t)ctx.cus * (shape.bwd_mult > 0 ? shape.bwd_mult : 8);
     if (!segmented) grid = std::min(grid, ceil_div(single_groups, bwd_block<KK>() / 64));
     hipLaunchKernelGGL((k_matrix_bwd<KK, FX, ZZ>), dim3((unsigned)grid), dim3(bwd_block<KK>()), 0,
                        stream, m);

@@ -137,51 +137,57 @@ __global__ __launch_bounds__(pairs_block<K>()) void k_pairs_bwd(PairsBwdArgs arg
 
 namespace {
 
-int grid_for(int64_t n, int block) {
+int grid_for(int64_t n, int block, int64_t want = 0) {
   int64_t blocks = (n + block - 1) / block;
+  if (want > 0 && want < blocks) blocks = want;  // persistent grid-stride launch
   const int64_t cap = 1 << 20;  // grid-stride beyond this
   return (int)(blocks < 1 ? 1 : (blocks > cap ? cap : blocks));
 }
 
 template <int K, bool FIXED, bool Z3>
-hipError_t fwd3(const PairsFwdArgs& a, bool save, hipStream_t s) {
+hipError_t fwd3(const PairsFwdArgs& a, bool save, hipStream_t s, int64_t g) {
   constexpr int B = pairs_block<K>();
+  const dim3 grid(grid_for(a.a.count, B, g));
   if (save)
-    hipLaunchKernelGGL((k_pairs_fwd<K, FIXED, Z3, true>), dim3(grid_for(a.a.count, B)), dim3(B), 0, s, a);
+    hipLaunchKernelGGL((k_pairs_fwd<K, FIXED, Z3, true>), grid, dim3(B), 0, s, a);
   else
-    hipLaunchKernelGGL((k_pairs_fwd<K, FIXED, Z3, false>), dim3(grid_for(a.a.count, B)), dim3(B), 0, s, a);
+    hipLaunchKernelGGL((k_pairs_fwd<K, FIXED, Z3, false>), grid, dim3(B), 0, s, a);
   return hipGetLastError();
 }
 
 template <int K, bool FIXED>
-hipError_t fwd2(const PairsFwdArgs& a, bool z3, bool save, hipStream_t s) {
-  return z3 ? fwd3<K, FIXED, true>(a, save, s) : fwd3<K, FIXED, false>(a, save, s);
+hipError_t fwd2(const PairsFwdArgs& a, bool z3, bool save, hipStream_t s, int64_t g) {
+  return z3 ? fwd3<K, FIXED, true>(a, save, s, g) : fwd3<K, FIXED, false>(a, save, s, g);
 }
 
 template <int K, bool FIXED, bool Z3>
-hipError_t bwd3(const PairsBwdArgs& a, hipStream_t s) {
+hipError_t bwd3(const PairsBwdArgs& a, hipStream_t s, int64_t g) {
   constexpr int B = pairs_block<K>();
-  hipLaunchKernelGGL((k_pairs_bwd<K, FIXED, Z3>), dim3(grid_for(a.a.count, B)), dim3(B), 0, s, a);
+  hipLaunchKernelGGL((k_pairs_bwd<K, FIXED, Z3>), dim3(grid_for(a.a.count, B, g)), dim3(B), 0, s,
+                     a);
   return hipGetLastError();
 }
 
 template <int K, bool FIXED>
-hipError_t bwd2(const PairsBwdArgs& a, bool z3, hipStream_t s) {
-  return z3 ? bwd3<K, FIXED, true>(a, s) : bwd3<K, FIXED, false>(a, s);
+hipError_t bwd2(const PairsBwdArgs& a, bool z3, hipStream_t s, int64_t g) {
+  return z3 ? bwd3<K, FIXED, true>(a, s, g) : bwd3<K, FIXED, false>(a, s, g);
 }
 
 }  // namespace
 
 hipError_t launch_pairs_fwd(const PairsFwdArgs& args, int K, bool fixed, bool z3, bool save,
-                            hipStream_t stream) {
-  if (K == 4) return fixed ? fwd2<4, true>(args, z3, save, stream) : fwd2<4, false>(args, z3, save, stream);
-  return fixed ? fwd2<8, true>(args, z3, save, stream) : fwd2<8, false>(args, z3, save, stream);
+                            hipStream_t stream, const LaunchShape& shape) {
+  const int64_t g = shape.grid;
+  if (K == 4)
+    return fixed ? fwd2<4, true>(args, z3, save, stream, g) : fwd2<4, false>(args, z3, save, stream, g);
+  return fixed ? fwd2<8, true>(args, z3, save, stream, g) : fwd2<8, false>(args, z3, save, stream, g);
 }
 
 hipError_t launch_pairs_bwd(const PairsBwdArgs& args, int K, bool fixed, bool z3,
-                            hipStream_t stream) {
-  if (K == 4) return fixed ? bwd2<4, true>(args, z3, stream) : bwd2<4, false>(args, z3, stream);
-  return fixed ? bwd2<8, true>(args, z3, stream) : bwd2<8, false>(args, z3, stream);
+                            hipStream_t stream, const LaunchShape& shape) {
+  const int64_t g = shape.grid;
+  if (K == 4) return fixed ? bwd2<4, true>(args, z3, stream, g) : bwd2<4, false>(args, z3, stream, g);
+  return fixed ? bwd2<8, true>(args, z3, stream, g) : bwd2<8, false>(args, z3, stream, g);
 }
 
 }  // namespace dgal
