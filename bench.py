@@ -58,6 +58,9 @@ def parse():
     p.add_argument("--no-plain", action="store_true", help="skip the plain per-op GPU form")
     p.add_argument("--copy-calib-mib", type=int, default=0,
                    help="also run a plain device copy of this size (HBM counter calibration)")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the built-in launch shapes (default: the library's autotuner "
+                        "picks them during the warm-up)")
     p.add_argument("--graph", action="store_true",
                    help="replay a captured HIP graph of the step instead of eager launches")
     return p.parse_args()
@@ -301,12 +304,18 @@ def main():
     has_bwd = getattr(step, "has_bwd", True)
     stream = torch.cuda.current_stream().cuda_stream
 
-    for _ in range(args.warmup):
+    # warm-up; with the autotuner on, the first forward and backward time their
+    # candidate launch shapes here (synchronising) and keep the fastest
+    if not args.no_autotune:
+        dg.set_autotune(True)
+    for _ in range(max(1, args.warmup)):
         step.fwd(stream)
         if has_bwd:
             step.bwd(stream)
     torch.cuda.synchronize()
+    dg.set_autotune(False)
     dg.check_errors()
+    tuned = dg.autotune_report()[1].strip().splitlines()
 
     # --graph: the forward and the backward of one step are captured once into
     # a HIP graph (the library allocates nothing per call and needs no host
@@ -414,7 +423,8 @@ def main():
         "config": {"workload": names[wl], "pairs": int(step.pairs),
                    ("box_dim" if step.kind == "box" else "kmax"): int(step.a.shape[1]),
                    "parallelism": "single GPU",
-                   "launch": "HIP graph replay" if args.graph else "eager"},
+                   "launch": "HIP graph replay" if args.graph else "eager",
+                   "launch_shapes": tuned or "built-in"},
         "kernels_ms": {k: round(v, 4) for k, v in kernels.items()},
         "step_ms_events": round(step_ms_events, 4),
         "roofline": roof,

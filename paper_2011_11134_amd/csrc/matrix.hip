@@ -198,13 +198,49 @@ struct CullArgs {
   int* err;
 };
 
+// Segment s without the checks of load_segment: the tile walk only reaches
+// segments that k_seg_prep accepted.
+__device__ __forceinline__ Segment tile_segment(const SegArgs& a, int s) {
+  Segment g;
+  if (a.a_off == nullptr) {
+    g.a0 = 0;
+    g.b0 = 0;
+    g.na = a.a_count;
+    g.nb = a.b_count;
+    g.out0 = 0;
+  } else {
+    g.a0 = a.a_off[s];
+    g.b0 = a.b_off[s];
+    g.na = a.a_off[s + 1] - g.a0;
+    g.nb = a.b_off[s + 1] - g.b0;
+    g.out0 = a.out_off[s];
+  }
+  g.ok = true;
+  return g;
+}
+
+// Sign bit of the difference hi - lo: set when lo > hi, clear when they are
+// equal (the closed test keeps touching boxes).
+__device__ __forceinline__ uint32_t gap_bits(float hi, float lo) {
+  return __float_as_uint(hi - lo);
+}
+// The same for the open test: an exact +0 difference (touching extents) also
+// sets the sign bit (0 - 1 wraps to all ones).
+__device__ __forceinline__ uint32_t open_gap_bits(float hi, float lo) {
+  return __float_as_uint(hi - lo) - 1u;
+}
+
 // FILL == false: write every pair of the tile (0 for the culled ones, which
 // stays, or 1 on the self diagonal; the exact kernel later overwrites the
 // survivors) and count the survivors of every tile; FILL == true: write the
 // survivors' output indices into their tile's range of the work list (the
 // same decisions, in the same order).  The tile walk is wave-uniform, so its
-// indices, the segment and the rows' bounds live in scalar registers and
-// every output row segment is addressed from a scalar base.
+// indices, the segment and the rows' bounds live in scalar registers.  The
+// test of a (row, column) pair is one OR of the sign bits of its four (2D) or
+// six (3D) bound differences, so that the vector unit does the work and the
+// scalar unit only counts: overlapping closed boxes (touching ones go to the
+// exact kernel) with overlapping open z extents survive; invalid columns and
+// rows, and empty z extents, carry x1 = -inf.
 template <int K, bool FIXED, bool Z3, bool FILL>
 __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
   constexpr int WAVES = kCullBlock / 64;
@@ -217,11 +253,10 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
   for (int64_t u = (int64_t)blockIdx.x * WAVES + wave; u < total; u += (int64_t)gridDim.x * WAVES) {
     const int s = segmented ? find_segment(m.seg.tile_prefix, m.seg.nseg, u) : 0;
     const int64_t lu = segmented ? u - m.seg.tile_prefix[s] : u;
-    const Segment g = load_segment(m.seg, s);
-    if (!g.ok) continue;  // unreachable: rejected segments own no tiles
+    const Segment g = tile_segment(m.seg, s);
     const int64_t nct = col_tiles_of(g);
     int64_t tr, tc;
-    if (lu < (int64_t)0xffffffff) {
+    if (lu < (int64_t)0xffffffff && nct < (int64_t)0xffffffff) {
       const uint32_t q = (uint32_t)lu / (uint32_t)nct;
       tr = q;
       tc = lu - (int64_t)q * nct;
@@ -239,11 +274,10 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
       base = m.tile_start[u];
     }
 
-    // row bounds: lane j < nr bounds row j, then every lane holds all of
-    // them; a row whose z-extent is empty meets nothing
+    // row bounds: lane j < nr bounds row j, then every lane holds all of them
     Bounds rl = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
     if (lane < nr) rl = box_bounds<K, FIXED, Z3>(m.a, g.a0 + r0 + lane);
-    if (lane >= nr || (Z3 && !(rl.hi > rl.lo))) rl.x1 = -__builtin_inff();  // meets no column
+    if (lane >= nr || (Z3 && !(rl.hi > rl.lo))) rl.x1 = -__builtin_inff();
     Bounds rb[kTileRows];
 #pragma unroll
     for (int j = 0; j < kTileRows; ++j) {
@@ -254,35 +288,53 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
       rb[j].lo = lane_bcast(rl.lo, j);
       rb[j].hi = lane_bcast(rl.hi, j);
     }
-    int64_t n = 0;  // survivors so far (uniform)
+    uint32_t n = 0;  // survivors so far (uniform; at most kTileRows * kTileCols)
     // the next 64 column boxes are loaded while the current ones are tested
     Bounds nxt = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
     if (cb + lane < ce) nxt = box_bounds<K, FIXED, Z3>(m.b, g.b0 + cb + lane);
     for (int64_t c0 = cb; c0 < ce; c0 += 64) {
       const bool valid = c0 + lane < ce;
-      const Bounds cbx = nxt;
+      Bounds cbx = nxt;
       if (c0 + 64 + lane < ce) nxt = box_bounds<K, FIXED, Z3>(m.b, g.b0 + c0 + 64 + lane);
-      const bool cok = valid && (!Z3 || cbx.hi > cbx.lo);
-      float* out_c = out_rows + c0;
+      if (!valid || (Z3 && !(cbx.hi > cbx.lo))) cbx.x1 = -__builtin_inff();
       // the self diagonal crosses this chunk at lane r0 + j - c0
       const int64_t dd = r0 - c0;
       const bool dchunk = m.seg.self_pairs && dd > -kTileRows && dd < 64;
-      const int d0 = (int)(dchunk ? dd : -kTileRows - 64);
+      uint64_t mk[kTileRows];
 #pragma unroll
       for (int j = 0; j < kTileRows; ++j) {
-        // closed bounds overlap (touching pairs go to the exact test), open z
-        // extents overlap, not the diagonal of a self block
-        const bool diag = lane == d0 + j;
-        bool keep = cok && cbx.x0 <= rb[j].x1 && rb[j].x0 <= cbx.x1 && cbx.y0 <= rb[j].y1 &&
-                    rb[j].y0 <= cbx.y1 && !diag;
-        if (Z3) keep = keep && cbx.lo < rb[j].hi && rb[j].lo < cbx.hi;
-        if (!FILL && valid && j < nr) out_c[(int64_t)j * g.nb + lane] = diag ? 1.f : 0.f;
-        const uint64_t mk = __ballot(keep);
-        if (FILL && keep) {
-          const int64_t slot = base + n + __popcll(mk & below);
-          if (slot < m.capacity) m.pair_id[slot] = g.out0 + (r0 + j) * g.nb + c0 + lane;
+        uint32_t bits = gap_bits(rb[j].x1, cbx.x0) | gap_bits(cbx.x1, rb[j].x0) |
+                        gap_bits(rb[j].y1, cbx.y0) | gap_bits(cbx.y1, rb[j].y0);
+        if (Z3) bits |= open_gap_bits(rb[j].hi, cbx.lo) | open_gap_bits(cbx.hi, rb[j].lo);
+        mk[j] = __ballot((int32_t)bits >= 0);
+      }
+      if (dchunk) {  // rare: the chunk holds part of the diagonal
+        const int d = (int)dd;
+#pragma unroll
+        for (int j = 0; j < kTileRows; ++j)
+          if (d + j >= 0 && d + j < 64) mk[j] &= ~(1ull << (d + j));
+      }
+      if (!FILL && valid) {
+        float* out_c = out_rows + c0 + lane;
+        if (!dchunk) {
+#pragma unroll
+          for (int j = 0; j < kTileRows; ++j)
+            if (j < nr) out_c[(int64_t)j * g.nb] = 0.f;
+        } else {
+#pragma unroll
+          for (int j = 0; j < kTileRows; ++j)
+            if (j < nr) out_c[(int64_t)j * g.nb] = (lane == (int)dd + j) ? 1.f : 0.f;
         }
-        n += __popcll(mk);
+      }
+#pragma unroll
+      for (int j = 0; j < kTileRows; ++j) {
+        if (FILL && mk[j] != 0ull) {
+          if ((mk[j] >> lane) & 1ull) {
+            const int64_t slot = base + n + __popcll(mk[j] & below);
+            if (slot < m.capacity) m.pair_id[slot] = g.out0 + (r0 + j) * g.nb + c0 + lane;
+          }
+        }
+        n += (uint32_t)__popcll(mk[j]);
       }
     }
     if (!FILL && lane == 0) {
