@@ -120,6 +120,8 @@ int dgal_iou_pairs(dgal_ctx *ctx, dgal_polys a, dgal_polys b, float *iou,
  * ceil(cols / 256) tiles per segment with both sides non-empty).  All pointers
  * are device memory; the forward overwrites everything, including *count.
  * Entries are laid out tile by tile, in a fixed order. */
+#define DGAL_TILE_MASK_WORDS (DGAL_TILE_ROWS * DGAL_TILE_COLS / 64 + 2)
+
 typedef struct {
   int64_t *pair_id;       /* [capacity] index into the flat iou output               */
   uint8_t *nx;            /* [capacity]                                               */
@@ -130,6 +132,11 @@ typedef struct {
   int64_t *tile_start;    /* [tile_capacity] first entry of each tile                 */
   int32_t *tile_count;    /* [tile_capacity] entries of each tile                     */
   int64_t tile_capacity;  /* >= number of tiles, else DGAL_ECAPACITY (deferred)       */
+  uint64_t *tile_mask;    /* [tile_capacity][DGAL_TILE_MASK_WORDS] per tile, written by
+                             the forward: words 0..31 the survivor bits (word
+                             c * DGAL_TILE_ROWS + r: row r, columns 64c .. 64c + 63
+                             of the tile), word 32 the output index of the tile's
+                             first element, word 33 its block's row length      */
 } dgal_saved;
 
 /* Most segments one matrix call may hold. */

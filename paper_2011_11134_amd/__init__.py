@@ -23,6 +23,7 @@ DGAL_OK, DGAL_EINVAL, DGAL_ECAPACITY, DGAL_EHIP = 0, -1, -2, -3
 DGAL_PAIRS, DGAL_MATRIX = 0, 1
 MAX_SEGMENTS = 4096
 TILE_ROWS, TILE_COLS = 8, 256
+TILE_MASK_WORDS = TILE_ROWS * TILE_COLS // 64 + 2  # survivor bits, tile origin, row length
 
 _vp = ctypes.c_void_p
 
@@ -37,7 +38,8 @@ class Saved(ctypes.Structure):
     """dgal_saved"""
     _fields_ = [("pair_id", _vp), ("nx", _vp), ("xflags", _vp),
                 ("capacity", ctypes.c_int64), ("count", _vp),
-                ("tile_start", _vp), ("tile_count", _vp), ("tile_capacity", ctypes.c_int64)]
+                ("tile_start", _vp), ("tile_count", _vp), ("tile_capacity", ctypes.c_int64),
+                ("tile_mask", _vp)]
 
 
 class Boxes(ctypes.Structure):
@@ -329,12 +331,15 @@ class SavedPairs:
         self.count = torch.empty(1, dtype=torch.int64, device=device)
         self.tile_start = torch.empty(max(tiles, 1), dtype=torch.int64, device=device)
         self.tile_count = torch.empty(max(tiles, 1), dtype=torch.int32, device=device)
+        self.tile_mask = torch.empty((max(tiles, 1), TILE_MASK_WORDS), dtype=torch.int64,
+                                     device=device)
         self.capacity = capacity
         self.tiles = tiles
 
     def struct(self):
         return Saved(_ptr(self.pair_id), _ptr(self.nx), _ptr(self.xflags), self.capacity,
-                     _ptr(self.count), _ptr(self.tile_start), _ptr(self.tile_count), self.tiles)
+                     _ptr(self.count), _ptr(self.tile_start), _ptr(self.tile_count), self.tiles,
+                     _ptr(self.tile_mask))
 
 
 def segments(n_a, n_b, a_off, b_off=None, self_pairs=False, device=None):

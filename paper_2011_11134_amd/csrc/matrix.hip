@@ -4,17 +4,16 @@
 //
 // The forward is split by register pressure into lean cull kernels and one
 // dense exact kernel, with no shared counter anywhere:
-//   k_matrix_cull<FILL = false> -- one wavefront per tile of kTileRows rows x
-//     kTileCols columns of one segment.  The rows' axis-aligned bounds (and
-//     z-extents) sit in scalar registers; each lane bounds its column boxes 64
-//     at a time, tests them against the rows, writes every pair's initial
-//     value (0, or the self diagonal's 1) straight to the output row segments
-//     (coalesced) and counts the survivors into the tile table.
+//   k_matrix_cull -- one wavefront per tile of kTileRows rows x kTileCols
+//     columns of one segment.  The rows' axis-aligned bounds (and z-extents)
+//     sit in scalar registers; each lane bounds its column boxes 64 at a
+//     time, tests them against the rows, writes every pair's initial value
+//     (0, or the self diagonal's 1) straight to the output row segments
+//     (coalesced), and records the tile's survivor mask and count.
 //   k_scan_totals, k_scan_apply -- exclusive prefix of the tile counts in two
 //     parallel passes, so the work list is laid out tile by tile,
 //     deterministically.
-//   k_matrix_cull<FILL = true> -- the same cull again; survivors go to their
-//     tile's range.
+//   k_matrix_fill -- reads the masks; survivors go to their tile's range.
 //   k_matrix_exact -- one lane per survivor with every lane busy: the exact
 //     pair forward, the IoU written to its place in the output, nx / xflags
 //     kept in the work list for the backward.
@@ -28,6 +27,7 @@
 // atomics.
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "geom.hpp"
 #include "internal.hpp"
@@ -40,7 +40,7 @@ constexpr int kCullBlock = 256;   // four independent wavefronts
 constexpr int kScanBlock = 1024;
 constexpr int kExactBlock = 256;
 constexpr int kMaxSeg = DGAL_MAX_SEGMENTS;
-static_assert(kTileCols % 64 == 0 && kTileCols <= 65536, "tile columns");
+static_assert(kTileCols == 256, "four 64-column chunks per tile");
 
 struct Segment {
   int64_t a0, b0, na, nb, out0;
@@ -195,8 +195,13 @@ struct CullArgs {
   int64_t* tile_start;
   int32_t* tile_count;
   int64_t tile_capacity;
+  uint64_t* tile_mask;  // [tile_capacity][kMaskWords]
   int* err;
 };
+
+constexpr int kBitWords = kTileRows * (kTileCols / 64);  // survivor bits of a tile
+constexpr int kMaskWords = DGAL_TILE_MASK_WORDS;            // + tile origin + row length
+static_assert(kMaskWords == kBitWords + 2 && kMaskWords <= 64, "mask words");
 
 // Segment s without the checks of load_segment: the tile walk only reaches
 // segments that k_seg_prep accepted.
@@ -224,60 +229,115 @@ __device__ __forceinline__ Segment tile_segment(const SegArgs& a, int s) {
 __device__ __forceinline__ uint32_t gap_bits(float hi, float lo) {
   return __float_as_uint(hi - lo);
 }
-// The same for the open test: an exact +0 difference (touching extents) also
-// sets the sign bit (0 - 1 wraps to all ones).
-__device__ __forceinline__ uint32_t open_gap_bits(float hi, float lo) {
-  return __float_as_uint(hi - lo) - 1u;
+template <int N, class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>()), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<N>(f, std::make_integer_sequence<int, N>());
 }
 
-// FILL == false: write every pair of the tile (0 for the culled ones, which
+// v_writelane: `val` (wave-uniform) into lane L (a constant) of `old`.
+template <int L>
+__device__ __forceinline__ uint32_t write_lane(uint32_t old, uint32_t val) {
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(old) : "s"(val), "n"(L));
+  return old;
+}
+
+// The largest float below v (finite v): lo < v <=> lo <= below(v), so the
+// open z test becomes the closed one on a lowered upper end.
+__device__ __forceinline__ float below(float v) {
+  const uint32_t b = __float_as_uint(v);
+  if ((b & 0x7fffffffu) == 0u) return -1.40129846e-45f;  // +-0 -> -denorm_min
+  return __uint_as_float((int32_t)b > 0 ? b - 1u : b + 1u);
+}
+
+// Walks a contiguous range of tiles: the segment is searched once, then
+// followed tile by tile (row-major within a segment, segments in order), so
+// that a tile costs no search and no division.
+struct TileCursor {
+  int s;
+  int64_t seg_end;  // first tile past segment s
+  Segment g;
+  int64_t nct, tr, tc;
+
+  __device__ void load(const SegArgs& seg, bool segmented) {
+    g = tile_segment(seg, s);
+    nct = col_tiles_of(g);
+    seg_end = segmented ? seg.tile_prefix[s + 1] : (int64_t)0x7fffffffffffffff;
+  }
+  __device__ void seek(const SegArgs& seg, bool segmented, int64_t u) {
+    s = segmented ? find_segment(seg.tile_prefix, seg.nseg, u) : 0;
+    load(seg, segmented);
+    const int64_t lu = segmented ? u - seg.tile_prefix[s] : u;
+    tr = lu / nct;
+    tc = lu - tr * nct;
+  }
+  // to tile u + 1 (u the current tile)
+  __device__ void next(const SegArgs& seg, bool segmented, int64_t u) {
+    if (++tc == nct) {
+      tc = 0;
+      ++tr;
+    }
+    if (u + 1 >= seg_end) {  // the next non-empty segment
+      do {
+        ++s;
+      } while (s < seg.nseg && seg.tile_prefix[s + 1] <= u + 1);
+      if (s < seg.nseg) {
+        load(seg, segmented);
+        tr = 0;
+        tc = 0;
+      }
+    }
+  }
+  __device__ int64_t r0() const { return tr * kTileRows; }
+  __device__ int64_t cb() const { return tc * kTileCols; }
+};
+
+// The contiguous range of tiles of wavefront `wid` out of `nw`.
+__device__ __forceinline__ void wave_tiles(int64_t total, int64_t wid, int64_t nw, int64_t& u0,
+                                           int64_t& u1) {
+  const int64_t per = (total + nw - 1) / nw;
+  u0 = wid * per;
+  u1 = u0 + per < total ? u0 + per : total;
+}
+
+// Count pass: writes every pair of the tile (0 for the culled ones, which
 // stays, or 1 on the self diagonal; the exact kernel later overwrites the
-// survivors) and count the survivors of every tile; FILL == true: write the
-// survivors' output indices into their tile's range of the work list (the
-// same decisions, in the same order).  The tile walk is wave-uniform, so its
-// indices, the segment and the rows' bounds live in scalar registers.  The
-// test of a (row, column) pair is one OR of the sign bits of its four (2D) or
-// six (3D) bound differences, so that the vector unit does the work and the
-// scalar unit only counts: overlapping closed boxes (touching ones go to the
-// exact kernel) with overlapping open z extents survive; invalid columns and
-// rows, and empty z extents, carry x1 = -inf.
-template <int K, bool FIXED, bool Z3, bool FILL>
+// survivors), the tile's survivor mask (kMaskWords words, chunk-major) and its
+// survivor count.  The tile walk is wave-uniform, so its indices, the segment
+// and the rows' bounds live in scalar registers.  The test of a (row, column)
+// pair is one OR of the sign bits of its four (2D) or six (3D) bound
+// differences, so that the vector unit does the work and the scalar unit only
+// counts: overlapping closed boxes (touching ones go to the exact kernel)
+// with overlapping open z extents (a closed test against upper ends lowered
+// by one ulp) survive; invalid columns and rows, and empty z extents, carry
+// x1 = -inf.
+template <int K, bool FIXED, bool Z3>
 __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
   constexpr int WAVES = kCullBlock / 64;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool segmented = m.seg.a_off != nullptr;
   const int64_t total = segmented ? m.seg.tile_prefix[m.seg.nseg] : m.single_tiles;
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  for (int64_t u = (int64_t)blockIdx.x * WAVES + wave; u < total; u += (int64_t)gridDim.x * WAVES) {
-    const int s = segmented ? find_segment(m.seg.tile_prefix, m.seg.nseg, u) : 0;
-    const int64_t lu = segmented ? u - m.seg.tile_prefix[s] : u;
-    const Segment g = tile_segment(m.seg, s);
-    const int64_t nct = col_tiles_of(g);
-    int64_t tr, tc;
-    if (lu < (int64_t)0xffffffff && nct < (int64_t)0xffffffff) {
-      const uint32_t q = (uint32_t)lu / (uint32_t)nct;
-      tr = q;
-      tc = lu - (int64_t)q * nct;
-    } else {
-      tr = lu / nct;
-      tc = lu - tr * nct;
-    }
-    const int64_t r0 = tr * kTileRows, cb = tc * kTileCols;
+  int64_t u0, u1;
+  wave_tiles(total, (int64_t)blockIdx.x * WAVES + wave, (int64_t)gridDim.x * WAVES, u0, u1);
+  TileCursor cur;
+  if (u0 < u1) cur.seek(m.seg, segmented, u0);
+  for (int64_t u = u0; u < u1; cur.next(m.seg, segmented, u), ++u) {
+    const Segment& g = cur.g;
+    const int64_t r0 = cur.r0(), cb = cur.cb();
     const int nr = (int)min((int64_t)kTileRows, g.na - r0);
     const int64_t ce = min(g.nb, cb + kTileCols);
     float* out_rows = m.iou + g.out0 + r0 * g.nb;
-    int64_t base = 0;
-    if (FILL) {
-      if (u >= m.tile_capacity) continue;
-      base = m.tile_start[u];
-    }
 
     // row bounds: lane j < nr bounds row j, then every lane holds all of them
     Bounds rl = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
     if (lane < nr) rl = box_bounds<K, FIXED, Z3>(m.a, g.a0 + r0 + lane);
     if (lane >= nr || (Z3 && !(rl.hi > rl.lo))) rl.x1 = -__builtin_inff();
+    if (Z3) rl.hi = below(rl.hi);
     Bounds rb[kTileRows];
 #pragma unroll
     for (int j = 0; j < kTileRows; ++j) {
@@ -288,15 +348,20 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
       rb[j].lo = lane_bcast(rl.lo, j);
       rb[j].hi = lane_bcast(rl.hi, j);
     }
-    uint32_t n = 0;  // survivors so far (uniform; at most kTileRows * kTileCols)
+    uint32_t n = 0;         // survivors so far (uniform; at most kTileRows * kTileCols)
+    uint32_t mlo = 0u, mhi = 0u;  // lane w < kBitWords: mask word w of the tile
     // the next 64 column boxes are loaded while the current ones are tested
     Bounds nxt = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
     if (cb + lane < ce) nxt = box_bounds<K, FIXED, Z3>(m.b, g.b0 + cb + lane);
-    for (int64_t c0 = cb; c0 < ce; c0 += 64) {
+#pragma unroll
+    for (int ci = 0; ci < kTileCols / 64; ++ci) {
+      const int64_t c0 = cb + ci * 64;
+      if (c0 >= ce) break;
       const bool valid = c0 + lane < ce;
       Bounds cbx = nxt;
       if (c0 + 64 + lane < ce) nxt = box_bounds<K, FIXED, Z3>(m.b, g.b0 + c0 + 64 + lane);
       if (!valid || (Z3 && !(cbx.hi > cbx.lo))) cbx.x1 = -__builtin_inff();
+      if (Z3) cbx.hi = below(cbx.hi);
       // the self diagonal crosses this chunk at lane r0 + j - c0
       const int64_t dd = r0 - c0;
       const bool dchunk = m.seg.self_pairs && dd > -kTileRows && dd < 64;
@@ -305,7 +370,7 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
       for (int j = 0; j < kTileRows; ++j) {
         uint32_t bits = gap_bits(rb[j].x1, cbx.x0) | gap_bits(cbx.x1, rb[j].x0) |
                         gap_bits(rb[j].y1, cbx.y0) | gap_bits(cbx.y1, rb[j].y0);
-        if (Z3) bits |= open_gap_bits(rb[j].hi, cbx.lo) | open_gap_bits(cbx.hi, rb[j].lo);
+        if (Z3) bits |= gap_bits(rb[j].hi, cbx.lo) | gap_bits(cbx.hi, rb[j].lo);
         mk[j] = __ballot((int32_t)bits >= 0);
       }
       if (dchunk) {  // rare: the chunk holds part of the diagonal
@@ -314,32 +379,94 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
         for (int j = 0; j < kTileRows; ++j)
           if (d + j >= 0 && d + j < 64) mk[j] &= ~(1ull << (d + j));
       }
-      if (!FILL && valid) {
-        float* out_c = out_rows + c0 + lane;
-        if (!dchunk) {
+      // word ci * kTileRows + j of the tile goes to that lane
+      auto put = [&](auto jc) {
+        constexpr int J = decltype(jc)::value;
+        mlo = write_lane<J>(mlo, (uint32_t)mk[J % kTileRows]);
+        mhi = write_lane<J>(mhi, (uint32_t)(mk[J % kTileRows] >> 32));
+        n += (uint32_t)__popcll(mk[J % kTileRows]);
+      };
+      static_for<kTileRows>([&](auto j) {
+        constexpr int J = decltype(j)::value;
+        if (ci == 0) put(std::integral_constant<int, 0 * kTileRows + J>());
+        if (ci == 1) put(std::integral_constant<int, 1 * kTileRows + J>());
+        if (ci == 2) put(std::integral_constant<int, 2 * kTileRows + J>());
+        if (ci == 3) put(std::integral_constant<int, 3 * kTileRows + J>());
+      });
+    }
+    // the tile's output rows, each one contiguous run of up to 256 values (0,
+    // or 1 where a self block's diagonal crosses); the exact kernel later
+    // overwrites the survivors
+    const int64_t dg = m.seg.self_pairs ? r0 - cb : INT64_MIN / 2;  // diagonal column of row 0
+    for (int j = 0; j < nr; ++j) {
+      float* row = out_rows + (int64_t)j * g.nb + cb;
+      const bool drow = dg + j >= 0 && dg + j < kTileCols;  // uniform
 #pragma unroll
-          for (int j = 0; j < kTileRows; ++j)
-            if (j < nr) out_c[(int64_t)j * g.nb] = 0.f;
-        } else {
-#pragma unroll
-          for (int j = 0; j < kTileRows; ++j)
-            if (j < nr) out_c[(int64_t)j * g.nb] = (lane == (int)dd + j) ? 1.f : 0.f;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < kTileRows; ++j) {
-        if (FILL && mk[j] != 0ull) {
-          if ((mk[j] >> lane) & 1ull) {
-            const int64_t slot = base + n + __popcll(mk[j] & below);
-            if (slot < m.capacity) m.pair_id[slot] = g.out0 + (r0 + j) * g.nb + c0 + lane;
-          }
-        }
-        n += (uint32_t)__popcll(mk[j]);
+      for (int ci = 0; ci < kTileCols / 64; ++ci) {
+        const int col = ci * 64 + lane;
+        if (cb + col < ce) row[col] = (drow && col == dg + j) ? 1.f : 0.f;
       }
     }
-    if (!FILL && lane == 0) {
-      if (u < m.tile_capacity) m.tile_count[u] = (int32_t)n;
-      else atomicOr(m.err, kErrCapacity);
+    if (u < m.tile_capacity) {
+      // the tile's state for the fill pass: bits, origin, row length
+      uint64_t mword = ((uint64_t)mhi << 32) | mlo;
+      if (lane == kBitWords) mword = (uint64_t)(g.out0 + r0 * g.nb + cb);
+      if (lane == kBitWords + 1) mword = (uint64_t)g.nb;
+      if (lane < kMaskWords) m.tile_mask[u * kMaskWords + lane] = mword;
+      if (lane == 0) m.tile_count[u] = (int32_t)n;
+    } else if (lane == 0) {
+      atomicOr(m.err, kErrCapacity);
+    }
+  }
+}
+
+// Fill pass: the survivors' output indices, read from the tile state the
+// count pass wrote (bits, origin, row length), go to the tile's range of the
+// work list (chunk-major, the order of the bits).  A tile costs one round of
+// independent loads; no segment lookup.
+__global__ __launch_bounds__(kCullBlock) void k_matrix_fill(CullArgs m) {
+  constexpr int WAVES = kCullBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool segmented = m.seg.a_off != nullptr;
+  int64_t total = segmented ? m.seg.tile_prefix[m.seg.nseg] : m.single_tiles;
+  total = total < m.tile_capacity ? total : m.tile_capacity;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int64_t u0, u1;
+  wave_tiles(total, (int64_t)blockIdx.x * WAVES + wave, (int64_t)gridDim.x * WAVES, u0, u1);
+  // the next tile's state and start are loaded while this tile is written
+  uint64_t word_next = 0ull;
+  int64_t start_next = 0;
+  if (u0 < u1) {
+    word_next = lane < kMaskWords ? m.tile_mask[u0 * kMaskWords + lane] : 0ull;
+    start_next = m.tile_start[u0];
+  }
+  for (int64_t u = u0; u < u1; ++u) {
+    const uint64_t word = word_next;
+    const int64_t start = start_next;
+    if (u + 1 < u1) {
+      word_next = lane < kMaskWords ? m.tile_mask[(u + 1) * kMaskWords + lane] : 0ull;
+      start_next = m.tile_start[u + 1];
+    }
+    uint64_t words = __ballot(lane < kBitWords && word != 0ull);  // uniform: non-empty words
+    if (words == 0ull) continue;
+    const int64_t origin = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(word >> 32), kBitWords) << 32) |
+                                     __builtin_amdgcn_readlane((uint32_t)word, kBitWords));
+    const int64_t nb = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(word >> 32), kBitWords + 1) << 32) |
+                                 __builtin_amdgcn_readlane((uint32_t)word, kBitWords + 1));
+    int64_t next = start;
+    while (words != 0ull) {
+      const int w = __builtin_ctzll(words);
+      words &= words - 1ull;
+      const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)word, w);
+      const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(word >> 32), w);
+      const uint64_t mk = ((uint64_t)hi << 32) | lo;
+      if ((mk >> lane) & 1ull) {
+        const int j = w % kTileRows, c = w / kTileRows;
+        const int64_t slot = next + __popcll(mk & below);
+        if (slot < m.capacity) m.pair_id[slot] = origin + j * nb + c * 64 + lane;
+      }
+      next += __popcll(mk);
     }
   }
 }
@@ -709,7 +836,7 @@ void dispatch(int K, bool fixed, bool z3, F&& f) {
 
 bool valid_saved(const dgal_saved* s) {
   return s != nullptr && s->pair_id && s->nx && s->xflags && s->count && s->capacity >= 0 &&
-         s->tile_start && s->tile_count && s->tile_capacity >= 0;
+         s->tile_start && s->tile_count && s->tile_mask && s->tile_capacity >= 0;
 }
 
 void zero(float* p, int64_t n, hipStream_t stream) {
@@ -785,6 +912,7 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
   c.tile_start = saved->tile_start;
   c.tile_count = saved->tile_count;
   c.tile_capacity = saved->tile_capacity;
+  c.tile_mask = saved->tile_mask;
   c.err = ctx.err;
   ExactArgs x;
   x.seg = sa;
@@ -806,7 +934,7 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
   dispatch(K, fixed, a.zlo != nullptr, [&](auto k, auto fx, auto z) {
     constexpr int KK = decltype(k)::value;
     constexpr bool FX = decltype(fx)::value, ZZ = decltype(z)::value;
-    hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ, false>), dim3((unsigned)cull_grid),
+    hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ>), dim3((unsigned)cull_grid),
                        dim3(kCullBlock), 0, stream, c);
     const int64_t chunks = std::max<int64_t>(1, ceil_div(saved->tile_capacity, kScanChunk));
     hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)chunks), dim3(kScanBlock), 0, stream,
@@ -816,7 +944,8 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
                        sa.tile_prefix, sa.nseg, single_tiles, saved->tile_capacity, ctx.scan,
                        saved->tile_start, saved->tile_count, saved->count, saved->capacity,
                        ctx.err);
-    hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ, true>), dim3((unsigned)cull_grid),
+    // the fill walks ~8 resident waves per SIMD, each over a contiguous range of tiles
+    hipLaunchKernelGGL(k_matrix_fill, dim3((unsigned)std::max<int64_t>(1, (int64_t)ctx.cus * 8)),
                        dim3(kCullBlock), 0, stream, c);
     hipLaunchKernelGGL((k_matrix_exact<KK, FX, ZZ>), dim3(exact_grid), dim3(kExactBlock), 0,
                        stream, x);
