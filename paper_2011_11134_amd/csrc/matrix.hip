@@ -422,8 +422,9 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
 
 // Fill pass: the survivors' output indices, read from the tile state the
 // count pass wrote (bits, origin, row length), go to the tile's range of the
-// work list (chunk-major, the order of the bits).  A tile costs one round of
-// independent loads; no segment lookup.
+// work list (chunk-major, the order of the bits): lane w writes the bits of
+// word w, from the exclusive prefix of the words' counts.  A tile costs one
+// round of independent loads (prefetched), no segment lookup.
 __global__ __launch_bounds__(kCullBlock) void k_matrix_fill(CullArgs m) {
   constexpr int WAVES = kCullBlock / 64;
   const int lane = threadIdx.x & 63;
@@ -431,7 +432,6 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_fill(CullArgs m) {
   const bool segmented = m.seg.a_off != nullptr;
   int64_t total = segmented ? m.seg.tile_prefix[m.seg.nseg] : m.single_tiles;
   total = total < m.tile_capacity ? total : m.tile_capacity;
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   int64_t u0, u1;
   wave_tiles(total, (int64_t)blockIdx.x * WAVES + wave, (int64_t)gridDim.x * WAVES, u0, u1);
   // the next tile's state and start are loaded while this tile is written
@@ -448,25 +448,30 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_fill(CullArgs m) {
       word_next = lane < kMaskWords ? m.tile_mask[(u + 1) * kMaskWords + lane] : 0ull;
       start_next = m.tile_start[u + 1];
     }
-    uint64_t words = __ballot(lane < kBitWords && word != 0ull);  // uniform: non-empty words
-    if (words == 0ull) continue;
+    const uint64_t bits = lane < kBitWords ? word : 0ull;
+    if (__ballot(bits != 0ull) == 0ull) continue;  // uniform: an empty tile
     const int64_t origin = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(word >> 32), kBitWords) << 32) |
                                      __builtin_amdgcn_readlane((uint32_t)word, kBitWords));
     const int64_t nb = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(word >> 32), kBitWords + 1) << 32) |
                                  __builtin_amdgcn_readlane((uint32_t)word, kBitWords + 1));
-    int64_t next = start;
-    while (words != 0ull) {
-      const int w = __builtin_ctzll(words);
-      words &= words - 1ull;
-      const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)word, w);
-      const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(word >> 32), w);
-      const uint64_t mk = ((uint64_t)hi << 32) | lo;
-      if ((mk >> lane) & 1ull) {
-        const int j = w % kTileRows, c = w / kTileRows;
-        const int64_t slot = next + __popcll(mk & below);
-        if (slot < m.capacity) m.pair_id[slot] = origin + j * nb + c * 64 + lane;
-      }
-      next += __popcll(mk);
+    // every lane writes the survivors of its own word: its first slot is the
+    // exclusive prefix of the words' bit counts
+    const int cnt = __popcll(bits);
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < kBitWords; d <<= 1) {
+      const int o = __shfl_up(incl, d);
+      if (lane >= d) incl += o;
+    }
+    int64_t slot = start + (incl - cnt);
+    const int j = lane % kTileRows, c = lane / kTileRows;
+    const int64_t first = origin + (int64_t)j * nb + c * 64;
+    uint64_t w = bits;
+    while (w != 0ull) {
+      const int b = __builtin_ctzll(w);
+      w &= w - 1ull;
+      if (slot < m.capacity) m.pair_id[slot] = first + b;
+      ++slot;
     }
   }
 }
