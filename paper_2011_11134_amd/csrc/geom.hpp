@@ -164,6 +164,15 @@ struct PairResult {
   uint32_t codes[K / 2];  // 2K provenance codes, 4 per word, 0xFF padded
 };
 
+// Waves per SIMD that the LDS of a pair_forward kernel allows at K = 8
+// (144 bytes a lane against 160 KiB a CU); the register allocator is held
+// to the same count, which costs a few spilled values instead of half the
+// occupancy.  Kernels at K = 4 are left to the allocator.
+template <int K>
+constexpr int fwd_waves_per_simd() {
+  return K == 8 ? 4 : 1;
+}
+
 // Forward of one pair.  s_pt / s_cd address this lane's column of a
 // [2K][BLOCK] LDS buffer (element stride BLOCK).  EMIT: the ordered
 // intersection vertices are also returned in ov[0..2K) (absolute frame,
@@ -198,7 +207,10 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
   // Their sign bits are shifted, highest table index first, into words whose
   // bit i*K+j is set when the value is negative (or -0); D is the largest
   // component of the vertex differences, omin the smallest magnitude.
-  float oP[K][K];
+  // The 4-slot kernels keep the table for the crossings; the 8-slot ones
+  // (64 values) recompute the two values a crossing needs, from registers.
+  constexpr bool KEEP_OP = K == 4;
+  float oP[KEEP_OP ? K : 1][KEEP_OP ? K : 1];
   uint32_t negp[NW], negq[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
@@ -213,7 +225,7 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
       const float dx = P.x[i] - Q.x[j], dy = P.y[i] - Q.y[j];
       const float op = eqx[j] * dy - eqy[j] * dx;
       const float oq = epy[i] * dx - epx[i] * dy;
-      oP[i][j] = op;
+      if constexpr (KEEP_OP) oP[i][j] = op;
       const int w = (i * K + j) >> 5;
       negp[w] = __builtin_amdgcn_alignbit(negp[w], __float_as_uint(op), 31);
       negq[w] = __builtin_amdgcn_alignbit(negq[w], __float_as_uint(oq), 31);
@@ -222,18 +234,14 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
       omin = fminf(omin, (FIXED || (i < n1 && j < n2)) ? mo : __builtin_inff());
     }
   }
-  if (!(omin > kCertify * E * D)) {
+  const bool exact = !(omin > kCertify * E * D);
+  if (exact) {
     // Exact signs in fp64; exact zeros take the sign of Q moved by (eps,
     // eps^2).  Rare, so it is written for few registers rather than speed:
     // Q is staged in this lane's (still unused) LDS column and each row of
     // the table is a runtime loop over Q's edges.
 #pragma unroll
     for (int k = 0; k < K; ++k) s_pt[k * BLOCK] = make_float2(Q.x[k], Q.y[k]);
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      negp[w] = 0u;
-      negq[w] = 0u;
-    }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const float pnx = next_of<K, FIXED>(P.x, i, n1), pny = next_of<K, FIXED>(P.y, i, n1);
@@ -250,11 +258,17 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
         const double oq = orient64(P.x[i], P.y[i], pnx, pny, q.x, q.y);
         const bool bp = op > 0.0 || (op == 0.0 && tie_q);
         const bool bq = oq > 0.0 || (oq == 0.0 && tie_p);
-        negp[w] |= (uint32_t)!bp << (sh + j);
-        negq[w] |= (uint32_t)!bq << (sh + j);
-        const float o = (float)op;
+        // each bit is replaced in place: the fp32 words stay live on both
+        // sides of the branch, so their sign chains are not sunk past it
+        // (which would hold all K*K products in registers)
+        const uint32_t bit = 1u << (sh + j);
+        negp[w] = (negp[w] & ~bit) | (bp ? 0u : bit);
+        negq[w] = (negq[w] & ~bit) | (bq ? 0u : bit);
+        if constexpr (KEEP_OP) {
+          const float o = (float)op;
 #pragma unroll
-        for (int t = 0; t < K; ++t) oP[i][t] = t == j ? o : oP[i][t];
+          for (int t = 0; t < K; ++t) oP[i][t] = t == j ? o : oP[i][t];
+        }
       }
     }
   }
@@ -316,8 +330,25 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
         // two values have opposite signs (or one is an exact zero that the
         // tie rule signed), so the difference is never zero for coordinates
         // whose products stay normal floats
-        const float o0 = oP[i][j];
-        const float t = o0 * fast_rcp(o0 - oP[inx][j]);
+        float o0, o1;
+        if constexpr (KEEP_OP) {
+          o0 = oP[i][j];
+          o1 = oP[inx][j];
+        } else if (!exact) {
+          // the table's expression, recomputed; the empty asm hides that it
+          // is the same value, which would otherwise keep all K*K products
+          // live from the table to here (certified signs survive any
+          // difference in rounding between the two evaluations)
+          float qx = Q.x[j], qy = Q.y[j];
+          asm volatile("" : "+v"(qx), "+v"(qy));
+          o0 = eqx[j] * (P.y[i] - qy) - eqy[j] * (P.x[i] - qx);
+          o1 = eqx[j] * (P.y[inx] - qy) - eqy[j] * (P.x[inx] - qx);
+        } else {
+          const int jn = next_idx<K, FIXED>(j, n2);
+          o0 = (float)orient64(Q.x[j], Q.y[j], Q.x[jn], Q.y[jn], P.x[i], P.y[i]);
+          o1 = (float)orient64(Q.x[j], Q.y[j], Q.x[jn], Q.y[jn], P.x[inx], P.y[inx]);
+        }
+        const float t = o0 * fast_rcp(o0 - o1);
         put(true, fmaf(t, epx[i], lpx[i]), fmaf(t, epy[i], lpy[i]), kCodeX | (i << 3) | j);
       }
     }

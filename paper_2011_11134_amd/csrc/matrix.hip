@@ -627,7 +627,8 @@ __device__ __forceinline__ bool locate(const SegArgs& sa, int64_t pid, Segment& 
 }
 
 template <int K, bool FIXED, bool Z3>
-__global__ __launch_bounds__(kExactBlock) void k_matrix_exact(ExactArgs m) {
+__global__ __launch_bounds__(kExactBlock)
+__attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_matrix_exact(ExactArgs m) {
   constexpr int CAP = 2 * K;
   __shared__ float2 s_pt[CAP * kExactBlock];
   __shared__ uint8_t s_cd[CAP * kExactBlock];

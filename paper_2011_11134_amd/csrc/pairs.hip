@@ -13,7 +13,8 @@ constexpr int pairs_block() {
 }
 
 template <int K, bool FIXED, bool Z3, bool SAVE>
-__global__ __launch_bounds__(pairs_block<K>()) void k_pairs_fwd(PairsFwdArgs args) {
+__global__ __launch_bounds__(pairs_block<K>())
+__attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_pairs_fwd(PairsFwdArgs args) {
   constexpr int BLOCK = pairs_block<K>();
   constexpr int CAP = 2 * K;
   __shared__ float2 s_pt[CAP * BLOCK];

@@ -15,7 +15,8 @@ constexpr int prim_block() {
 // Intersection polygon of each pair: ordered vertices (absolute frame, cap
 // slots per row, 0 past nx), nx and xflags.
 template <int K, bool FIXED>
-__global__ __launch_bounds__(prim_block<K>()) void k_intersect_fwd(IntersectArgs args) {
+__global__ __launch_bounds__(prim_block<K>())
+__attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_intersect_fwd(IntersectArgs args) {
   constexpr int BLOCK = prim_block<K>();
   constexpr int CAP = 2 * K;
   __shared__ float2 s_pt[CAP * BLOCK];
