@@ -9,7 +9,11 @@ are resident in HBM before timing starts:
   c1 / c4:      the same on 1,024 rectangle pairs / 262,144 mixed 3..8-gon pairs;
   c2:           4096 x 4096 IoU matrix, forward;
   c5:           64 scenes of 3D boxes, per-scene self-pair IoU, forward and
-                backward (saved non-empty pairs).
+                backward (saved non-empty pairs);
+  c3b:          c3's pairs as box-parameter rows (corners formed in-kernel),
+                forward and backward to the parameters;
+  c3i:          the exported intersection primitive on c3's pairs (ordered
+                polygons, nx, xflags) and its backward.
 Prints one JSON line (rank 0, one GPU).  The timed region is `steps` steps
 back to back (eager launches, or --graph: replays of one captured HIP graph
 of the step); kernel launch durations come from HIP events on the launch
@@ -38,9 +42,14 @@ FP32_PEAK_TFLOPS = 157.3
 #                         + 2 x 32 B gradients                                = 141
 #   8-slot polygons:      2 x (64 + 1) B vertices and counts; flags 16 B
 #   boxes by parameters:  2 x 20 B (cx, cy, w, l, yaw) + 13 B  /  + 4 + 9 + 2 x 20 B
+#   intersection primitive (rectangles), forward: 2 x 32 B vertices + 8 x 8 B
+#                         ordered vertices + 1 B nx + 8 B flags              = 137
+#                         backward: 2 x 32 B vertices + 8 x 8 B vertex
+#                         gradients + 9 B saved + 2 x 32 B gradients         = 201
 BYTES = {
     ("rect", "fwd"): 77, ("rect", "bwd"): 141,
     ("box", "fwd"): 53, ("box", "bwd"): 93,
+    ("isect", "fwd"): 137, ("isect", "bwd"): 201,
     ("poly", "fwd"): 130 + 4 + 1 + 16, ("poly", "bwd"): 130 + 4 + 1 + 16 + 128,
 }
 # Algorithmic fp32 operations per rectangle pair (FMA = 2), counted from the
@@ -53,7 +62,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "c3b"])
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "c3b", "c3i"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true", help="skip the plain per-op GPU form")
     p.add_argument("--copy-calib-mib", type=int, default=0,
@@ -166,6 +175,41 @@ class BoxesStep:
         assert st == 0, st
 
 
+class IntersectStep:
+    """The exported intersection primitive on rectangle pairs: ordered
+    intersection polygons with nx / xflags, then the gradient of
+    sum <grad_xy, polygon> back to both inputs, fixed device buffers."""
+
+    def __init__(self, dg, torch, d):
+        self.dg = dg
+        self.a = torch.from_numpy(d["a_xy"]).cuda()
+        self.b = torch.from_numpy(d["b_xy"]).cuda()
+        self.g = torch.from_numpy(d["grad_xy"]).cuda()
+        n, ka = self.a.shape[:2]
+        cap = ka + self.b.shape[1]
+        self.n = self.pairs = n
+        self.xy = torch.empty((n, cap, 2), device="cuda")
+        self.nx = torch.empty(n, dtype=torch.uint8, device="cuda")
+        self.xf = torch.empty((n, cap), dtype=torch.uint8, device="cuda")
+        self.ga = torch.empty_like(self.a)
+        self.gb = torch.empty_like(self.b)
+        self.pa, _ = dg.polys(self.a)
+        self.pb, _ = dg.polys(self.b)
+        self.ctx = dg.context()
+        self.kind = "isect"
+
+    def fwd(self, stream):
+        st = self.dg.lib.dgal_intersect(self.ctx, self.pa, self.pb, self.xy.data_ptr(),
+                                        self.nx.data_ptr(), self.xf.data_ptr(), stream)
+        assert st == 0, st
+
+    def bwd(self, stream):
+        st = self.dg.lib.dgal_intersect_backward(self.ctx, self.pa, self.pb, self.g.data_ptr(),
+                                                 self.nx.data_ptr(), self.xf.data_ptr(),
+                                                 self.ga.data_ptr(), self.gb.data_ptr(), stream)
+        assert st == 0, st
+
+
 class MatrixStep:
     """4096 x 4096 IoU matrix (forward only) or per-scene 3D self pairs
     (forward + backward) with fixed device buffers."""
@@ -258,25 +302,78 @@ def plain_baseline(torch, d, steps=5, warmup=2):
             "form": "torch ops + autograd on the GPU (bench_plain.py)"}
 
 
-def cpu_baseline(d, kind):
-    """The FP64 oracle, as it stands, on the host cores: forward + analytic
-    backward of the whole workload, repeated for at least 1 s of wall time
-    (at least 3 runs), median run."""
-    import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
-    a, b, g = d["a_xy"], d["b_xy"], d["grad"]
-    anv, bnv = d.get("a_nv"), d.get("b_nv")
+def _timed_runs(fn, min_s=1.0):
+    """Median wall time of fn() over at least 3 runs and min_s seconds."""
     times = []
     start = time.perf_counter()
-    while len(times) < 3 or time.perf_counter() - start < 1.0:
+    while len(times) < 3 or time.perf_counter() - start < min_s:
         t0 = time.perf_counter()
-        iou, nx, xf, _ = oracle.iou_pairs(a, b, anv, bnv, threads=threads)
-        oracle.iou_pairs_grad(a, b, g, nx, xf, anv, bnv, threads=threads)
+        fn()
         times.append(time.perf_counter() - t0)
-    t = statistics.median(times)
-    return {"value": round(len(a) / t, 1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"whole workload ({len(a)} pairs, forward + backward) x {len(times)} runs, "
-                      f"median {t:.4f} s per run"}
+    return statistics.median(times), len(times)
+
+
+def cpu_baseline(d, wl, kind):
+    """The FP64 oracle, as it stands, on the host cores, on the workload or a
+    bounded sample of it: forward + analytic backward (forward only for the
+    c2 matrix), repeated for at least 1 s of wall time (at least 3 runs),
+    median run, as pairs/s."""
+    import numpy as np
+
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    if kind in ("rect", "poly"):
+        a, b, g = d["a_xy"], d["b_xy"], d["grad"]
+        anv, bnv = d.get("a_nv"), d.get("b_nv")
+
+        def run():
+            iou, nx, xf, _ = oracle.iou_pairs(a, b, anv, bnv, threads=threads)
+            oracle.iou_pairs_grad(a, b, g, nx, xf, anv, bnv, threads=threads)
+        pairs, what = len(a), f"whole workload ({len(a)} pairs, forward + backward)"
+    elif kind == "box":
+        a, b, g = d["a_box"], d["b_box"], d["grad"]
+
+        def run():
+            iou, nx, xf, _ = oracle.iou_boxes(a, b, threads=threads)
+            oracle.iou_boxes_grad(a, b, g, nx, xf, threads=threads)
+        pairs, what = len(a), f"whole workload ({len(a)} box pairs, forward + backward)"
+    elif kind == "isect":
+        a, b, g = d["a_xy"], d["b_xy"], d["grad_xy"]
+
+        def run():
+            xy, nx, xf, _ = oracle.intersect_pairs(a, b, threads=threads)
+            oracle.intersect_pairs_grad(a, b, g, nx, xf, threads=threads)
+        pairs, what = len(a), f"whole workload ({len(a)} pairs, intersection + backward)"
+    elif wl == "c2":
+        # the oracle's matrix routine runs on one thread: the first 128 rows
+        # against all 4096 columns
+        threads = 1
+        a, b = d["a_xy"][:128], d["b_xy"]
+
+        def run():
+            oracle.iou_matrix(a, b)
+        pairs, what = len(a) * len(b), f"rows 0..127 x {len(b)} columns of the matrix, forward"
+    else:
+        # c5 on one thread: the first scenes up to about 1 M self pairs,
+        # forward + backward
+        threads = 1
+        off = d["off"]
+        sizes = (off[1:] - off[:-1]) ** 2
+        ns = int(np.searchsorted(np.cumsum(sizes), 1 << 20)) + 1
+        ns = min(ns, len(sizes))
+        o = off[:ns + 1]
+        xy = d["a_xy"][:o[-1]]
+        z = (d["a_zlo"][:o[-1]], d["a_zhi"][:o[-1]])
+        g = d["grad"][:int(sizes[:ns].sum())]
+
+        def run():
+            oracle.iou_matrix(xy, a_z=z, a_off=o, self_pairs=True)
+            oracle.iou_matrix_grad(g, xy, a_z=z, a_off=o, self_pairs=True)
+        pairs = int(sizes[:ns].sum())
+        what = f"first {ns} scenes ({pairs} self pairs), forward + backward"
+    t, runs = _timed_runs(run)
+    return {"value": round(pairs / t, 1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{what} x {runs} runs, median {t:.4f} s per run"}
 
 
 def main():
@@ -299,6 +396,8 @@ def main():
         step = PairsStep(dg, torch, d)
     elif wl == "c3b":
         step = BoxesStep(dg, torch, d)
+    elif wl == "c3i":
+        step = IntersectStep(dg, torch, d)
     else:
         step = MatrixStep(dg, torch, d, wl)
     has_bwd = getattr(step, "has_bwd", True)
@@ -381,7 +480,7 @@ def main():
         kname = "k_matrix_fwd" if dom == "fwd" else "k_matrix_bwd"
     else:
         bytes_total = BYTES[(step.kind, dom)] * step.pairs
-        kname = f"k_pairs_{dom}"
+        kname = {"box": "k_boxes", "isect": "k_intersect"}.get(step.kind, "k_pairs") + f"_{dom}"
     hbm_gbs = bytes_total / dur_s / 1e9
     roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(wl, kname),
@@ -401,8 +500,8 @@ def main():
         torch.cuda.synchronize()
 
     cpu = None
-    if not args.no_cpu_baseline and step.kind in ("rect", "poly"):
-        cpu = cpu_baseline(d, step.kind)
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(d, wl, step.kind)
     plain = None
     if not args.no_plain and step.kind in ("rect", "poly"):
         plain = plain_baseline(torch, d)
@@ -414,7 +513,9 @@ def main():
              "c4": "c4: 262,144 convex 3..8-gon pairs, forward + backward",
              "c5": "c5: 64 scenes (U{50..2000} boxes), per-scene 3D self-pair IoU, forward + backward",
              "c3b": "c3 boxes: 1,048,576 rotated-box pairs as (cx, cy, w, l, yaw) rows, corners "
-                    "formed in-kernel, forward + backward to the parameters"}
+                    "formed in-kernel, forward + backward to the parameters",
+             "c3i": "c3 intersection primitive: 1,048,576 rotated-rectangle pairs, ordered "
+                    "intersection polygons + nx + xflags, backward from per-vertex gradients"}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4),

@@ -331,8 +331,10 @@ int dgal_intersect_backward(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const flo
   args.cap = a.kmax + b.kmax;
   args.ga_xy = grad_a_xy;
   args.gb_xy = grad_b_xy;
+  args.rows_vec = args.cap == 2 * K && aligned(grad_xy, 16) && aligned(xflags, (uintptr_t)(2 * K)) &&
+                  aligned(grad_a_xy, 16) && aligned(grad_b_xy, 16);
   const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
-                     args.a.vec4 && args.b.vec4;
+                     args.a.vec4 && args.b.vec4 && args.rows_vec;
   return status_of(dgal::launch_intersect_bwd(args, K, fixed, static_cast<hipStream_t>(stream)));
 }
 

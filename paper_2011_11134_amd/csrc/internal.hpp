@@ -60,6 +60,7 @@ struct IntersectBwdArgs {
   const uint8_t* nx;
   const uint8_t* xflags;
   int cap;
+  bool rows_vec;  // cap == 2K; gradient rows and outputs 16-byte, flag rows cap-byte aligned
   float* ga_xy;
   float* gb_xy;
 };

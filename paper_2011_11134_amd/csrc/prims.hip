@@ -79,16 +79,36 @@ __global__ __launch_bounds__(prim_block<K>()) void k_intersect_bwd(IntersectBwdA
     const float2* gin = reinterpret_cast<const float2*>(args.grad_xy) + i * (int64_t)args.cap;
     uint32_t codes[K / 2];
     float2 G[CAP];
-#pragma unroll
-    for (int w = 0; w < K / 2; ++w) codes[w] = 0xffffffffu;
-#pragma unroll
-    for (int k = 0; k < CAP; ++k) {
-      if (k < args.cap) {
-        const uint32_t c = row[k];
-        codes[k >> 2] = (codes[k >> 2] & ~(0xffu << ((k & 3) * 8))) | (c << ((k & 3) * 8));
-        G[k] = gin[k];
+    if (FIXED || args.rows_vec) {  // whole rows in 16-byte (8-byte flag) loads
+      if constexpr (K == 4) {
+        const uint2 c = *reinterpret_cast<const uint2*>(row);
+        codes[0] = c.x;
+        codes[1] = c.y;
       } else {
-        G[k] = make_float2(0.f, 0.f);
+        const uint4 c = *reinterpret_cast<const uint4*>(row);
+        codes[0] = c.x;
+        codes[1] = c.y;
+        codes[2] = c.z;
+        codes[3] = c.w;
+      }
+#pragma unroll
+      for (int k = 0; k < CAP; k += 2) {
+        const float4 v = *reinterpret_cast<const float4*>(gin + k);
+        G[k] = make_float2(v.x, v.y);
+        G[k + 1] = make_float2(v.z, v.w);
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < K / 2; ++w) codes[w] = 0xffffffffu;
+#pragma unroll
+      for (int k = 0; k < CAP; ++k) {
+        if (k < args.cap) {
+          const uint32_t c = row[k];
+          codes[k >> 2] = (codes[k >> 2] & ~(0xffu << ((k & 3) * 8))) | (c << ((k & 3) * 8));
+          G[k] = gin[k];
+        } else {
+          G[k] = make_float2(0.f, 0.f);
+        }
       }
     }
     float2 gP[K], gQ[K];
@@ -96,10 +116,18 @@ __global__ __launch_bounds__(prim_block<K>()) void k_intersect_bwd(IntersectBwdA
                                           s_g + tid, s_tab, gP, gQ);
     float* oa = args.ga_xy + i * (int64_t)args.a.kmax * 2;
     float* ob = args.gb_xy + i * (int64_t)args.b.kmax * 2;
+    if (FIXED) {  // rows of exactly K vertices, 16-byte aligned
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (k < args.a.kmax) *reinterpret_cast<float2*>(oa + 2 * k) = gP[k];
-      if (k < args.b.kmax) *reinterpret_cast<float2*>(ob + 2 * k) = gQ[k];
+      for (int k = 0; k < K; k += 2) {
+        *reinterpret_cast<float4*>(oa + 2 * k) = make_float4(gP[k].x, gP[k].y, gP[k + 1].x, gP[k + 1].y);
+        *reinterpret_cast<float4*>(ob + 2 * k) = make_float4(gQ[k].x, gQ[k].y, gQ[k + 1].x, gQ[k + 1].y);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (k < args.a.kmax) *reinterpret_cast<float2*>(oa + 2 * k) = gP[k];
+        if (k < args.b.kmax) *reinterpret_cast<float2*>(ob + 2 * k) = gQ[k];
+      }
     }
   }
 }

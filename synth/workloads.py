@@ -113,6 +113,17 @@ def c3_boxes(n=1 << 20, seed=None, three_d=False):
     return out
 
 
+def c3_intersect(n=1 << 20, seed=None):
+    """c3's rectangle pairs for the exported intersection primitive, with an
+    upstream gradient per intersection vertex: grad_xy [n, 8, 2] U[-1, 1]
+    (slots past a pair's vertex count are ignored by the backward)."""
+    d = c3_pairs(n=n, seed=seed)
+    rng = _rng(6, None if seed is None else seed + 2)
+    return {"a_xy": d["a_xy"], "b_xy": d["b_xy"],
+            "grad_xy": rng.uniform(-1.0, 1.0, (n, 8, 2)).astype(np.float32),
+            "kind": "intersect"}
+
+
 def bev_boxes(rng, n):
     return _draw_boxes(rng, n, (0.0, -40.0), (70.0, 40.0), None, None,
                        w_range=(1.5, 2.2), l_range=(3.5, 5.0))
@@ -229,6 +240,7 @@ WORKLOADS = {
     "c4": c4_polygons,
     "c5": c5_scenes,
     "c3b": c3_boxes,
+    "c3i": c3_intersect,
 }
 
 

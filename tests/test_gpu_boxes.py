@@ -62,6 +62,14 @@ def test_boxes_2d(dg):
     _say(str(_check_boxes(dg, d["a_box"], d["b_box"], d["grad"])))
 
 
+def test_boxes_full_size(dg):
+    """The benchmark's box workload: 1,048,576 box-parameter pairs, every pair
+    against the oracle."""
+    d = synth.c3_boxes()
+    _say(f"case: boxes 2D full {len(d['a_box'])} pairs")
+    _say(str(_check_boxes(dg, d["a_box"], d["b_box"], d["grad"])))
+
+
 def test_boxes_3d(dg):
     n = 32768 + 5
     _say(f"case: boxes 3D {n} pairs")

@@ -85,6 +85,41 @@ def test_intersect_rectangles_ragged_many_blocks(dg):
     _say(str(_check_intersect(dg, d["a_xy"], d["b_xy"], seed=2)))
 
 
+def test_intersect_full_size(dg):
+    """The benchmark's intersection workload: 1,048,576 rectangle pairs with
+    its per-vertex upstream gradient, the backward fed the GPU's own nx /
+    xflags as the benchmark does; every pair against the oracle."""
+    d = synth.c3_intersect()
+    a, b, g = d["a_xy"], d["b_xy"], d["grad_xy"]
+    n = len(a)
+    _say(f"case: intersect c3 full {n} pairs")
+    ta, tb = dev_t(a), dev_t(b)
+    xy, nx, xf = dg.intersect(ta, tb)
+    ga, gb = dg.intersect_backward(ta, tb, dev_t(g), nx, xf)
+    dg.check_errors()
+    xy, nx, xf = xy.cpu().numpy(), nx.cpu().numpy(), xf.cpu().numpy()
+    ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
+    r_xy, r_nx, r_xf, bad = oracle.intersect_pairs(a, b, threads=16)
+    assert bad == 0
+    marg = oracle.pair_margins(a, b, threads=16)
+    keep = oracle.filtered_mask(marg)
+    assert keep.mean() > 0.9
+    assert np.array_equal(nx[keep], r_nx[keep])
+    assert np.array_equal(xf[keep], r_xf[keep])
+    assert np.all((nx == 0) | ((nx >= 3) & (nx <= 8)))
+    scale = np.maximum(1.0, np.maximum(np.abs(a).reshape(n, -1).max(1),
+                                       np.abs(b).reshape(n, -1).max(1)))
+    err = np.abs(xy.astype(np.float64) - r_xy).reshape(n, -1).max(1)
+    tol = _vertex_tol(scale, marg[:, 1])
+    assert np.all(err[keep] <= tol[keep]), np.max(err[keep] / tol[keep])
+    r_ga, r_gb = oracle.intersect_pairs_grad(a, b, g, r_nx, r_xf, threads=16)
+    gerr = grad_rel_err(np.concatenate([ga.reshape(n, -1), gb.reshape(n, -1)], 1),
+                        np.concatenate([r_ga.reshape(n, -1), r_gb.reshape(n, -1)], 1))
+    assert gerr[keep].max() <= GRAD_TOL, gerr[keep].max()
+    _say(str({"filtered": float(keep.mean()), "max_vertex_err_over_tol":
+              float(np.max(err[keep] / tol[keep])), "max_grad_err": float(gerr[keep].max())}))
+
+
 def test_intersect_polygons(dg):
     _say("case: intersect c4 polygons 8192 pairs")
     d = synth.c4_polygons(n=8192, seed=92)
