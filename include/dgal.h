@@ -24,8 +24,10 @@
  *     host before anything is enqueued; on error nothing is enqueued.  No C++
  *     exception crosses this interface.
  *   - Per-element data (vertex counts outside [3, kmax], clockwise or
- *     non-convex polygons) is not validated: results for such elements are
- *     unspecified, but every memory access stays in bounds.  An intersection
+ *     non-convex polygons) is not validated on the fast path: results for
+ *     such elements are unspecified, but every memory access stays in
+ *     bounds.  dgal_validate checks it, and dgal_set_validate (or
+ *     DGAL_DEBUG_VALIDATE=1) turns the check on before every call.  An intersection
  *     that would overflow its capacity (possible only for invalid polygons)
  *     sets a sticky device error that dgal_check reports as DGAL_ECAPACITY.
  *   - A context may be used from one host thread at a time.
@@ -234,6 +236,34 @@ int dgal_area(dgal_ctx *ctx, dgal_polys p, float *area, void *stream);
  * upstream gradient (cyclic neighbours; padded slots written 0). */
 int dgal_area_backward(dgal_ctx *ctx, dgal_polys p, const float *grad_area,
                        float *grad_xy, void *stream);
+
+/* The input contract of Sec. III, checked per polygon: the vertex count is
+ * in [3, kmax], every turn v[k-1] -> v[k] -> v[k+1] is strictly left (the
+ * orientation of the three fp32 vertices evaluated in fp64 as
+ * (v[k] - v[k-1]) x (v[k+1] - v[k-1]) is > 0), and the boundary turns around
+ * exactly once (a star polygon such as the pentagram turns left at every
+ * vertex but winds twice).  z is ignored.
+ *   status [p.count] uint8, overwritten (may be NULL): 0 valid, 1 vertex
+ *     count out of range, 2 a turn not strictly left (clockwise order, a
+ *     reflex, straight or repeated vertex), 3 winds more than once.
+ *   n_bad: device int64 scalar (may be NULL), overwritten with the number of
+ *     invalid polygons (zeroed by a kernel on the stream, so the call can be
+ *     captured in a graph).
+ * DGAL_EINVAL: ctx NULL, invalid p (as elsewhere), both outputs NULL, n_bad
+ * not 8-byte aligned. */
+int dgal_validate(dgal_ctx *ctx, dgal_polys p, uint8_t *status, int64_t *n_bad,
+                  void *stream);
+
+/* Input checking before every call (off by default; on at dgal_create when
+ * the environment holds DGAL_DEBUG_VALIDATE=1).  While on, dgal_iou_pairs,
+ * dgal_iou_matrix, dgal_iou_backward, dgal_intersect and
+ * dgal_intersect_backward first run dgal_validate's check on their polygon
+ * sets, wait for it on the stream, and return DGAL_EINVAL, enqueueing
+ * nothing else, if any polygon breaks the contract.  A debugging aid: it
+ * synchronises the stream, so calls must not be captured in a graph while
+ * it is on.  dgal_area and its backward accept any simple polygon and are
+ * not checked.  DGAL_EINVAL: ctx NULL. */
+int dgal_set_validate(dgal_ctx *ctx, int32_t enable);
 
 /* Launch-shape autotuning of the batched kernels (the grid of the pair
  * kernels, the persistent grids of the matrix kernels).  While enabled, the

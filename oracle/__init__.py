@@ -33,6 +33,8 @@ def lib():
         i64, i32 = ctypes.c_int64, ctypes.c_int
         L.oracle_polygon_valid.argtypes = [_f64p, i32]
         L.oracle_polygon_valid.restype = i32
+        L.oracle_polygon_statuses.argtypes = [i64, i64, _f32p, _u8p, i32, _u8p]
+        L.oracle_polygon_statuses.restype = None
         L.oracle_intersect.argtypes = [_f64p, i32, _f64p, i32, _f64p, _u8p]
         L.oracle_intersect.restype = i32
         L.oracle_area.argtypes = [_f64p, i32]
@@ -254,6 +256,17 @@ def filtered_mask(margins):
 def polygon_valid(xy):
     xy = np.ascontiguousarray(xy, dtype=np.float64)
     return bool(lib().oracle_polygon_valid(_p(xy, _f64p), xy.shape[0]))
+
+
+def polygon_status(xy, nv=None):
+    """Input-contract status of each polygon of a [n, kmax, 2] fp32 array
+    (Sec. III): 0 valid, 1 vertex count outside [3, kmax], 2 a turn not
+    strictly left, 3 winds more than once.  uint8 [n]."""
+    keep, args = _poly2(xy, nv)
+    n = keep[0].shape[0]
+    out = np.zeros(n, np.uint8)
+    lib().oracle_polygon_statuses(0, n, *args, _p(out, _u8p))
+    return out
 
 
 def intersect(p, q):

@@ -428,17 +428,49 @@ static void load_z(const float *lo, const float *hi, int64_t i, double *z) {
   z[1] = (double)hi[i];
 }
 
-/* Returns 1 iff the polygon is valid (Sec. III): 3..8 vertices, strictly
- * convex, counter-clockwise. */
+/* Input contract of Sec. III for one polygon given by its fp32 coordinates
+ * (read as doubles): returns 0 if valid, 1 if the vertex count is outside
+ * [3, kmax] (kmax <= 8), 2 if some turn v_k-1 -> v_k -> v_k+1 is not strictly
+ * left (clockwise order, a reflex or straight vertex, a repeated vertex),
+ * 3 if every turn is left but the boundary turns around more than once (a
+ * star polygon such as the pentagram).  The total turning is the sum of the
+ * exterior angles, atan2 of each pair of consecutive edges; with every turn
+ * left it is 2 pi times the number of times the boundary winds. */
+static int polygon_status(const point *v, int n) {
+  double turning = 0.0;
+  for (int k = 0; k < n; ++k) {
+    point a = v[(k + n - 1) % n], b = v[k], c = v[(k + 1) % n];
+    if (!(orient(a, b, c) > 0)) return 2;
+    point u = psub(b, a), w = psub(c, b);
+    turning += atan2(cross2(u, w), u.x * w.x + u.y * w.y);
+  }
+  const double turns = turning / (2.0 * acos(-1.0));
+  return fabs(turns - 1.0) < 0.5 ? 0 : 3;
+}
+
+int oracle_polygon_status(const float *xy, int n, int kmax) {
+  if (kmax < 3 || kmax > ORC_MAXV || n < 3 || n > kmax) return 1;
+  point v[ORC_MAXV];
+  for (int k = 0; k < n; ++k) v[k] = mkpt((double)xy[2 * k], (double)xy[2 * k + 1]);
+  return polygon_status(v, n);
+}
+
+/* Returns 1 iff the polygon (fp64 coordinates) is valid (Sec. III): 3..8
+ * vertices, strictly convex, counter-clockwise, winding once. */
 int oracle_polygon_valid(const double *xy, int n) {
   if (n < 3 || n > ORC_MAXV) return 0;
-  for (int k = 0; k < n; ++k) {
-    point a = mkpt(xy[2 * ((k + n - 1) % n)], xy[2 * ((k + n - 1) % n) + 1]);
-    point b = mkpt(xy[2 * k], xy[2 * k + 1]);
-    point c = mkpt(xy[2 * ((k + 1) % n)], xy[2 * ((k + 1) % n) + 1]);
-    if (!(orient(a, b, c) > 0)) return 0;
+  point v[ORC_MAXV];
+  for (int k = 0; k < n; ++k) v[k] = mkpt(xy[2 * k], xy[2 * k + 1]);
+  return polygon_status(v, n) == 0;
+}
+
+/* Status of polygons [lo, hi) of a [count][kmax][2] fp32 array. */
+void oracle_polygon_statuses(int64_t lo, int64_t hi, const float *xy, const uint8_t *nv, int kmax,
+                             uint8_t *status) {
+  for (int64_t i = lo; i < hi; ++i) {
+    const int n = nv ? (int)nv[i] : kmax;
+    status[i] = (uint8_t)oracle_polygon_status(xy + i * (int64_t)kmax * 2, n, kmax);
   }
-  return 1;
 }
 
 /* Intersection polygon of one pair; writes m vertices and codes, returns m

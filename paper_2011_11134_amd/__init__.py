@@ -51,7 +51,7 @@ EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
            "dgal_iou_pairs", "dgal_iou_matrix", "dgal_iou_backward",
            "dgal_intersect", "dgal_intersect_backward", "dgal_area", "dgal_area_backward",
            "dgal_iou_boxes", "dgal_iou_boxes_backward", "dgal_set_autotune",
-           "dgal_autotune_report")
+           "dgal_autotune_report", "dgal_validate", "dgal_set_validate")
 
 
 def _load():
@@ -92,6 +92,10 @@ def _load():
     L.dgal_set_autotune.restype = ctypes.c_int
     L.dgal_autotune_report.argtypes = [_vp, ctypes.c_char_p, i64]
     L.dgal_autotune_report.restype = ctypes.c_int
+    L.dgal_validate.argtypes = [_vp, Polys, _vp, _vp, _vp]
+    L.dgal_validate.restype = ctypes.c_int
+    L.dgal_set_validate.argtypes = [_vp, i32]
+    L.dgal_set_validate.restype = ctypes.c_int
     return L
 
 
@@ -431,6 +435,26 @@ def iou_matrix_backward(grad, saved, seg, a_xy, b_xy=None, a_nv=None, b_nv=None,
                               _stream(a_xy)),
         "dgal_iou_backward(matrix)")
     return ga, gb, gaz, gbz
+
+
+def validate(xy, nv=None):
+    """Input-contract status of each polygon (Sec. III), checked on the GPU:
+    (status uint8 [n]: 0 valid, 1 vertex count outside [3, kmax], 2 a turn
+    not strictly left, 3 winds more than once; number of invalid polygons)."""
+    p, keep = polys(xy, nv)
+    n = xy.shape[0]
+    status = torch.empty(n, dtype=torch.uint8, device=xy.device)
+    n_bad = torch.empty(1, dtype=torch.int64, device=xy.device)
+    _ok(lib.dgal_validate(context(xy.device), p, _ptr(status), _ptr(n_bad), _stream(xy)),
+        "dgal_validate")
+    return status, int(n_bad.item())
+
+
+def set_validate(enable=True, device=None):
+    """Turns the input check before every call on (or off) for a device's
+    context; while on, a call with an invalid polygon raises DgalError
+    (DGAL_EINVAL) and enqueues nothing."""
+    _ok(lib.dgal_set_validate(context(device), int(bool(enable))), "dgal_set_validate")
 
 
 def set_autotune(enable=True, device=None):

@@ -1,6 +1,7 @@
 // api.hip -- the C ABI declared in include/dgal.h: argument validation on the
 // host, then kernel dispatch on the caller's stream.  No allocation per call.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <map>
@@ -18,6 +19,8 @@ enum { kTunePairsFwd, kTunePairsBwd, kTuneMatrixFwd, kTuneMatrixBwd };
 struct dgal_ctx {
   dgal::CtxView v;
   bool tune = false;
+  bool validate = false;         // check every input polygon before each call
+  int64_t* n_bad = nullptr;      // device counter of the input check
   std::map<TuneKey, dgal::LaunchShape> tuned;
 };
 
@@ -101,6 +104,29 @@ std::vector<dgal::LaunchShape> matrix_bwd_shapes() {
   return v;
 }
 
+// With input checking on (dgal_set_validate, or DGAL_DEBUG_VALIDATE=1 in the
+// environment when the context was created), every polygon of the call's
+// sets is checked on the device against the contract of Sec. III, and the
+// call waits for the count: DGAL_EINVAL if any polygon breaks it.
+int debug_validate(dgal_ctx* ctx, hipStream_t s, const dgal_polys& a, const dgal_polys* b) {
+  if (!ctx->validate) return DGAL_OK;
+  if (!valid_polys(a) || (b && !valid_polys(*b))) return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  const dgal_polys* sets[2] = {&a, b};
+  for (const dgal_polys* p : sets) {
+    if (p == nullptr || p->count == 0) continue;
+    const dgal::PolyArgs pa = poly_args(*p, 8);
+    if (dgal::launch_validate(pa, nullptr, ctx->n_bad, s) != hipSuccess) return DGAL_EHIP;
+    int64_t host = 0;
+    if (hipMemcpyAsync(&host, ctx->n_bad, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return DGAL_EHIP;
+    if (host != 0) return DGAL_EINVAL;
+  }
+  return DGAL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -130,13 +156,17 @@ int dgal_create(dgal_ctx** out, int hip_device) {
           hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c->v.scan), sizeof(int64_t) * dgal::kScanTotals) !=
           hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->n_bad), sizeof(int64_t)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     if (c->v.err) (void)hipFree(c->v.err);
     if (c->v.prefix) (void)hipFree(c->v.prefix);
     if (c->v.scan) (void)hipFree(c->v.scan);
+    if (c->n_bad) (void)hipFree(c->n_bad);
     delete c;
     return DGAL_EHIP;
   }
+  const char* dbg = getenv("DGAL_DEBUG_VALIDATE");
+  c->validate = dbg != nullptr && strcmp(dbg, "1") == 0;
   *out = c;
   return DGAL_OK;
 }
@@ -147,6 +177,7 @@ void dgal_destroy(dgal_ctx* ctx) {
   if (ctx->v.err) (void)hipFree(ctx->v.err);
   if (ctx->v.prefix) (void)hipFree(ctx->v.prefix);
   if (ctx->v.scan) (void)hipFree(ctx->v.scan);
+  if (ctx->n_bad) (void)hipFree(ctx->n_bad);
   delete ctx;
 }
 
@@ -184,6 +215,7 @@ int dgal_iou_pairs(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* iou, uint8_
   if ((a.zlo == nullptr) != (b.zlo == nullptr)) return DGAL_EINVAL;
   if (a.count > 0 && iou == nullptr) return DGAL_EINVAL;
   if (a.count == 0) return DGAL_OK;
+  if (int st = debug_validate(ctx, static_cast<hipStream_t>(stream), a, &b)) return st;
   DeviceGuard g(ctx->v.device);
   if (!g.ok) return DGAL_EHIP;
   const int K = reg_k(a.kmax, b.kmax);
@@ -216,6 +248,7 @@ int dgal_iou_backward(dgal_ctx* ctx, int32_t mode, dgal_polys a, dgal_polys b,
   if (ctx == nullptr || !valid_polys(a) || !valid_polys(b)) return DGAL_EINVAL;
   const bool z3 = a.zlo != nullptr;
   if ((a.zlo == nullptr) != (b.zlo == nullptr)) return DGAL_EINVAL;
+  if (int st = debug_validate(ctx, static_cast<hipStream_t>(stream), a, &b)) return st;
   if (mode == DGAL_PAIRS) {
     (void)a_off;
     (void)b_off;
@@ -277,6 +310,7 @@ int dgal_iou_matrix(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const int64_t* a_
                     void* stream) {
   if (ctx == nullptr) return DGAL_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (int st = debug_validate(ctx, s, a, dgal::same_polys(a, b) ? nullptr : &b)) return st;
   const TuneKey key(kTuneMatrixFwd, reg_k(a.kmax, b.kmax), a.nv == nullptr && b.nv == nullptr,
                     a.zlo != nullptr, a_off != nullptr);
   return run_tuned(ctx, key, matrix_fwd_shapes(), s, [&](const dgal::LaunchShape& sh) {
@@ -292,6 +326,7 @@ int dgal_intersect(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* out_xy, uin
   if (a.count == 0) return DGAL_OK;
   if (out_xy == nullptr || nx == nullptr || xflags == nullptr || !aligned(out_xy, 8))
     return DGAL_EINVAL;
+  if (int st = debug_validate(ctx, static_cast<hipStream_t>(stream), a, &b)) return st;
   DeviceGuard g(ctx->v.device);
   if (!g.ok) return DGAL_EHIP;
   const int K = reg_k(a.kmax, b.kmax);
@@ -319,6 +354,7 @@ int dgal_intersect_backward(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const flo
       grad_b_xy == nullptr)
     return DGAL_EINVAL;
   if (!aligned(grad_xy, 8) || !aligned(grad_a_xy, 8) || !aligned(grad_b_xy, 8)) return DGAL_EINVAL;
+  if (int st = debug_validate(ctx, static_cast<hipStream_t>(stream), a, &b)) return st;
   DeviceGuard g(ctx->v.device);
   if (!g.ok) return DGAL_EHIP;
   const int K = reg_k(a.kmax, b.kmax);
@@ -380,6 +416,23 @@ bool valid_boxes(const dgal_boxes& a, const dgal_boxes& b) {
 }  // namespace
 
 extern "C" {
+
+int dgal_validate(dgal_ctx* ctx, dgal_polys p, uint8_t* status, int64_t* n_bad, void* stream) {
+  if (ctx == nullptr || !valid_polys(p)) return DGAL_EINVAL;
+  if (status == nullptr && n_bad == nullptr) return DGAL_EINVAL;
+  if (n_bad != nullptr && !aligned(n_bad, 8)) return DGAL_EINVAL;
+  if (p.count > 0 && p.xy == nullptr) return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  return status_of(
+      dgal::launch_validate(poly_args(p, 8), status, n_bad, static_cast<hipStream_t>(stream)));
+}
+
+int dgal_set_validate(dgal_ctx* ctx, int32_t enable) {
+  if (ctx == nullptr) return DGAL_EINVAL;
+  ctx->validate = enable != 0;
+  return DGAL_OK;
+}
 
 int dgal_set_autotune(dgal_ctx* ctx, int32_t enable) {
   if (ctx == nullptr) return DGAL_EINVAL;

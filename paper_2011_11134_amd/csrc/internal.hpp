@@ -176,5 +176,9 @@ hipError_t launch_area(const PolyArgs& p, const float* grad, float* out, int K, 
                        bool backward, hipStream_t stream);
 hipError_t launch_boxes_fwd(const BoxesFwdArgs& args, bool z3, bool save, hipStream_t stream);
 hipError_t launch_boxes_bwd(const BoxesBwdArgs& args, bool z3, hipStream_t stream);
+// Input-contract status per polygon (status may be NULL) and the number of
+// invalid ones (n_bad may be NULL; zeroed first, on the stream).
+hipError_t launch_validate(const PolyArgs& p, uint8_t* status, int64_t* n_bad,
+                           hipStream_t stream);
 
 }  // namespace dgal

@@ -709,3 +709,44 @@ def test_boxes_grad_vs_finite_differences(orc):
         err = (np.linalg.norm(an - fdr, axis=1) / den)[keep]
         assert keep.sum() > 300, keep.sum()
         assert err.max() <= 1e-5, np.sort(err)[-5:]
+
+
+def _star(p, q, k=8, r=1.0, phase=0.1):
+    """Vertices of the star polygon {p/q} (q = 1: the regular p-gon), padded
+    to k slots."""
+    v = [[r * math.cos(phase + 2 * math.pi * q * t / p), r * math.sin(phase + 2 * math.pi * q * t / p)]
+         for t in range(p)]
+    v += [v[0]] * (k - p)
+    return v
+
+
+def test_polygon_status_geometric_facts(orc):
+    """The input contract of Sec. III (convex, counter-clockwise): a regular
+    p-gon is valid, its reverse is clockwise, a star polygon {p/q} turns
+    left at every vertex but winds q times, a straight or repeated vertex is
+    not a strict left turn, and vertex counts outside [3, kmax] are refused."""
+    cases, nv, want = [], [], []
+
+    def add(v, n, code):
+        cases.append(v + [v[0]] * (8 - len(v)))
+        nv.append(n)
+        want.append(code)
+
+    for p in range(3, 9):
+        add(_star(p, 1, p), p, 0)
+        add(_star(p, 1, p)[::-1], p, 2)
+    add(_star(5, 2, 5), 5, 3)
+    add(_star(7, 2, 7), 7, 3)
+    add(_star(7, 3, 7), 7, 3)
+    add(_star(8, 3, 8), 8, 3)
+    add([[0, 0], [1, 0], [1, 0], [1, 1], [0, 1]], 5, 2)         # repeated vertex
+    add([[0, 0], [0.5, 0], [1, 0], [1, 1], [0, 1]], 5, 2)       # straight vertex
+    add([[0, 0], [2, 0], [2, 1], [1, 1], [1, 2], [0, 2]], 6, 2)  # L-shape (reflex)
+    add([[0, 0], [1, 0], [1, 1], [0, 1]], 2, 1)
+    add([[0, 0], [1, 0], [1, 1], [0, 1]], 0, 1)
+    add([[0, 0], [1, 0], [1, 1], [0, 1]], 9, 1)
+    xy = np.array(cases, np.float32)
+    st = orc.polygon_status(xy, np.array(nv, np.uint8))
+    assert list(st) == want
+    # fixed-count form (nv NULL => kmax) on the valid p = 8 case
+    assert list(orc.polygon_status(xy[10:12])) == [0, 2]
