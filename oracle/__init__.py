@@ -35,6 +35,19 @@ def lib():
         L.oracle_polygon_valid.restype = i32
         L.oracle_polygon_statuses.argtypes = [i64, i64, _f32p, _u8p, i32, _u8p]
         L.oracle_polygon_statuses.restype = None
+        _u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.oracle_simple_inter_area.argtypes = [_f64p, i32, _f64p, i32]
+        L.oracle_simple_inter_area.restype = ctypes.c_double
+        L.oracle_simple_iou_pairs.argtypes = ([i64, i64, _f32p, _u8p, i32, _f32p, _u8p, i32,
+                                               _f64p, _u64p, _u64p, _u8p])
+        L.oracle_simple_iou_pairs.restype = i64
+        L.oracle_simple_iou_pairs_grad.argtypes = ([i64, i64, _f32p, _u8p, i32, _f32p, _u8p,
+                                                    i32, _f64p, _f64p, _f64p])
+        L.oracle_simple_iou_pairs_grad.restype = None
+        L.oracle_simple_margins.argtypes = [i64, i64, _f32p, _u8p, i32, _f32p, _u8p, i32, _f64p]
+        L.oracle_simple_margins.restype = None
+        L.oracle_simple_valid.argtypes = [_f64p, i32]
+        L.oracle_simple_valid.restype = i32
         L.oracle_intersect.argtypes = [_f64p, i32, _f64p, i32, _f64p, _u8p]
         L.oracle_intersect.restype = i32
         L.oracle_area.argtypes = [_f64p, i32]
@@ -445,3 +458,77 @@ def iou_boxes_grad(a, b, g, nx, xflags, threads=1):
                                                 _p(g, _f64p), _p(nx, _u8p), _p(xflags, _u8p),
                                                 _p(ga, _f64p), _p(gb, _f64p)), n, threads)
     return ga, gb
+
+
+# ------------------------------------------------ simple (non-convex) polygons
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def simple_inter_area(p, q):
+    """Area of the intersection of two simple counter-clockwise polygons
+    ([n, 2] each, fp64) by the vertical slab decomposition."""
+    p = np.ascontiguousarray(p, np.float64)
+    q = np.ascontiguousarray(q, np.float64)
+    return float(lib().oracle_simple_inter_area(_p(p, _f64p), p.shape[0], _p(q, _f64p),
+                                                q.shape[0]))
+
+
+def simple_valid(xy):
+    """True if the [n, 2] polygon is simple, counter-clockwise, 3..8 vertices."""
+    xy = np.ascontiguousarray(xy, np.float64)
+    return bool(lib().oracle_simple_valid(_p(xy, _f64p), xy.shape[0]))
+
+
+def simple_iou_pairs(a_xy, b_xy, a_nv=None, b_nv=None, threads=1):
+    """IoU of elementwise pairs of simple polygons and the saved state.
+    Returns (iou f64 [n], xmask u64 [n], smask u64 [n], inside u8 [n],
+    n_invalid)."""
+    ka_keep, ka_args = _poly2(a_xy, a_nv)
+    kb_keep, kb_args = _poly2(b_xy, b_nv)
+    n = ka_keep[0].shape[0]
+    assert kb_keep[0].shape[0] == n
+    iou = np.zeros(n, np.float64)
+    xm = np.zeros(n, np.uint64)
+    sm = np.zeros(n, np.uint64)
+    ins = np.zeros(n, np.uint8)
+    L = lib()
+    bad = _run(lambda lo, hi: L.oracle_simple_iou_pairs(lo, hi, *ka_args, *kb_args,
+                                                        _p(iou, _f64p), _p(xm, _u64p),
+                                                        _p(sm, _u64p), _p(ins, _u8p)),
+               n, threads)
+    return iou, xm, sm, ins, int(sum(bad))
+
+
+def simple_iou_pairs_grad(a_xy, b_xy, g, a_nv=None, b_nv=None, threads=1):
+    """Gradient of sum(g * IoU) over pairs of simple polygons: (ga, gb) f64."""
+    ka_keep, ka_args = _poly2(a_xy, a_nv)
+    kb_keep, kb_args = _poly2(b_xy, b_nv)
+    n, ka = ka_keep[0].shape[:2]
+    kb = kb_keep[0].shape[1]
+    g = np.ascontiguousarray(g, np.float64)
+    ga = np.zeros((n, ka, 2), np.float64)
+    gb = np.zeros((n, kb, 2), np.float64)
+    L = lib()
+    _run(lambda lo, hi: L.oracle_simple_iou_pairs_grad(lo, hi, *ka_args, *kb_args, _p(g, _f64p),
+                                                       _p(ga, _f64p), _p(gb, _f64p)), n, threads)
+    return ga, gb
+
+
+def simple_margins(a_xy, b_xy, a_nv=None, b_nv=None, threads=1):
+    """[n, 2]: vertex-to-edge distance over the pair's size, smallest |sin| of
+    a crossing."""
+    ka_keep, ka_args = _poly2(a_xy, a_nv)
+    kb_keep, kb_args = _poly2(b_xy, b_nv)
+    n = ka_keep[0].shape[0]
+    out = np.zeros((n, 2), np.float64)
+    L = lib()
+    _run(lambda lo, hi: L.oracle_simple_margins(lo, hi, *ka_args, *kb_args, _p(out, _f64p)),
+         n, threads)
+    return out
+
+
+def simple_filtered_mask(margins, dist=1e-4, sin=1e-3):
+    """Pairs in general position: no vertex within dist * size of an edge of
+    the other polygon, no crossing at |sin| below sin."""
+    return (margins[:, 0] >= dist) & (margins[:, 1] >= sin)

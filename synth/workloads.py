@@ -175,6 +175,46 @@ def random_convex(rng, n, kmin=3, kmax=8, min_turn=1e-3):
     return xy, nv
 
 
+def random_simple(rng, n, centers, kmin=3, kmax=8, min_gap=0.15, rmin=0.4, rmax=1.6):
+    """n simple, counter-clockwise, generally non-convex polygons [n, kmax, 2]
+    fp32 (zero padded) and counts [n] u8: vertices at strictly increasing
+    angles about the given centres ([n, 2]), each angular gap in
+    [min_gap, 0.9 pi] (so the centre is inside and the polygon is star-shaped
+    about it), radii U[rmin, rmax]."""
+    nv = rng.integers(kmin, kmax + 1, n).astype(np.uint8)
+    gaps = np.zeros((n, kmax))
+    todo = np.arange(n)
+    while todo.size:
+        t = todo.size
+        k = nv[todo]
+        mask = np.arange(kmax)[None, :] < k[:, None]
+        g = np.where(mask, rng.uniform(0.2, 1.0, (t, kmax)), 0.0)
+        g = g / g.sum(1, keepdims=True) * (2 * math.pi)
+        ok = np.all(np.where(mask, (g >= min_gap) & (g <= 0.9 * math.pi), True), axis=1)
+        gaps[todo[ok]] = g[ok]
+        todo = todo[~ok]
+    start = rng.uniform(0.0, 2 * math.pi, (n, 1))
+    ang = start + np.cumsum(gaps, axis=1) - gaps
+    r = rng.uniform(rmin, rmax, (n, kmax))
+    mask = np.arange(kmax)[None, :] < nv[:, None]
+    px = np.where(mask, centers[:, :1] + r * np.cos(ang), 0.0)
+    py = np.where(mask, centers[:, 1:] + r * np.sin(ang), 0.0)
+    return np.stack([px, py], axis=-1).astype(np.float32), nv
+
+
+def c4_simple(n=1 << 18, seed=None):
+    """262,144 pairs of simple 3..8-gons, generally non-convex (star-shaped
+    about their centres): centres U[-1, 1]^2, the second polygon's centre
+    moved by N(0, 0.5^2) per axis; grad U[-1, 1]."""
+    rng = _rng(7, seed)
+    ca = rng.uniform(-1.0, 1.0, (n, 2))
+    cb = ca + rng.normal(0.0, 0.5, (n, 2))
+    a, anv = random_simple(rng, n, ca)
+    b, bnv = random_simple(rng, n, cb)
+    g = rng.uniform(-1.0, 1.0, n).astype(np.float32)
+    return {"a_xy": a, "a_nv": anv, "b_xy": b, "b_nv": bnv, "grad": g, "kind": "simple"}
+
+
 def c4_polygons(n=1 << 18, seed=None):
     rng = _rng(3, seed)
     a, anv = random_convex(rng, n)
@@ -241,6 +281,7 @@ WORKLOADS = {
     "c5": c5_scenes,
     "c3b": c3_boxes,
     "c3i": c3_intersect,
+    "c4n": c4_simple,
 }
 
 
