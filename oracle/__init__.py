@@ -516,19 +516,22 @@ def simple_iou_pairs_grad(a_xy, b_xy, g, a_nv=None, b_nv=None, threads=1):
 
 
 def simple_margins(a_xy, b_xy, a_nv=None, b_nv=None, threads=1):
-    """[n, 2]: vertex-to-edge distance over the pair's size, smallest |sin| of
-    a crossing."""
+    """[n, 3]: vertex-to-edge distance over the pair's size, smallest |sin| of
+    a crossing, intersection area over the smaller polygon's (1 if
+    disjoint)."""
     ka_keep, ka_args = _poly2(a_xy, a_nv)
     kb_keep, kb_args = _poly2(b_xy, b_nv)
     n = ka_keep[0].shape[0]
-    out = np.zeros((n, 2), np.float64)
+    out = np.zeros((n, 3), np.float64)
     L = lib()
     _run(lambda lo, hi: L.oracle_simple_margins(lo, hi, *ka_args, *kb_args, _p(out, _f64p)),
          n, threads)
     return out
 
 
-def simple_filtered_mask(margins, dist=1e-4, sin=1e-3):
+def simple_filtered_mask(margins, dist=1e-4, sin=1e-3, sliver=1e-4):
     """Pairs in general position: no vertex within dist * size of an edge of
-    the other polygon, no crossing at |sin| below sin."""
-    return (margins[:, 0] >= dist) & (margins[:, 1] >= sin)
+    the other polygon, no crossing at |sin| below sin, and no intersection
+    smaller than sliver times the smaller polygon (the convex filter's
+    criteria)."""
+    return (margins[:, 0] >= dist) & (margins[:, 1] >= sin) & (margins[:, 2] >= sliver)

@@ -277,14 +277,17 @@ void oracle_simple_iou_pairs_grad(int64_t lo, int64_t hi, const float *a_xy, con
 /* Degeneracy margins of simple-polygon pairs [lo, hi): out[i][0] = smallest
  * distance from a vertex of either polygon to an edge of the other, over the
  * pair's size L (diagonal of the joint bounding box); out[i][1] = smallest
- * |sin| of the angle between two crossing edges (1 if none). */
+ * |sin| of the angle between two crossing edges (1 if none); out[i][2] = the
+ * intersection area over the smaller polygon's area (1 if they do not meet):
+ * a sliver has an IoU whose fp32 evaluation is all rounding. */
 void oracle_simple_margins(int64_t lo, int64_t hi, const float *a_xy, const uint8_t *a_nv, int ka,
                            const float *b_xy, const uint8_t *b_nv, int kb, double *out) {
   for (int64_t i = lo; i < hi; ++i) {
     spt P[SMP_MAXV], Q[SMP_MAXV];
     const int n1 = s_load(a_xy, a_nv, i, ka, P), n2 = s_load(b_xy, b_nv, i, kb, Q);
-    out[2 * i] = 0.0;
-    out[2 * i + 1] = 0.0;
+    out[3 * i] = 0.0;
+    out[3 * i + 1] = 0.0;
+    out[3 * i + 2] = 0.0;
     if (n1 < 0 || n2 < 0) continue;
     double x0 = P[0].x, x1 = P[0].x, y0 = P[0].y, y1 = P[0].y;
     for (int k = 0; k < n1; ++k) {
@@ -316,8 +319,11 @@ void oracle_simple_margins(int64_t lo, int64_t hi, const float *a_xy, const uint
           smin = fmin(smin, fabs(ux * vy - uy * vx) / (hypot(ux, uy) * hypot(vx, vy)));
         }
       }
-    out[2 * i] = L > 0 ? dmin / L : 0.0;
-    out[2 * i + 1] = smin;
+    out[3 * i] = L > 0 ? dmin / L : 0.0;
+    out[3 * i + 1] = smin;
+    const double I = s_slab_area(P, n1, Q, n2);
+    const double amin = fmin(s_shoelace(P, n1), s_shoelace(Q, n2));
+    out[3 * i + 2] = I > 0.0 ? (amin > 0 ? I / amin : 0.0) : 1.0;
   }
 }
 
