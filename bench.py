@@ -13,7 +13,9 @@ are resident in HBM before timing starts:
   c3b:          c3's pairs as box-parameter rows (corners formed in-kernel),
                 forward and backward to the parameters;
   c3i:          the exported intersection primitive on c3's pairs (ordered
-                polygons, nx, xflags) and its backward.
+                polygons, nx, xflags) and its backward;
+  c4n:          262,144 pairs of simple, generally non-convex 3..8-gons,
+                forward and backward.
 Prints one JSON line (rank 0, one GPU).  The timed region is `steps` steps
 back to back (eager launches, or --graph: replays of one captured HIP graph
 of the step); kernel launch durations come from HIP events on the launch
@@ -46,8 +48,11 @@ FP32_PEAK_TFLOPS = 157.3
 #                         ordered vertices + 1 B nx + 8 B flags              = 137
 #                         backward: 2 x 32 B vertices + 8 x 8 B vertex
 #                         gradients + 9 B saved + 2 x 32 B gradients         = 201
+#   simple polygons:      2 x (64 + 1) B + 4 B IoU + 17 B saved (two uint64
+#                         masks, one inclusion byte)  /  + 4 + 17 + 2 x 64 B
 BYTES = {
     ("rect", "fwd"): 77, ("rect", "bwd"): 141,
+    ("simple", "fwd"): 130 + 4 + 17, ("simple", "bwd"): 130 + 4 + 17 + 128,
     ("box", "fwd"): 53, ("box", "bwd"): 93,
     ("isect", "fwd"): 137, ("isect", "bwd"): 201,
     ("poly", "fwd"): 130 + 4 + 1 + 16, ("poly", "bwd"): 130 + 4 + 1 + 16 + 128,
@@ -62,7 +67,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "c3b", "c3i"])
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "c3b", "c3i", "c4n"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true", help="skip the plain per-op GPU form")
     p.add_argument("--copy-calib-mib", type=int, default=0,
@@ -210,6 +215,44 @@ class IntersectStep:
         assert st == 0, st
 
 
+class SimpleStep:
+    """Forward + backward of simple (not necessarily convex) polygon pairs
+    with fixed device buffers."""
+
+    def __init__(self, dg, torch, d):
+        self.dg = dg
+        self.a = torch.from_numpy(d["a_xy"]).cuda()
+        self.b = torch.from_numpy(d["b_xy"]).cuda()
+        self.anv = torch.from_numpy(d["a_nv"]).cuda()
+        self.bnv = torch.from_numpy(d["b_nv"]).cuda()
+        self.g = torch.from_numpy(d["grad"]).cuda()
+        n = self.a.shape[0]
+        self.n = self.pairs = n
+        self.iou = torch.empty(n, device="cuda")
+        self.xm = torch.empty(n, dtype=torch.int64, device="cuda")
+        self.sm = torch.empty(n, dtype=torch.int64, device="cuda")
+        self.ins = torch.empty(n, dtype=torch.uint8, device="cuda")
+        self.ga = torch.empty_like(self.a)
+        self.gb = torch.empty_like(self.b)
+        self.pa, _ = dg.polys(self.a, self.anv)
+        self.pb, _ = dg.polys(self.b, self.bnv)
+        self.ctx = dg.context()
+        self.kind = "simple"
+
+    def fwd(self, stream):
+        st = self.dg.lib.dgal_iou_simple_pairs(self.ctx, self.pa, self.pb, self.iou.data_ptr(),
+                                               self.xm.data_ptr(), self.sm.data_ptr(),
+                                               self.ins.data_ptr(), stream)
+        assert st == 0, st
+
+    def bwd(self, stream):
+        st = self.dg.lib.dgal_iou_simple_backward(self.ctx, self.pa, self.pb, self.g.data_ptr(),
+                                                  self.xm.data_ptr(), self.sm.data_ptr(),
+                                                  self.ins.data_ptr(), self.ga.data_ptr(),
+                                                  self.gb.data_ptr(), stream)
+        assert st == 0, st
+
+
 class MatrixStep:
     """4096 x 4096 IoU matrix (forward only) or per-scene 3D self pairs
     (forward + backward) with fixed device buffers."""
@@ -337,6 +380,13 @@ def cpu_baseline(d, wl, kind):
             iou, nx, xf, _ = oracle.iou_boxes(a, b, threads=threads)
             oracle.iou_boxes_grad(a, b, g, nx, xf, threads=threads)
         pairs, what = len(a), f"whole workload ({len(a)} box pairs, forward + backward)"
+    elif kind == "simple":
+        a, b, g, anv, bnv = d["a_xy"], d["b_xy"], d["grad"], d["a_nv"], d["b_nv"]
+
+        def run():
+            oracle.simple_iou_pairs(a, b, anv, bnv, threads=threads)
+            oracle.simple_iou_pairs_grad(a, b, g, anv, bnv, threads=threads)
+        pairs, what = len(a), f"whole workload ({len(a)} simple polygon pairs, forward + backward)"
     elif kind == "isect":
         a, b, g = d["a_xy"], d["b_xy"], d["grad_xy"]
 
@@ -398,6 +448,8 @@ def main():
         step = BoxesStep(dg, torch, d)
     elif wl == "c3i":
         step = IntersectStep(dg, torch, d)
+    elif wl == "c4n":
+        step = SimpleStep(dg, torch, d)
     else:
         step = MatrixStep(dg, torch, d, wl)
     has_bwd = getattr(step, "has_bwd", True)
@@ -480,7 +532,8 @@ def main():
         kname = "k_matrix_fwd" if dom == "fwd" else "k_matrix_bwd"
     else:
         bytes_total = BYTES[(step.kind, dom)] * step.pairs
-        kname = {"box": "k_boxes", "isect": "k_intersect"}.get(step.kind, "k_pairs") + f"_{dom}"
+        kname = {"box": "k_boxes", "isect": "k_intersect",
+                 "simple": "k_simple"}.get(step.kind, "k_pairs") + f"_{dom}"
     hbm_gbs = bytes_total / dur_s / 1e9
     roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(wl, kname),
@@ -515,7 +568,9 @@ def main():
              "c3b": "c3 boxes: 1,048,576 rotated-box pairs as (cx, cy, w, l, yaw) rows, corners "
                     "formed in-kernel, forward + backward to the parameters",
              "c3i": "c3 intersection primitive: 1,048,576 rotated-rectangle pairs, ordered "
-                    "intersection polygons + nx + xflags, backward from per-vertex gradients"}
+                    "intersection polygons + nx + xflags, backward from per-vertex gradients",
+             "c4n": "c4 simple: 262,144 pairs of simple (about half non-convex) 3..8-gons, "
+                    "forward + backward"}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4),

@@ -237,6 +237,49 @@ int dgal_area(dgal_ctx *ctx, dgal_polys p, float *area, void *stream);
 int dgal_area_backward(dgal_ctx *ctx, dgal_polys p, const float *grad_area,
                        float *grad_xy, void *stream);
 
+/* IoU of SIMPLE polygons: counter-clockwise, not self-intersecting, not
+ * necessarily convex (Sec. III keeps polygons convex and plans arbitrary
+ * ones; Sec. VI lists arbitrary shapes as future work).  Elementwise pairs,
+ * 2D only.  The intersection area is half the boundary integral of
+ * x dy - y dx (Green's theorem): each edge contributes the cross product of
+ * its end points times the fraction of the edge inside the other polygon,
+ * found from the edge's crossings with the other boundary and the inclusion
+ * of its start vertex; no intersection polygon is formed.  Orientation signs
+ * and degenerate contacts follow the same rules as the convex path.
+ *   a, b: as for dgal_iou_pairs (kmax 3..8, counts optional), zlo/zhi NULL.
+ *   iou [count] fp32, overwritten.
+ *   Saved state for dgal_iou_simple_backward (all three NULL => forward
+ *   only; otherwise all non-NULL), overwritten:
+ *     xmask [count] uint64 (8-byte aligned): bit 8*i + j set when edge i of
+ *       a crosses edge j of b (edge i runs from vertex i to vertex i+1 mod n);
+ *     smask [count] uint64: the same bit set when, in addition, edge i of a
+ *       enters b there (vertex i of a lies right of edge j of b);
+ *     inside [count] uint8: bit 0 when vertex 0 of a is inside b, bit 1 when
+ *       vertex 0 of b is inside a.
+ * Self-intersecting or clockwise input is not detected (results unspecified,
+ * accesses in bounds); dgal_set_validate does not apply (its check is the
+ * convex contract).
+ * DGAL_EINVAL: ctx NULL, invalid a or b, a.count != b.count, a z-extent
+ * given, saved pointers partly NULL or misaligned, iou NULL with count > 0. */
+int dgal_iou_simple_pairs(dgal_ctx *ctx, dgal_polys a, dgal_polys b, float *iou,
+                          uint64_t *xmask, uint64_t *smask, uint8_t *inside,
+                          void *stream);
+
+/* Backward of dgal_iou_simple_pairs from its saved state: moving a vertex
+ * moves its two edges, and the intersection area changes by each edge's
+ * outward normal (dy, -dx) times the integral, over the edge's parts inside
+ * the other polygon, of how far along the edge the point moves with the
+ * vertex; the polygon areas by the shoelace formula; then the quotient rule
+ * of IoU.
+ *   grad_iou [count] fp32; xmask, smask, inside as saved by the forward.
+ *   grad_a_xy [count][a.kmax][2], grad_b_xy [count][b.kmax][2] fp32 (8-byte
+ *   aligned), overwritten, padded slots written 0.
+ * DGAL_EINVAL: as the forward, plus a NULL or misaligned pointer. */
+int dgal_iou_simple_backward(dgal_ctx *ctx, dgal_polys a, dgal_polys b,
+                             const float *grad_iou, const uint64_t *xmask,
+                             const uint64_t *smask, const uint8_t *inside,
+                             float *grad_a_xy, float *grad_b_xy, void *stream);
+
 /* The input contract of Sec. III, checked per polygon: the vertex count is
  * in [3, kmax], every turn v[k-1] -> v[k] -> v[k+1] is strictly left (the
  * orientation of the three fp32 vertices evaluated in fp64 as

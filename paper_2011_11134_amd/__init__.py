@@ -51,7 +51,8 @@ EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
            "dgal_iou_pairs", "dgal_iou_matrix", "dgal_iou_backward",
            "dgal_intersect", "dgal_intersect_backward", "dgal_area", "dgal_area_backward",
            "dgal_iou_boxes", "dgal_iou_boxes_backward", "dgal_set_autotune",
-           "dgal_autotune_report", "dgal_validate", "dgal_set_validate")
+           "dgal_autotune_report", "dgal_validate", "dgal_set_validate",
+           "dgal_iou_simple_pairs", "dgal_iou_simple_backward")
 
 
 def _load():
@@ -96,6 +97,10 @@ def _load():
     L.dgal_validate.restype = ctypes.c_int
     L.dgal_set_validate.argtypes = [_vp, i32]
     L.dgal_set_validate.restype = ctypes.c_int
+    L.dgal_iou_simple_pairs.argtypes = [_vp, Polys, Polys, _vp, _vp, _vp, _vp, _vp]
+    L.dgal_iou_simple_pairs.restype = ctypes.c_int
+    L.dgal_iou_simple_backward.argtypes = [_vp, Polys, Polys, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.dgal_iou_simple_backward.restype = ctypes.c_int
     return L
 
 
@@ -437,6 +442,42 @@ def iou_matrix_backward(grad, saved, seg, a_xy, b_xy=None, a_nv=None, b_nv=None,
     return ga, gb, gaz, gbz
 
 
+def iou_simple_pairs(a_xy, b_xy, a_nv=None, b_nv=None, save=True):
+    """IoU of elementwise pairs of simple (not necessarily convex) polygons.
+    Returns (iou [n], xmask, smask, inside): the saved state as int64 [n]
+    tensors holding the uint64 masks, and uint8 [n]; None when save=False."""
+    pa, _ = polys(a_xy, a_nv)
+    pb, _ = polys(b_xy, b_nv)
+    n, dev = a_xy.shape[0], a_xy.device
+    iou = torch.empty(n, dtype=torch.float32, device=dev)
+    xm = sm = ins = None
+    if save:
+        xm = torch.empty(n, dtype=torch.int64, device=dev)
+        sm = torch.empty(n, dtype=torch.int64, device=dev)
+        ins = torch.empty(n, dtype=torch.uint8, device=dev)
+    _ok(lib.dgal_iou_simple_pairs(context(dev), pa, pb, _ptr(iou), _ptr(xm), _ptr(sm), _ptr(ins),
+                                  _stream(a_xy)), "dgal_iou_simple_pairs")
+    return iou, xm, sm, ins
+
+
+def iou_simple_backward(a_xy, b_xy, grad, xmask, smask, inside, a_nv=None, b_nv=None):
+    """Gradient of sum(grad * IoU) for simple polygon pairs from the saved
+    state: (grad_a [n, ka, 2], grad_b [n, kb, 2])."""
+    pa, _ = polys(a_xy, a_nv)
+    pb, _ = polys(b_xy, b_nv)
+    dev = a_xy.device
+    _need(grad, torch.float32, "grad", dev)
+    _need(xmask, torch.int64, "xmask", dev)
+    _need(smask, torch.int64, "smask", dev)
+    _need(inside, torch.uint8, "inside", dev)
+    ga = torch.empty_like(a_xy)
+    gb = torch.empty_like(b_xy)
+    _ok(lib.dgal_iou_simple_backward(context(dev), pa, pb, _ptr(grad), _ptr(xmask), _ptr(smask),
+                                     _ptr(inside), _ptr(ga), _ptr(gb), _stream(a_xy)),
+        "dgal_iou_simple_backward")
+    return ga, gb
+
+
 def validate(xy, nv=None):
     """Input-contract status of each polygon (Sec. III), checked on the GPU:
     (status uint8 [n]: 0 valid, 1 vertex count outside [3, kmax], 2 a turn
@@ -499,6 +540,25 @@ class IoUPairs(torch.autograd.Function):
         a_xy, b_xy, nx, xf = ctx.saved_tensors
         a_nv, b_nv = ctx.nvs
         ga, gb, _, _ = iou_pairs_backward(a_xy, b_xy, g.contiguous().float(), nx, xf, a_nv, b_nv)
+        return ga, gb, None, None
+
+
+class IoUSimplePairs(torch.autograd.Function):
+    """IoU of elementwise pairs of simple (not necessarily convex) polygons;
+    backward by the library's kernel from the saved crossing state."""
+
+    @staticmethod
+    def forward(ctx, a_xy, b_xy, a_nv=None, b_nv=None):
+        iou, xm, sm, ins = iou_simple_pairs(a_xy, b_xy, a_nv, b_nv, save=True)
+        ctx.save_for_backward(a_xy, b_xy, xm, sm, ins)
+        ctx.nvs = (a_nv, b_nv)
+        return iou
+
+    @staticmethod
+    def backward(ctx, g):
+        a_xy, b_xy, xm, sm, ins = ctx.saved_tensors
+        a_nv, b_nv = ctx.nvs
+        ga, gb = iou_simple_backward(a_xy, b_xy, g.contiguous().float(), xm, sm, ins, a_nv, b_nv)
         return ga, gb, None, None
 
 

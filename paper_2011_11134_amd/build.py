@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgal.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "pairs.hip", "matrix.hip", "prims.hip", "boxes.hip", "validate.hip"]
+SOURCES = ["api.hip", "pairs.hip", "matrix.hip", "prims.hip", "boxes.hip", "validate.hip", "simple.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

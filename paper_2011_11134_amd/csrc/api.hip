@@ -417,6 +417,54 @@ bool valid_boxes(const dgal_boxes& a, const dgal_boxes& b) {
 
 extern "C" {
 
+int dgal_iou_simple_pairs(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* iou, uint64_t* xmask,
+                          uint64_t* smask, uint8_t* inside, void* stream) {
+  if (ctx == nullptr || !valid_polys(a) || !valid_polys(b)) return DGAL_EINVAL;
+  if (a.count != b.count || a.zlo != nullptr || b.zlo != nullptr) return DGAL_EINVAL;
+  const bool save = xmask != nullptr;
+  if ((smask != nullptr) != save || (inside != nullptr) != save) return DGAL_EINVAL;
+  if (save && (!aligned(xmask, 8) || !aligned(smask, 8))) return DGAL_EINVAL;
+  if (a.count == 0) return DGAL_OK;
+  if (iou == nullptr) return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  const int K = reg_k(a.kmax, b.kmax);
+  dgal::SimpleFwdArgs args;
+  args.a = poly_args(a, K);
+  args.b = poly_args(b, K);
+  args.iou = iou;
+  args.xmask = xmask;
+  args.smask = smask;
+  args.inside = inside;
+  return status_of(dgal::launch_simple_fwd(args, K, static_cast<hipStream_t>(stream)));
+}
+
+int dgal_iou_simple_backward(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const float* grad_iou,
+                             const uint64_t* xmask, const uint64_t* smask, const uint8_t* inside,
+                             float* grad_a_xy, float* grad_b_xy, void* stream) {
+  if (ctx == nullptr || !valid_polys(a) || !valid_polys(b)) return DGAL_EINVAL;
+  if (a.count != b.count || a.zlo != nullptr || b.zlo != nullptr) return DGAL_EINVAL;
+  if (a.count == 0) return DGAL_OK;
+  if (grad_iou == nullptr || xmask == nullptr || smask == nullptr || inside == nullptr ||
+      grad_a_xy == nullptr || grad_b_xy == nullptr)
+    return DGAL_EINVAL;
+  if (!aligned(xmask, 8) || !aligned(smask, 8) || !aligned(grad_a_xy, 8) || !aligned(grad_b_xy, 8))
+    return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  const int K = reg_k(a.kmax, b.kmax);
+  dgal::SimpleBwdArgs args;
+  args.a = poly_args(a, K);
+  args.b = poly_args(b, K);
+  args.grad = grad_iou;
+  args.xmask = xmask;
+  args.smask = smask;
+  args.inside = inside;
+  args.ga_xy = grad_a_xy;
+  args.gb_xy = grad_b_xy;
+  return status_of(dgal::launch_simple_bwd(args, K, static_cast<hipStream_t>(stream)));
+}
+
 int dgal_validate(dgal_ctx* ctx, dgal_polys p, uint8_t* status, int64_t* n_bad, void* stream) {
   if (ctx == nullptr || !valid_polys(p)) return DGAL_EINVAL;
   if (status == nullptr && n_bad == nullptr) return DGAL_EINVAL;

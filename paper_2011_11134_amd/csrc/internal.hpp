@@ -86,6 +86,26 @@ struct BoxesBwdArgs {
   float* gb;
 };
 
+// Simple (not necessarily convex) polygon pairs: IoU and the saved state
+// (crossing mask, entering mask, vertex-0 inclusion bits).
+struct SimpleFwdArgs {
+  PolyArgs a, b;
+  float* iou;
+  uint64_t* xmask;  // NULL: forward only (then smask and inside are NULL too)
+  uint64_t* smask;
+  uint8_t* inside;
+};
+
+struct SimpleBwdArgs {
+  PolyArgs a, b;
+  const float* grad;
+  const uint64_t* xmask;
+  const uint64_t* smask;
+  const uint8_t* inside;
+  float* ga_xy;
+  float* gb_xy;
+};
+
 // Grid shapes of one call, chosen by the autotuner (0 = built-in default).
 // grid: workgroups of a grid-stride elementwise kernel (0 => one lane per
 // item); the matrix multipliers scale the persistent grids by the CU count.
@@ -176,6 +196,8 @@ hipError_t launch_area(const PolyArgs& p, const float* grad, float* out, int K, 
                        bool backward, hipStream_t stream);
 hipError_t launch_boxes_fwd(const BoxesFwdArgs& args, bool z3, bool save, hipStream_t stream);
 hipError_t launch_boxes_bwd(const BoxesBwdArgs& args, bool z3, hipStream_t stream);
+hipError_t launch_simple_fwd(const SimpleFwdArgs& args, int K, hipStream_t stream);
+hipError_t launch_simple_bwd(const SimpleBwdArgs& args, int K, hipStream_t stream);
 // Input-contract status per polygon (status may be NULL) and the number of
 // invalid ones (n_bad may be NULL; zeroed first, on the stream).
 hipError_t launch_validate(const PolyArgs& p, uint8_t* status, int64_t* n_bad,
