@@ -34,6 +34,13 @@ constexpr int simple_block() {
   return K == 8 ? 128 : 256;
 }
 
+// At K = 8 both kernels are held to 4 waves per SIMD (at most 128 VGPRs, a
+// few values spilled): left alone they take 149 / 160 registers and run 3.
+template <int K>
+constexpr int simple_waves() {
+  return K == 8 ? 4 : 1;
+}
+
 // Row masks of the tie-ruled sign table: bit j of spr[i] when P_i is strictly
 // left of Q's edge j, bit j of sqr[i] when Q_j is strictly left of P's edge i.
 // Returns true when the lane took the exact fp64 branch.
@@ -123,25 +130,25 @@ __device__ __forceinline__ uint32_t vertex0_inclusion(const Poly<K>& P, int n1, 
 // Parity of the set bits of a byte.
 __device__ __forceinline__ uint32_t parity8(uint32_t v) { return __builtin_popcount(v & 0xffu) & 1u; }
 
-// Per-edge sums over the crossings: for P's edge i, L = sum s (1 - t),
-// W1 = sum s (1 - t)^2 / 2, W2 = sum s (1 - t^2) / 2 with s = +1 where the
-// edge enters Q; the same for Q's edges (M, V1, V2) with the opposite sign
-// (an edge of P entering Q is an edge of Q leaving P at that point).
+// Per-edge sums over the crossings: for P's edge i, L = sum s (1 - t) and
+// W1 = sum s (1 - t)^2 / 2 with s = +1 where the edge enters Q; the same for
+// Q's edges (M, V1) with the opposite sign (an edge of P entering Q is an
+// edge of Q leaving P at that point).  The integral of t over the inside
+// part is the inside length minus that of (1 - t), so it needs no sum.
 template <int K, bool GRAD>
 __device__ __forceinline__ void crossing_sums(const Poly<K>& P, int n1, const Poly<K>& Q, int n2,
                                               const float (&epx)[K], const float (&epy)[K],
                                               const float (&eqx)[K], const float (&eqy)[K],
                                               const uint32_t (&xrow)[K], const uint32_t (&erow)[K],
                                               bool exact, float (&L)[K], float (&W1)[K],
-                                              float (&W2)[K], float (&M)[K], float (&V1)[K],
-                                              float (&V2)[K]) {
+                                              float (&M)[K], float (&V1)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     L[k] = 0.f;
     M[k] = 0.f;
     if (GRAD) {
-      W1[k] = W2[k] = 0.f;
-      V1[k] = V2[k] = 0.f;
+      W1[k] = 0.f;
+      V1[k] = 0.f;
     }
   }
 #pragma unroll
@@ -180,9 +187,7 @@ __device__ __forceinline__ void crossing_sums(const Poly<K>& P, int n1, const Po
         M[j] = fmaf(-sg, us, M[j]);
         if (GRAD) {
           W1[i] = fmaf(0.5f * sg, ut * ut, W1[i]);
-          W2[i] = fmaf(0.5f * sg, fmaf(-t, t, 1.f), W2[i]);
           V1[j] = fmaf(-0.5f * sg, us * us, V1[j]);
-          V2[j] = fmaf(-0.5f * sg, fmaf(-s, s, 1.f), V2[j]);
         }
       }
     }
@@ -243,7 +248,8 @@ __device__ __forceinline__ void edge_cross(const Poly<K>& P, int n1, const Poly<
 }
 
 template <int K>
-__global__ __launch_bounds__(simple_block<K>()) void k_simple_fwd(SimpleFwdArgs args) {
+__global__ __launch_bounds__(simple_block<K>())
+__attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_fwd(SimpleFwdArgs args) {
   constexpr int BLOCK = simple_block<K>();
   __shared__ float2 s_q[K * BLOCK];
   const int tid = threadIdx.x;
@@ -273,9 +279,8 @@ __global__ __launch_bounds__(simple_block<K>()) void k_simple_fwd(SimpleFwdArgs 
       sm |= (uint64_t)erow[i] << (8 * i);
     }
     const uint32_t inside = vertex0_inclusion<K>(P, n1, Q, n2, spr, sqr);
-    float L[K], M[K], W1[K], W2[K], V1[K], V2[K];
-    crossing_sums<K, false>(P, n1, Q, n2, epx, epy, eqx, eqy, xrow, erow, exact, L, W1, W2, M, V1,
-                            V2);
+    float L[K], M[K], W1[K], V1[K];
+    crossing_sums<K, false>(P, n1, Q, n2, epx, epy, eqx, eqy, xrow, erow, exact, L, W1, M, V1);
     float ep[K], eq[K], cp[K], cq[K];
     vertex_inclusion<K>(inside, xrow, ep, eq);
     edge_cross<K>(P, n1, Q, n2, cp, cq);
@@ -301,7 +306,8 @@ __global__ __launch_bounds__(simple_block<K>()) void k_simple_fwd(SimpleFwdArgs 
 }
 
 template <int K>
-__global__ __launch_bounds__(simple_block<K>()) void k_simple_bwd(SimpleBwdArgs args) {
+__global__ __launch_bounds__(simple_block<K>())
+__attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_bwd(SimpleBwdArgs args) {
   const int64_t n = args.a.count;
   for (int64_t p = (int64_t)blockIdx.x * simple_block<K>() + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * simple_block<K>()) {
@@ -320,9 +326,8 @@ __global__ __launch_bounds__(simple_block<K>()) void k_simple_bwd(SimpleBwdArgs 
       xrow[i] = (uint32_t)(xm >> (8 * i)) & 0xffu;
       erow[i] = (uint32_t)(sm >> (8 * i)) & 0xffu;
     }
-    float L[K], M[K], W1[K], W2[K], V1[K], V2[K];
-    crossing_sums<K, true>(P, n1, Q, n2, epx, epy, eqx, eqy, xrow, erow, false, L, W1, W2, M, V1,
-                           V2);
+    float L[K], M[K], W1[K], V1[K];
+    crossing_sums<K, true>(P, n1, Q, n2, epx, epy, eqx, eqy, xrow, erow, false, L, W1, M, V1);
     float ep[K], eq[K], cp[K], cq[K];
     vertex_inclusion<K>(inside, xrow, ep, eq);
     edge_cross<K>(P, n1, Q, n2, cp, cq);
@@ -343,13 +348,15 @@ __global__ __launch_bounds__(simple_block<K>()) void k_simple_bwd(SimpleBwdArgs 
     const float ru = live ? fast_rcp(u) : 0.f;
     const float g = args.grad[p];
     const float cI = g * (a1 + a2) * ru * ru, cA = -g * inter * ru * ru;
-    // inside-part weights of each edge: W1 = int (1 - t), W2 = int t
+    // inside-part weights of each edge: W1 = int (1 - t), W2 = int t =
+    // inside length - W1 (the same for Q's edges: V1, V2)
+    float W2[K], V2[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       W1[k] = fmaf(0.5f, ep[k], W1[k]);
-      W2[k] = fmaf(0.5f, ep[k], W2[k]);
+      W2[k] = ep[k] + L[k] - W1[k];
       V1[k] = fmaf(0.5f, eq[k], V1[k]);
-      V2[k] = fmaf(0.5f, eq[k], V2[k]);
+      V2[k] = eq[k] + M[k] - V1[k];
     }
     float* oa = args.ga_xy + p * (int64_t)args.a.kmax * 2;
     float* ob = args.gb_xy + p * (int64_t)args.b.kmax * 2;
