@@ -135,62 +135,72 @@ __device__ __forceinline__ uint32_t parity8(uint32_t v) { return __builtin_popco
 // Q's edges (M, V1) with the opposite sign (an edge of P entering Q is an
 // edge of Q leaving P at that point).  The integral of t over the inside
 // part is the inside length minus that of (1 - t), so it needs no sum.
-template <int K, bool GRAD>
+//
+// Each edge of P walks the set bits of its crossing row (a wavefront takes
+// as many steps as its busiest lane's row has crossings); the crossed edge of
+// Q is read from this lane's LDS column (s_q: Q's vertices) and its sums are
+// kept there too (s_acc: (M, V1) per edge of Q).
+template <int K, bool GRAD, int BLOCK>
 __device__ __forceinline__ void crossing_sums(const Poly<K>& P, int n1, const Poly<K>& Q, int n2,
                                               const float (&epx)[K], const float (&epy)[K],
-                                              const float (&eqx)[K], const float (&eqy)[K],
                                               const uint32_t (&xrow)[K], const uint32_t (&erow)[K],
-                                              bool exact, float (&L)[K], float (&W1)[K],
-                                              float (&M)[K], float (&V1)[K]) {
+                                              bool exact, float2* __restrict__ s_q,
+                                              float2* __restrict__ s_acc, float (&L)[K],
+                                              float (&W1)[K], float (&M)[K], float (&V1)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
+    s_q[k * BLOCK] = make_float2(Q.x[k], Q.y[k]);
+    s_acc[k * BLOCK] = make_float2(0.f, 0.f);
     L[k] = 0.f;
-    M[k] = 0.f;
-    if (GRAD) {
-      W1[k] = 0.f;
-      V1[k] = 0.f;
-    }
+    W1[k] = 0.f;
   }
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     const int inx = next_idx<K, false>(i, n1);
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      if ((xrow[i] >> j) & 1u) {
-        const int jn = next_idx<K, false>(j, n2);
-        // the table's expressions, recomputed; the empty asm keeps the
-        // compiler from holding all K*K table values live until here
-        float qx = Q.x[j], qy = Q.y[j];
-        asm volatile("" : "+v"(qx), "+v"(qy));
-        float o0, o1;
-        if (!exact) {
-          o0 = eqx[j] * (P.y[i] - qy) - eqy[j] * (P.x[i] - qx);
-          o1 = eqx[j] * (P.y[inx] - qy) - eqy[j] * (P.x[inx] - qx);
-        } else {
-          o0 = (float)orient64(qx, qy, Q.x[jn], Q.y[jn], P.x[i], P.y[i]);
-          o1 = (float)orient64(qx, qy, Q.x[jn], Q.y[jn], P.x[inx], P.y[inx]);
-        }
-        // The crossing point X = P_i + t e_i; its parameter on Q's edge is
-        // X's projection onto that edge, not a second independent quotient:
-        // where the edges meet at a shallow angle both parameters are
-        // uncertain along the edges, and only a shared point keeps the two
-        // edges' contributions consistent (an error of X along the boundary
-        // then changes the area in proportion to the angle only).
-        const float t = fminf(fmaxf(o0 * fast_rcp(o0 - o1), 0.f), 1.f);
-        const float rx = fmaf(t, epx[i], P.x[i] - qx), ry = fmaf(t, epy[i], P.y[i] - qy);
-        const float s = fminf(
-            fmaxf((rx * eqx[j] + ry * eqy[j]) * fast_rcp(fmaf(eqx[j], eqx[j], eqy[j] * eqy[j])), 0.f),
-            1.f);
-        const float sg = ((erow[i] >> j) & 1u) ? 1.f : -1.f;
-        const float ut = 1.f - t, us = 1.f - s;
-        L[i] = fmaf(sg, ut, L[i]);
-        M[j] = fmaf(-sg, us, M[j]);
-        if (GRAD) {
-          W1[i] = fmaf(0.5f * sg, ut * ut, W1[i]);
-          V1[j] = fmaf(-0.5f * sg, us * us, V1[j]);
-        }
+    uint32_t row = xrow[i];
+    const uint32_t er = erow[i];
+    while (row) {
+      const uint32_t j = (uint32_t)__builtin_ctz(row);
+      row &= row - 1u;
+      const uint32_t jn = j + 1u < (uint32_t)n2 ? j + 1u : 0u;
+      const float2 q = s_q[j * BLOCK], qn = s_q[jn * BLOCK];
+      // the sign table's expressions (Q's edge as next_of - vertex)
+      const float fx = qn.x - q.x, fy = qn.y - q.y;
+      float o0, o1;
+      if (!exact) {
+        o0 = fx * (P.y[i] - q.y) - fy * (P.x[i] - q.x);
+        o1 = fx * (P.y[inx] - q.y) - fy * (P.x[inx] - q.x);
+      } else {
+        o0 = (float)orient64(q.x, q.y, qn.x, qn.y, P.x[i], P.y[i]);
+        o1 = (float)orient64(q.x, q.y, qn.x, qn.y, P.x[inx], P.y[inx]);
       }
+      // The crossing point X = P_i + t e_i; its parameter on Q's edge is X's
+      // projection onto that edge, not a second independent quotient: where
+      // the edges meet at a shallow angle both parameters are uncertain
+      // along the edges, and only a shared point keeps the two edges'
+      // contributions consistent (an error of X along the boundary then
+      // changes the area in proportion to the angle only).
+      const float t = fminf(fmaxf(o0 * fast_rcp(o0 - o1), 0.f), 1.f);
+      const float rx = fmaf(t, epx[i], P.x[i] - q.x), ry = fmaf(t, epy[i], P.y[i] - q.y);
+      const float s =
+          fminf(fmaxf((rx * fx + ry * fy) * fast_rcp(fmaf(fx, fx, fy * fy)), 0.f), 1.f);
+      const float sg = ((er >> j) & 1u) ? 1.f : -1.f;
+      const float ut = 1.f - t, us = 1.f - s;
+      L[i] = fmaf(sg, ut, L[i]);
+      float2 a = s_acc[j * BLOCK];
+      a.x = fmaf(-sg, us, a.x);
+      if (GRAD) {
+        W1[i] = fmaf(0.5f * sg, ut * ut, W1[i]);
+        a.y = fmaf(-0.5f * sg, us * us, a.y);
+      }
+      s_acc[j * BLOCK] = a;
     }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float2 a = s_acc[k * BLOCK];
+    M[k] = a.x;
+    V1[k] = a.y;
   }
 }
 
@@ -252,6 +262,7 @@ __global__ __launch_bounds__(simple_block<K>())
 __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_fwd(SimpleFwdArgs args) {
   constexpr int BLOCK = simple_block<K>();
   __shared__ float2 s_q[K * BLOCK];
+  __shared__ float2 s_acc[K * BLOCK];
   const int tid = threadIdx.x;
   const int64_t n = args.a.count;
   for (int64_t p = (int64_t)blockIdx.x * BLOCK + tid; p < n; p += (int64_t)gridDim.x * BLOCK) {
@@ -280,7 +291,8 @@ __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_fwd(Simple
     }
     const uint32_t inside = vertex0_inclusion<K>(P, n1, Q, n2, spr, sqr);
     float L[K], M[K], W1[K], V1[K];
-    crossing_sums<K, false>(P, n1, Q, n2, epx, epy, eqx, eqy, xrow, erow, exact, L, W1, M, V1);
+    crossing_sums<K, false, BLOCK>(P, n1, Q, n2, epx, epy, xrow, erow, exact, s_q + tid,
+                                   s_acc + tid, L, W1, M, V1);
     float ep[K], eq[K], cp[K], cq[K];
     vertex_inclusion<K>(inside, xrow, ep, eq);
     edge_cross<K>(P, n1, Q, n2, cp, cq);
@@ -308,9 +320,12 @@ __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_fwd(Simple
 template <int K>
 __global__ __launch_bounds__(simple_block<K>())
 __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_bwd(SimpleBwdArgs args) {
+  constexpr int BLOCK = simple_block<K>();
+  __shared__ float2 s_q[K * BLOCK];
+  __shared__ float2 s_acc[K * BLOCK];
+  const int tid = threadIdx.x;
   const int64_t n = args.a.count;
-  for (int64_t p = (int64_t)blockIdx.x * simple_block<K>() + threadIdx.x; p < n;
-       p += (int64_t)gridDim.x * simple_block<K>()) {
+  for (int64_t p = (int64_t)blockIdx.x * BLOCK + tid; p < n; p += (int64_t)gridDim.x * BLOCK) {
     const int n1 = poly_count(args.a.nv, p, args.a.kmax);
     const int n2 = poly_count(args.b.nv, p, args.b.kmax);
     Poly<K> P, Q;
@@ -327,7 +342,8 @@ __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_bwd(Simple
       erow[i] = (uint32_t)(sm >> (8 * i)) & 0xffu;
     }
     float L[K], M[K], W1[K], V1[K];
-    crossing_sums<K, true>(P, n1, Q, n2, epx, epy, eqx, eqy, xrow, erow, false, L, W1, M, V1);
+    crossing_sums<K, true, BLOCK>(P, n1, Q, n2, epx, epy, xrow, erow, false, s_q + tid, s_acc + tid,
+                                  L, W1, M, V1);
     float ep[K], eq[K], cp[K], cq[K];
     vertex_inclusion<K>(inside, xrow, ep, eq);
     edge_cross<K>(P, n1, Q, n2, cp, cq);
