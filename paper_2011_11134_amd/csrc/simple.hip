@@ -34,11 +34,12 @@ constexpr int simple_block() {
   return K == 8 ? 128 : 256;
 }
 
-// At K = 8 both kernels are held to 4 waves per SIMD (at most 128 VGPRs, a
-// few values spilled): left alone they take 149 / 160 registers and run 3.
+// At K = 8 both kernels are held to 3 waves per SIMD (at most 168 VGPRs):
+// left alone the backward takes more and runs 2; held to 4 it spills
+// 36 bytes a lane to scratch (HBM traffic) and measured slower.
 template <int K>
 constexpr int simple_waves() {
-  return K == 8 ? 4 : 1;
+  return K == 8 ? 3 : 1;
 }
 
 // Row masks of the tie-ruled sign table: bit j of spr[i] when P_i is strictly
