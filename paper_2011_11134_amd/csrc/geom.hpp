@@ -297,6 +297,23 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
     lpx[k] = P.x[k] - P.x[0];
     lpy[k] = P.y[k] - P.y[0];
   }
+  // polygon areas in the same frame (P_0 at the origin), here so that the
+  // polygons' registers are free once the crossings are placed
+  {
+    float s1 = 0.f, s2 = 0.f;
+    const float qx0 = Q.x[0] - P.x[0], qy0 = Q.y[0] - P.y[0];
+#pragma unroll
+    for (int k = 1; k + 1 < K; ++k) {
+      if (FIXED || k + 1 < n1) s1 += lpx[k] * lpy[k + 1] - lpy[k] * lpx[k + 1];
+      if (FIXED || k + 1 < n2) {
+        const float ux = Q.x[k] - P.x[0] - qx0, uy = Q.y[k] - P.y[0] - qy0;
+        const float vx = Q.x[k + 1] - P.x[0] - qx0, vy = Q.y[k + 1] - P.y[0] - qy0;
+        s2 += ux * vy - uy * vx;
+      }
+    }
+    res.a1 = 0.5f * s1;
+    res.a2 = 0.5f * s2;
+  }
   int cnt = 0;
   // Appends a point; only invalid input can pass the capacity, and its
   // extra points then overwrite the last slot (the overflow is reported).
@@ -422,20 +439,6 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
 #pragma unroll
   for (int w = 0; w < K / 2; ++w) res.codes[w] = codes[w];
 
-  // polygon areas in the same frame (P_0 at the origin)
-  float s1 = 0.f, s2 = 0.f;
-  const float qx0 = Q.x[0] - P.x[0], qy0 = Q.y[0] - P.y[0];
-#pragma unroll
-  for (int k = 1; k + 1 < K; ++k) {
-    if (FIXED || k + 1 < n1) s1 += lpx[k] * lpy[k + 1] - lpy[k] * lpx[k + 1];
-    if (FIXED || k + 1 < n2) {
-      const float ux = Q.x[k] - P.x[0] - qx0, uy = Q.y[k] - P.y[0] - qy0;
-      const float vx = Q.x[k + 1] - P.x[0] - qx0, vy = Q.y[k + 1] - P.y[0] - qy0;
-      s2 += ux * vy - uy * vx;
-    }
-  }
-  res.a1 = 0.5f * s1;
-  res.a2 = 0.5f * s2;
 }
 
 // IoU from the areas (2D), with the conventions: empty intersection or a

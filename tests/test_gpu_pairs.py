@@ -205,6 +205,44 @@ def test_autograd_function(dg):
     assert err[keep].max() <= GRAD_TOL
 
 
+def test_autograd_vs_central_differences(dg):
+    """The differentiation form on 4,096 pairs of the 1 Mi rectangle workload's
+    distribution: torch.autograd through the library's backward against
+    central differences of the FP64 IoU at h = 1e-3 (Richardson on h and h/2,
+    which removes the h^2 term), on pairs whose nx / xflags stay the same at
+    every perturbed point (the IoU is smooth there)."""
+    d = synth.c3_pairs(n=4096, seed=72)
+    a32, b32, g32 = d["a_xy"], d["b_xy"], d["grad"]
+    a = dev_t(a32).requires_grad_(True)
+    b = dev_t(b32).requires_grad_(True)
+    iou = dg.IoUPairs.apply(a, b)
+    (iou * dev_t(g32)).sum().backward()
+    gpu = np.concatenate([a.grad.cpu().numpy().reshape(4096, -1),
+                          b.grad.cpu().numpy().reshape(4096, -1)], 1).astype(np.float64)
+    a64, b64 = a32.astype(np.float64), b32.astype(np.float64)
+    _, nx0, xf0 = oracle.iou_pairs_f64(a64, b64)
+    stable = np.ones(4096, bool)
+    fd = np.zeros((4096, 16))
+    for c in range(16):
+        poly, k, ax = c // 8, (c % 8) // 2, c % 2
+
+        def at(step):
+            aa, bb = a64.copy(), b64.copy()
+            (aa if poly == 0 else bb)[:, k, ax] += step
+            v, nx, xf = oracle.iou_pairs_f64(aa, bb)
+            stable[:] &= (nx == nx0) & np.all(xf == xf0, axis=1)
+            return v
+
+        h = 1e-3
+        d1 = (at(h) - at(-h)) / (2 * h)
+        d2 = (at(h / 2) - at(-h / 2)) / h
+        fd[:, c] = g32 * (4 * d2 - d1) / 3
+    assert stable.mean() > 0.9
+    err = grad_rel_err(gpu, fd)
+    assert err[stable].max() <= GRAD_TOL, err[stable].max()
+    _say(str({"pairs_smooth_at_h": int(stable.sum()), "max_grad_err_vs_fd": float(err[stable].max())}))
+
+
 def test_invalid_arguments(dg):
     ctx = dg.context()
     ok = dg.Polys(0, None, None, None, 1, 4)  # pointer checked only when used
