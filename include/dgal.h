@@ -256,9 +256,10 @@ int dgal_area_backward(dgal_ctx *ctx, dgal_polys p, const float *grad_area,
  *       enters b there (vertex i of a lies right of edge j of b);
  *     inside [count] uint8: bit 0 when vertex 0 of a is inside b, bit 1 when
  *       vertex 0 of b is inside a.
- * Self-intersecting or clockwise input is not detected (results unspecified,
- * accesses in bounds); dgal_set_validate does not apply (its check is the
- * convex contract).
+ * Self-intersecting or clockwise input is not detected on the fast path
+ * (results unspecified, accesses in bounds); dgal_validate_simple checks it,
+ * and with dgal_set_validate on, this entry point and its backward run that
+ * check first.
  * DGAL_EINVAL: ctx NULL, invalid a or b, a.count != b.count, a z-extent
  * given, saved pointers partly NULL or misaligned, iou NULL with count > 0. */
 int dgal_iou_simple_pairs(dgal_ctx *ctx, dgal_polys a, dgal_polys b, float *iou,
@@ -297,6 +298,17 @@ int dgal_iou_simple_backward(dgal_ctx *ctx, dgal_polys a, dgal_polys b,
 int dgal_validate(dgal_ctx *ctx, dgal_polys p, uint8_t *status, int64_t *n_bad,
                   void *stream);
 
+/* The simple-polygon contract of dgal_iou_simple_pairs, checked per polygon:
+ * the vertex count is in [3, kmax]; no two non-adjacent edges touch or cross
+ * (collinear edges that do not overlap are allowed) and no two adjacent
+ * edges fold back onto each other; the shoelace area is positive
+ * (counter-clockwise).  Every test is the fp64 sign of the fp32 vertices
+ * evaluated in a fixed order.  status: 0 valid, 1 vertex count out of
+ * range, 2 edges meet or overlap, 3 area not positive; n_bad and errors as
+ * for dgal_validate. */
+int dgal_validate_simple(dgal_ctx *ctx, dgal_polys p, uint8_t *status,
+                         int64_t *n_bad, void *stream);
+
 /* Input checking before every call (off by default; on at dgal_create when
  * the environment holds DGAL_DEBUG_VALIDATE=1).  While on, dgal_iou_pairs,
  * dgal_iou_matrix, dgal_iou_backward, dgal_intersect and
@@ -305,7 +317,8 @@ int dgal_validate(dgal_ctx *ctx, dgal_polys p, uint8_t *status, int64_t *n_bad,
  * nothing else, if any polygon breaks the contract.  A debugging aid: it
  * synchronises the stream, so calls must not be captured in a graph while
  * it is on.  dgal_area and its backward accept any simple polygon and are
- * not checked.  DGAL_EINVAL: ctx NULL. */
+ * not checked; dgal_iou_simple_pairs and its backward run the check of
+ * dgal_validate_simple instead.  DGAL_EINVAL: ctx NULL. */
 int dgal_set_validate(dgal_ctx *ctx, int32_t enable);
 
 /* Launch-shape autotuning of the batched kernels (the grid of the pair

@@ -48,6 +48,8 @@ def lib():
         L.oracle_simple_margins.restype = None
         L.oracle_simple_valid.argtypes = [_f64p, i32]
         L.oracle_simple_valid.restype = i32
+        L.oracle_simple_statuses.argtypes = [i64, i64, _f32p, _u8p, i32, _u8p]
+        L.oracle_simple_statuses.restype = None
         L.oracle_intersect.argtypes = [_f64p, i32, _f64p, i32, _f64p, _u8p]
         L.oracle_intersect.restype = i32
         L.oracle_area.argtypes = [_f64p, i32]
@@ -478,6 +480,17 @@ def simple_valid(xy):
     """True if the [n, 2] polygon is simple, counter-clockwise, 3..8 vertices."""
     xy = np.ascontiguousarray(xy, np.float64)
     return bool(lib().oracle_simple_valid(_p(xy, _f64p), xy.shape[0]))
+
+
+def simple_status(xy, nv=None):
+    """Simple-polygon contract status of each polygon of a [n, kmax, 2] fp32
+    array: 0 valid, 1 vertex count outside [3, kmax], 2 edges meet or
+    overlap, 3 area not positive (clockwise or flat).  uint8 [n]."""
+    keep, args = _poly2(xy, nv)
+    n = keep[0].shape[0]
+    out = np.zeros(n, np.uint8)
+    lib().oracle_simple_statuses(0, n, *args, _p(out, _u8p))
+    return out
 
 
 def simple_iou_pairs(a_xy, b_xy, a_nv=None, b_nv=None, threads=1):

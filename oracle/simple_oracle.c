@@ -327,13 +327,36 @@ void oracle_simple_margins(int64_t lo, int64_t hi, const float *a_xy, const uint
   }
 }
 
-/* Input check for simple polygons: 1 if the polygon has 3..8 vertices, no
+/* Input check for simple polygons: 0 if the polygon has 3..8 vertices, no
  * two non-adjacent edges meet, no two adjacent edges overlap, and its
- * shoelace area is positive (counter-clockwise). */
+ * shoelace area is positive (counter-clockwise); else 1 (vertex count),
+ * 2 (edges meet or overlap) or 3 (area not positive). */
+static int s_status(const spt *v, int n);
+
 int oracle_simple_valid(const double *xy, int n) {
   if (n < 3 || n > SMP_MAXV) return 0;
   spt v[SMP_MAXV];
   for (int k = 0; k < n; ++k) v[k] = (spt){xy[2 * k], xy[2 * k + 1]};
+  return s_status(v, n) == 0;
+}
+
+/* Status of polygons [lo, hi) of a [count][kmax][2] fp32 array. */
+void oracle_simple_statuses(int64_t lo, int64_t hi, const float *xy, const uint8_t *nv, int kmax,
+                            uint8_t *status) {
+  for (int64_t i = lo; i < hi; ++i) {
+    const int n = nv ? (int)nv[i] : kmax;
+    if (n < 3 || n > kmax || n > SMP_MAXV) {
+      status[i] = 1;
+      continue;
+    }
+    spt v[SMP_MAXV];
+    const float *r = xy + i * (int64_t)kmax * 2;
+    for (int k = 0; k < n; ++k) v[k] = (spt){(double)r[2 * k], (double)r[2 * k + 1]};
+    status[i] = (uint8_t)s_status(v, n);
+  }
+}
+
+static int s_status(const spt *v, int n) {
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j) {
       spt a = v[i], b = v[(i + 1) % n], c = v[j], d = v[(j + 1) % n];
@@ -347,7 +370,7 @@ int oracle_simple_valid(const double *xy, int n) {
         spt w = (j == i + 1) ? d : c;               /* far end of edge j */
         if (s_orient(u, s, w) == 0.0 &&
             ((u.x - s.x) * (w.x - s.x) + (u.y - s.y) * (w.y - s.y)) > 0)
-          return 0;
+          return 2;
         continue;
       }
       const int s1 = s_sign(o1), s2 = s_sign(o2), s3 = s_sign(o3), s4 = s_sign(o4);
@@ -360,8 +383,8 @@ int oracle_simple_valid(const double *xy, int n) {
           const double ly2 = fmin(c.y, d.y), hy2 = fmax(c.y, d.y);
           if (hi1 < lo2 || hi2 < lo1 || hy1 < ly2 || hy2 < ly1) continue;
         }
-        return 0;
+        return 2;
       }
     }
-  return s_shoelace(v, n) > 0.0;
+  return s_shoelace(v, n) > 0.0 ? 0 : 3;
 }

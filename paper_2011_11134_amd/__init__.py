@@ -52,7 +52,7 @@ EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
            "dgal_intersect", "dgal_intersect_backward", "dgal_area", "dgal_area_backward",
            "dgal_iou_boxes", "dgal_iou_boxes_backward", "dgal_set_autotune",
            "dgal_autotune_report", "dgal_validate", "dgal_set_validate",
-           "dgal_iou_simple_pairs", "dgal_iou_simple_backward")
+           "dgal_iou_simple_pairs", "dgal_iou_simple_backward", "dgal_validate_simple")
 
 
 def _load():
@@ -95,6 +95,8 @@ def _load():
     L.dgal_autotune_report.restype = ctypes.c_int
     L.dgal_validate.argtypes = [_vp, Polys, _vp, _vp, _vp]
     L.dgal_validate.restype = ctypes.c_int
+    L.dgal_validate_simple.argtypes = [_vp, Polys, _vp, _vp, _vp]
+    L.dgal_validate_simple.restype = ctypes.c_int
     L.dgal_set_validate.argtypes = [_vp, i32]
     L.dgal_set_validate.restype = ctypes.c_int
     L.dgal_iou_simple_pairs.argtypes = [_vp, Polys, Polys, _vp, _vp, _vp, _vp, _vp]
@@ -488,6 +490,19 @@ def validate(xy, nv=None):
     n_bad = torch.empty(1, dtype=torch.int64, device=xy.device)
     _ok(lib.dgal_validate(context(xy.device), p, _ptr(status), _ptr(n_bad), _stream(xy)),
         "dgal_validate")
+    return status, int(n_bad.item())
+
+
+def validate_simple(xy, nv=None):
+    """Simple-polygon contract status of each polygon, checked on the GPU:
+    (status uint8 [n]: 0 valid, 1 vertex count outside [3, kmax], 2 edges
+    meet or overlap, 3 area not positive; number of invalid polygons)."""
+    p, keep = polys(xy, nv)
+    n = xy.shape[0]
+    status = torch.empty(n, dtype=torch.uint8, device=xy.device)
+    n_bad = torch.empty(1, dtype=torch.int64, device=xy.device)
+    _ok(lib.dgal_validate_simple(context(xy.device), p, _ptr(status), _ptr(n_bad), _stream(xy)),
+        "dgal_validate_simple")
     return status, int(n_bad.item())
 
 

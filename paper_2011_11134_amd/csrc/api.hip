@@ -108,7 +108,8 @@ std::vector<dgal::LaunchShape> matrix_bwd_shapes() {
 // environment when the context was created), every polygon of the call's
 // sets is checked on the device against the contract of Sec. III, and the
 // call waits for the count: DGAL_EINVAL if any polygon breaks it.
-int debug_validate(dgal_ctx* ctx, hipStream_t s, const dgal_polys& a, const dgal_polys* b) {
+int debug_validate(dgal_ctx* ctx, hipStream_t s, const dgal_polys& a, const dgal_polys* b,
+                   bool simple = false) {
   if (!ctx->validate) return DGAL_OK;
   if (!valid_polys(a) || (b && !valid_polys(*b))) return DGAL_EINVAL;
   DeviceGuard g(ctx->v.device);
@@ -117,7 +118,7 @@ int debug_validate(dgal_ctx* ctx, hipStream_t s, const dgal_polys& a, const dgal
   for (const dgal_polys* p : sets) {
     if (p == nullptr || p->count == 0) continue;
     const dgal::PolyArgs pa = poly_args(*p, 8);
-    if (dgal::launch_validate(pa, nullptr, ctx->n_bad, s) != hipSuccess) return DGAL_EHIP;
+    if (dgal::launch_validate(pa, nullptr, ctx->n_bad, simple, s) != hipSuccess) return DGAL_EHIP;
     int64_t host = 0;
     if (hipMemcpyAsync(&host, ctx->n_bad, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -426,6 +427,7 @@ int dgal_iou_simple_pairs(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* iou,
   if (save && (!aligned(xmask, 8) || !aligned(smask, 8))) return DGAL_EINVAL;
   if (a.count == 0) return DGAL_OK;
   if (iou == nullptr) return DGAL_EINVAL;
+  if (int st = debug_validate(ctx, static_cast<hipStream_t>(stream), a, &b, true)) return st;
   DeviceGuard g(ctx->v.device);
   if (!g.ok) return DGAL_EHIP;
   const int K = reg_k(a.kmax, b.kmax);
@@ -450,6 +452,7 @@ int dgal_iou_simple_backward(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const fl
     return DGAL_EINVAL;
   if (!aligned(xmask, 8) || !aligned(smask, 8) || !aligned(grad_a_xy, 8) || !aligned(grad_b_xy, 8))
     return DGAL_EINVAL;
+  if (int st = debug_validate(ctx, static_cast<hipStream_t>(stream), a, &b, true)) return st;
   DeviceGuard g(ctx->v.device);
   if (!g.ok) return DGAL_EHIP;
   const int K = reg_k(a.kmax, b.kmax);
@@ -472,8 +475,20 @@ int dgal_validate(dgal_ctx* ctx, dgal_polys p, uint8_t* status, int64_t* n_bad, 
   if (p.count > 0 && p.xy == nullptr) return DGAL_EINVAL;
   DeviceGuard g(ctx->v.device);
   if (!g.ok) return DGAL_EHIP;
-  return status_of(
-      dgal::launch_validate(poly_args(p, 8), status, n_bad, static_cast<hipStream_t>(stream)));
+  return status_of(dgal::launch_validate(poly_args(p, 8), status, n_bad, false,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+int dgal_validate_simple(dgal_ctx* ctx, dgal_polys p, uint8_t* status, int64_t* n_bad,
+                         void* stream) {
+  if (ctx == nullptr || !valid_polys(p)) return DGAL_EINVAL;
+  if (status == nullptr && n_bad == nullptr) return DGAL_EINVAL;
+  if (n_bad != nullptr && !aligned(n_bad, 8)) return DGAL_EINVAL;
+  if (p.count > 0 && p.xy == nullptr) return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  return status_of(dgal::launch_validate(poly_args(p, 8), status, n_bad, true,
+                                         static_cast<hipStream_t>(stream)));
 }
 
 int dgal_set_validate(dgal_ctx* ctx, int32_t enable) {

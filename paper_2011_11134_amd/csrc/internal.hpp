@@ -199,8 +199,9 @@ hipError_t launch_boxes_bwd(const BoxesBwdArgs& args, bool z3, hipStream_t strea
 hipError_t launch_simple_fwd(const SimpleFwdArgs& args, int K, hipStream_t stream);
 hipError_t launch_simple_bwd(const SimpleBwdArgs& args, int K, hipStream_t stream);
 // Input-contract status per polygon (status may be NULL) and the number of
-// invalid ones (n_bad may be NULL; zeroed first, on the stream).
-hipError_t launch_validate(const PolyArgs& p, uint8_t* status, int64_t* n_bad,
+// invalid ones (n_bad may be NULL; zeroed first, on the stream); the convex
+// contract, or the simple-polygon one.
+hipError_t launch_validate(const PolyArgs& p, uint8_t* status, int64_t* n_bad, bool simple,
                            hipStream_t stream);
 
 }  // namespace dgal

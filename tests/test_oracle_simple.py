@@ -60,6 +60,24 @@ def test_simple_validity_facts(orc):
     assert not orc.simple_valid(np.array([[0, 0], [1, 1], [1, 0], [0, 1]], float))  # bow tie
     assert not orc.simple_valid(np.array([[0, 0], [2, 0], [1, 0], [1, 1]], float))  # folds back
     assert orc.simple_valid(np.array([[0, 0], [1, 0], [2, 0], [1, 1]], float))      # straight vertex
+    # status codes on fp32 rows: valid, edges meet / overlap, clockwise, count
+    rows = [
+        ([[0, 0], [2, 0], [2, 1], [1, 1], [1, 2], [0, 2]], 6, 0),            # L shape
+        ([[0, 0], [0, 2], [1, 2], [1, 1], [2, 1], [2, 0]], 6, 3),            # L, clockwise
+        ([[0, 0], [3, 0], [3, 2], [2, 2], [2, 1], [1, 1], [1, 2], [0, 2]], 8, 0),  # U: collinear top edges apart
+        ([[0, 0], [1, 1], [1, 0], [0, 1]], 4, 2),                            # bow tie
+        ([[0, 0], [2, 0], [1, 0], [1, 1]], 4, 2),                            # folds back
+        ([[0, 0], [1, 0], [1, 0], [1, 1], [0, 1]], 5, 2),                    # repeated vertex
+        ([[0, 0], [1, 0], [2, 0], [1, 1]], 4, 0),                            # straight vertex
+        ([[0, 0], [2, 0], [2, 2], [1, 0.0], [0, 2]], 5, 2),                  # vertex on an edge
+        ([[0, 0], [1, 0], [0, 1]], 2, 1),
+        ([[0, 0], [1, 0], [0, 1]], 9, 1),
+    ]
+    xy = np.zeros((len(rows), 8, 2), np.float32)
+    for r, (v, n, _) in enumerate(rows):
+        xy[r, :len(v)] = v
+    nv = np.array([r[1] for r in rows], np.uint8)
+    assert list(orc.simple_status(xy, nv)) == [r[2] for r in rows]
 
 
 def test_slab_area_exact_fan(orc):
