@@ -351,22 +351,29 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
         if constexpr (KEEP_OP) {
           o0 = oP[i][j];
           o1 = oP[inx][j];
-        } else if (!exact) {
-          // the table's expression, recomputed; the empty asm hides that it
-          // is the same value, which would otherwise keep all K*K products
-          // live from the table to here (certified signs survive any
-          // difference in rounding between the two evaluations)
-          float qx = Q.x[j], qy = Q.y[j];
-          asm volatile("" : "+v"(qx), "+v"(qy));
-          o0 = eqx[j] * (P.y[i] - qy) - eqy[j] * (P.x[i] - qx);
-          o1 = eqx[j] * (P.y[inx] - qy) - eqy[j] * (P.x[inx] - qx);
+          const float t = o0 * fast_rcp(o0 - o1);
+          put(true, fmaf(t, epx[i], lpx[i]), fmaf(t, epy[i], lpy[i]), kCodeX | (i << 3) | j);
         } else {
+          // The table's expressions, recomputed from copies of the vertices
+          // that an empty asm makes opaque: otherwise the compiler keeps the
+          // K*K table values, or the edge vectors and the local frame, live
+          // from the table to here (certified signs survive any difference
+          // in rounding between the two evaluations).
+          float qx = Q.x[j], qy = Q.y[j], px = P.x[i], py = P.y[i];
+          asm volatile("" : "+v"(qx), "+v"(qy), "+v"(px), "+v"(py));
           const int jn = next_idx<K, FIXED>(j, n2);
-          o0 = (float)orient64(Q.x[j], Q.y[j], Q.x[jn], Q.y[jn], P.x[i], P.y[i]);
-          o1 = (float)orient64(Q.x[j], Q.y[j], Q.x[jn], Q.y[jn], P.x[inx], P.y[inx]);
+          const float fx = Q.x[jn] - qx, fy = Q.y[jn] - qy;
+          const float ex = P.x[inx] - px, ey = P.y[inx] - py;
+          if (!exact) {
+            o0 = fx * (py - qy) - fy * (px - qx);
+            o1 = fx * (P.y[inx] - qy) - fy * (P.x[inx] - qx);
+          } else {
+            o0 = (float)orient64(qx, qy, Q.x[jn], Q.y[jn], px, py);
+            o1 = (float)orient64(qx, qy, Q.x[jn], Q.y[jn], P.x[inx], P.y[inx]);
+          }
+          const float t = o0 * fast_rcp(o0 - o1);
+          put(true, fmaf(t, ex, px - P.x[0]), fmaf(t, ey, py - P.y[0]), kCodeX | (i << 3) | j);
         }
-        const float t = o0 * fast_rcp(o0 - o1);
-        put(true, fmaf(t, epx[i], lpx[i]), fmaf(t, epy[i], lpy[i]), kCodeX | (i << 3) | j);
       }
     }
   }

@@ -131,6 +131,22 @@ def test_near_degenerate_fallback(dg):
     assert np.array_equal(gpu["nx"], nx)
 
 
+@pytest.mark.parametrize("shift,scale", [((1.0e4, -3.0e4), 1.0), ((0.0, 0.0), 2.0 ** -10),
+                                         ((0.0, 0.0), 2.0 ** 10), ((-5.0e3, 7.0e3), 2.0 ** -4)])
+def test_precision_far_and_scaled(dg, shift, scale):
+    """IoU is invariant to translation and scale; the kernels work in the
+    frame of the first polygon's first vertex, where differences of nearby
+    fp32 coordinates are exact, so pairs far from the origin or at other
+    scales keep the 1e-5 IoU bound against the oracle on the same fp32
+    inputs (power-of-two scales keep the shapes exact)."""
+    d = synth.c1_pairs(n=8192, seed=73)
+    off = np.array(shift, np.float64)
+    a = (d["a_xy"].astype(np.float64) * scale + off).astype(np.float32)
+    b = (d["b_xy"].astype(np.float64) * scale + off).astype(np.float32)
+    _say(f"case: c1 pairs shifted {shift} scaled {scale}")
+    _say(str(compare_pairs(dg, a, b, grad=d["grad"], require_filtered_frac=0.9)))
+
+
 def test_empty_and_single(dg):
     e = np.zeros((0, 4, 2), np.float32)
     iou, nx, xf = dg.iou_pairs(dev_t(e), dev_t(e))
