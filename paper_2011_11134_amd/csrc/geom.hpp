@@ -340,40 +340,56 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
     const uint32_t r = sqr[i];
     const uint32_t rn = FIXED ? ((r >> 1) | (r << (K - 1))) : ((r >> 1) | ((r & 1u) << (n2 - 1)));
     const uint32_t xm = (spr[i] ^ spr[inx]) & (r ^ rn) & jmask;
+    // P edge i meets Q edge j at P_i + t e_i, t = o_i / (o_i - o_i1); the two
+    // values have opposite signs (or one is an exact zero that the tie rule
+    // signed), so the difference is never zero for coordinates whose
+    // products stay normal floats.  Crossings are placed in ascending j.
+    if constexpr (KEEP_OP) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-      if ((FIXED || i < n1) && ((xm >> j) & 1u)) {
-        // P edge i meets Q edge j at P_i + t e_i, t = o_i / (o_i - o_i1); the
-        // two values have opposite signs (or one is an exact zero that the
-        // tie rule signed), so the difference is never zero for coordinates
-        // whose products stay normal floats
-        float o0, o1;
-        if constexpr (KEEP_OP) {
-          o0 = oP[i][j];
-          o1 = oP[inx][j];
+      for (int j = 0; j < K; ++j) {
+        if ((FIXED || i < n1) && ((xm >> j) & 1u)) {
+          const float o0 = oP[i][j], o1 = oP[inx][j];
           const float t = o0 * fast_rcp(o0 - o1);
           put(true, fmaf(t, epx[i], lpx[i]), fmaf(t, epy[i], lpy[i]), kCodeX | (i << 3) | j);
-        } else {
-          // The table's expressions, recomputed from copies of the vertices
-          // that an empty asm makes opaque: otherwise the compiler keeps the
-          // K*K table values, or the edge vectors and the local frame, live
-          // from the table to here (certified signs survive any difference
-          // in rounding between the two evaluations).
-          float qx = Q.x[j], qy = Q.y[j], px = P.x[i], py = P.y[i];
-          asm volatile("" : "+v"(qx), "+v"(qy), "+v"(px), "+v"(py));
-          const int jn = next_idx<K, FIXED>(j, n2);
-          const float fx = Q.x[jn] - qx, fy = Q.y[jn] - qy;
-          const float ex = P.x[inx] - px, ey = P.y[inx] - py;
-          if (!exact) {
-            o0 = fx * (py - qy) - fy * (px - qx);
-            o1 = fx * (P.y[inx] - qy) - fy * (P.x[inx] - qx);
-          } else {
-            o0 = (float)orient64(qx, qy, Q.x[jn], Q.y[jn], px, py);
-            o1 = (float)orient64(qx, qy, Q.x[jn], Q.y[jn], P.x[inx], P.y[inx]);
-          }
-          const float t = o0 * fast_rcp(o0 - o1);
-          put(true, fmaf(t, ex, px - P.x[0]), fmaf(t, ey, py - P.y[0]), kCodeX | (i << 3) | j);
         }
+      }
+    } else {
+      // Eight slots: the edge walks the set bits of its row (a convex Q is
+      // crossed at most twice by an edge, so a wavefront takes at most two
+      // steps) and selects Q's edge from registers.  The table's expressions
+      // are recomputed from copies of P's vertex that an empty asm makes
+      // opaque: otherwise the compiler keeps the K*K table values, or the
+      // edge vectors and the local frame, live from the table to here
+      // (certified signs survive any difference in rounding between the two
+      // evaluations).
+      float px = P.x[i], py = P.y[i];
+      asm volatile("" : "+v"(px), "+v"(py));
+      const float ex = P.x[inx] - px, ey = P.y[inx] - py;
+      const float lx = px - P.x[0], ly = py - P.y[0];
+      uint32_t row = (FIXED || i < n1) ? xm : 0u;
+      while (row) {
+        const int j = __builtin_ctz(row);
+        row &= row - 1u;
+        const int jn = FIXED ? ((j + 1) & (K - 1)) : (j + 1 < n2 ? j + 1 : 0);
+        float qx = Q.x[0], qy = Q.y[0], qnx = Q.x[0], qny = Q.y[0];
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+          qx = k == j ? Q.x[k] : qx;
+          qy = k == j ? Q.y[k] : qy;
+          qnx = k == jn ? Q.x[k] : qnx;
+          qny = k == jn ? Q.y[k] : qny;
+        }
+        float o0, o1;
+        if (!exact) {
+          const float fx = qnx - qx, fy = qny - qy;
+          o0 = fx * (py - qy) - fy * (px - qx);
+          o1 = fx * (P.y[inx] - qy) - fy * (P.x[inx] - qx);
+        } else {
+          o0 = (float)orient64(qx, qy, qnx, qny, px, py);
+          o1 = (float)orient64(qx, qy, qnx, qny, P.x[inx], P.y[inx]);
+        }
+        const float t = o0 * fast_rcp(o0 - o1);
+        put(true, fmaf(t, ex, lx), fmaf(t, ey, ly), kCodeX | (uint32_t)(i << 3) | (uint32_t)j);
       }
     }
   }
