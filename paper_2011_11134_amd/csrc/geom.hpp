@@ -671,27 +671,56 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   constexpr uint32_t S = BLOCK * sizeof(float2);
   const uint32_t n1S = (uint32_t)n1 * S, nqS = (uint32_t)(K + n2) * S;
   auto code_at = [&](int r) { return (codes[r >> 2] >> ((r & 3) * 8)) & 0xffu; };
-  SlotGeom g0, gc, gn;
+  SlotGeom g0, gc;
   const float2 X0 = rebuild_slot<K, FIXED, BLOCK>(code_at(0), n1S, nqS, s_tab, s_v, g0);
   const float2 X1 = rebuild_slot<K, FIXED, BLOCK>(code_at(1), n1S, nqS, s_tab, s_v, gc);
-  gn = gc;
   float2 prev = X0, cur = X1, last = X0;
   float acc = 0.f;  // twice the intersection area, about X0
+  if constexpr (K == 4) {
+    // Every slot is visited (a wavefront mostly runs to its eighth slot
+    // anyway); slots at or past nx are masked by selects, not branches, so
+    // that the rolling window needs no copies: a masked slot routes a zero
+    // gradient with t = 1/den = 0 (its rebuilt point, from a padding code,
+    // may be far off or infinite and is never multiplied in).
 #pragma unroll
-  for (int r = 1; r < CAP; ++r) {
-    if (r < m) {
+    for (int r = 1; r < CAP; ++r) {
+      const bool live = r < m;
       float2 nxt = X0;
-      if (r + 1 < CAP && r + 1 < m) {
-        nxt = rebuild_slot<K, FIXED, BLOCK>(code_at(r + 1), n1S, nqS, s_tab, s_v, gn);
-        acc += (cur.x - X0.x) * (nxt.y - X0.y) - (cur.y - X0.y) * (nxt.x - X0.x);
+      SlotGeom gn = gc;
+      if (r + 1 < CAP) {
+        const float2 xr = rebuild_slot<K, FIXED, BLOCK>(code_at(r + 1), n1S, nqS, s_tab, s_v, gn);
+        const bool has = r + 1 < m;
+        nxt = has ? xr : X0;
+        const float term = (cur.x - X0.x) * (nxt.y - X0.y) - (cur.y - X0.y) * (nxt.x - X0.x);
+        acc += has ? term : 0.f;
       }
       // d(2I)/dX_r = (y_r+1 - y_r-1, x_r-1 - x_r+1)
-      route_slot(nxt.y - prev.y, prev.x - nxt.x, gc.t, gc.idn, gc.oa, gc.ob, gc.oc, gc.od, s_v,
-                 s_g);
-      last = cur;
+      route_slot(live ? nxt.y - prev.y : 0.f, live ? prev.x - nxt.x : 0.f, live ? gc.t : 0.f,
+                 live ? gc.idn : 0.f, gc.oa, gc.ob, gc.oc, gc.od, s_v, s_g);
+      last = live ? cur : last;
       prev = cur;
       cur = nxt;
       gc = gn;
+    }
+  } else {
+    // sixteen slots, of which a wavefront's polygons use far fewer: stop at
+    // the longest (branches, at the price of copies of the rolling window)
+#pragma unroll
+    for (int r = 1; r < CAP; ++r) {
+      if (r < m) {
+        float2 nxt = X0;
+        SlotGeom gn = gc;
+        if (r + 1 < CAP && r + 1 < m) {
+          nxt = rebuild_slot<K, FIXED, BLOCK>(code_at(r + 1), n1S, nqS, s_tab, s_v, gn);
+          acc += (cur.x - X0.x) * (nxt.y - X0.y) - (cur.y - X0.y) * (nxt.x - X0.x);
+        }
+        route_slot(nxt.y - prev.y, prev.x - nxt.x, gc.t, gc.idn, gc.oa, gc.ob, gc.oc, gc.od, s_v,
+                   s_g);
+        last = cur;
+        prev = cur;
+        cur = nxt;
+        gc = gn;
+      }
     }
   }
   if (m > 0) route_slot(X1.y - last.y, last.x - X1.x, g0.t, g0.idn, g0.oa, g0.ob, g0.oc, g0.od,
