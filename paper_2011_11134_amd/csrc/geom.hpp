@@ -445,7 +445,26 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
   }
 #pragma unroll
   for (int r = 1; r < CAP; ++r) {
-    if (r < m) {
+    if constexpr (K == 4) {
+      // every slot is read (the key's low bits always name one of this
+      // lane's slots) and the ones at or past m are masked by selects, so
+      // that the rolling pair needs no register copies; a dead slot may hold
+      // anything and is never added in
+      const bool live = r < m;
+      const int slot = (int)(key[r] & (uint32_t)(CAP - 1));
+      const float2 v = s_pt[slot * BLOCK];
+      const float vx = v.x - x[0], vy = v.y - y[0];
+      if (r >= 2) {
+        const float term = px_prev * vy - py_prev * vx;
+        acc += live ? term : 0.f;
+      }
+      px_prev = vx;
+      py_prev = vy;
+      const uint32_t c = live ? (uint32_t)s_cd[slot * BLOCK] : 0xffu;
+      const int sh = (r & 3) * 8;
+      codes[r >> 2] = (codes[r >> 2] & ~(0xffu << sh)) | (c << sh);
+      if (EMIT) ov[r] = live ? make_float2(v.x + P.x[0], v.y + P.y[0]) : make_float2(0.f, 0.f);
+    } else if (r < m) {
       const int slot = (int)(key[r] & (uint32_t)(CAP - 1));
       const float2 v = s_pt[slot * BLOCK];
       const float vx = v.x - x[0], vy = v.y - y[0];
