@@ -686,6 +686,7 @@ struct BwdArgs {
   const int32_t* tile_count;
   int64_t tile_capacity;
   int cap;
+  bool flags_vec;  // cap == 2K and s_flags aligned to cap bytes: whole-row loads
   float* ga_xy;
   float* gb_xy;  // unused when self_pairs
   float* ga_z;
@@ -703,7 +704,13 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int CAP = 2 * K;
   constexpr int ROW = 2 * K + 2;  // accumulated floats per row: xy slots, then (zlo, zhi)
-  __shared__ float s_acc[WAVES][kTileRows * ROW];
+  // Each quarter of the wavefront adds into its own copy of the row sums:
+  // the entries of a row group come from few rows, so one copy would see
+  // up to 64 lanes adding into the same 8 rows' words (serialised LDS
+  // atomics); four copies cut that by four and are summed at the end.
+  constexpr int COPIES = 4;
+  constexpr int ACC = kTileRows * ROW;
+  __shared__ float s_acc[WAVES][COPIES * ACC];
   __shared__ float2 s_v[CAP * BLOCK];
   __shared__ float2 s_g[CAP * BLOCK];
   __shared__ uint2 s_tab[256];
@@ -725,7 +732,7 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
     const int nr = (int)min((int64_t)kTileRows, g.na - r0);
     const int64_t nct = col_tiles_of(g);
     const int64_t t0 = (segmented ? m.seg.tile_prefix[s] : 0) + tr * nct;
-    for (int i = lane; i < kTileRows * ROW; i += 64) acc_w[i] = 0.f;
+    for (int i = lane; i < COPIES * ACC; i += 64) acc_w[i] = 0.f;
     wave_sync();
     // the row group's tiles are consecutive, so are their entries
     const int64_t t1 = t0 + nct - 1;
@@ -751,14 +758,28 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
         load_poly<K, FIXED>(m.a.xy, ia, m.a.kmax, m.a.vec4, n1, P);
         load_poly<K, FIXED>(m.b.xy, ib, m.b.kmax, m.b.vec4, n2, Q);
         uint32_t codes[K / 2];
-#pragma unroll
-        for (int w = 0; w < K / 2; ++w) codes[w] = 0xffffffffu;
         const uint8_t* row = m.s_flags + e * (int64_t)m.cap;
+        if (m.flags_vec) {
+          if constexpr (K == 4) {
+            const uint2 w = *reinterpret_cast<const uint2*>(row);
+            codes[0] = w.x;
+            codes[1] = w.y;
+          } else {
+            const uint4 w = *reinterpret_cast<const uint4*>(row);
+            codes[0] = w.x;
+            codes[1] = w.y;
+            codes[2] = w.z;
+            codes[3] = w.w;
+          }
+        } else {
 #pragma unroll
-        for (int k = 0; k < CAP; ++k) {
-          if (k < m.cap) {
-            const uint32_t cc = row[k];
-            codes[k >> 2] = (codes[k >> 2] & ~(0xffu << ((k & 3) * 8))) | (cc << ((k & 3) * 8));
+          for (int w = 0; w < K / 2; ++w) codes[w] = 0xffffffffu;
+#pragma unroll
+          for (int k = 0; k < CAP; ++k) {
+            if (k < m.cap) {
+              const uint32_t cc = row[k];
+              codes[k >> 2] = (codes[k >> 2] & ~(0xffu << ((k & 3) * 8))) | (cc << ((k & 3) * 8));
+            }
           }
         }
         // self pairs: pair (k, i) gives box i the column-role gradient of an
@@ -776,7 +797,7 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
         float2 gP[K], gQ[K], gz1, gz2;
         pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
                                            s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2);
-        float* acc = acc_w + rl * ROW;
+        float* acc = acc_w + (lane >> 4) * ACC + rl * ROW;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           if (FIXED || k < n1) {
@@ -809,7 +830,9 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
     for (int i = lane; i < nr * ROW; i += 64) {
       const int rl = i / ROW, k = i - rl * ROW;
       const int64_t ia = g.a0 + r0 + rl;
-      const float v = acc_w[i];
+      float v = acc_w[i];
+#pragma unroll
+      for (int c = 1; c < COPIES; ++c) v += acc_w[c * ACC + i];
       if (k < 2 * K) {
         if (k < 2 * m.a.kmax) m.ga_xy[ia * (int64_t)m.a.kmax * 2 + k] = v;
       } else if (Z3) {
@@ -1004,6 +1027,8 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
   m.pair_id = saved->pair_id;
   m.s_nx = saved->nx;
   m.s_flags = saved->xflags;
+  m.flags_vec = a.kmax + b.kmax == 2 * reg_k(a.kmax, b.kmax) &&
+                aligned(saved->xflags, (uintptr_t)(a.kmax + b.kmax));
   m.capacity = saved->capacity;
   m.tile_start = saved->tile_start;
   m.tile_count = saved->tile_count;
