@@ -471,7 +471,7 @@ def main():
     # --graph: the forward and the backward of one step are captured once into
     # a HIP graph (the library allocates nothing per call and needs no host
     # sync) and the graph is replayed; by default the two are launched eagerly
-    # (same throughput on this path: one kernel each, ~2.5 us apart).
+    # (graph replay measured a few percent slower on every workload).
     if args.graph:
         g_step = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g_step):
