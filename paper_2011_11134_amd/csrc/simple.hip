@@ -336,11 +336,14 @@ __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_bwd(Simple
     (void)edges<K>(P, n1, Q, n2, epx, epy, eqx, eqy);
     const uint64_t xm = args.xmask[p], sm = args.smask[p];
     const uint32_t inside = args.inside[p];
+    // only the bits of real edge pairs are read, so that a mask that does not
+    // fit the pair (invalid saved state) still addresses this lane's slots
+    const uint32_t jmask = (1u << n2) - 1u;
     uint32_t xrow[K], erow[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      xrow[i] = (uint32_t)(xm >> (8 * i)) & 0xffu;
-      erow[i] = (uint32_t)(sm >> (8 * i)) & 0xffu;
+      xrow[i] = i < n1 ? (uint32_t)(xm >> (8 * i)) & jmask : 0u;
+      erow[i] = (uint32_t)(sm >> (8 * i)) & jmask;
     }
     float L[K], M[K], W1[K], V1[K];
     crossing_sums<K, true, BLOCK>(P, n1, Q, n2, epx, epy, xrow, erow, false, s_q + tid, s_acc + tid,
