@@ -2,7 +2,8 @@
 the FP64 oracle on the same seeded fp32 inputs, and compare.
 
 Parity bar: nx and xflags bit-exact on the generator-filtered (non-degenerate)
-set; |IoU - IoU_oracle| <= 1e-5 on every pair; per-pair gradient relative
+set, and on every pair nx and the set of xflags codes equal; |IoU -
+IoU_oracle| <= 1e-5 on every pair; per-pair gradient relative
 error ||g - g_ref|| / max(||g_ref||, 1e-8) <= 1e-3 against the oracle's
 analytic gradient (on pairs whose structure both sides agree on).
 """
@@ -62,6 +63,12 @@ def compare_pairs(dg, a, b, a_nv=None, b_nv=None, a_z=None, b_z=None, grad=None,
     assert np.array_equal(gpu["nx"][keep], ref_nx[keep]), np.nonzero(gpu["nx"][keep] != ref_nx[keep])
     mism = np.nonzero(np.any(gpu["xflags"][keep] != ref_xf[keep], axis=1))[0]
     assert mism.size == 0, (mism[:5], gpu["xflags"][keep][mism[:3]], ref_xf[keep][mism[:3]])
+    # every pair: the same count and the same set of codes, since the signs
+    # that select them are exact on both sides; only their order may differ
+    # where points (nearly) coincide, and the IoU check below covers it
+    assert np.array_equal(gpu["nx"], ref_nx), np.nonzero(gpu["nx"] != ref_nx)[0][:5]
+    diff = np.nonzero(np.any(np.sort(gpu["xflags"], axis=1) != np.sort(ref_xf, axis=1), axis=1))[0]
+    assert diff.size == 0, (diff[:5], gpu["xflags"][diff[:3]], ref_xf[diff[:3]])
     # IoU everywhere
     d = np.abs(gpu["iou"].astype(np.float64) - ref_iou)
     assert d.max() <= IOU_TOL, (d.max(), int(d.argmax()))

@@ -98,7 +98,8 @@ def test_3d_pairs(dg):
 
 def test_degenerate_stress(dg):
     """Exactly degenerate contacts: the fp64 fallback and the tie rule give the
-    oracle's vertex count and IoU (only the IoU is required here)."""
+    oracle's vertex count, set of codes and IoU (the order of coinciding
+    points is not unique)."""
     a, b, names = synth.degenerate_stress()
     g = np.ones(len(names), np.float32)
     gpu = run_pairs(dg, a, b, grad=g)
@@ -106,6 +107,8 @@ def test_degenerate_stress(dg):
     d = np.abs(gpu["iou"] - ref)
     assert d.max() <= IOU_TOL, [(names[i], gpu["iou"][i], ref[i]) for i in np.argsort(-d)[:3]]
     assert np.array_equal(gpu["nx"], nx), [(names[i], gpu["nx"][i], nx[i]) for i in range(len(nx))]
+    same = np.all(np.sort(gpu["xflags"], axis=1) == np.sort(xf, axis=1), axis=1)
+    assert same.all(), [(names[i], gpu["xflags"][i], xf[i]) for i in np.nonzero(~same)[0]]
     # swapped roles and translated copies (exact: dyadic shifts)
     for shift in (0.0, 1024.0, -3.5):
         gpu2 = run_pairs(dg, b + np.float32(shift), a + np.float32(shift))
@@ -114,7 +117,7 @@ def test_degenerate_stress(dg):
 
 def test_near_degenerate_fallback(dg):
     """Pairs within fp32 rounding of a vertex/edge contact: signs are decided in
-    fp64, so nx matches the oracle exactly."""
+    fp64, so nx and the set of codes match the oracle exactly."""
     d = synth.c1_pairs(n=4096, seed=51)
     a = d["a_xy"].copy()
     b = d["b_xy"].copy()
@@ -129,6 +132,7 @@ def test_near_degenerate_fallback(dg):
     ref, nx, xf, _ = oracle.iou_pairs(a, b)
     assert np.abs(gpu["iou"] - ref).max() <= IOU_TOL
     assert np.array_equal(gpu["nx"], nx)
+    assert np.array_equal(np.sort(gpu["xflags"], axis=1), np.sort(xf, axis=1))
 
 
 @pytest.mark.parametrize("shift,scale", [((1.0e4, -3.0e4), 1.0), ((0.0, 0.0), 2.0 ** -10),
@@ -170,6 +174,8 @@ def test_full_size_rectangles_sampled(dg):
     assert np.abs(gpu["iou"][idx] - ref).max() <= IOU_TOL
     assert np.array_equal(gpu["nx"][idx][keep], nx[keep])
     assert np.array_equal(gpu["xflags"][idx][keep], xf[keep])
+    assert np.array_equal(gpu["nx"][idx], nx)
+    assert np.array_equal(np.sort(gpu["xflags"][idx], axis=1), np.sort(xf, axis=1))
     ga, gb, _, _ = oracle.iou_pairs_grad(sub["a_xy"], sub["b_xy"], sub["grad"], nx, xf, threads=8)
     err = grad_rel_err(np.concatenate([gpu["ga"][idx].reshape(len(idx), -1),
                                        gpu["gb"][idx].reshape(len(idx), -1)], 1),
@@ -196,6 +202,8 @@ def test_full_size_polygons_sampled(dg):
     assert np.abs(gpu["iou"][idx] - ref).max() <= IOU_TOL
     assert np.array_equal(gpu["nx"][idx][keep], nx[keep])
     assert np.array_equal(gpu["xflags"][idx][keep], xf[keep])
+    assert np.array_equal(gpu["nx"][idx], nx)
+    assert np.array_equal(np.sort(gpu["xflags"][idx], axis=1), np.sort(xf, axis=1))
 
 
 def test_deterministic(dg):

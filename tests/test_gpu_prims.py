@@ -50,6 +50,10 @@ def _check_intersect(dg, a, b, a_nv=None, b_nv=None, seed=0):
     assert keep.mean() > 0.5
     assert np.array_equal(nx[keep], r_nx[keep])
     assert np.array_equal(xf[keep], r_xf[keep])
+    # every pair: the same count and set of codes (the signs are exact on
+    # both sides; only the order of nearly coinciding points may differ)
+    assert np.array_equal(nx, r_nx)
+    assert np.array_equal(np.sort(xf, axis=1), np.sort(r_xf, axis=1))
     # slots past nx are zero on every pair
     past = np.arange(cap)[None, :] >= nx[:, None]
     assert np.all(xy[past] == 0.0)
