@@ -32,9 +32,13 @@
  *                each piece for inclusion (crossing number).
  *
  * The state the GPU path saves (edge crossing mask, entering-edge mask, the
- * inclusion of each polygon's vertex 0 in the other) is also produced here
- * from the same plain tests.  Inputs in general position are assumed where
- * this matters (the tests compare on pairs whose margins exclude contact).
+ * inclusion of each polygon's vertex 0 in the other) is also produced here,
+ * for the configuration in which Q is moved by (eps, eps^2), eps -> 0+: the
+ * tie rule that resolves contacts for convex input, so that a contact
+ * (a vertex on an edge, collinear overlapping edges, shared vertices) gives
+ * one definite state.  The area is exact without it; the gradient assumes
+ * general position (the tests compare it on pairs whose margins exclude
+ * contact).
  */
 #include <math.h>
 #include <stdint.h>
@@ -60,6 +64,59 @@ static int s_cross(spt a, spt b, spt c, spt d, double *t, double *s) {
   *t = o1 / (o1 - o2); /* along ab */
   *s = o3 / (o3 - o4); /* along cd */
   return 1;
+}
+
+/* Signs under the tie rule, Q moved by d = (eps, eps^2):
+ *   side of P's point p of Q's moved edge c->d:
+ *     orient(c + d, e + d, p) = o + f.y eps - f.x eps^2,  f = e - c;
+ *   side of Q's moved point q of P's edge a->b:
+ *     orient(a, b, q + d) = o - e.y eps + e.x eps^2,  e = b - a.
+ * The first non-zero coefficient decides; neither is zero for an edge of
+ * non-zero length. */
+static int s_tie_pq(spt c, spt e, spt p) {
+  const double o = s_orient(c, e, p);
+  if (o != 0.0) return s_sign(o);
+  if (e.y != c.y) return s_sign(e.y - c.y);
+  return s_sign(c.x - e.x);
+}
+
+static int s_tie_qp(spt a, spt b, spt q) {
+  const double o = s_orient(a, b, q);
+  if (o != 0.0) return s_sign(o);
+  if (b.y != a.y) return s_sign(a.y - b.y);
+  return s_sign(b.x - a.x);
+}
+
+/* P's point p inside Q moved by d (even-odd, ray towards +x): a vertex of
+ * the moved Q is above p when its y is >= p's (eps^2 > 0); an edge that
+ * straddles the ray meets it right of p when p is left of the edge going
+ * up, right of it going down. */
+static int s_tie_inside_pq(spt p, const spt *Q, int n) {
+  int c = 0;
+  for (int k = 0; k < n; ++k) {
+    spt a = Q[k], b = Q[(k + 1) % n];
+    const int ua = a.y >= p.y, ub = b.y >= p.y;
+    if (ua != ub) {
+      const int s = s_tie_pq(a, b, p);
+      if (ub ? s > 0 : s < 0) c ^= 1;
+    }
+  }
+  return c;
+}
+
+/* Q's moved point q + d inside P: a vertex of P is above q + d when its y
+ * is > q's; the side test is the moved point's. */
+static int s_tie_inside_qp(spt q, const spt *P, int n) {
+  int c = 0;
+  for (int k = 0; k < n; ++k) {
+    spt a = P[k], b = P[(k + 1) % n];
+    const int ua = a.y > q.y, ub = b.y > q.y;
+    if (ua != ub) {
+      const int s = s_tie_qp(a, b, q);
+      if (ub ? s > 0 : s < 0) c ^= 1;
+    }
+  }
+  return c;
 }
 
 /* Crossing-number inclusion of p in polygon v (even-odd). */
@@ -200,11 +257,13 @@ double oracle_simple_inter_area(const double *p, int n1, const double *q, int n2
   return s_slab_area(P, n1, Q, n2);
 }
 
-/* Batched forward over pairs [lo, hi): IoU, and the saved state: xmask bit
- * i*8+j when edge i of a properly crosses edge j of b; smask bit i*8+j when,
- * in addition, a's vertex i is strictly right of b's edge j (edge i enters
- * b there); inside bit 0 when a's vertex 0 is inside b, bit 1 when b's
- * vertex 0 is inside a.  Returns the number of pairs with invalid counts. */
+/* Batched forward over pairs [lo, hi): IoU, and the saved state, all with b
+ * moved by the tie rule's (eps, eps^2): xmask bit i*8+j when edge i of a
+ * crosses edge j of b (the ends of each lie on opposite sides of the
+ * other's line); smask bit i*8+j when, in addition, a's vertex i is right
+ * of b's edge j (edge i enters b there); inside bit 0 when a's vertex 0 is
+ * inside b, bit 1 when b's vertex 0 is inside a.  Returns the number of
+ * pairs with invalid counts. */
 int64_t oracle_simple_iou_pairs(int64_t lo, int64_t hi, const float *a_xy, const uint8_t *a_nv,
                                 int ka, const float *b_xy, const uint8_t *b_nv, int kb,
                                 double *iou, uint64_t *xmask, uint64_t *smask, uint8_t *inside) {
@@ -225,17 +284,19 @@ int64_t oracle_simple_iou_pairs(int64_t lo, int64_t hi, const float *a_xy, const
       uint64_t xm = 0, sm = 0;
       for (int e = 0; e < n1; ++e)
         for (int f = 0; f < n2; ++f) {
-          double t, s;
           spt a = P[e], b = P[(e + 1) % n1], c = Q[f], d = Q[(f + 1) % n2];
-          if (s_cross(a, b, c, d, &t, &s)) {
+          const int sa = s_tie_pq(c, d, a), sb = s_tie_pq(c, d, b);
+          const int sc = s_tie_qp(a, b, c), sd = s_tie_qp(a, b, d);
+          if (sa != sb && sc != sd) {
             xm |= 1ull << (e * 8 + f);
-            if (s_orient(c, d, a) < 0) sm |= 1ull << (e * 8 + f);
+            if (sa < 0) sm |= 1ull << (e * 8 + f);
           }
         }
       xmask[i] = xm;
       smask[i] = sm;
     }
-    if (inside) inside[i] = (uint8_t)(s_inside(P[0], Q, n2) | (s_inside(Q[0], P, n1) << 1));
+    if (inside)
+      inside[i] = (uint8_t)(s_tie_inside_pq(P[0], Q, n2) | (s_tie_inside_qp(Q[0], P, n1) << 1));
   }
   return bad;
 }

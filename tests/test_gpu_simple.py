@@ -1,7 +1,8 @@
 """GPU parity of the simple-polygon (non-convex) IoU path through the C ABI
 against the FP64 simple-polygon oracle: IoU to 1e-5 on every pair, the saved
-crossing / entering masks and vertex-0 inclusion bit-exact on pairs in
-general position, gradients to 1e-3 relative."""
+crossing / entering masks and vertex-0 inclusion bit-exact on every pair
+(contacts resolved by the tie rule on both sides), gradients to 1e-3
+relative on pairs in general position."""
 import numpy as np
 import pytest
 import torch
@@ -47,6 +48,10 @@ def _check(dg, a, b, a_nv=None, b_nv=None, grad=None, min_keep=0.9):
     assert np.array_equal(xm[keep], r_xm[keep])
     assert np.array_equal(sm[keep], r_sm[keep])
     assert np.array_equal(ins[keep], r_ins[keep])
+    # every pair: the masks are functions of exact, tie-ruled signs alone
+    assert np.array_equal(xm, r_xm), np.nonzero(xm != r_xm)[0][:5]
+    assert np.array_equal(sm, r_sm), np.nonzero(sm != r_sm)[0][:5]
+    assert np.array_equal(ins, r_ins), np.nonzero(np.any(ins != r_ins, axis=-1) if ins.ndim > 1 else ins != r_ins)[0][:5]
     r_ga, r_gb = oracle.simple_iou_pairs_grad(a, b, grad, a_nv, b_nv, threads=16)
     g = np.concatenate([ga.cpu().numpy().reshape(n, -1), gb.cpu().numpy().reshape(n, -1)], 1)
     r = np.concatenate([r_ga.reshape(n, -1), r_gb.reshape(n, -1)], 1)
@@ -95,7 +100,8 @@ def test_convex_inputs_match_convex_path(dg):
 def test_rectilinear_contacts(dg):
     """Integer rectilinear shapes (exact in fp32) touch along edges and at
     vertices; the tie rule resolves every contact as a motion of b, and the
-    area is continuous in that motion, so the IoU is the exact one."""
+    area is continuous in that motion, so the IoU is the exact one and the
+    saved state is the oracle's (which applies the same rule)."""
     rng = np.random.default_rng(305)
     shapes = []
     for _ in range(4000):
@@ -112,9 +118,12 @@ def test_rectilinear_contacts(dg):
     an = np.array([s[1] for s in shapes[:2000]], np.uint8)
     bn = np.array([s[1] for s in shapes[2000:]], np.uint8)
     _say("case: rectilinear contacts 2000")
-    iou, _, _, _ = dg.iou_simple_pairs(dev_t(a), dev_t(b), dev_t(an), dev_t(bn))
-    ref = oracle.simple_iou_pairs(a, b, an, bn)[0]
+    iou, xm, sm, ins = dg.iou_simple_pairs(dev_t(a), dev_t(b), dev_t(an), dev_t(bn))
+    ref, r_xm, r_sm, r_ins, _ = oracle.simple_iou_pairs(a, b, an, bn)
     assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
+    # the contacts are exact, so the tie-ruled masks are the oracle's too
+    assert np.array_equal(_u64(xm), r_xm) and np.array_equal(_u64(sm), r_sm)
+    assert np.array_equal(ins.cpu().numpy(), r_ins)
 
 
 def test_identical_disjoint_empty(dg):

@@ -199,6 +199,67 @@ def test_closed_form_rotated_squares(orc):
     assert abs(iou45[0] - 1 / math.sqrt(2)) <= 1e-14 and nx45[0] == 8
 
 
+def _moved_codes(p, q, eps):
+    """Codes of the intersection of p with q moved by (eps, eps^2), eps a
+    small exact rational: P_i strictly inside the moved q, Q_j (moved)
+    strictly inside p, and the proper crossings of their edges."""
+    P = X.fpoly(p)
+    Q = [(x + eps, y + eps * eps) for x, y in X.fpoly(q)]
+    n1, n2 = len(P), len(Q)
+    codes = set()
+    for i in range(n1):
+        if all(X.orient(Q[j], Q[(j + 1) % n2], P[i]) > 0 for j in range(n2)):
+            codes.add(i)
+    for j in range(n2):
+        if all(X.orient(P[i], P[(i + 1) % n1], Q[j]) > 0 for i in range(n1)):
+            codes.add(0x10 | j)
+    for i in range(n1):
+        a, b = P[i], P[(i + 1) % n1]
+        for j in range(n2):
+            c, d = Q[j], Q[(j + 1) % n2]
+            o = [X.orient(c, d, a), X.orient(c, d, b), X.orient(a, b, c), X.orient(a, b, d)]
+            assert all(v != 0 for v in o)  # the moved pair has no contact
+            if (o[0] > 0) != (o[1] > 0) and (o[2] > 0) != (o[3] > 0):
+                codes.add(0x40 | (i << 3) | j)
+    return codes
+
+
+def test_tie_rule_codes_are_the_moved_pairs(orc):
+    """Exact contacts (shared and collinear edges, vertices on edges, corner
+    touches, identical polygons): the oracle's vertex count and set of codes
+    are those of the pair with b moved by (eps, eps^2) (eps = 2^-12, below
+    every ratio of these small dyadic orientations), computed in exact
+    rationals.  The cyclic order of points that coincide is a convention."""
+    from fractions import Fraction
+    eps = Fraction(1, 2 ** 12)
+    sa, sb, _ = synth.degenerate_stress()
+    rng = np.random.default_rng(26)
+    # integer rectangles and diamonds on a small grid: contacts are common
+    shapes = []
+    for _ in range(400):
+        x0, y0 = rng.integers(-3, 3, 2)
+        w, h = rng.integers(1, 4, 2)
+        if rng.integers(0, 2):
+            v = [(x0, y0), (x0 + w, y0), (x0 + w, y0 + h), (x0, y0 + h)]
+        else:
+            v = [(x0 + w, y0), (x0, y0 + w), (x0 - w, y0), (x0, y0 - w)]
+        shapes.append(v)
+    ga = np.array(shapes[:200], np.float32)
+    gb = np.array(shapes[200:], np.float32)
+    checked = contacts = 0
+    for a, b in ((sa, sb), (sb, sa), (ga, gb), (gb, ga)):
+        _, nx, xf, bad = orc.iou_pairs(a, b)
+        assert bad == 0
+        for i in range(len(a)):
+            want = _moved_codes(a[i].astype(np.float64), b[i].astype(np.float64), eps)
+            got = [int(c) for c in xf[i, :nx[i]]]
+            assert len(got) == len(set(got)) and set(got) == want, (i, got, sorted(want))
+            P, Q = X.fpoly(a[i]), X.fpoly(b[i])
+            contacts += any(X.orient(Q[j], Q[(j + 1) % 4], v) == 0 for v in P for j in range(4))
+            checked += 1
+    assert checked == 2 * len(sa) + 400 and contacts > 100
+
+
 def test_identity_disjoint_nested(orc):
     d = synth.c4_polygons(n=300, seed=21)
     a, anv = d["a_xy"], d["a_nv"]

@@ -140,6 +140,70 @@ def test_rectilinear_cell_count(orc):
         assert orc.simple_inter_area(p, q) == float(cells)
 
 
+def _moved_state(p, q, eps):
+    """Saved state of the pair with q moved by (eps, eps^2), eps a small
+    exact rational: crossing and entering masks by strict sign tests of the
+    exact orientations, vertex-0 inclusion by the crossing-number test on
+    exact rationals (for small eps the moved pair has no contact)."""
+    from fractions import Fraction
+    P = X.fpoly(p)
+    Q = [(x + eps, y + eps * eps) for x, y in X.fpoly(q)]
+    n1, n2 = len(P), len(Q)
+
+    def sgn(v):
+        return (v > 0) - (v < 0)
+
+    def inside(pt, V):
+        c = 0
+        for k in range(len(V)):
+            (ax, ay), (bx, by) = V[k], V[(k + 1) % len(V)]
+            if (ay > pt[1]) != (by > pt[1]):
+                x = ax + (pt[1] - ay) * (bx - ax) / (by - ay)
+                assert x != pt[0]
+                c ^= int(x > pt[0])
+        return c
+
+    xm = sm = 0
+    for i in range(n1):
+        a, b = P[i], P[(i + 1) % n1]
+        for j in range(n2):
+            c, d = Q[j], Q[(j + 1) % n2]
+            s1, s2 = sgn(X.orient(c, d, a)), sgn(X.orient(c, d, b))
+            s3, s4 = sgn(X.orient(a, b, c)), sgn(X.orient(a, b, d))
+            assert 0 not in (s1, s2, s3, s4)
+            if s1 != s2 and s3 != s4:
+                xm |= 1 << (8 * i + j)
+                if s1 < 0:
+                    sm |= 1 << (8 * i + j)
+    return xm, sm, inside(P[0], Q) | (inside(Q[0], P) << 1)
+
+
+def test_tie_rule_state_is_the_moved_pairs(orc):
+    """Integer rectilinear shapes touch along edges and at vertices; the
+    oracle's saved state (crossing / entering masks, vertex-0 inclusion) is
+    that of the pair with q moved by (eps, eps^2): here eps = 2^-12, below
+    every ratio of the integer orientations, so the moved pair's exact state
+    equals the limit the tie rule names."""
+    from fractions import Fraction
+    rng = np.random.default_rng(207)
+    eps = Fraction(1, 2 ** 12)
+    contacts = 0
+    for _ in range(300):
+        p, q = _rect_shapes(rng), _rect_shapes(rng)
+        a = np.zeros((1, 8, 2), np.float32)
+        b = np.zeros((1, 8, 2), np.float32)
+        a[0, :len(p)], b[0, :len(q)] = p, q
+        an, bn = np.array([len(p)], np.uint8), np.array([len(q)], np.uint8)
+        _, xm, sm, ins, bad = orc.simple_iou_pairs(a, b, an, bn)
+        assert bad == 0
+        r_xm, r_sm, r_ins = _moved_state(p, q, eps)
+        assert (int(xm[0]), int(sm[0]), int(ins[0])) == (r_xm, r_sm, r_ins)
+        P, Q = X.fpoly(p), X.fpoly(q)
+        contacts += any(X.orient(Q[j], Q[(j + 1) % len(Q)], v) == 0
+                        for v in P for j in range(len(Q)))
+    assert contacts > 100  # the set is mostly degenerate
+
+
 def test_convex_inputs_match_convex_oracle(orc):
     for d in (synth.c1_pairs(n=400, seed=204), synth.c4_polygons(n=400, seed=205)):
         a, b = d["a_xy"], d["b_xy"]
@@ -167,6 +231,24 @@ def test_convex_inputs_match_convex_oracle(orc):
                 nxt = codes[(k + 1) % m]
                 on_a = nxt == (e + 1) % n1 or (nxt >= 0x40 and (nxt >> 3) & 7 == e)
                 assert bool((int(sm[i]) >> (e * 8 + (c & 7))) & 1) == on_a
+
+
+def test_degenerate_convex_pairs_match_convex_oracle(orc):
+    """Exactly degenerate convex contacts (shared edges, a vertex on an edge,
+    collinear overlaps, corner touches), both roles: the two oracles apply the
+    same tie rule, so the crossing mask and vertex-0 inclusion follow from
+    the convex oracle's codes on every pair."""
+    a, b, names = synth.degenerate_stress()
+    for p, q in ((a, b), (b, a)):
+        _, nx, xf, _ = orc.iou_pairs(p, q)
+        _, xm, _, ins, bad = orc.simple_iou_pairs(p, q)
+        assert bad == 0
+        for i in range(len(p)):
+            codes = [int(c) for c in xf[i, :nx[i]]]
+            cross = sum(1 << (((c >> 3) & 7) * 8 + (c & 7)) for c in codes if c >= 0x40)
+            assert int(xm[i]) == cross, (names[i], hex(int(xm[i])), codes)
+            assert int(ins[i]) & 1 == int(0 in codes), names[i]
+            assert (int(ins[i]) >> 1) & 1 == int(0x10 in codes), names[i]
 
 
 def test_symmetry_identity_scaling(orc):
