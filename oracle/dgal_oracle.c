@@ -56,7 +56,6 @@
 #define ORC_CAP (2 * ORC_MAXV) /* most vertices of an intersection (R5) */
 
 typedef struct { double x, y; } point;
-typedef struct { double a, b, c; } line;  /* a*x + b*y + c = 0 (Sec. III) */
 typedef struct { double v[3]; } hvec;     /* homogeneous 3-vector */
 typedef struct {
   int n;
@@ -93,29 +92,19 @@ static hvec hpoint(point p) {
   return r;
 }
 
-/* Sec. III: the line through two points, as equation coefficients.  In
- * homogeneous coordinates it is the cross product (p,1) x (q,1). */
-static line line_through(point p, point q) {
-  hvec h = hcross(hpoint(p), hpoint(q));
-  line l;
-  l.a = h.v[0];
-  l.b = h.v[1];
-  l.c = h.v[2];
-  return l;
-}
-
-static hvec hline(line l) {
-  hvec r;
-  r.v[0] = l.a;
-  r.v[1] = l.b;
-  r.v[2] = l.c;
-  return r;
-}
-
-/* Meeting point of two lines: homogeneous cross product, dehomogenised. */
-static point line_meet(line l1, line l2) {
-  hvec h = hcross(hline(l1), hline(l2));
-  return mkpt(h.v[0] / h.v[2], h.v[1] / h.v[2]);
+/* Meeting point of P's edge a->b with the line of Q's edge c->d (the meet of
+ * the two lines of Sec. III), placed along a->b at t = o(a) / (o(a) - o(b)),
+ * o = orient(c, d, .).  For fp32-valued points each orientation is exact up
+ * to its last rounding, and at a crossing the two have opposite signs (or one
+ * is zero), so t keeps full precision at any angle between the edges.  The
+ * dehomogenised cross product of the two lines' coefficients gives the same
+ * point in exact arithmetic but divides by the cross product of the edge
+ * directions, which loses about 1/sin(angle) ulps: near-parallel edges that
+ * share an end then meet visibly off the segment. */
+static point edge_meet(point a, point b, point c, point d) {
+  const double oa = orient(c, d, a), ob = orient(c, d, b);
+  const double t = oa / (oa - ob);
+  return mkpt(a.x + t * (b.x - a.x), a.y + t * (b.y - a.y));
 }
 
 /* R3.  Sign of orient(Q_j, Q_j1, p) with Q moved by (eps, eps^2):
@@ -179,7 +168,7 @@ static int intersect(const point *P, int n1, const point *Q, int n2,
     for (int j = 0; j < n2; ++j) {
       int j1 = (j + 1) % n2;
       if (sp[i][j] != sp[i1][j] && sq[j][i] != sq[j1][i]) {
-        cand[m] = line_meet(line_through(P[i], P[i1]), line_through(Q[j], Q[j1]));
+        cand[m] = edge_meet(P[i], P[i1], Q[j], Q[j1]);
         ccode[m] = (uint8_t)(0x40 | (i << 3) | j);
         ++m;
       }
@@ -237,8 +226,7 @@ static point vertex_from_code(const point *P, int n1, const point *Q, int n2,
   if (code < 0x10) return P[code];
   if (code < 0x40) return Q[code & 0x0F];
   int i = (code >> 3) & 7, j = code & 7;
-  return line_meet(line_through(P[i], P[(i + 1) % n1]),
-                   line_through(Q[j], Q[(j + 1) % n2]));
+  return edge_meet(P[i], P[(i + 1) % n1], Q[j], Q[(j + 1) % n2]);
 }
 
 /* R6: z-overlap of two extents. */
@@ -288,7 +276,9 @@ static void area_grad(const point *v, int n, double gA, point *gv) {
 }
 
 /* Chain rule of X = meet(line(a,b), line(c,d)) through the homogeneous form
- * (Sec. III, lines from two points).  G = dL/dX; adds dL/da.. into ga..gd. */
+ * (Sec. III: a line's coefficients are the cross product (p,1) x (q,1) of
+ * two of its points, and two lines meet at the dehomogenised cross product
+ * of their coefficients).  G = dL/dX; adds dL/da.. into ga..gd. */
 static void line_meet_grad(point a, point b, point c, point d, point G,
                            point *ga, point *gb, point *gc, point *gd) {
   hvec ah = hpoint(a), bh = hpoint(b), ch = hpoint(c), dh = hpoint(d);

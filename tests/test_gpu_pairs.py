@@ -135,6 +135,17 @@ def test_near_degenerate_fallback(dg):
     assert np.array_equal(np.sort(gpu["xflags"], axis=1), np.sort(xf, axis=1))
 
 
+@pytest.mark.parametrize("sigma", [1e-6, 1e-7])
+def test_near_identical_boxes(dg, sigma):
+    """b within about an ulp of a: nearly parallel edges that share ends, and
+    a filtered set that is nearly empty; IoU on every pair, count and codes
+    on every pair."""
+    d = synth.c1_pairs(n=65536, seed=5000, center_sigma=sigma, yaw_sigma=sigma)
+    _say(f"case: near-identical boxes sigma {sigma}")
+    s = compare_pairs(dg, d["a_xy"], d["b_xy"], grad=d["grad"], require_filtered_frac=0.0)
+    _say(str(s))
+
+
 @pytest.mark.parametrize("shift,scale", [((1.0e4, -3.0e4), 1.0), ((0.0, 0.0), 2.0 ** -10),
                                          ((0.0, 0.0), 2.0 ** 10), ((-5.0e3, 7.0e3), 2.0 ** -4)])
 def test_precision_far_and_scaled(dg, shift, scale):

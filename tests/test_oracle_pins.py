@@ -224,6 +224,28 @@ def _moved_codes(p, q, eps):
     return codes
 
 
+def test_near_identical_boxes_exact(orc):
+    """Boxes within about an ulp of each other: edges that are nearly parallel
+    and share an end (angles down to ~1e-12) still give the exact IoU, never
+    above 1, on every pair (exact rational clipping of the same fp32 inputs).
+    Placing such a crossing by the meet of the two lines' coefficients in fp64
+    was ~1e-4 off here."""
+    checked = 0
+    for sig in (1e-7, 1e-6):
+        d = synth.c1_pairs(n=150, seed=5000, center_sigma=sig, yaw_sigma=sig)
+        a, b = d["a_xy"], d["b_xy"]
+        iou, nx, xf, bad = orc.iou_pairs(a, b)
+        assert bad == 0 and np.all(iou <= 1.0)
+        for i in range(len(a)):
+            P, Q = X.fpoly(a[i]), X.fpoly(b[i])
+            inter = X.clip(P, Q)
+            ia = X.area(inter) if len(inter) >= 3 else 0
+            ex = ia / (X.area(P) + X.area(Q) - ia)
+            assert abs(iou[i] - float(ex)) <= 1e-12, (sig, i, iou[i], float(ex))
+            checked += 1
+    assert checked == 300
+
+
 def test_tie_rule_codes_are_the_moved_pairs(orc):
     """Exact contacts (shared and collinear edges, vertices on edges, corner
     touches, identical polygons): the oracle's vertex count and set of codes
@@ -265,7 +287,7 @@ def test_identity_disjoint_nested(orc):
     a, anv = d["a_xy"], d["a_nv"]
     iou, nx, xf, bad = orc.iou_pairs(a, a, anv, anv)
     # identical polygons resolve (tie rule) into crossings of adjacent edges at
-    # the shared vertices; their homogeneous meet loses ~1/sin(turn) ulps
+    # the shared vertices, each placed at an end of its edge (t = 0 or 1)
     assert np.all(np.abs(iou - 1.0) <= 1e-12)
     # disjoint: shift far away
     b = a.copy()
