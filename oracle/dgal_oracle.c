@@ -31,8 +31,7 @@
  * points where an edge of P crosses an edge of Q; ordered counter-clockwise
  * they give the area by the shoelace formula.
  *
- * Readings where the paper is silent (each one is also listed in the design
- * notes of the repository):
+ * Readings where the paper is silent:
  *   R1 flag encoding: P vertex i -> i; Q vertex j -> 0x10|j; crossing of P edge
  *      i with Q edge j -> 0x40|(i<<3)|j; unused slot -> 0xFF.  Edge i runs from
  *      vertex i to vertex (i+1) mod n.

@@ -166,8 +166,9 @@ struct PairResult {
 
 // Waves per SIMD that the LDS of a pair_forward kernel allows at K = 8
 // (144 bytes a lane against 160 KiB a CU); the register allocator is held
-// to the same count, which costs a few spilled values instead of half the
-// occupancy.  Kernels at K = 4 are left to the allocator.
+// to the same count (at most 128 VGPRs, met without spilling; left alone it
+// takes more and halves the occupancy).  Kernels at K = 4 are left to the
+// allocator.
 template <int K>
 constexpr int fwd_waves_per_simd() {
   return K == 8 ? 4 : 1;
