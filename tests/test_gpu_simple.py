@@ -126,6 +126,29 @@ def test_rectilinear_contacts(dg):
     assert np.array_equal(ins.cpu().numpy(), r_ins)
 
 
+def test_snapped_simple_polygons(dg):
+    """Random simple 3..8-gons snapped to a grid of 1/4: collinear edges,
+    vertices on edges and shared vertices everywhere; IoU on every pair and
+    the tie-ruled masks bit-exact on every pair."""
+    rng = np.random.default_rng(1900)
+    n = 20000
+    c = rng.uniform(-1, 1, (n, 2))
+    a, an = synth.random_simple(rng, n, c, kmin=3, kmax=8)
+    b, bn = synth.random_simple(rng, n, c + rng.normal(0, 0.4, (n, 2)), kmin=3, kmax=8)
+    a = np.round(a * 4).astype(np.float32)
+    b = np.round(b * 4).astype(np.float32)
+    keep = (oracle.simple_status(a, an) == 0) & (oracle.simple_status(b, bn) == 0)
+    a, b, an, bn = a[keep], b[keep], an[keep], bn[keep]
+    _say(f"case: snapped simple polygons {len(a)}")
+    iou, xm, sm, ins = dg.iou_simple_pairs(dev_t(a), dev_t(b), dev_t(an), dev_t(bn))
+    dg.check_errors()
+    ref, r_xm, r_sm, r_ins, bad = oracle.simple_iou_pairs(a, b, an, bn, threads=16)
+    assert bad == 0
+    assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
+    assert np.array_equal(_u64(xm), r_xm) and np.array_equal(_u64(sm), r_sm)
+    assert np.array_equal(ins.cpu().numpy(), r_ins)
+
+
 def test_identical_disjoint_empty(dg):
     d = synth.c4_simple(n=4096, seed=306)
     a, an = dev_t(d["a_xy"]), dev_t(d["a_nv"])
