@@ -135,6 +135,27 @@ def test_near_degenerate_fallback(dg):
     assert np.array_equal(np.sort(gpu["xflags"], axis=1), np.sort(xf, axis=1))
 
 
+def test_grid_contacts(dg):
+    """Integer rectangles and diamonds on a small grid: shared and collinear
+    edges, vertices on edges and corner touches on most pairs; count and set
+    of codes equal the oracle's on every pair, IoU on every pair."""
+    rng = np.random.default_rng(2200)
+    shapes = []
+    for _ in range(40000):
+        x0, y0 = rng.integers(-3, 3, 2)
+        w, h = rng.integers(1, 4, 2)
+        if rng.integers(0, 2):
+            v = [(x0, y0), (x0 + w, y0), (x0 + w, y0 + h), (x0, y0 + h)]
+        else:
+            v = [(x0 + w, y0), (x0, y0 + w), (x0 - w, y0), (x0, y0 - w)]
+        shapes.append(v)
+    a = np.array(shapes[:20000], np.float32)
+    b = np.array(shapes[20000:], np.float32)
+    _say("case: grid contacts 20000")
+    g = rng.uniform(-1, 1, 20000).astype(np.float32)
+    _say(str(compare_pairs(dg, a, b, grad=g, require_filtered_frac=0.0)))
+
+
 @pytest.mark.parametrize("sigma", [1e-6, 1e-7])
 def test_near_identical_boxes(dg, sigma):
     """b within about an ulp of a: nearly parallel edges that share ends, and
