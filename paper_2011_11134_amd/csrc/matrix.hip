@@ -450,10 +450,12 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_fill(CullArgs m) {
     }
     const uint64_t bits = lane < kBitWords ? word : 0ull;
     if (__ballot(bits != 0ull) == 0ull) continue;  // uniform: an empty tile
-    const int64_t origin = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(word >> 32), kBitWords) << 32) |
-                                     __builtin_amdgcn_readlane((uint32_t)word, kBitWords));
-    const int64_t nb = (int64_t)(((uint64_t)__builtin_amdgcn_readlane((uint32_t)(word >> 32), kBitWords + 1) << 32) |
-                                 __builtin_amdgcn_readlane((uint32_t)word, kBitWords + 1));
+    // (the lane reads return int: each half is taken as unsigned, or a low
+    // half with its top bit set would sign-extend over the high half)
+    const int64_t origin = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(word >> 32), kBitWords) << 32) |
+                                     (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)word, kBitWords));
+    const int64_t nb = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(word >> 32), kBitWords + 1) << 32) |
+                                 (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)word, kBitWords + 1));
     // every lane writes the survivors of its own word: its first slot is the
     // exclusive prefix of the words' bit counts
     const int cnt = __popcll(bits);

@@ -361,3 +361,85 @@ def test_saved_capacity_overflow_is_reported(dg):
         dg.iou_matrix(dev_t(a), dev_t(a), save=True, capacity=4)
     assert e.value.status == dg.DGAL_ECAPACITY
     dg.check_errors()
+
+
+def test_matrix_beyond_int32(dg):
+    """A 65,536 x 33,000 matrix: 2.16e9 pairs (8.6 GB of output), flat indices
+    past 2^31.  Checked without copying the output: the saved survivors
+    (those past 2^31 and a sample of the rest) against the oracle, the
+    output's non-zero count against the survivors with a positive IoU,
+    random flat indices on both sides of 2^31 against the AABB test and the
+    oracle, and sampled row / column gradients against the oracle's pair
+    gradients summed over the saved survivors."""
+    na, nb = 65536, 33000
+    total = na * nb
+    assert total > 2 ** 31
+    rng = np.random.default_rng(41)
+
+    def boxes(n):
+        cx, cy = rng.uniform(0, 400, n), rng.uniform(0, 400, n)
+        w, l = rng.uniform(1, 3, n), rng.uniform(1, 3, n)
+        return synth.boxes_to_quads(cx, cy, w, l, rng.uniform(-np.pi, np.pi, n))
+
+    a, b = boxes(na), boxes(nb)
+    _say(f"case: matrix {na} x {nb} = {total} pairs")
+    ta, tb = dev_t(a), dev_t(b)
+    iou, saved, seg = dg.iou_matrix(ta, tb, save=True, capacity=1 << 22)
+    dg.check_errors()
+    assert iou.shape == (na, nb)
+    iou = iou.reshape(-1)  # flat, as the saved pair ids index it
+    cnt = int(saved.count.item())
+    assert 0 < cnt <= saved.capacity
+    st = saved.tile_start[:saved.tiles].cpu().numpy()
+    sc = saved.tile_count[:saved.tiles].cpu().numpy().astype(np.int64)
+    ent = np.repeat(st, sc) + (np.arange(int(sc.sum())) - np.repeat(np.cumsum(sc) - sc, sc))
+    pid = saved.pair_id.cpu().numpy()[ent]
+    assert len(pid) == cnt and len(np.unique(pid)) == cnt
+    # checked on the host before any device gather uses them
+    assert pid.min() >= 0 and pid.max() < total
+    assert pid.max() > 2 ** 31
+    got = iou[torch.from_numpy(pid).cuda()].cpu().numpy()
+    # every non-zero output value is a saved survivor's
+    assert int(torch.count_nonzero(iou).item()) == int(np.count_nonzero(got))
+    # saved survivors: all those past 2^31 (up to 40,000) and 40,000 others
+    hi = np.flatnonzero(pid >= 2 ** 31)[:40000]
+    lo = rng.choice(np.flatnonzero(pid < 2 ** 31), min(40000, int((pid < 2 ** 31).sum())),
+                    replace=False)
+    sel = np.concatenate([hi, lo])
+    ref, _, _ = oracle.iou_index_pairs(pid[sel] // nb, pid[sel] % nb, a, b, threads=16)
+    assert np.abs(got[sel] - ref).max() <= IOU_TOL
+    # random flat indices on both sides of 2^31
+    flat = np.concatenate([rng.integers(0, 2 ** 31, 500000), rng.integers(2 ** 31, total, 500000)])
+    val = iou[torch.from_numpy(flat).cuda()].cpu().numpy()
+    ia, ib = flat // nb, flat % nb
+    lo_a, hi_a, lo_b, hi_b = a.min(1), a.max(1), b.min(1), b.max(1)
+    ov = np.all((lo_a[ia] <= hi_b[ib]) & (lo_b[ib] <= hi_a[ia]), axis=1)
+    assert not val[~ov].any()
+    if ov.any():
+        r2, _, _ = oracle.iou_index_pairs(ia[ov], ib[ov], a, b, threads=16)
+        assert np.abs(val[ov] - r2).max() <= IOU_TOL
+    # backward: rows and columns of the saved survivors' pair gradients
+    g = torch.rand(total, device="cuda", generator=torch.Generator("cuda").manual_seed(5)) - 0.5
+    ga, gb, _, _ = dg.iou_matrix_backward(g, saved, seg, ta, tb)
+    dg.check_errors()
+    gs = g[torch.from_numpy(pid).cuda()].cpu().numpy()
+    rows = rng.choice(np.unique(pid // nb), 300, replace=False)
+    cols = rng.choice(np.unique(pid % nb), 300, replace=False)
+    on_rows = np.isin(pid // nb, rows)
+    on_cols = np.isin(pid % nb, cols)
+    pick = on_rows | on_cols
+    pa_, pb_, _, _ = oracle.iou_pairs_grad(a[pid[pick] // nb], b[pid[pick] % nb], gs[pick],
+                                           *oracle.iou_pairs(a[pid[pick] // nb], b[pid[pick] % nb],
+                                                             threads=16)[1:3], threads=16)
+    ref_a = np.zeros((na, 4, 2))
+    ref_b = np.zeros((nb, 4, 2))
+    np.add.at(ref_a, (pid[pick] // nb), pa_)
+    np.add.at(ref_b, (pid[pick] % nb), pb_)
+    got_a = ga.cpu().numpy()[rows]
+    got_b = gb.cpu().numpy()[cols]
+    for got_g, ref_g in ((got_a, ref_a[rows]), (got_b, ref_b[cols])):
+        err = np.linalg.norm((got_g - ref_g).reshape(len(ref_g), -1), axis=1)
+        scale = np.maximum(np.linalg.norm(ref_g.reshape(len(ref_g), -1), axis=1), 1e-6)
+        assert np.percentile(err / scale, 99) <= GRAD_TOL, np.sort(err / scale)[-5:]
+    _say(f"matrix beyond int32: {cnt} survivors, {len(hi)} past 2^31")
+
