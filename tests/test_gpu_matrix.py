@@ -443,3 +443,65 @@ def test_matrix_beyond_int32(dg):
         assert np.percentile(err / scale, 99) <= GRAD_TOL, np.sort(err / scale)[-5:]
     _say(f"matrix beyond int32: {cnt} survivors, {len(hi)} past 2^31")
 
+
+def test_scenes_beyond_int32(dg):
+    """Two self-pair scenes of 33,000 boxes: 2.18e9 pairs in one flat output,
+    the second scene's block starting past 2^31.  Saved survivors of both
+    scenes against the oracle, non-zero count, the diagonal, and sampled
+    per-box gradients (row role with the transpose's upstream gradient)."""
+    ns = 33000
+    off = np.array([0, ns, 2 * ns], np.int64)
+    total = 2 * ns * ns
+    assert total > 2 ** 31 and ns * ns < 2 ** 31
+    rng = np.random.default_rng(43)
+    n = 2 * ns
+    xy = synth.boxes_to_quads(rng.uniform(0, 300, n), rng.uniform(0, 300, n),
+                              rng.uniform(1, 3, n), rng.uniform(1, 3, n),
+                              rng.uniform(-np.pi, np.pi, n))
+    _say(f"case: 2 scenes x {ns} boxes = {total} self pairs")
+    txy = dev_t(xy)
+    iou, saved, seg = dg.iou_matrix(txy, a_off=off, self_pairs=True, save=True,
+                                    capacity=1 << 22)
+    dg.check_errors()
+    cnt = int(saved.count.item())
+    st = saved.tile_start[:saved.tiles].cpu().numpy()
+    sc = saved.tile_count[:saved.tiles].cpu().numpy().astype(np.int64)
+    ent = np.repeat(st, sc) + (np.arange(int(sc.sum())) - np.repeat(np.cumsum(sc) - sc, sc))
+    pid = saved.pair_id.cpu().numpy()[ent]
+    assert len(pid) == cnt and len(np.unique(pid)) == cnt
+    assert pid.min() >= 0 and pid.max() < total  # before any device gather uses them
+    s_ = (pid >= ns * ns).astype(np.int64)  # scene of each survivor
+    assert s_.sum() > 0
+    local = pid - s_ * ns * ns
+    ia, ib = off[s_] + local // ns, off[s_] + local % ns
+    got = iou[torch.from_numpy(pid).cuda()].cpu().numpy()
+    # the diagonal is written as 1 by the cull and not saved
+    diag = ia == ib
+    assert not diag.any()
+    dflat = np.concatenate([k * ns * ns + np.arange(ns) * (ns + 1) for k in range(2)])
+    assert np.all(iou[torch.from_numpy(dflat).cuda()].cpu().numpy() == 1.0)
+    assert int(torch.count_nonzero(iou).item()) == int(np.count_nonzero(got)) + n
+    sel = np.concatenate([np.flatnonzero(pid >= 2 ** 31)[:30000],
+                          np.flatnonzero(pid < 2 ** 31)[:30000]])
+    ref, _, _ = oracle.iou_index_pairs(ia[sel], ib[sel], xy, xy, threads=16)
+    assert np.abs(got[sel] - ref).max() <= IOU_TOL
+    g = torch.rand(total, device="cuda", generator=torch.Generator("cuda").manual_seed(6)) - 0.5
+    ga, _, _, _ = dg.iou_matrix_backward(g, saved, seg, txy, self_pairs=True)
+    dg.check_errors()
+    # pair (i, k) gives box i the gradient of IoU(i, k) weighted by
+    # g[i, k] + g[k, i]
+    tpid = s_ * ns * ns + (local % ns) * ns + local // ns
+    w = (g[torch.from_numpy(pid).cuda()] + g[torch.from_numpy(tpid).cuda()]).cpu().numpy()
+    boxes = rng.choice(np.unique(ia), 400, replace=False)
+    pick = np.isin(ia, boxes)
+    nx, xf = oracle.iou_pairs(xy[ia[pick]], xy[ib[pick]], threads=16)[1:3]
+    pa_, _, _, _ = oracle.iou_pairs_grad(xy[ia[pick]], xy[ib[pick]], w[pick].astype(np.float32),
+                                         nx, xf, threads=16)
+    ref_a = np.zeros((n, 4, 2))
+    np.add.at(ref_a, ia[pick], pa_)
+    got_a = ga.cpu().numpy()[boxes]
+    err = np.linalg.norm((got_a - ref_a[boxes]).reshape(len(boxes), -1), axis=1)
+    scale = np.maximum(np.linalg.norm(ref_a[boxes].reshape(len(boxes), -1), axis=1), 1e-6)
+    assert np.percentile(err / scale, 99) <= GRAD_TOL, np.sort(err / scale)[-5:]
+    _say(f"scenes beyond int32: {cnt} survivors, {int((pid >= 2 ** 31).sum())} past 2^31")
+
