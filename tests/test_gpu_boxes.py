@@ -85,6 +85,32 @@ def test_boxes_match_corner_path(dg):
     assert (iou_b - iou_v).abs().max().item() <= IOU_TOL
 
 
+def test_boxes_axis_aligned_contacts(dg):
+    """Axis-aligned boxes (yaw 0) on integer centres with integer sizes: the
+    fp32 and fp64 corners are the same exact values, shared and collinear
+    edges and corner touches are common, and the count and set of codes
+    equal the oracle's on every pair."""
+    rng = np.random.default_rng(115)
+    n = 20000
+
+    def boxes():
+        return np.stack([rng.integers(-3, 4, n), rng.integers(-3, 4, n),
+                         rng.integers(1, 4, n), rng.integers(1, 4, n), np.zeros(n)],
+                        1).astype(np.float32)
+
+    a, b = boxes(), boxes()
+    _say("case: axis-aligned integer boxes 20000")
+    iou, nx, xf = dg.iou_boxes(dev_t(a), dev_t(b))
+    dg.check_errors()
+    iou, nx, xf = iou.cpu().numpy(), nx.cpu().numpy(), xf.cpu().numpy()
+    r_iou, r_nx, r_xf, bad = oracle.iou_boxes(a, b, threads=8)
+    assert bad == 0
+    assert np.abs(iou - r_iou).max() <= IOU_TOL
+    assert np.array_equal(nx, r_nx)
+    assert np.array_equal(np.sort(xf, axis=1), np.sort(r_xf, axis=1))
+    assert (nx > 0).mean() > 0.15  # a fifth of the pairs overlap
+
+
 def test_boxes_autograd_and_edges(dg):
     d = synth.c3_boxes(n=1000, seed=114)
     a = dev_t(d["a_box"]).requires_grad_(True)
