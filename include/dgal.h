@@ -153,7 +153,8 @@ typedef struct {
  *   a_off, b_off  DEVICE int64 [nseg+1], non-decreasing, within [0, count]
  *   out_off       DEVICE int64 [nseg]
  *   out_size      number of fp32 elements the caller allocated at iou
- *   iou           flat fp32 output
+ *   iou           flat fp32 output; element indices are 64-bit, so an output
+ *                 may hold more than 2^31 elements
  *   saved         REQUIRED: the forward's work list, also the state that
  *                 dgal_iou_backward needs (a forward-only caller may discard it).
  * Offsets live on the device so that the call can be captured in a HIP graph;
