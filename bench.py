@@ -423,7 +423,8 @@ def cpu_baseline(d, wl, kind):
             oracle.iou_matrix(xy, a_z=z, a_off=o, self_pairs=True)
             oracle.iou_matrix_grad(g, xy, a_z=z, a_off=o, self_pairs=True)
         pairs = int(sizes[:ns].sum())
-        what = f"first {ns} scenes ({pairs} self pairs), forward + backward"
+        what = (f"first {ns} scene{'s' if ns > 1 else ''} ({pairs} self pairs), "
+                "forward + backward")
     t, runs = _timed_runs(run)
     return {"value": round(pairs / t, 1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{what} x {runs} runs, median {t:.4f} s per run"}
