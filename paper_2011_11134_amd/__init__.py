@@ -390,8 +390,10 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
     Returns (iou, saved, seg): iou is [na, nb] for one block or flat
     (blocks concatenated row-major) with segments; saved is the SavedPairs
     work list (the backward's state; None when save=False); seg is the tuple
-    of device offsets.  capacity bounds the survivors of the cull (default
-    max(65536, pairs / 16)); exceeding it raises (check=True)."""
+    of device offsets.  capacity bounds the survivors of the cull; exceeding
+    a given one raises (check=True).  By default it is max(65536, pairs / 16),
+    and (check=True) a call that finds more survivors is repeated once with
+    room for all of them."""
     if self_pairs:
         b_xy, b_nv, b_z, b_off = a_xy, a_nv, a_z, a_off
     pa, ka = polys(a_xy, a_nv, a_z)
@@ -401,16 +403,31 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
         seg = _segments(a_xy.shape[0], b_xy.shape[0], a_off, b_off, self_pairs, dev)
     d_a, d_b, d_o, nseg, total, tiles = seg
     iou = torch.empty(total, dtype=torch.float32, device=dev)
+    sized = capacity is not None
     if capacity is None:
         capacity = max(1 << 16, total // 16)
-    saved = SavedPairs(capacity, a_xy.shape[1] + b_xy.shape[1], tiles, dev)
-    st = saved.struct()
-    _ok(lib.dgal_iou_matrix(context(dev), pa, pb, _ptr(d_a), _ptr(d_b), _ptr(d_o), nseg,
-                            int(bool(self_pairs)), _ptr(iou), total, ctypes.byref(st),
-                            _stream(a_xy)),
-        "dgal_iou_matrix")
+
+    def run(cap):
+        sv = SavedPairs(cap, a_xy.shape[1] + b_xy.shape[1], tiles, dev)
+        st = sv.struct()
+        _ok(lib.dgal_iou_matrix(context(dev), pa, pb, _ptr(d_a), _ptr(d_b), _ptr(d_o), nseg,
+                                int(bool(self_pairs)), _ptr(iou), total, ctypes.byref(st),
+                                _stream(a_xy)),
+            "dgal_iou_matrix")
+        return sv
+
+    saved = run(capacity)
     if check:
-        check_errors(dev)
+        try:
+            check_errors(dev)
+        except DgalError as e:
+            # a default capacity too small for this input: the count holds how
+            # many pairs survived the cull, so the call is repeated once with
+            # room for all of them
+            if sized or e.status != DGAL_ECAPACITY:
+                raise
+            saved = run(int(saved.count.item()))
+            check_errors(dev)
     if d_a is None:
         iou = iou.view(a_xy.shape[0], b_xy.shape[0])
     return iou, (saved if save else None), (d_a, d_b, d_o, nseg)

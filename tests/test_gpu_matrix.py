@@ -363,6 +363,29 @@ def test_saved_capacity_overflow_is_reported(dg):
     dg.check_errors()
 
 
+def test_default_capacity_grows(dg):
+    """Boxes crowded so that nearly every pair survives the cull, far more
+    than the default capacity (pairs / 16): the binding repeats the call
+    once with room for all survivors; IoU and gradients match the oracle."""
+    d = synth.c2_matrix(n=1500, m=1500, seed=16)
+    a = _crowd(d["a_xy"], 0.01)
+    ta = dev_t(a)
+    iou, saved, seg = dg.iou_matrix(ta, ta, save=True)
+    cnt = int(saved.count.item())
+    assert cnt > 1500 * 1500 // 16 and saved.capacity >= cnt
+    rng = np.random.default_rng(17)
+    r, c = rng.integers(0, 1500, 20000), rng.integers(0, 1500, 20000)
+    ref, _, _ = oracle.iou_index_pairs(r, c, a, a, threads=8)
+    assert np.abs(iou.cpu().numpy()[r, c] - ref).max() <= IOU_TOL
+    g = rng.uniform(-1, 1, (1500, 1500)).astype(np.float32)
+    ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g).reshape(-1), saved, seg, ta, ta)
+    ref_a, ref_b, _, _ = oracle.iou_matrix_grad(g.reshape(-1), a, a)
+    for got, rr in ((ga.cpu().numpy(), ref_a), (gb.cpu().numpy(), ref_b)):
+        err = np.linalg.norm((got - rr).reshape(len(rr), -1), axis=1)
+        scale = np.maximum(np.linalg.norm(rr.reshape(len(rr), -1), axis=1), 1e-6)
+        assert np.percentile(err / scale, 99) <= 5 * GRAD_TOL
+
+
 def test_matrix_beyond_int32(dg):
     """A 65,536 x 33,000 matrix: 2.16e9 pairs (8.6 GB of output), flat indices
     past 2^31.  Checked without copying the output: the saved survivors
