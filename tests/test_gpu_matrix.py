@@ -363,6 +363,54 @@ def test_saved_capacity_overflow_is_reported(dg):
     dg.check_errors()
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_random_ragged_segments(dg, seed):
+    """Random ragged segmentations (empty segments included, sizes that are
+    not multiples of the 8 x 256 tile): two sets, and 3D self-pair scenes;
+    IoU on every pair and gradients against the oracle."""
+    rng = np.random.default_rng(3000 + seed)
+    na, nb = int(rng.integers(1, 700)), int(rng.integers(1, 700))
+    d = synth.c2_matrix(n=na, m=nb, seed=3100 + seed)
+    a = _crowd(d["a_xy"], float(rng.uniform(0.05, 0.3)))
+    b = _crowd(d["b_xy"], float(rng.uniform(0.05, 0.3)))
+    ns = int(rng.integers(1, 7))
+    a_off = np.concatenate([[0], np.sort(rng.integers(0, na + 1, ns - 1)), [na]]).astype(np.int64)
+    b_off = np.concatenate([[0], np.sort(rng.integers(0, nb + 1, ns - 1)), [nb]]).astype(np.int64)
+    _say(f"case: two sets {na} x {nb}, segments {a_off.tolist()} / {b_off.tolist()}")
+    iou, saved, seg = dg.iou_matrix(dev_t(a), dev_t(b), a_off=a_off, b_off=b_off, save=True)
+    ref, _ = oracle.iou_matrix(a, b, a_off=a_off, b_off=b_off)
+    if ref.size:
+        assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
+    g = rng.uniform(-1, 1, ref.shape[0]).astype(np.float32)
+    ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(a), dev_t(b))
+    ra, rb, _, _ = oracle.iou_matrix_grad(g, a, b, a_off=a_off, b_off=b_off)
+    for got, rr in ((ga.cpu().numpy(), ra), (gb.cpu().numpy(), rb)):
+        err = np.linalg.norm((got - rr).reshape(len(rr), -1), axis=1)
+        scale = np.maximum(np.linalg.norm(rr.reshape(len(rr), -1), axis=1), 1e-6)
+        assert np.percentile(err / scale, 99) <= GRAD_TOL
+    sizes = rng.integers(0, 300, int(rng.integers(1, 9)))
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    if n == 0:
+        return
+    d5 = synth.c5_scenes(scenes=1, nmin=n, nmax=n, seed=3200 + seed)
+    xy = _crowd(d5["a_xy"][:n], float(rng.uniform(0.1, 0.4)))
+    lo, hi = d5["a_zlo"][:n], d5["a_zhi"][:n]
+    _say(f"case: scenes {sizes.tolist()}")
+    z = (dev_t(lo), dev_t(hi))
+    iou, saved, seg = dg.iou_matrix(dev_t(xy), a_z=z, a_off=off, self_pairs=True, save=True)
+    ref, _ = oracle.iou_matrix(xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
+    g = rng.uniform(-1, 1, ref.shape[0]).astype(np.float32)
+    ga, _, gz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(xy), a_z=z, self_pairs=True)
+    ra, _, rz, _ = oracle.iou_matrix_grad(g, xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    got = np.concatenate([ga.cpu().numpy().reshape(n, -1), gz.cpu().numpy()], 1)
+    rr = np.concatenate([ra.reshape(n, -1), rz], 1)
+    err = np.linalg.norm(got - rr, axis=1)
+    scale = np.maximum(np.linalg.norm(rr, axis=1), 1e-6)
+    assert np.percentile(err / scale, 99) <= GRAD_TOL
+
+
 def test_default_capacity_grows(dg):
     """Boxes crowded so that nearly every pair survives the cull, far more
     than the default capacity (pairs / 16): the binding repeats the call
