@@ -411,6 +411,36 @@ def test_random_ragged_segments(dg, seed):
     assert np.percentile(err / scale, 99) <= GRAD_TOL
 
 
+def test_max_segments(dg):
+    """DGAL_MAX_SEGMENTS (4096) self-pair scenes of 0..6 boxes each: the
+    segment prefix spread over the prefix kernel's threads, many empty and
+    one-box scenes; IoU and gradients against the oracle."""
+    rng = np.random.default_rng(44)
+    sizes = rng.integers(0, 7, dg.MAX_SEGMENTS)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    d = synth.c5_scenes(scenes=1, nmin=n, nmax=n, seed=45)
+    xy, lo, hi = d["a_xy"][:n], d["a_zlo"][:n], d["a_zhi"][:n]
+    # every scene's boxes near one point, so that they overlap
+    centre = np.repeat(rng.uniform(0, 50, (len(sizes), 2)), sizes, axis=0)
+    xy = (xy - xy.mean(1, keepdims=True) + centre[:, None, :]
+          + rng.normal(0, 0.5, (n, 1, 2))).astype(np.float32)
+    _say(f"case: {len(sizes)} scenes, {n} boxes")
+    z = (dev_t(lo), dev_t(hi))
+    iou, saved, seg = dg.iou_matrix(dev_t(xy), a_z=z, a_off=off, self_pairs=True, save=True)
+    ref, _ = oracle.iou_matrix(xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
+    assert np.count_nonzero(ref) > 3 * n
+    g = rng.uniform(-1, 1, ref.shape[0]).astype(np.float32)
+    ga, _, gz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(xy), a_z=z, self_pairs=True)
+    ra, _, rz, _ = oracle.iou_matrix_grad(g, xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    got = np.concatenate([ga.cpu().numpy().reshape(n, -1), gz.cpu().numpy()], 1)
+    rr = np.concatenate([ra.reshape(n, -1), rz], 1)
+    err = np.linalg.norm(got - rr, axis=1)
+    scale = np.maximum(np.linalg.norm(rr, axis=1), 1e-6)
+    assert np.percentile(err / scale, 99) <= GRAD_TOL
+
+
 def test_default_capacity_grows(dg):
     """Boxes crowded so that nearly every pair survives the cull, far more
     than the default capacity (pairs / 16): the binding repeats the call
