@@ -363,3 +363,49 @@ def test_graph_replay_matches_eager(dg):
         del junk
     dg.check_errors()
 
+
+def test_pairs_beyond_int32_elements(dg):
+    """2^28 + 1000 rectangle pairs (element offsets of the [n, 4, 2] inputs
+    and gradients past 2^31; ~39 GB of device memory), built on the device;
+    sampled pairs across the whole range against the oracle: IoU, count and
+    codes, gradients on the non-degenerate ones."""
+    n = (1 << 28) + 1000
+    gen = torch.Generator("cuda").manual_seed(71)
+
+    def quads(cx, cy, w, l, yaw):
+        c, s_ = torch.cos(yaw), torch.sin(yaw)
+        ux, uy = 0.5 * w * c, 0.5 * w * s_
+        vx, vy = -0.5 * l * s_, 0.5 * l * c
+        xs = torch.stack([cx - ux - vx, cx + ux - vx, cx + ux + vx, cx - ux + vx], 1)
+        ys = torch.stack([cy - uy - vy, cy + uy - vy, cy + uy + vy, cy - uy + vy], 1)
+        return torch.stack([xs, ys], 2).contiguous()
+
+    def u(lo, hi):
+        return torch.rand(n, device="cuda", generator=gen) * (hi - lo) + lo
+
+    cx, cy, w, l, yaw = u(-2, 2), u(-2, 2), u(1, 3), u(1, 3), u(-3.14, 3.14)
+    a = quads(cx, cy, w, l, yaw)
+    b = quads(cx + u(-0.5, 0.5), cy + u(-0.5, 0.5), w + u(-0.1, 0.1), l + u(-0.1, 0.1),
+              yaw + u(-0.2, 0.2))
+    del cx, cy, w, l, yaw
+    g = u(-1, 1)
+    _say(f"case: {n} rectangle pairs")
+    iou, nx, xf = dg.iou_pairs(a, b)
+    ga, gb, _, _ = dg.iou_pairs_backward(a, b, g, nx, xf)
+    dg.check_errors()
+    rng = np.random.default_rng(72)
+    idx = np.concatenate([rng.integers(0, n, 30000), np.arange(n - 1000, n)])
+    ti = torch.from_numpy(idx).cuda()
+    sa, sb, sg = a[ti].cpu().numpy(), b[ti].cpu().numpy(), g[ti].cpu().numpy()
+    ref, r_nx, r_xf, bad = oracle.iou_pairs(sa, sb, threads=16)
+    assert bad == 0
+    assert np.abs(iou[ti].cpu().numpy() - ref).max() <= IOU_TOL
+    assert np.array_equal(nx[ti].cpu().numpy(), r_nx)
+    assert np.array_equal(np.sort(xf[ti].cpu().numpy(), axis=1), np.sort(r_xf, axis=1))
+    keep = oracle.filtered_mask(oracle.pair_margins(sa, sb, threads=16))
+    r_ga, r_gb = oracle.iou_pairs_grad(sa, sb, sg, r_nx, r_xf, threads=16)[:2]
+    err = grad_rel_err(np.concatenate([ga[ti].cpu().numpy().reshape(len(idx), -1),
+                                       gb[ti].cpu().numpy().reshape(len(idx), -1)], 1),
+                       np.concatenate([r_ga.reshape(len(idx), -1), r_gb.reshape(len(idx), -1)], 1))
+    assert keep.mean() > 0.9 and err[keep].max() <= GRAD_TOL
+
