@@ -76,6 +76,42 @@ def _check_intersect(dg, a, b, a_nv=None, b_nv=None, seed=0):
             "max_grad_err": float(gerr[keep].max())}
 
 
+def test_intersect_grid_contacts(dg):
+    """Integer rectangles and diamonds on a small grid (contacts on most
+    pairs): count and set of codes equal the oracle's on every pair, and
+    every vertex the oracle places at a code is the GPU's vertex of that code
+    to a few ulp of the coordinates (the order of coinciding points is free)."""
+    rng = np.random.default_rng(2300)
+    shapes = []
+    for _ in range(20000):
+        x0, y0 = rng.integers(-3, 3, 2)
+        w, h = rng.integers(1, 4, 2)
+        if rng.integers(0, 2):
+            v = [(x0, y0), (x0 + w, y0), (x0 + w, y0 + h), (x0, y0 + h)]
+        else:
+            v = [(x0 + w, y0), (x0, y0 + w), (x0 - w, y0), (x0, y0 - w)]
+        shapes.append(v)
+    a = np.array(shapes[:10000], np.float32)
+    b = np.array(shapes[10000:], np.float32)
+    _say("case: intersect grid contacts 10000")
+    xy, nx, xf = dg.intersect(dev_t(a), dev_t(b))
+    dg.check_errors()
+    xy, nx, xf = xy.cpu().numpy(), nx.cpu().numpy(), xf.cpu().numpy()
+    r_xy, r_nx, r_xf, bad = oracle.intersect_pairs(a, b, threads=8)
+    assert bad == 0
+    assert np.array_equal(nx, r_nx)
+    assert np.array_equal(np.sort(xf, axis=1), np.sort(r_xf, axis=1))
+    # match vertices by code (codes are unique within a pair)
+    worst = 0.0
+    for i in np.flatnonzero(nx):
+        m = int(nx[i])
+        pos = {int(c): xy[i, k] for k, c in enumerate(xf[i, :m])}
+        for k, c in enumerate(r_xf[i, :m]):
+            worst = max(worst, float(np.abs(pos[int(c)] - r_xy[i, k]).max()))
+    assert worst <= 8 * 2.0 ** -24 * 8, worst
+    assert (nx > 0).mean() > 0.15
+
+
 def test_intersect_rectangles(dg):
     _say("case: intersect c1 rectangles 1024 pairs")
     d = synth.c1_pairs()
