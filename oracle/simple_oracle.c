@@ -8,7 +8,7 @@
  *
  * Paper: Y. Zhong, "Differentiable Computational Geometry for 2D and 3D machine
  * learning", arXiv 2011.11134.  Sec. III keeps polygons convex and plans
- * support for arbitrary polygons; Sec. VI lists arbitrary shapes as future
+ * support for arbitrary polygons; Sec. V lists arbitrary shapes as future
  * work.  This file computes, for simple polygons P and Q, the plain
  * definitions:
  *
