@@ -4,12 +4,14 @@ on one MI355X.
 
 A step is one pass of the whole path over one batch of synthetic inputs that
 are resident in HBM before timing starts:
-  c3 (default): 1,048,576 rotated-rectangle pairs, forward (IoU + saved nx /
+  c5 (default): 64 scenes of U{50..2000} 3D boxes, per-scene self-pair IoU
+                (~94 M pairs), forward (cull, work list, exact pairs) and
+                backward from the saved work list: the largest workload, and
+                the one the pairs/s metric is quoted on;
+  c3:           1,048,576 rotated-rectangle pairs, forward (IoU + saved nx /
                 xflags) and backward (gradients for both boxes) kernels;
   c1 / c4:      the same on 1,024 rectangle pairs / 262,144 mixed 3..8-gon pairs;
   c2:           4096 x 4096 IoU matrix, forward;
-  c5:           64 scenes of 3D boxes, per-scene self-pair IoU, forward and
-                backward (saved non-empty pairs);
   c3b:          c3's pairs as box-parameter rows (corners formed in-kernel),
                 forward and backward to the parameters;
   c3i:          the exported intersection primitive on c3's pairs (ordered
@@ -17,9 +19,10 @@ are resident in HBM before timing starts:
   c4n:          262,144 pairs of simple, generally non-convex 3..8-gons,
                 forward and backward.
 Prints one JSON line (rank 0, one GPU).  The timed region is `steps` steps
-back to back (eager launches, or --graph: replays of one captured HIP graph
-of the step); kernel launch durations come from HIP events on the launch
-stream around the same number of back-to-back launches of each kernel.
+back to back: replays of one captured HIP graph of the step (--eager: the
+library's calls launched one by one).  Kernel durations for the roofline come
+from the library's per-kernel timing mode (HIP events on the launch stream
+around each kernel), run after the timed region.
 """
 import argparse
 import json
@@ -70,7 +73,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "c3b", "c3i", "c4n"])
+    p.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5", "c3b", "c3i", "c4n"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true", help="skip the plain per-op GPU form")
     p.add_argument("--copy-calib-mib", type=int, default=0,
@@ -78,8 +81,10 @@ def parse():
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the built-in launch shapes (default: the library's autotuner "
                         "picks them during the warm-up)")
-    p.add_argument("--graph", action="store_true",
-                   help="replay a captured HIP graph of the step instead of eager launches")
+    p.add_argument("--eager", action="store_true",
+                   help="launch the step's calls one by one instead of replaying a captured "
+                        "HIP graph of the step")
+    p.add_argument("--graph", action="store_true", help="(the default) replay a HIP graph")
     return p.parse_args()
 
 
@@ -112,6 +117,16 @@ def stored_traffic(workload, kernel):
     return None if ent is None else int(ent["bytes"])
 
 
+def _elementwise_bytes(kind, kernel, pairs):
+    """(bound, algorithmic bytes per launch, basis) of an elementwise kernel:
+    its inputs read once and its outputs written once (the BYTES table)."""
+    direction = kernel.rsplit("_", 1)[-1]
+    per = BYTES.get((kind, direction))
+    if per is None:
+        return "hbm", 0, f"{kernel}: not priced"
+    return "hbm", per * pairs, f"{per} B per pair x {pairs} pairs"
+
+
 class PairsStep:
     """Forward + backward of elementwise pairs with fixed device buffers."""
 
@@ -135,6 +150,9 @@ class PairsStep:
         self.ctx = dg.context()
         self.kind = "rect" if ka == 4 and self.anv is None else "poly"
         self.pairs = n
+
+    def algorithmic_bytes(self, kernel):
+        return _elementwise_bytes(self.kind, kernel, self.pairs)
 
     def fwd(self, stream):
         st = self.dg.lib.dgal_iou_pairs(self.ctx, self.pa, self.pb, self.iou.data_ptr(),
@@ -171,6 +189,9 @@ class BoxesStep:
         self.ctx = dg.context()
         self.kind = "box"
 
+    def algorithmic_bytes(self, kernel):
+        return _elementwise_bytes(self.kind, kernel, self.pairs)
+
     def fwd(self, stream):
         st = self.dg.lib.dgal_iou_boxes(self.ctx, self.ba, self.bb, self.iou.data_ptr(),
                                         self.nx.data_ptr(), self.xf.data_ptr(), stream)
@@ -205,6 +226,9 @@ class IntersectStep:
         self.pb, _ = dg.polys(self.b)
         self.ctx = dg.context()
         self.kind = "isect"
+
+    def algorithmic_bytes(self, kernel):
+        return _elementwise_bytes(self.kind, kernel, self.pairs)
 
     def fwd(self, stream):
         st = self.dg.lib.dgal_intersect(self.ctx, self.pa, self.pb, self.xy.data_ptr(),
@@ -241,6 +265,9 @@ class SimpleStep:
         self.pb, _ = dg.polys(self.b, self.bnv)
         self.ctx = dg.context()
         self.kind = "simple"
+
+    def algorithmic_bytes(self, kernel):
+        return _elementwise_bytes(self.kind, kernel, self.pairs)
 
     def fwd(self, stream):
         st = self.dg.lib.dgal_iou_simple_pairs(self.ctx, self.pa, self.pb, self.iou.data_ptr(),
@@ -297,6 +324,31 @@ class MatrixStep:
     def _p(self, t):
         return None if t is None else t.data_ptr()
 
+    def algorithmic_bytes(self, kernel):
+        """(bound, bytes per launch, basis): what each kernel of the matrix
+        path must read and write at least, every input once.  A box is
+        32 B of corners (+ 8 B of z-extent in 3D); a saved work-list entry is
+        an 8 B pair id, 1 B nx and 8 B of flags."""
+        box = 32 + (8 if self.self_pairs else 0)
+        boxes = len(self.a) + (0 if self.self_pairs else len(self.b))
+        surv = int(self.saved.count.item())
+        g_reads = 8 if self.self_pairs else 4  # the entry's g (and its transpose's)
+        if kernel == "k_matrix_cull":
+            return ("hbm", 4 * self.pairs + box * boxes,
+                    f"4 B of output per pair x {self.pairs} pairs + {box} B x {boxes} boxes")
+        if kernel == "k_matrix_exact":
+            return ("hbm", 21 * surv + box * boxes,
+                    f"21 B per survivor (8 id + 4 IoU + 1 nx + 8 flags) x {surv} + "
+                    f"{box} B x {boxes} boxes")
+        if kernel == "k_matrix_fill":
+            return "hbm", 8 * surv, f"8 B pair id per survivor x {surv}"
+        if kernel == "k_matrix_bwd":
+            per = 17 + g_reads
+            return ("hbm", per * surv + 2 * box * boxes,
+                    f"{per} B per survivor (17 saved + {g_reads} upstream) x {surv} + "
+                    f"2 x {box} B (read, written) x {boxes} boxes")
+        return "hbm", 0, f"{kernel}: not priced"
+
     def fwd(self, stream):
         dg = self.dg
         d_a, d_b, d_o, nseg = self.seg
@@ -317,21 +369,36 @@ class MatrixStep:
         assert st == 0, st
 
 
-def plain_baseline(torch, d, steps=5, warmup=2):
+def plain_baseline(torch, d, wl, steps=5, warmup=2):
     """The plain per-op GPU form (torch ops + autograd) on the same workload:
-    forward + backward pairs/s."""
-    from bench_plain import iou_pairs_plain
-    a = torch.from_numpy(d["a_xy"]).cuda().requires_grad_(True)
-    b = torch.from_numpy(d["b_xy"]).cuda().requires_grad_(True)
-    anv = None if d.get("a_nv") is None else torch.from_numpy(d["a_nv"]).cuda()
-    bnv = None if d.get("b_nv") is None else torch.from_numpy(d["b_nv"]).cuda()
-    g = torch.from_numpy(d["grad"]).cuda()
+    forward + backward pairs/s.  Scenes: each scene's pairs formed by
+    broadcasting, one scene at a time (bench_plain.iou3d_scenes_plain)."""
+    from bench_plain import iou3d_scenes_plain, iou_pairs_plain
+    if wl == "c5":
+        xy = torch.from_numpy(d["a_xy"]).cuda().requires_grad_(True)
+        lo = torch.from_numpy(d["a_zlo"]).cuda().requires_grad_(True)
+        hi = torch.from_numpy(d["a_zhi"]).cuda().requires_grad_(True)
+        g = torch.from_numpy(d["grad"]).cuda()
+        off = d["off"]
+        pairs = int(d["out_off"][-1])
 
-    def step():
-        a.grad = None
-        b.grad = None
-        iou = iou_pairs_plain(a, b, anv, bnv)
-        iou.backward(g)
+        def step():
+            for t in (xy, lo, hi):
+                t.grad = None
+            iou3d_scenes_plain(xy, lo, hi, off).backward(g)
+    else:
+        a = torch.from_numpy(d["a_xy"]).cuda().requires_grad_(True)
+        b = torch.from_numpy(d["b_xy"]).cuda().requires_grad_(True)
+        anv = None if d.get("a_nv") is None else torch.from_numpy(d["a_nv"]).cuda()
+        bnv = None if d.get("b_nv") is None else torch.from_numpy(d["b_nv"]).cuda()
+        g = torch.from_numpy(d["grad"]).cuda()
+        pairs = len(d["a_xy"])
+
+        def step():
+            a.grad = None
+            b.grad = None
+            iou = iou_pairs_plain(a, b, anv, bnv)
+            iou.backward(g)
 
     for _ in range(warmup):
         step()
@@ -343,9 +410,11 @@ def plain_baseline(torch, d, steps=5, warmup=2):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    return {"value": round(len(d["a_xy"]) / (ms * 1e-3), 1), "unit": "pairs/s",
-            "ms_per_step": round(ms, 4), "steps": steps,
-            "form": "torch ops + autograd on the GPU (bench_plain.py)"}
+    form = "torch ops + autograd on the GPU (bench_plain.py)"
+    if wl == "c5":
+        form += ", every ordered pair of a scene by broadcasting, scene by scene"
+    return {"value": round(pairs / (ms * 1e-3), 1), "unit": "pairs/s",
+            "ms_per_step": round(ms, 4), "steps": steps, "form": form}
 
 
 def _timed_runs(fn, min_s=1.0):
@@ -363,71 +432,119 @@ def cpu_baseline(d, wl, kind):
     """The FP64 oracle, as it stands, on the host cores, on the workload or a
     bounded sample of it: forward + analytic backward (forward only for the
     c2 matrix), repeated for at least 1 s of wall time (at least 3 runs),
-    median run, as pairs/s."""
-    import numpy as np
-
+    median run, as pairs/s; on the host's cores (up to 16 threads, the
+    batch split in contiguous ranges) and on one thread."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    cores = max(1, min(16, os.cpu_count() or 1))
     if kind in ("rect", "poly"):
         a, b, g = d["a_xy"], d["b_xy"], d["grad"]
         anv, bnv = d.get("a_nv"), d.get("b_nv")
 
-        def run():
+        def run(threads):
             iou, nx, xf, _ = oracle.iou_pairs(a, b, anv, bnv, threads=threads)
             oracle.iou_pairs_grad(a, b, g, nx, xf, anv, bnv, threads=threads)
         pairs, what = len(a), f"whole workload ({len(a)} pairs, forward + backward)"
     elif kind == "box":
         a, b, g = d["a_box"], d["b_box"], d["grad"]
 
-        def run():
+        def run(threads):
             iou, nx, xf, _ = oracle.iou_boxes(a, b, threads=threads)
             oracle.iou_boxes_grad(a, b, g, nx, xf, threads=threads)
         pairs, what = len(a), f"whole workload ({len(a)} box pairs, forward + backward)"
     elif kind == "simple":
         a, b, g, anv, bnv = d["a_xy"], d["b_xy"], d["grad"], d["a_nv"], d["b_nv"]
 
-        def run():
+        def run(threads):
             oracle.simple_iou_pairs(a, b, anv, bnv, threads=threads)
             oracle.simple_iou_pairs_grad(a, b, g, anv, bnv, threads=threads)
         pairs, what = len(a), f"whole workload ({len(a)} simple polygon pairs, forward + backward)"
     elif kind == "isect":
         a, b, g = d["a_xy"], d["b_xy"], d["grad_xy"]
 
-        def run():
+        def run(threads):
             xy, nx, xf, _ = oracle.intersect_pairs(a, b, threads=threads)
             oracle.intersect_pairs_grad(a, b, g, nx, xf, threads=threads)
         pairs, what = len(a), f"whole workload ({len(a)} pairs, intersection + backward)"
     elif wl == "c2":
         # the oracle's matrix routine runs on one thread: the first 128 rows
         # against all 4096 columns
-        threads = 1
+        cores = 1
         a, b = d["a_xy"][:128], d["b_xy"]
 
-        def run():
+        def run(threads):
             oracle.iou_matrix(a, b)
         pairs, what = len(a) * len(b), f"rows 0..127 x {len(b)} columns of the matrix, forward"
     else:
-        # c5 on one thread: the first scenes up to about 1 M self pairs,
-        # forward + backward
-        threads = 1
-        off = d["off"]
-        sizes = (off[1:] - off[:-1]) ** 2
-        ns = int(np.searchsorted(np.cumsum(sizes), 1 << 20)) + 1
-        ns = min(ns, len(sizes))
-        o = off[:ns + 1]
-        xy = d["a_xy"][:o[-1]]
-        z = (d["a_zlo"][:o[-1]], d["a_zhi"][:o[-1]])
-        g = d["grad"][:int(sizes[:ns].sum())]
+        return _cpu_baseline_scenes(d)
+    t, runs = _timed_runs(lambda: run(cores))
+    out = {"value": round(pairs / t, 1), "unit": "pairs/s", "cores": cores, "kind": "oracle",
+           "sample": f"{what} x {runs} runs, median {t:.4f} s per run",
+           "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+    if cores > 1:
+        t1, r1 = _timed_runs(lambda: run(1))
+        out["value_1_thread"] = round(pairs / t1, 1)
+        out["sample_1_thread"] = f"the same on one thread x {r1} runs, median {t1:.4f} s"
+    return out
 
-        def run():
-            oracle.iou_matrix(xy, a_z=z, a_off=o, self_pairs=True)
-            oracle.iou_matrix_grad(g, xy, a_z=z, a_off=o, self_pairs=True)
-        pairs = int(sizes[:ns].sum())
-        what = (f"first {ns} scene{'s' if ns > 1 else ''} ({pairs} self pairs), "
-                "forward + backward")
-    t, runs = _timed_runs(run)
-    return {"value": round(pairs / t, 1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{what} x {runs} runs, median {t:.4f} s per run"}
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _cpu_baseline_scenes(d, frac=0.1, seed=2011):
+    """The oracle's per-scene self-pair matrix, forward + analytic backward,
+    on a seeded sample of 10% of the scenes (every pair of each sampled
+    scene), run on one thread and on the host's cores (the sampled scenes in
+    parallel, one per thread; ctypes releases the GIL), at least 3 runs each,
+    median; pairs/s scales linearly to the whole workload (each pair costs the
+    same on average, independent of its scene)."""
+    import numpy as np
+
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    off, xy, lo, hi, g = d["off"], d["a_xy"], d["a_zlo"], d["a_zhi"], d["grad"]
+    out_off = d["out_off"]
+    nsc = len(off) - 1
+    pick = np.sort(np.random.default_rng(seed).choice(nsc, max(1, round(frac * nsc)),
+                                                      replace=False))
+    jobs = []
+    for s in pick:
+        o0, o1 = int(off[s]), int(off[s + 1])
+        jobs.append((xy[o0:o1], (lo[o0:o1], hi[o0:o1]), np.array([0, o1 - o0], np.int64),
+                     g[out_off[s]:out_off[s + 1]]))
+    pairs = int(sum((off[s + 1] - off[s]) ** 2 for s in pick))
+
+    def one(job):
+        x, z, o, gg = job
+        oracle.iou_matrix(x, a_z=z, a_off=o, self_pairs=True)
+        oracle.iou_matrix_grad(gg, x, a_z=z, a_off=o, self_pairs=True)
+
+    def serial():
+        for j in jobs:
+            one(j)
+
+    threads = max(1, min(len(jobs), os.cpu_count() or 1, 16))
+
+    def parallel():
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, jobs))
+
+    t1, r1 = _timed_runs(serial, min_s=0.0)
+    tn, rn = _timed_runs(parallel, min_s=0.0)
+    return {"value": round(pairs / tn, 1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": (f"seeded 10% of the scenes ({len(pick)} of {nsc}: {pairs} self pairs), "
+                       f"forward + backward, one scene per thread, x {rn} runs, median "
+                       f"{tn:.3f} s per run; scales to the whole workload by pairs"),
+            "value_1_thread": round(pairs / t1, 1),
+            "sample_1_thread": f"the same sample on one thread x {r1} runs, median {t1:.3f} s",
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def main():
@@ -473,11 +590,11 @@ def main():
     dg.check_errors()
     tuned = dg.autotune_report()[1].strip().splitlines()
 
-    # --graph: the forward and the backward of one step are captured once into
-    # a HIP graph (the library allocates nothing per call and needs no host
-    # sync) and the graph is replayed; by default the two are launched eagerly
-    # (graph replay measured a few percent slower on every workload).
-    if args.graph:
+    # The step is captured once into a HIP graph (the library allocates
+    # nothing per call and needs no host synchronisation) and replayed;
+    # --eager launches the calls one by one instead.
+    use_graph = not args.eager
+    if use_graph:
         g_step = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g_step):
             cs = torch.cuda.current_stream().cuda_stream
@@ -498,7 +615,7 @@ def main():
 
     # Timed region: exactly `steps` steps, bracketed by synchronize, with one
     # event pair on the launch stream around it (an event between kernels
-    # would add ~5 us of queue work per event to every step).
+    # would add queue work to every step).
     e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -511,44 +628,35 @@ def main():
     dg.check_errors()
     step_ms_events = e_start.elapsed_time(e_end) / args.steps
 
-    # Launch durations of each kernel: the same number of launches back to
-    # back on the launch stream between two events (the average includes the
-    # dispatch gap between consecutive launches, ~1 us).
-    def launch_ms(fn):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            fn(stream)
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / args.steps
-
-    fwd_ms = launch_ms(step.fwd)
-    bwd_ms = launch_ms(step.bwd) if has_bwd else 0.0
+    # Kernel durations: the library's per-kernel timing mode brackets every
+    # kernel it launches with two HIP events on the launch stream (and waits
+    # for each), over `steps` more steps launched one by one.
+    dg.set_profiling(True)
+    for _ in range(args.steps):
+        step.fwd(stream)
+        if has_bwd:
+            step.bwd(stream)
+    torch.cuda.synchronize()
+    prof = dg.profile_report()
+    dg.set_profiling(False)
     dg.check_errors()
-
-    kernels = {"fwd": fwd_ms, "bwd": bwd_ms} if has_bwd else {"fwd": fwd_ms}
-    dom = max(kernels, key=kernels.get)
-    dur_s = kernels[dom] * 1e-3
-    if step.kind == "matrix":
-        # the output stream: 4 B per pair written (inputs are a few MB)
-        bytes_total = 4 * step.pairs
-        kname = "k_matrix_fwd" if dom == "fwd" else "k_matrix_bwd"
-    else:
-        bytes_total = BYTES[(step.kind, dom)] * step.pairs
-        kname = {"box": "k_boxes", "isect": "k_intersect",
-                 "simple": "k_simple"}.get(step.kind, "k_pairs") + f"_{dom}"
-    hbm_gbs = bytes_total / dur_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    per_launch = {k: ms / n for k, (n, ms) in prof.items()}
+    per_step = {k: ms / args.steps for k, (n, ms) in prof.items()}
+    kname = max(per_step, key=per_step.get)  # the dominant kernel of a step
+    dur_s = per_launch[kname] * 1e-3
+    bound, bytes_launch, basis = step.algorithmic_bytes(kname)
+    hbm_gbs = bytes_launch / dur_s / 1e9
+    roof = {"bound": bound, "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(wl, kname),
-            "kernel": kname, "kernel_ms": round(kernels[dom], 4),
-            "bytes_per_launch": bytes_total}
-    if (step.kind, dom) in FLOPS:
-        tf = FLOPS[(step.kind, dom)] * step.pairs / dur_s / 1e12
+            "kernel": kname, "kernel_ms": round(per_launch[kname], 4),
+            "bytes_per_launch": int(bytes_launch), "bytes_basis": basis}
+    flops = FLOPS.get((step.kind, kname[-3:]))
+    if flops is not None:
+        tf = flops * step.pairs / dur_s / 1e12
         roof["alu"] = {"achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": round(tf / FP32_PEAK_TFLOPS, 4),
-                       "flops_per_pair": FLOPS[(step.kind, dom)]}
+                       "frac": round(tf / FP32_PEAK_TFLOPS, 4), "flops_per_pair": flops}
+    kernels = {k: {"ms_per_launch": round(per_launch[k], 4),
+                   "launches_per_step": round(prof[k][0] / args.steps, 2)} for k in prof}
 
     if args.copy_calib_mib:
         src = torch.empty(args.copy_calib_mib << 18, dtype=torch.float32, device="cuda")
@@ -561,8 +669,8 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(d, wl, step.kind)
     plain = None
-    if not args.no_plain and step.kind in ("rect", "poly"):
-        plain = plain_baseline(torch, d)
+    if not args.no_plain and (step.kind in ("rect", "poly") or wl == "c5"):
+        plain = plain_baseline(torch, d, wl)
 
     value = step.pairs * args.steps / elapsed
     names = {"c1": "c1: 1,024 rotated-rectangle pairs, forward + backward",
@@ -584,9 +692,9 @@ def main():
         "config": {"workload": names[wl], "pairs": int(step.pairs),
                    ("box_dim" if step.kind == "box" else "kmax"): int(step.a.shape[1]),
                    "parallelism": "single GPU",
-                   "launch": "HIP graph replay" if args.graph else "eager",
+                   "launch": "HIP graph replay" if use_graph else "eager",
                    "launch_shapes": tuned or "built-in"},
-        "kernels_ms": {k: round(v, 4) for k, v in kernels.items()},
+        "kernels": kernels,
         "step_ms_events": round(step_ms_events, 4),
         "roofline": roof,
         "cpu_baseline": cpu,

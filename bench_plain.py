@@ -24,6 +24,46 @@ def _cross(ax, ay, bx, by):
 def iou_pairs_plain(a, b, a_nv=None, b_nv=None):
     """a, b: [n, K, 2] fp32 CUDA tensors (requires_grad allowed); a_nv/b_nv:
     optional [n] vertex counts.  Returns IoU [n] fp32 (autograd-able)."""
+    inter, a1, a2, m = inter_areas_plain(a, b, a_nv, b_nv)
+    u = a1 + a2 - inter
+    ok = (m > 0) & (u > 0)
+    u_safe = torch.where(ok, u, torch.ones_like(u))
+    return torch.where(ok, inter / u_safe, torch.zeros_like(u))
+
+
+def iou3d_scenes_plain(xy, zlo, zhi, off):
+    """Per-scene self-pair 3D IoU, the plain way: every ordered pair of a
+    scene's boxes formed by broadcasting, the 2D geometry above, times the
+    z-overlap over the union volume; the diagonal is 1.  xy [n, 4, 2], zlo,
+    zhi [n] (requires_grad allowed), off: host offsets [scenes + 1].  Returns
+    the flat blocks, row-major per scene, concatenated (autograd-able)."""
+    out = []
+    for s in range(len(off) - 1):
+        o0, o1 = int(off[s]), int(off[s + 1])
+        n = o1 - o0
+        if n == 0:
+            continue
+        A = xy[o0:o1]
+        a = A[:, None].expand(n, n, *A.shape[1:]).reshape(n * n, *A.shape[1:])
+        b = A[None, :].expand(n, n, *A.shape[1:]).reshape(n * n, *A.shape[1:])
+        inter, a1, a2, m = inter_areas_plain(a, b)
+        lo, hi = zlo[o0:o1], zhi[o0:o1]
+        lo1, hi1 = lo[:, None].expand(n, n).reshape(-1), hi[:, None].expand(n, n).reshape(-1)
+        lo2, hi2 = lo[None, :].expand(n, n).reshape(-1), hi[None, :].expand(n, n).reshape(-1)
+        hz = torch.minimum(hi1, hi2) - torch.maximum(lo1, lo2)
+        v = inter * hz
+        u = a1 * (hi1 - lo1) + a2 * (hi2 - lo2) - v
+        ok = (m > 0) & (hz > 0) & (u > 0)
+        u_safe = torch.where(ok, u, torch.ones_like(u))
+        iou = torch.where(ok, v / u_safe, torch.zeros_like(u))
+        eye = torch.eye(n, dtype=torch.bool, device=xy.device).reshape(-1)
+        out.append(torch.where(eye, torch.ones_like(iou), iou))
+    return torch.cat(out)
+
+
+def inter_areas_plain(a, b, a_nv=None, b_nv=None):
+    """Intersection area, the two polygon areas and the intersection's vertex
+    count of elementwise pairs (the steps in the module docstring)."""
     n, K = a.shape[0], a.shape[1]
     dev = a.device
     k_idx = torch.arange(K, device=dev)
@@ -85,7 +125,4 @@ def iou_pairs_plain(a, b, a_nv=None, b_nv=None):
 
     a1 = area(px, py, n1, nxt1)
     a2 = area(qx, qy, n2, nxt2)
-    u = a1 + a2 - inter
-    ok = (m > 0) & (u > 0)
-    u_safe = torch.where(ok, u, torch.ones_like(u))
-    return torch.where(ok, inter / u_safe, torch.zeros_like(u))
+    return inter, a1, a2, m

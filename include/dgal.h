@@ -149,7 +149,11 @@ typedef struct {
  * row-major block of iou starting at element out_off[s].  With a_off ==
  * b_off == out_off == NULL (nseg ignored) there is one block a.count x b.count
  * at iou[0].  self_pairs != 0 means b is a (same pointers and counts; each
- * segment's block is square): the diagonal of each block is exactly 1.
+ * segment's block is square): the diagonal of each block is exactly 1, and
+ * entries (r, c) and (c, r) are the IoU of one unordered pair, evaluated with
+ * the lower-indexed polygon first (so the tie rule moves the higher-indexed
+ * one, and z-overlap ties go to the lower-indexed one): the block is
+ * symmetric and each pair has one derivative structure.
  *   a_off, b_off  DEVICE int64 [nseg+1], non-decreasing, within [0, count]
  *   out_off       DEVICE int64 [nseg]
  *   out_size      number of fp32 elements the caller allocated at iou
@@ -183,7 +187,10 @@ enum { DGAL_PAIRS = 0, DGAL_MATRIX = 1 };
  *                   written by dgal_iou_matrix with the same a, b, offsets and
  *                   self_pairs; nx / xflags ignored.  With self_pairs the
  *                   gradient of both roles accumulates into grad_a_* and
- *                   grad_b_* must be NULL; the diagonal contributes nothing.
+ *                   grad_b_* must be NULL; the diagonal contributes nothing,
+ *                   and each unordered pair's gradient (the lower index as
+ *                   the first polygon) is weighted by the sum of its two
+ *                   entries' upstream gradients.
  * Outputs (overwritten; padded vertex slots are written 0):
  *   grad_a_xy [a.count][a.kmax][2], grad_b_xy [b.count][b.kmax][2] fp32
  *   grad_a_z, grad_b_z [count][2] fp32 = (d/dzlo, d/dzhi); NULL for 2D.
@@ -240,7 +247,7 @@ int dgal_area_backward(dgal_ctx *ctx, dgal_polys p, const float *grad_area,
 
 /* IoU of SIMPLE polygons: counter-clockwise, not self-intersecting, not
  * necessarily convex (Sec. III keeps polygons convex and plans arbitrary
- * ones; Sec. VI lists arbitrary shapes as future work).  Elementwise pairs,
+ * ones; Sec. V lists arbitrary shapes as future work).  Elementwise pairs,
  * 2D only.  The intersection area is half the boundary integral of
  * x dy - y dx (Green's theorem): each edge contributes the cross product of
  * its end points times the fraction of the edge inside the other polygon,
@@ -339,6 +346,20 @@ int dgal_set_autotune(dgal_ctx *ctx, int32_t enable);
  * size) and returns the number of tuned kinds; DGAL_EINVAL for ctx NULL, a
  * negative size, or buf NULL with size > 0. */
 int dgal_autotune_report(dgal_ctx *ctx, char *buf, int64_t size);
+
+/* Per-kernel timing, a measuring aid (off by default).  While enabled, every
+ * kernel the library launches is bracketed by two HIP events on the caller's
+ * stream and waited for, and its duration is added to its kernel's total;
+ * calls therefore synchronise and must not be captured in a graph.  Enabling
+ * resets the totals.  DGAL_EINVAL: ctx NULL; DGAL_EHIP: event creation. */
+int dgal_set_profiling(dgal_ctx *ctx, int32_t enable);
+
+/* Writes one line per kernel timed since profiling was enabled,
+ * "<kernel> <launches> <total milliseconds>", into buf (NUL-terminated,
+ * truncated to size) and returns the number of kernels; DGAL_EINVAL for ctx
+ * NULL, a negative size, or buf NULL with size > 0; DGAL_EHIP if an event
+ * call failed while timing. */
+int dgal_profile_report(dgal_ctx *ctx, char *buf, int64_t size);
 
 /* Rotated boxes by their parameters (Sec. IV-A case study), the corners
  * formed in-kernel: corner k = (cx, cy) + R(yaw) (+-l/2, +-w/2),

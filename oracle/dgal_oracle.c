@@ -45,6 +45,14 @@
  *   R6 3D IoU: BEV intersection area times z-overlap over the union volume.
  *   R7 gradient at a change of combinatorial type: the one-sided gradient of
  *      the structure recorded in the flags.
+ *   R8 self-pair matrices (one set against itself, as in the per-scene 3D
+ *      IoU of Sec. IV-A): entries (r, c) and (c, r) hold the IoU of one
+ *      unordered pair, evaluated once with the lower-indexed polygon as P and
+ *      the higher-indexed one as Q (the polygon the tie rule R3 moves, and the
+ *      second argument of the z-overlap ties).  The matrix is then symmetric
+ *      and each unordered pair has one derivative structure, so the summed
+ *      gradient of a pair keeps the translation and rotation invariances also
+ *      where the tie rule decides.
  */
 #include <math.h>
 #include <stddef.h>
@@ -797,7 +805,8 @@ int64_t oracle_iou_index_pairs(int64_t lo, int64_t hi, const int64_t *ia,
 /* Segmented IoU matrix: for each segment s, rows a[a_off[s]..a_off[s+1]) and
  * columns b[b_off[s]..b_off[s+1]) fill the row-major block that starts at
  * out_off[s].  self_pairs != 0 means b is a (same offsets) and the diagonal
- * of each block is 1 (the IoU of a polygon with itself). */
+ * of each block is 1 (the IoU of a polygon with itself); entry (r, c) is then
+ * the pair evaluated with the lower index first (R8). */
 void oracle_iou_matrix(int nseg, const int64_t *a_off, const int64_t *b_off,
                        const int64_t *out_off, int self_pairs, const float *a_xy,
                        const uint8_t *a_nv, int ka, const float *a_zlo,
@@ -814,6 +823,11 @@ void oracle_iou_matrix(int nseg, const int64_t *a_off, const int64_t *b_off,
           *o = 1.0;
           continue;
         }
+        if (self_pairs && r > c) { /* R8: the unordered pair, lower index first */
+          int64_t t = ia;
+          ia = ib;
+          ib = t;
+        }
         oracle_iou_index_pairs(0, 1, &ia, &ib, a_xy, a_nv, ka, a_zlo, a_zhi, b_xy,
                                b_nv, kb, b_zlo, b_zhi, o, NULL, NULL);
       }
@@ -822,8 +836,10 @@ void oracle_iou_matrix(int nseg, const int64_t *a_off, const int64_t *b_off,
 
 /* Gradient of sum g * IoU over a segmented matrix (layout as above).  Rows
  * accumulate into ga, columns into gb (into ga as well when self_pairs, whose
- * diagonal is the constant 1 and contributes nothing).  Outputs are
- * overwritten.  ga_z/gb_z may be NULL for 2D. */
+ * diagonal is the constant 1 and contributes nothing; entry (r, c) with r > c
+ * is the pair (c, r) of R8, so its P gradient goes to box c and its Q
+ * gradient to box r).  Outputs are overwritten.  ga_z/gb_z may be NULL for
+ * 2D. */
 void oracle_iou_matrix_grad(int nseg, const int64_t *a_off, const int64_t *b_off,
                             const int64_t *out_off, int self_pairs,
                             const float *a_xy, const uint8_t *a_nv, int ka,
@@ -849,6 +865,11 @@ void oracle_iou_matrix_grad(int nseg, const int64_t *a_off, const int64_t *b_off
       for (int64_t c = 0; c < nb; ++c) {
         if (self_pairs && r == c) continue;
         int64_t ia = a_off[s] + r, ib = b_off[s] + c;
+        if (self_pairs && r > c) { /* R8 */
+          int64_t t = ia;
+          ia = ib;
+          ib = t;
+        }
         point P[ORC_MAXV], Q[ORC_MAXV], gP[ORC_MAXV], gQ[ORC_MAXV];
         double z1[2], z2[2], gz1[2], gz2[2];
         uint8_t nx, flags[ORC_CAP];

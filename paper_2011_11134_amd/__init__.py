@@ -52,7 +52,8 @@ EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
            "dgal_intersect", "dgal_intersect_backward", "dgal_area", "dgal_area_backward",
            "dgal_iou_boxes", "dgal_iou_boxes_backward", "dgal_set_autotune",
            "dgal_autotune_report", "dgal_validate", "dgal_set_validate",
-           "dgal_iou_simple_pairs", "dgal_iou_simple_backward", "dgal_validate_simple")
+           "dgal_iou_simple_pairs", "dgal_iou_simple_backward", "dgal_validate_simple",
+           "dgal_set_profiling", "dgal_profile_report")
 
 
 def _load():
@@ -93,6 +94,10 @@ def _load():
     L.dgal_set_autotune.restype = ctypes.c_int
     L.dgal_autotune_report.argtypes = [_vp, ctypes.c_char_p, i64]
     L.dgal_autotune_report.restype = ctypes.c_int
+    L.dgal_set_profiling.argtypes = [_vp, i32]
+    L.dgal_set_profiling.restype = ctypes.c_int
+    L.dgal_profile_report.argtypes = [_vp, ctypes.c_char_p, i64]
+    L.dgal_profile_report.restype = ctypes.c_int
     L.dgal_validate.argtypes = [_vp, Polys, _vp, _vp, _vp]
     L.dgal_validate.restype = ctypes.c_int
     L.dgal_validate_simple.argtypes = [_vp, Polys, _vp, _vp, _vp]
@@ -384,7 +389,7 @@ def _segments(n_a, n_b, a_off, b_off, self_pairs, dev):
 
 
 def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=None, b_off=None,
-               self_pairs=False, save=False, capacity=None, check=True, seg=None):
+               self_pairs=False, save=False, capacity=None, check=True, seg=None, saved=None):
     """IoU matrix (one a x b block, or segments such as per-scene self pairs).
 
     Returns (iou, saved, seg): iou is [na, nb] for one block or flat
@@ -393,7 +398,12 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
     of device offsets.  capacity bounds the survivors of the cull; exceeding
     a given one raises (check=True).  By default it is max(65536, pairs / 16),
     and (check=True) a call that finds more survivors is repeated once with
-    room for all of them."""
+    room for all of them.
+
+    Capturable use (a HIP graph, or a loop that must not synchronise): pass
+    `seg` from segments() and a SavedPairs as `saved` (reused, nothing is
+    allocated for it), with check=False; an overflow is then reported by the
+    next check_errors()."""
     if self_pairs:
         b_xy, b_nv, b_z, b_off = a_xy, a_nv, a_z, a_off
     pa, ka = polys(a_xy, a_nv, a_z)
@@ -403,12 +413,17 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
         seg = _segments(a_xy.shape[0], b_xy.shape[0], a_off, b_off, self_pairs, dev)
     d_a, d_b, d_o, nseg, total, tiles = seg
     iou = torch.empty(total, dtype=torch.float32, device=dev)
-    sized = capacity is not None
+    given = saved
+    sized = capacity is not None or given is not None
     if capacity is None:
-        capacity = max(1 << 16, total // 16)
+        capacity = given.capacity if given is not None else max(1 << 16, total // 16)
+    cap_codes = a_xy.shape[1] + b_xy.shape[1]
+    if given is not None and (given.tiles < tiles or given.xflags.shape[1] != cap_codes):
+        raise ValueError(f"saved holds {given.tiles} tiles of {given.xflags.shape[1]} codes; "
+                         f"this call needs {tiles} tiles of {cap_codes}")
 
     def run(cap):
-        sv = SavedPairs(cap, a_xy.shape[1] + b_xy.shape[1], tiles, dev)
+        sv = given if given is not None else SavedPairs(cap, cap_codes, tiles, dev)
         st = sv.struct()
         _ok(lib.dgal_iou_matrix(context(dev), pa, pb, _ptr(d_a), _ptr(d_b), _ptr(d_o), nseg,
                                 int(bool(self_pairs)), _ptr(iou), total, ctypes.byref(st),
@@ -416,6 +431,8 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
             "dgal_iou_matrix")
         return sv
 
+    if check:
+        check_errors(dev)  # an earlier call's deferred error is its own, raised here
     saved = run(capacity)
     if check:
         try:
@@ -423,10 +440,14 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
         except DgalError as e:
             # a default capacity too small for this input: the count holds how
             # many pairs survived the cull, so the call is repeated once with
-            # room for all of them
+            # room for all of them.  Any other error (an intersection over its
+            # capacity, rejected offsets) is raised.
             if sized or e.status != DGAL_ECAPACITY:
                 raise
-            saved = run(int(saved.count.item()))
+            cnt = int(saved.count.item())
+            if cnt <= saved.capacity:
+                raise
+            saved = run(cnt)
             check_errors(dev)
     if d_a is None:
         iou = iou.view(a_xy.shape[0], b_xy.shape[0])
@@ -544,6 +565,25 @@ def autotune_report(device=None):
     if n < 0:
         raise DgalError(n, "dgal_autotune_report")
     return n, buf.value.decode()
+
+
+def set_profiling(enable=True, device=None):
+    """Per-kernel timing on a device's context (every launch waited for: a
+    measuring aid, not for graph capture); enabling resets the totals."""
+    _ok(lib.dgal_set_profiling(context(device), int(bool(enable))), "dgal_set_profiling")
+
+
+def profile_report(device=None):
+    """{kernel: (launches, total ms)} timed since profiling was enabled."""
+    buf = ctypes.create_string_buffer(8192)
+    n = lib.dgal_profile_report(context(device), buf, len(buf))
+    if n < 0:
+        raise DgalError(n, "dgal_profile_report")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, launches, ms = line.split()
+        out[name] = (int(launches), float(ms))
+    return out
 
 
 def check_errors(device=None):
@@ -664,11 +704,18 @@ class IoU3DPairs(torch.autograd.Function):
 
 
 class IoUMatrix(torch.autograd.Function):
-    """IoU matrix of two polygon sets; backward from the saved non-empty pairs."""
+    """IoU matrix of two polygon sets; backward from the saved non-empty pairs.
+
+    apply(a_xy, b_xy, capacity=None, work=None): `work` = (seg, saved) from
+    segments() and a SavedPairs makes the forward capturable (no allocation
+    for the work list, no synchronisation; overflows are reported by
+    check_errors())."""
 
     @staticmethod
-    def forward(ctx, a_xy, b_xy, capacity=None):
-        iou, saved, seg = iou_matrix(a_xy, b_xy, save=True, capacity=capacity)
+    def forward(ctx, a_xy, b_xy, capacity=None, work=None):
+        seg, sv = (None, None) if work is None else work
+        iou, saved, seg = iou_matrix(a_xy, b_xy, save=True, capacity=capacity,
+                                     check=work is None, seg=seg, saved=sv)
         ctx.saved_list = saved
         ctx.seg = seg
         ctx.save_for_backward(a_xy, b_xy)
@@ -679,18 +726,25 @@ class IoUMatrix(torch.autograd.Function):
         a_xy, b_xy = ctx.saved_tensors
         ga, gb, _, _ = iou_matrix_backward(g.contiguous().float().reshape(-1), ctx.saved_list,
                                            ctx.seg, a_xy, b_xy)
-        return ga, gb, None
+        return ga, gb, None, None
 
 
 class IoU3DScenes(torch.autograd.Function):
     """Per-scene self-pairwise 3D IoU of boxes (BEV polygons with z-extents);
-    scene s holds boxes off[s]..off[s+1] and owns an off-diagonal block of the
-    flat output (its diagonal is 1 with zero gradient)."""
+    scene s holds boxes off[s]..off[s+1] and owns a block of the flat output
+    (its diagonal is 1 with zero gradient; entries (r, c) and (c, r) are one
+    unordered pair, the lower index evaluated first).
+
+    apply(xy, zlo, zhi, off, capacity=None, work=None): `work` = (seg, saved)
+    from segments(..., self_pairs=True) and a SavedPairs makes the forward
+    capturable in a HIP graph (no allocation for the work list, no
+    synchronisation; overflows are reported by check_errors())."""
 
     @staticmethod
-    def forward(ctx, xy, zlo, zhi, off, capacity=None):
+    def forward(ctx, xy, zlo, zhi, off, capacity=None, work=None):
+        seg, sv = (None, None) if work is None else work
         iou, saved, seg = iou_matrix(xy, a_z=(zlo, zhi), a_off=off, self_pairs=True, save=True,
-                                     capacity=capacity)
+                                     capacity=capacity, check=work is None, seg=seg, saved=sv)
         ctx.saved_list = saved
         ctx.seg = seg
         ctx.save_for_backward(xy, zlo, zhi)
@@ -701,4 +755,4 @@ class IoU3DScenes(torch.autograd.Function):
         xy, zlo, zhi = ctx.saved_tensors
         ga, _, gaz, _ = iou_matrix_backward(g.contiguous().float(), ctx.saved_list, ctx.seg, xy,
                                             a_z=(zlo, zhi), self_pairs=True)
-        return ga, gaz[:, 0], gaz[:, 1], None, None
+        return ga, gaz[:, 0], gaz[:, 1], None, None, None

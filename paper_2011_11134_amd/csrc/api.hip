@@ -18,6 +18,7 @@ enum { kTunePairsFwd, kTunePairsBwd, kTuneMatrixFwd, kTuneMatrixBwd };
 
 struct dgal_ctx {
   dgal::CtxView v;
+  dgal::Profiler prof;           // per-kernel timing (v.prof points here while on)
   bool tune = false;
   bool validate = false;         // check every input polygon before each call
   int64_t* n_bad = nullptr;      // device counter of the input check
@@ -146,6 +147,7 @@ int dgal_create(dgal_ctx** out, int hip_device) {
   c->v.err = nullptr;
   c->v.prefix = nullptr;
   c->v.scan = nullptr;
+  c->v.prof = nullptr;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
       cus <= 0)
@@ -175,6 +177,8 @@ int dgal_create(dgal_ctx** out, int hip_device) {
 void dgal_destroy(dgal_ctx* ctx) {
   if (ctx == nullptr) return;
   DeviceGuard g(ctx->v.device);
+  if (ctx->prof.e0) (void)hipEventDestroy(ctx->prof.e0);
+  if (ctx->prof.e1) (void)hipEventDestroy(ctx->prof.e1);
   if (ctx->v.err) (void)hipFree(ctx->v.err);
   if (ctx->v.prefix) (void)hipFree(ctx->v.prefix);
   if (ctx->v.scan) (void)hipFree(ctx->v.scan);
@@ -236,7 +240,10 @@ int dgal_iou_pairs(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* iou, uint8_
   hipStream_t s = static_cast<hipStream_t>(stream);
   return run_tuned(ctx, TuneKey(kTunePairsFwd, K, fixed, z3, save), pair_grids(ctx->v.cus), s,
                    [&](const dgal::LaunchShape& sh) {
-                     return status_of(dgal::launch_pairs_fwd(args, K, fixed, z3, save, s, sh));
+                     dgal::prof_begin(ctx->v.prof, s);
+                     const hipError_t e = dgal::launch_pairs_fwd(args, K, fixed, z3, save, s, sh);
+                     dgal::prof_end(ctx->v.prof, "k_pairs_fwd", s);
+                     return status_of(e);
                    });
 }
 
@@ -289,7 +296,10 @@ int dgal_iou_backward(dgal_ctx* ctx, int32_t mode, dgal_polys a, dgal_polys b,
     hipStream_t s = static_cast<hipStream_t>(stream);
     return run_tuned(ctx, TuneKey(kTunePairsBwd, K, fixed, z3, 0), pair_grids(ctx->v.cus), s,
                      [&](const dgal::LaunchShape& sh) {
-                       return status_of(dgal::launch_pairs_bwd(args, K, fixed, z3, s, sh));
+                       dgal::prof_begin(ctx->v.prof, s);
+                       const hipError_t e = dgal::launch_pairs_bwd(args, K, fixed, z3, s, sh);
+                       dgal::prof_end(ctx->v.prof, "k_pairs_bwd", s);
+                       return status_of(e);
                      });
   }
   if (mode == DGAL_MATRIX) {
@@ -342,7 +352,13 @@ int dgal_intersect(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* out_xy, uin
   args.err = ctx->v.err;
   const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
                      args.a.vec4 && args.b.vec4 && args.rows_vec;
-  return status_of(dgal::launch_intersect_fwd(args, K, fixed, static_cast<hipStream_t>(stream)));
+  const hipError_t e_ = [&] {
+    dgal::prof_begin(ctx->v.prof, static_cast<hipStream_t>(stream));
+    const hipError_t r_ = dgal::launch_intersect_fwd(args, K, fixed, static_cast<hipStream_t>(stream));
+    dgal::prof_end(ctx->v.prof, "k_intersect_fwd", static_cast<hipStream_t>(stream));
+    return r_;
+  }();
+  return status_of(e_);
 }
 
 int dgal_intersect_backward(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const float* grad_xy,
@@ -372,7 +388,13 @@ int dgal_intersect_backward(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const flo
                   aligned(grad_a_xy, 16) && aligned(grad_b_xy, 16);
   const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
                      args.a.vec4 && args.b.vec4 && args.rows_vec;
-  return status_of(dgal::launch_intersect_bwd(args, K, fixed, static_cast<hipStream_t>(stream)));
+  const hipError_t e_ = [&] {
+    dgal::prof_begin(ctx->v.prof, static_cast<hipStream_t>(stream));
+    const hipError_t r_ = dgal::launch_intersect_bwd(args, K, fixed, static_cast<hipStream_t>(stream));
+    dgal::prof_end(ctx->v.prof, "k_intersect_bwd", static_cast<hipStream_t>(stream));
+    return r_;
+  }();
+  return status_of(e_);
 }
 
 int dgal_area(dgal_ctx* ctx, dgal_polys p, float* area, void* stream) {
@@ -384,8 +406,14 @@ int dgal_area(dgal_ctx* ctx, dgal_polys p, float* area, void* stream) {
   const int K = p.kmax <= 4 ? 4 : 8;
   const dgal::PolyArgs pa = poly_args(p, K);
   const bool fixed = p.nv == nullptr && p.kmax == K && pa.vec4;
-  return status_of(
-      dgal::launch_area(pa, nullptr, area, K, fixed, false, static_cast<hipStream_t>(stream)));
+  const hipError_t e_ = [&] {
+    dgal::prof_begin(ctx->v.prof, static_cast<hipStream_t>(stream));
+    const hipError_t r_ =
+        dgal::launch_area(pa, nullptr, area, K, fixed, false, static_cast<hipStream_t>(stream));
+    dgal::prof_end(ctx->v.prof, "k_area", static_cast<hipStream_t>(stream));
+    return r_;
+  }();
+  return status_of(e_);
 }
 
 int dgal_area_backward(dgal_ctx* ctx, dgal_polys p, const float* grad_area, float* grad_xy,
@@ -398,8 +426,14 @@ int dgal_area_backward(dgal_ctx* ctx, dgal_polys p, const float* grad_area, floa
   const int K = p.kmax <= 4 ? 4 : 8;
   const dgal::PolyArgs pa = poly_args(p, K);
   const bool fixed = p.nv == nullptr && p.kmax == K && pa.vec4;
-  return status_of(dgal::launch_area(pa, grad_area, grad_xy, K, fixed, true,
-                                     static_cast<hipStream_t>(stream)));
+  const hipError_t e_ = [&] {
+    dgal::prof_begin(ctx->v.prof, static_cast<hipStream_t>(stream));
+    const hipError_t r_ = dgal::launch_area(pa, grad_area, grad_xy, K, fixed, true,
+                                     static_cast<hipStream_t>(stream));
+    dgal::prof_end(ctx->v.prof, "k_area_bwd", static_cast<hipStream_t>(stream));
+    return r_;
+  }();
+  return status_of(e_);
 }
 
 }  // extern "C"
@@ -438,7 +472,13 @@ int dgal_iou_simple_pairs(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* iou,
   args.xmask = xmask;
   args.smask = smask;
   args.inside = inside;
-  return status_of(dgal::launch_simple_fwd(args, K, static_cast<hipStream_t>(stream)));
+  const hipError_t e_ = [&] {
+    dgal::prof_begin(ctx->v.prof, static_cast<hipStream_t>(stream));
+    const hipError_t r_ = dgal::launch_simple_fwd(args, K, static_cast<hipStream_t>(stream));
+    dgal::prof_end(ctx->v.prof, "k_simple_fwd", static_cast<hipStream_t>(stream));
+    return r_;
+  }();
+  return status_of(e_);
 }
 
 int dgal_iou_simple_backward(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const float* grad_iou,
@@ -465,7 +505,13 @@ int dgal_iou_simple_backward(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const fl
   args.inside = inside;
   args.ga_xy = grad_a_xy;
   args.gb_xy = grad_b_xy;
-  return status_of(dgal::launch_simple_bwd(args, K, static_cast<hipStream_t>(stream)));
+  const hipError_t e_ = [&] {
+    dgal::prof_begin(ctx->v.prof, static_cast<hipStream_t>(stream));
+    const hipError_t r_ = dgal::launch_simple_bwd(args, K, static_cast<hipStream_t>(stream));
+    dgal::prof_end(ctx->v.prof, "k_simple_bwd", static_cast<hipStream_t>(stream));
+    return r_;
+  }();
+  return status_of(e_);
 }
 
 int dgal_validate(dgal_ctx* ctx, dgal_polys p, uint8_t* status, int64_t* n_bad, void* stream) {
@@ -501,6 +547,39 @@ int dgal_set_autotune(dgal_ctx* ctx, int32_t enable) {
   if (ctx == nullptr) return DGAL_EINVAL;
   ctx->tune = enable != 0;
   return DGAL_OK;
+}
+
+int dgal_set_profiling(dgal_ctx* ctx, int32_t enable) {
+  if (ctx == nullptr) return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  if (enable) {
+    if (ctx->prof.e0 == nullptr && hipEventCreate(&ctx->prof.e0) != hipSuccess) return DGAL_EHIP;
+    if (ctx->prof.e1 == nullptr && hipEventCreate(&ctx->prof.e1) != hipSuccess) return DGAL_EHIP;
+    ctx->prof.n = 0;
+    ctx->prof.err = hipSuccess;
+    ctx->v.prof = &ctx->prof;
+  } else {
+    ctx->v.prof = nullptr;
+  }
+  return DGAL_OK;
+}
+
+int dgal_profile_report(dgal_ctx* ctx, char* buf, int64_t size) {
+  if (ctx == nullptr || (buf == nullptr && size > 0) || size < 0) return DGAL_EINVAL;
+  if (ctx->prof.err != hipSuccess) return DGAL_EHIP;
+  int64_t used = 0;
+  if (size > 0) buf[0] = '\0';
+  for (int k = 0; k < ctx->prof.n; ++k) {
+    char line[160];
+    const int n = snprintf(line, sizeof(line), "%s %lld %.6f\n", ctx->prof.name[k],
+                           (long long)ctx->prof.launches[k], ctx->prof.ms[k]);
+    if (n > 0 && used + n < size) {
+      memcpy(buf + used, line, (size_t)n + 1);
+      used += n;
+    }
+  }
+  return ctx->prof.n;
 }
 
 int dgal_autotune_report(dgal_ctx* ctx, char* buf, int64_t size) {
@@ -541,8 +620,14 @@ int dgal_iou_boxes(dgal_ctx* ctx, dgal_boxes a, dgal_boxes b, float* iou, uint8_
   args.nx = nx;
   args.xflags = xflags;
   args.err = ctx->v.err;
-  return status_of(dgal::launch_boxes_fwd(args, a.dim == 7, nx != nullptr,
-                                          static_cast<hipStream_t>(stream)));
+  const hipError_t e_ = [&] {
+    dgal::prof_begin(ctx->v.prof, static_cast<hipStream_t>(stream));
+    const hipError_t r_ = dgal::launch_boxes_fwd(args, a.dim == 7, nx != nullptr,
+                                          static_cast<hipStream_t>(stream));
+    dgal::prof_end(ctx->v.prof, "k_boxes_fwd", static_cast<hipStream_t>(stream));
+    return r_;
+  }();
+  return status_of(e_);
 }
 
 int dgal_iou_boxes_backward(dgal_ctx* ctx, dgal_boxes a, dgal_boxes b, const float* grad_iou,
@@ -564,7 +649,13 @@ int dgal_iou_boxes_backward(dgal_ctx* ctx, dgal_boxes a, dgal_boxes b, const flo
   args.xflags = xflags;
   args.ga = grad_a;
   args.gb = grad_b;
-  return status_of(dgal::launch_boxes_bwd(args, a.dim == 7, static_cast<hipStream_t>(stream)));
+  const hipError_t e_ = [&] {
+    dgal::prof_begin(ctx->v.prof, static_cast<hipStream_t>(stream));
+    const hipError_t r_ = dgal::launch_boxes_bwd(args, a.dim == 7, static_cast<hipStream_t>(stream));
+    dgal::prof_end(ctx->v.prof, "k_boxes_bwd", static_cast<hipStream_t>(stream));
+    return r_;
+  }();
+  return status_of(e_);
 }
 
 }  // extern "C"

@@ -114,6 +114,42 @@ struct LaunchShape {
   int cull_mult = 0, exact_mult = 0, bwd_mult = 0;
 };
 
+// Per-kernel timing of a context (dgal_set_profiling): each launch is
+// bracketed by two events on its stream and waited for, and its duration is
+// added to its kernel's total.  Names are string literals.
+struct Profiler {
+  static constexpr int kMax = 48;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int n = 0;
+  const char* name[kMax];
+  int64_t launches[kMax];
+  double ms[kMax];
+  hipError_t err = hipSuccess;
+};
+
+inline void prof_begin(Profiler* p, hipStream_t s) {
+  if (p != nullptr && p->err == hipSuccess) p->err = hipEventRecord(p->e0, s);
+}
+
+inline void prof_end(Profiler* p, const char* name, hipStream_t s) {
+  if (p == nullptr || p->err != hipSuccess) return;
+  float t = 0.f;
+  if ((p->err = hipEventRecord(p->e1, s)) != hipSuccess) return;
+  if ((p->err = hipEventSynchronize(p->e1)) != hipSuccess) return;
+  if ((p->err = hipEventElapsedTime(&t, p->e0, p->e1)) != hipSuccess) return;
+  int k = 0;
+  while (k < p->n && __builtin_strcmp(p->name[k], name) != 0) ++k;
+  if (k == p->n) {
+    if (p->n == Profiler::kMax) return;
+    p->name[k] = name;
+    p->launches[k] = 0;
+    p->ms[k] = 0.0;
+    ++p->n;
+  }
+  ++p->launches[k];
+  p->ms[k] += t;
+}
+
 // What the kernels need from a context.
 struct CtxView {
   int device;
@@ -121,6 +157,7 @@ struct CtxView {
   int* err;         // sticky device error word
   int64_t* prefix;  // [2][DGAL_MAX_SEGMENTS + 1]: tile and row-group prefixes
   int64_t* scan;    // [kScanTotals]: per-chunk totals of the tile scan
+  Profiler* prof;   // per-kernel timing, or NULL
 };
 
 // Chunks of 4096 tiles the tile scan can combine (2^24 tiles per call).

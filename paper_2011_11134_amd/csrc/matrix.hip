@@ -22,9 +22,10 @@
 // graph-capturable).  The backward (k_matrix_bwd) gives one wavefront a row
 // group: its tiles' entries are one contiguous range of the work list; the row
 // gradients are summed in LDS and every row is written once.  Self pairs need
-// nothing else (the column role of pair (k, i) equals the row role of pair
-// (i, k)); for two different sets the column gradients are added with global
-// atomics.
+// nothing else: entries (i, k) and (k, i) are one unordered pair evaluated with
+// the lower index first, so the row role of either entry is that pair's
+// gradient for the row's box, weighted by both entries' upstream gradients;
+// for two different sets the column gradients are added with global atomics.
 #include <algorithm>
 #include <type_traits>
 #include <utility>
@@ -643,7 +644,12 @@ __attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_matrix_exac
     Segment g;
     int64_t r = 0, c = 0;
     if (!locate(m.seg, pid, g, r, c)) continue;  // not written by the cull on these shapes
-    const int64_t ia = g.a0 + r, ib = g.b0 + c;
+    int64_t ia = g.a0 + r, ib = g.b0 + c;
+    if (m.seg.self_pairs && r > c) {  // one unordered pair: the lower index is P
+      const int64_t t = ia;
+      ia = ib;
+      ib = t;
+    }
     const int n1 = FIXED ? K : poly_count(m.a.nv, ia, m.a.kmax);
     const int n2 = FIXED ? K : poly_count(m.b.nv, ib, m.b.kmax);
     Poly<K> P, Q;
@@ -753,7 +759,15 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
         divmod(local, g.nb, rg, col);
         const int rl = (int)(rg - r0);
         if (rl < 0 || rl >= nr) continue;
-        const int64_t ia = g.a0 + rg, ib = g.b0 + col;
+        int64_t ia = g.a0 + rg, ib = g.b0 + col;
+        // self pairs: an entry below the diagonal was evaluated with the
+        // column's box as P (the lower index), so the row's box is Q there
+        const bool swapped = m.seg.self_pairs && rg > col;
+        if (swapped) {
+          const int64_t t = ia;
+          ia = ib;
+          ib = t;
+        }
         const int n1 = FIXED ? K : poly_count(m.a.nv, ia, m.a.kmax);
         const int n2 = FIXED ? K : poly_count(m.b.nv, ib, m.b.kmax);
         Poly<K> P, Q;
@@ -784,9 +798,9 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
             }
           }
         }
-        // self pairs: pair (k, i) gives box i the column-role gradient of an
-        // IoU that equals IoU(i, k); by symmetry it is the row-role gradient
-        // of (i, k)
+        // self pairs: entries (i, k) and (k, i) are one unordered pair with
+        // one structure, so the row's box takes its role's gradient of that
+        // pair weighted by both entries' upstream gradients
         float gw = m.grad[pid];
         if (m.seg.self_pairs) gw += m.grad[g.out0 + col * g.nb + rg];
         float lo1 = 0.f, hi1 = 0.f, lo2 = 0.f, hi2 = 0.f;
@@ -800,16 +814,17 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
         pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
                                            s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2);
         float* acc = acc_w + (lane >> 4) * ACC + rl * ROW;
+        const int nr_own = swapped ? n2 : n1;  // the row box's vertex count
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          if (FIXED || k < n1) {
-            atomicAdd(acc + 2 * k, gP[k].x);
-            atomicAdd(acc + 2 * k + 1, gP[k].y);
+          if (FIXED || k < nr_own) {
+            atomicAdd(acc + 2 * k, swapped ? gQ[k].x : gP[k].x);
+            atomicAdd(acc + 2 * k + 1, swapped ? gQ[k].y : gP[k].y);
           }
         }
         if (Z3) {
-          atomicAdd(acc + 2 * K, gz1.x);
-          atomicAdd(acc + 2 * K + 1, gz1.y);
+          atomicAdd(acc + 2 * K, swapped ? gz2.x : gz1.x);
+          atomicAdd(acc + 2 * K + 1, swapped ? gz2.y : gz1.y);
         }
         if (!m.seg.self_pairs) {
           float* ob = m.gb_xy + ib * (int64_t)m.b.kmax * 2;
@@ -870,11 +885,13 @@ bool valid_saved(const dgal_saved* s) {
          s->tile_start && s->tile_count && s->tile_mask && s->tile_capacity >= 0;
 }
 
-void zero(float* p, int64_t n, hipStream_t stream) {
+void zero(float* p, int64_t n, hipStream_t stream, Profiler* prof) {
   if (p != nullptr && n > 0) {
     const int64_t blocks = (n + 255) / 256;
+    prof_begin(prof, stream);
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)(blocks > 4096 ? 4096 : blocks)), dim3(256), 0,
                        stream, p, n);
+    prof_end(prof, "k_fill_zero", stream);
   }
 }
 
@@ -926,8 +943,10 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
   if (segmented) {
     sa.tile_prefix = ctx.prefix;
     sa.group_prefix = ctx.prefix + (kMaxSeg + 1);
+    prof_begin(ctx.prof, stream);
     hipLaunchKernelGGL(k_seg_prep, dim3(1), dim3(256), 0, stream, sa, ctx.err, ctx.prefix,
                        ctx.prefix + (kMaxSeg + 1));
+    prof_end(ctx.prof, "k_seg_prep", stream);
   } else {
     if (a.count == 0 || b.count == 0) return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
     single_tiles = ceil_div(a.count, kTileRows) * ceil_div(b.count, kTileCols);
@@ -965,21 +984,31 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
   dispatch(K, fixed, a.zlo != nullptr, [&](auto k, auto fx, auto z) {
     constexpr int KK = decltype(k)::value;
     constexpr bool FX = decltype(fx)::value, ZZ = decltype(z)::value;
+    prof_begin(ctx.prof, stream);
     hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ>), dim3((unsigned)cull_grid),
                        dim3(kCullBlock), 0, stream, c);
+    prof_end(ctx.prof, "k_matrix_cull", stream);
     const int64_t chunks = std::max<int64_t>(1, ceil_div(saved->tile_capacity, kScanChunk));
+    prof_begin(ctx.prof, stream);
     hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)chunks), dim3(kScanBlock), 0, stream,
                        sa.tile_prefix, sa.nseg, single_tiles, saved->tile_capacity,
                        saved->tile_count, ctx.scan);
+    prof_end(ctx.prof, "k_scan_totals", stream);
+    prof_begin(ctx.prof, stream);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)chunks), dim3(kScanBlock), 0, stream,
                        sa.tile_prefix, sa.nseg, single_tiles, saved->tile_capacity, ctx.scan,
                        saved->tile_start, saved->tile_count, saved->count, saved->capacity,
                        ctx.err);
+    prof_end(ctx.prof, "k_scan_apply", stream);
     // the fill walks ~8 resident waves per SIMD, each over a contiguous range of tiles
+    prof_begin(ctx.prof, stream);
     hipLaunchKernelGGL(k_matrix_fill, dim3((unsigned)std::max<int64_t>(1, (int64_t)ctx.cus * 8)),
                        dim3(kCullBlock), 0, stream, c);
+    prof_end(ctx.prof, "k_matrix_fill", stream);
+    prof_begin(ctx.prof, stream);
     hipLaunchKernelGGL((k_matrix_exact<KK, FX, ZZ>), dim3(exact_grid), dim3(kExactBlock), 0,
                        stream, x);
+    prof_end(ctx.prof, "k_matrix_exact", stream);
   });
   return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
 }
@@ -1003,19 +1032,21 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
   const int K = reg_k(a.kmax, b.kmax);
   const bool segmented = a_off != nullptr;
   // rows outside every row group keep zeros; row groups overwrite their rows
-  zero(grad_a_xy, a.count * a.kmax * 2, stream);
-  if (z3) zero(grad_a_z, a.count * 2, stream);
+  zero(grad_a_xy, a.count * a.kmax * 2, stream, ctx.prof);
+  if (z3) zero(grad_a_z, a.count * 2, stream, ctx.prof);
   if (!self_pairs) {
-    zero(grad_b_xy, b.count * b.kmax * 2, stream);
-    if (z3) zero(grad_b_z, b.count * 2, stream);
+    zero(grad_b_xy, b.count * b.kmax * 2, stream, ctx.prof);
+    if (z3) zero(grad_b_z, b.count * 2, stream, ctx.prof);
   }
   int64_t single_groups = 0;
   if (segmented) {
     // recomputed: another matrix call may have used the workspace since the forward
     sa.tile_prefix = ctx.prefix;
     sa.group_prefix = ctx.prefix + (kMaxSeg + 1);
+    prof_begin(ctx.prof, stream);
     hipLaunchKernelGGL(k_seg_prep, dim3(1), dim3(256), 0, stream, sa, ctx.err, ctx.prefix,
                        ctx.prefix + (kMaxSeg + 1));
+    prof_end(ctx.prof, "k_seg_prep", stream);
   } else {
     if (a.count == 0 || b.count == 0) return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
     single_groups = ceil_div(a.count, kTileRows);
@@ -1047,8 +1078,10 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
     constexpr bool FX = decltype(fx)::value, ZZ = decltype(z)::value;
     int64_t grid = (int64_t)ctx.cus * (shape.bwd_mult > 0 ? shape.bwd_mult : 8);
     if (!segmented) grid = std::min(grid, ceil_div(single_groups, bwd_block<KK>() / 64));
+    prof_begin(ctx.prof, stream);
     hipLaunchKernelGGL((k_matrix_bwd<KK, FX, ZZ>), dim3((unsigned)grid), dim3(bwd_block<KK>()), 0,
                        stream, m);
+    prof_end(ctx.prof, "k_matrix_bwd", stream);
   });
   return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
 }

@@ -81,6 +81,64 @@ def _check_matrix_exact(iou_flat, a, b, a_z=None, b_z=None, a_off=None, b_off=No
     return ia, ib, fl, ref, nx, xf
 
 
+def _grad_reference(a, b, g, ia, ib, fl, a_nv=None, b_nv=None, a_z=None, b_z=None,
+                    self_pairs=False):
+    """Reference of the matrix backward from the oracle's per-pair gradients
+    over the entries (ia[t], ib[t]) at flat index fl[t] (a superset of the
+    non-empty pairs: every other entry has zero gradient).  Returns, per box
+    of a and of b (one set when self_pairs), the summed gradient [n, 2K (+2)]
+    (xy, then d/dzlo, d/dzhi) and its scale: the sum over the box's pairs of
+    the norm of that pair's term.  An fp32 sum of terms that each carry a
+    relative error e is within e times that scale, whatever their
+    cancellation.  Self pairs: entry (r, c) is the pair with the lower index
+    first, and the diagonal is constant."""
+    if self_pairs:
+        keep = ia != ib
+        ia, ib, fl = ia[keep], ib[keep], fl[keep]
+        ia, ib = np.minimum(ia, ib), np.maximum(ia, ib)
+        b, b_nv, b_z = a, a_nv, a_z
+    sub = lambda v, i: None if v is None else v[i]
+    subz = lambda z, i: None if z is None else (z[0][i], z[1][i])
+    _, nx, xf = oracle.iou_index_pairs(ia, ib, a, b, a_nv, b_nv, a_z=a_z, b_z=b_z, threads=8)
+    gp, gq, gzp, gzq = oracle.iou_pairs_grad(a[ia], b[ib], g[fl], nx, xf, sub(a_nv, ia),
+                                             sub(b_nv, ib), subz(a_z, ia), subz(b_z, ib),
+                                             threads=8)
+    tp, tq = gp.reshape(len(ia), -1), gq.reshape(len(ib), -1)
+    if a_z is not None:
+        tp, tq = np.concatenate([tp, gzp], 1), np.concatenate([tq, gzq], 1)
+    out = []
+    sets = [(len(a), ia, tp, ib, tq)] if self_pairs else [(len(a), ia, tp, None, None),
+                                                          (len(b), ib, tq, None, None)]
+    for n, i1, t1, i2, t2 in sets:
+        ref = np.zeros((n, t1.shape[1]))
+        scale = np.zeros(n)
+        np.add.at(ref, i1, t1)
+        np.add.at(scale, i1, np.linalg.norm(t1, axis=1))
+        if i2 is not None:
+            np.add.at(ref, i2, t2)
+            np.add.at(scale, i2, np.linalg.norm(t2, axis=1))
+        out += [ref, scale]
+    return out
+
+
+def _box_grads(ga, gaz=None):
+    n = ga.shape[0]
+    parts = [ga.cpu().numpy().reshape(n, -1)]
+    if gaz is not None:
+        parts.append(gaz.cpu().numpy())
+    return np.concatenate(parts, 1)
+
+
+def _assert_box_grads(got, ref, scale, what):
+    """Every box: |g - g_ref| <= GRAD_TOL x (sum of its pair terms' norms);
+    a box with no contributing pair must be exactly zero."""
+    err = np.linalg.norm(got - ref, axis=1)
+    rel = err / np.maximum(scale, 1e-30)
+    k = int(np.argmax(rel))
+    assert rel[k] <= GRAD_TOL, (what, float(rel[k]), k, float(err[k]), float(scale[k]))
+    return float(rel.max())
+
+
 def test_matrix_small_dense_overlap(dg):
     d = synth.c2_matrix(n=300, m=257, seed=3)
     a, b = _crowd(d["a_xy"], 0.1), _crowd(d["b_xy"], 0.1)
@@ -121,11 +179,15 @@ def test_matrix_backward_small(dg):
     g = np.random.default_rng(5).uniform(-1, 1, (200, 150)).astype(np.float32)
     iou, saved, seg = dg.iou_matrix(dev_t(a), dev_t(b), save=True)
     ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g).reshape(-1), saved, seg, dev_t(a), dev_t(b))
-    ref_a, ref_b, _, _ = oracle.iou_matrix_grad(g.reshape(-1), a, b)
-    for got, ref in ((ga.cpu().numpy(), ref_a), (gb.cpu().numpy(), ref_b)):
-        err = np.linalg.norm((got - ref).reshape(len(ref), -1), axis=1)
-        scale = np.maximum(np.linalg.norm(ref.reshape(len(ref), -1), axis=1), 1e-6)
-        assert np.max(err / scale) <= 5 * GRAD_TOL, np.max(err / scale)
+    ia, ib, fl = _aabb_candidates(a, b)
+    ra, sa, rb, sb = _grad_reference(a, b, g.reshape(-1), ia, ib, fl)
+    # the per-pair reference is the oracle's matrix gradient
+    om_a, om_b, _, _ = oracle.iou_matrix_grad(g.reshape(-1), a, b)
+    assert np.abs(ra - om_a.reshape(len(a), -1)).max() <= 1e-12 * (1 + np.abs(om_a).max())
+    assert np.abs(rb - om_b.reshape(len(b), -1)).max() <= 1e-12 * (1 + np.abs(om_b).max())
+    ea = _assert_box_grads(_box_grads(ga), ra, sa, "rows")
+    eb = _assert_box_grads(_box_grads(gb), rb, sb, "columns")
+    _say(f"matrix backward small: max rel err rows {ea:.2e} columns {eb:.2e}")
     # autograd wrapper
     ta = dev_t(a).requires_grad_(True)
     tb = dev_t(b).requires_grad_(True)
@@ -170,11 +232,12 @@ def test_matrix_polygons(dg):
     g = np.random.default_rng(6).uniform(-1, 1, 180 * 220).astype(np.float32)
     ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(a), dev_t(b), dev_t(anv),
                                           dev_t(bnv))
-    ref_a, ref_b, _, _ = oracle.iou_matrix_grad(g, a, b, anv, bnv)
-    for got, ref in ((ga.cpu().numpy(), ref_a), (gb.cpu().numpy(), ref_b)):
-        err = np.linalg.norm((got - ref).reshape(len(ref), -1), axis=1)
-        scale = np.maximum(np.linalg.norm(ref.reshape(len(ref), -1), axis=1), 1e-6)
-        assert np.percentile(err / scale, 99) <= GRAD_TOL
+    ia, ib, fl = _aabb_candidates(a, b)
+    ra, sa, rb, sb = _grad_reference(a, b, g, ia, ib, fl, anv, bnv)
+    om_a, om_b, _, _ = oracle.iou_matrix_grad(g, a, b, anv, bnv)
+    assert np.abs(ra - om_a.reshape(len(a), -1)).max() <= 1e-12 * (1 + np.abs(om_a).max())
+    _assert_box_grads(_box_grads(ga), ra, sa, "rows")
+    _assert_box_grads(_box_grads(gb), rb, sb, "columns")
 
 
 def _scenes(scenes, nmin, nmax, seed, crowd):
@@ -201,14 +264,14 @@ def test_scenes_small_forward_backward(dg):
         assert np.all(np.diag(blk) == 1.0)
     ga, _, gaz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, txy, a_z=(tlo, thi),
                                            self_pairs=True)
+    ia, ib, fl = _aabb_candidates(xy, xy, off, off, True)
+    ref, scale = _grad_reference(xy, xy, g, ia, ib, fl, a_z=(lo, hi), b_z=(lo, hi),
+                                 self_pairs=True)
     ref_a, _, ref_z, _ = oracle.iou_matrix_grad(g, xy, a_z=(lo, hi), a_off=off, self_pairs=True)
-    got_all = np.concatenate([ga.cpu().numpy().reshape(len(xy), -1), gaz.cpu().numpy()], 1)
-    ref_all = np.concatenate([ref_a.reshape(len(xy), -1), ref_z], 1)
-    err = np.linalg.norm(got_all - ref_all, axis=1)
-    scale = np.maximum(np.linalg.norm(ref_all, axis=1), 1e-6)
-    assert np.percentile(err / scale, 99.5) <= GRAD_TOL, np.sort(err / scale)[-5:]
-    assert np.max(err) <= 1e-3 * np.max(scale)
-    _say(f"scenes small: {int(saved.count.item())} saved pairs")
+    om = np.concatenate([ref_a.reshape(len(xy), -1), ref_z], 1)
+    assert np.abs(ref - om).max() <= 1e-12 * (1 + np.abs(om).max())
+    e = _assert_box_grads(_box_grads(ga, gaz), ref, scale, "scenes")
+    _say(f"scenes small: {int(saved.count.item())} saved pairs, max rel err {e:.2e}")
 
 
 def test_scenes_with_empty_and_single_box_segments(dg):
@@ -238,11 +301,12 @@ def test_segmented_two_sets(dg):
     assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
     g = np.random.default_rng(11).uniform(-1, 1, ref.shape[0]).astype(np.float32)
     ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(a), dev_t(b))
-    ref_a, ref_b, _, _ = oracle.iou_matrix_grad(g, a, b, a_off=a_off, b_off=b_off)
-    for got, rr in ((ga.cpu().numpy(), ref_a), (gb.cpu().numpy(), ref_b)):
-        err = np.linalg.norm((got - rr).reshape(len(rr), -1), axis=1)
-        scale = np.maximum(np.linalg.norm(rr.reshape(len(rr), -1), axis=1), 1e-6)
-        assert np.percentile(err / scale, 99) <= GRAD_TOL
+    ia, ib, fl = _aabb_candidates(a, b, a_off, b_off)
+    ra, sa, rb, sb = _grad_reference(a, b, g, ia, ib, fl)
+    om_a, om_b, _, _ = oracle.iou_matrix_grad(g, a, b, a_off=a_off, b_off=b_off)
+    assert np.abs(rb - om_b.reshape(len(b), -1)).max() <= 1e-12 * (1 + np.abs(om_b).max())
+    _assert_box_grads(_box_grads(ga), ra, sa, "rows")
+    _assert_box_grads(_box_grads(gb), rb, sb, "columns")
 
 
 def test_scenes_full_size(dg):
@@ -270,22 +334,154 @@ def test_scenes_full_size(dg):
     ga, _, gaz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, txy, a_z=(tlo, thi),
                                            self_pairs=True)
     sel = nonempty & zov
-    pa, pb, pz1, pz2 = oracle.iou_pairs_grad(xy[ia[sel]], xy[ib[sel]], g[fl[sel]], nx[sel], xf[sel],
-                                             a_z=(lo[ia[sel]], hi[ia[sel]]),
-                                             b_z=(lo[ib[sel]], hi[ib[sel]]), threads=8)
-    ref_a = np.zeros((len(xy), 4, 2))
-    ref_z = np.zeros((len(xy), 2))
-    np.add.at(ref_a, ia[sel], pa)
-    np.add.at(ref_a, ib[sel], pb)
-    np.add.at(ref_z, ia[sel], pz1)
-    np.add.at(ref_z, ib[sel], pz2)
-    got_all = np.concatenate([ga.cpu().numpy().reshape(len(xy), -1), gaz.cpu().numpy()], 1)
-    ref_all = np.concatenate([ref_a.reshape(len(xy), -1), ref_z], 1)
-    err = np.linalg.norm(got_all - ref_all, axis=1)
-    scale = np.maximum(np.linalg.norm(ref_all, axis=1), 1e-6)
-    assert np.percentile(err / scale, 99.9) <= GRAD_TOL, np.sort(err / scale)[-5:]
-    _say(f"c5: {cnt} survivors, {int((snx > 0).sum())} non-empty, grad rel err p99.9 {np.percentile(err / scale, 99.9):.2e} "
-         f"max {np.max(err / scale):.2e}")
+    ref, scale = _grad_reference(xy, xy, g, ia[sel], ib[sel], fl[sel], a_z=(lo, hi),
+                                 b_z=(lo, hi), self_pairs=True)
+    e = _assert_box_grads(_box_grads(ga, gaz), ref, scale, "c5")
+    _say(f"c5: {cnt} survivors, {int((snx > 0).sum())} non-empty, grad rel err max {e:.2e} "
+         f"over {len(xy)} boxes")
+
+
+def _tie_scenes(seed, scenes=5):
+    """Scenes of 3D boxes full of exact contacts: integer axis-aligned boxes
+    with collinear and touching edges, exact duplicates, a common ground
+    plane (shared zlo) and shared tops, yaw-0 rows next to rotated boxes."""
+    rng = np.random.default_rng(seed)
+    xs, los, his, sizes = [], [], [], []
+    for s in range(scenes):
+        n_int = int(rng.integers(8, 40))
+        x0 = rng.integers(0, 6, n_int).astype(np.float64)
+        y0 = rng.integers(0, 6, n_int).astype(np.float64)
+        w = rng.integers(1, 4, n_int).astype(np.float64)
+        h = rng.integers(1, 4, n_int).astype(np.float64)
+        q = np.stack([np.stack([x0, y0], 1), np.stack([x0 + w, y0], 1),
+                      np.stack([x0 + w, y0 + h], 1), np.stack([x0, y0 + h], 1)], 1)
+        nr = int(rng.integers(2, 10))
+        rot = synth.boxes_to_quads(rng.uniform(1, 5, nr), rng.uniform(1, 5, nr),
+                                   rng.uniform(1, 3, nr), rng.uniform(1, 3, nr),
+                                   rng.uniform(-np.pi, np.pi, nr))
+        yaw0 = synth.boxes_to_quads(rng.integers(1, 5, 3).astype(float) + 0.5,
+                                    rng.integers(1, 5, 3).astype(float), np.full(3, 2.0),
+                                    np.full(3, 3.0), np.zeros(3))
+        xy = np.concatenate([q.astype(np.float32), rot, yaw0, q[:4].astype(np.float32)], 0)
+        n = len(xy)
+        lo = np.where(rng.uniform(size=n) < 0.6, 0.0, rng.integers(-1, 2, n)).astype(np.float32)
+        hi = (lo + rng.integers(1, 3, n)).astype(np.float32)
+        hi[::4] = 2.0
+        lo = np.minimum(lo, hi - 1.0).astype(np.float32)
+        xs.append(xy)
+        los.append(lo)
+        his.append(hi)
+        sizes.append(n)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return np.concatenate(xs), np.concatenate(los), np.concatenate(his), off
+
+
+def test_scenes_with_ties(dg):
+    """Self-pair scenes where the tie rule decides on most pairs (collinear and
+    touching integer edges, duplicate boxes, shared ground planes and tops):
+    IoU on every pair, the block exactly symmetric, and every box's gradient
+    against the oracle's (one structure per unordered pair, lower index
+    first), at the maximum."""
+    xy, lo, hi, off = _tie_scenes(61)
+    _say(f"case: tie scenes {np.diff(off).tolist()}")
+    z = (dev_t(lo), dev_t(hi))
+    iou, saved, seg = dg.iou_matrix(dev_t(xy), a_z=z, a_off=off, self_pairs=True, save=True)
+    dg.check_errors()
+    got = iou.cpu().numpy()
+    ref, out_off = oracle.iou_matrix(xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    assert np.abs(got - ref).max() <= IOU_TOL
+    for s in range(len(off) - 1):
+        n = int(off[s + 1] - off[s])
+        blk = got[out_off[s]:out_off[s + 1]].reshape(n, n)
+        assert np.array_equal(blk, blk.T), s
+    assert np.count_nonzero(ref) > 2 * len(xy)
+    g = np.random.default_rng(62).uniform(-1, 1, ref.shape[0]).astype(np.float32)
+    ga, _, gz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(xy), a_z=z, self_pairs=True)
+    ra, _, rz, _ = oracle.iou_matrix_grad(g, xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    ia, ib, fl = _aabb_candidates(xy, xy, off, off, True)
+    rr, scale = _grad_reference(xy, xy, g, ia, ib, fl, a_z=(lo, hi), b_z=(lo, hi),
+                                self_pairs=True)
+    om = np.concatenate([ra.reshape(len(xy), -1), rz], 1)
+    assert np.abs(rr - om).max() <= 1e-12 * (1 + np.abs(om).max())
+    e = _assert_box_grads(_box_grads(ga, gz), rr, scale, "tie scenes")
+    _say(f"tie scenes: {int(saved.count.item())} saved pairs, max rel err {e:.2e}")
+
+
+def test_scenes_full_size_graph_replay(dg):
+    """The benchmark's step as a user writes it: per-scene 3D self-pair IoU
+    forward + backward through the autograd wrapper in its capturable form
+    (device segment table and work list made before capture), captured in a
+    HIP graph at full size (64 scenes, ~94 M pairs) and replayed with eager
+    work in between; every replay equals the eager step bit for bit, and the
+    eager step equals the oracle on sampled boxes."""
+    d = synth.c5_scenes()
+    xy, lo, hi, off = d["a_xy"], d["a_zlo"], d["a_zhi"], d["off"]
+    _say(f"case: c5 graph replay, {len(xy)} boxes, {int(d['out_off'][-1])} pairs")
+    txy, tlo, thi = dev_t(xy), dev_t(lo), dev_t(hi)
+    g = dev_t(d["grad"])
+    seg = dg.segments(len(xy), len(xy), off, self_pairs=True)
+    work = (seg, dg.SavedPairs(1 << 21, 8, seg[5], txy.device))
+    params = [t.clone().requires_grad_(True) for t in (txy, tlo, thi)]
+
+    def step():
+        for p_ in params:
+            p_.grad = None
+        out = dg.IoU3DScenes.apply(params[0], params[1], params[2], off, None, work)
+        out.backward(g)
+        return out
+
+    out_e = step().detach().clone()
+    grads_e = [p_.grad.clone() for p_ in params]
+    dg.check_errors()
+    cnt = int(work[1].count.item())
+    assert 0 < cnt <= work[1].capacity
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            step()
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        out_g = step()
+    grads_g = [p_.grad for p_ in params]
+    for rep in range(3):
+        junk = torch.randn(1 << 22, device="cuda").sum()  # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_g, out_e), rep
+        # the row sums are added in LDS in an order that may vary from run to
+        # run, so the gradients agree to rounding
+        for a_, b_ in zip(grads_g, grads_e):
+            assert torch.allclose(a_, b_, atol=1e-6, rtol=1e-5), rep
+        del junk
+    dg.check_errors()
+    # the eager step against the oracle on sampled boxes (all their pairs)
+    rng = np.random.default_rng(63)
+    flat = out_e.cpu().numpy()
+    boxes = rng.choice(len(xy), 300, replace=False)
+    scene = np.searchsorted(off, boxes, side="right") - 1
+    ia_l, ib_l, fl_l = [], [], []
+    for bx, sc in zip(boxes, scene):
+        n = int(off[sc + 1] - off[sc])
+        r = int(bx - off[sc])
+        cols = np.arange(n)
+        ia_l += [np.full(n, bx), off[sc] + cols]
+        ib_l += [off[sc] + cols, np.full(n, bx)]
+        fl_l += [d["out_off"][sc] + r * n + cols, d["out_off"][sc] + cols * n + r]
+    ia, ib, fl = np.concatenate(ia_l), np.concatenate(ib_l), np.concatenate(fl_l)
+    fl, first = np.unique(fl, return_index=True)  # two sampled boxes may share entries
+    ia, ib = ia[first], ib[first]
+    v, _, _ = oracle.iou_index_pairs(np.minimum(ia, ib), np.maximum(ia, ib), xy, xy,
+                                     a_z=(lo, hi), b_z=(lo, hi), threads=8)
+    v = np.where(ia == ib, 1.0, v)
+    assert np.abs(flat[fl] - v).max() <= IOU_TOL
+    ov = (v != 0) & (ia != ib)
+    gz = torch.stack([grads_e[1], grads_e[2]], 1)
+    ref, scale = _grad_reference(xy, xy, d["grad"], ia[ov], ib[ov], fl[ov], a_z=(lo, hi),
+                                 b_z=(lo, hi), self_pairs=True)
+    e = _assert_box_grads(_box_grads(grads_e[0], gz)[boxes], ref[boxes], scale[boxes], "c5 graph")
+    _say(f"c5 graph replay: {cnt} survivors, sampled max rel err {e:.2e}")
 
 
 def test_graph_replay_matches_eager(dg):
@@ -383,11 +579,13 @@ def test_random_ragged_segments(dg, seed):
         assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
     g = rng.uniform(-1, 1, ref.shape[0]).astype(np.float32)
     ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(a), dev_t(b))
-    ra, rb, _, _ = oracle.iou_matrix_grad(g, a, b, a_off=a_off, b_off=b_off)
-    for got, rr in ((ga.cpu().numpy(), ra), (gb.cpu().numpy(), rb)):
-        err = np.linalg.norm((got - rr).reshape(len(rr), -1), axis=1)
-        scale = np.maximum(np.linalg.norm(rr.reshape(len(rr), -1), axis=1), 1e-6)
-        assert np.percentile(err / scale, 99) <= GRAD_TOL
+    if ref.size:
+        ia, ib, fl = _aabb_candidates(a, b, a_off, b_off)
+        ra, sa, rb, sb = _grad_reference(a, b, g, ia, ib, fl)
+        _assert_box_grads(_box_grads(ga), ra, sa, "rows")
+        _assert_box_grads(_box_grads(gb), rb, sb, "columns")
+    else:
+        assert not ga.any() and not gb.any()
     sizes = rng.integers(0, 300, int(rng.integers(1, 9)))
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     n = int(off[-1])
@@ -403,12 +601,10 @@ def test_random_ragged_segments(dg, seed):
     assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
     g = rng.uniform(-1, 1, ref.shape[0]).astype(np.float32)
     ga, _, gz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(xy), a_z=z, self_pairs=True)
-    ra, _, rz, _ = oracle.iou_matrix_grad(g, xy, a_z=(lo, hi), a_off=off, self_pairs=True)
-    got = np.concatenate([ga.cpu().numpy().reshape(n, -1), gz.cpu().numpy()], 1)
-    rr = np.concatenate([ra.reshape(n, -1), rz], 1)
-    err = np.linalg.norm(got - rr, axis=1)
-    scale = np.maximum(np.linalg.norm(rr, axis=1), 1e-6)
-    assert np.percentile(err / scale, 99) <= GRAD_TOL
+    ia, ib, fl = _aabb_candidates(xy, xy, off, off, True)
+    rr, scale = _grad_reference(xy, xy, g, ia, ib, fl, a_z=(lo, hi), b_z=(lo, hi),
+                                self_pairs=True)
+    _assert_box_grads(_box_grads(ga, gz), rr, scale, "scenes")
 
 
 def test_max_segments(dg):
@@ -433,12 +629,10 @@ def test_max_segments(dg):
     assert np.count_nonzero(ref) > 3 * n
     g = rng.uniform(-1, 1, ref.shape[0]).astype(np.float32)
     ga, _, gz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(xy), a_z=z, self_pairs=True)
-    ra, _, rz, _ = oracle.iou_matrix_grad(g, xy, a_z=(lo, hi), a_off=off, self_pairs=True)
-    got = np.concatenate([ga.cpu().numpy().reshape(n, -1), gz.cpu().numpy()], 1)
-    rr = np.concatenate([ra.reshape(n, -1), rz], 1)
-    err = np.linalg.norm(got - rr, axis=1)
-    scale = np.maximum(np.linalg.norm(rr, axis=1), 1e-6)
-    assert np.percentile(err / scale, 99) <= GRAD_TOL
+    ia, ib, fl = _aabb_candidates(xy, xy, off, off, True)
+    rr, scale = _grad_reference(xy, xy, g, ia, ib, fl, a_z=(lo, hi), b_z=(lo, hi),
+                                self_pairs=True)
+    _assert_box_grads(_box_grads(ga, gz), rr, scale, "scenes")
 
 
 def test_default_capacity_grows(dg):
@@ -457,11 +651,10 @@ def test_default_capacity_grows(dg):
     assert np.abs(iou.cpu().numpy()[r, c] - ref).max() <= IOU_TOL
     g = rng.uniform(-1, 1, (1500, 1500)).astype(np.float32)
     ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g).reshape(-1), saved, seg, ta, ta)
-    ref_a, ref_b, _, _ = oracle.iou_matrix_grad(g.reshape(-1), a, a)
-    for got, rr in ((ga.cpu().numpy(), ref_a), (gb.cpu().numpy(), ref_b)):
-        err = np.linalg.norm((got - rr).reshape(len(rr), -1), axis=1)
-        scale = np.maximum(np.linalg.norm(rr.reshape(len(rr), -1), axis=1), 1e-6)
-        assert np.percentile(err / scale, 99) <= 5 * GRAD_TOL
+    ia, ib, fl = _aabb_candidates(a, a)
+    ra, sa, rb, sb = _grad_reference(a, a, g.reshape(-1), ia, ib, fl)
+    _assert_box_grads(_box_grads(ga), ra, sa, "rows")
+    _assert_box_grads(_box_grads(gb), rb, sb, "columns")
 
 
 def test_matrix_beyond_int32(dg):
@@ -529,19 +722,10 @@ def test_matrix_beyond_int32(dg):
     on_rows = np.isin(pid // nb, rows)
     on_cols = np.isin(pid % nb, cols)
     pick = on_rows | on_cols
-    pa_, pb_, _, _ = oracle.iou_pairs_grad(a[pid[pick] // nb], b[pid[pick] % nb], gs[pick],
-                                           *oracle.iou_pairs(a[pid[pick] // nb], b[pid[pick] % nb],
-                                                             threads=16)[1:3], threads=16)
-    ref_a = np.zeros((na, 4, 2))
-    ref_b = np.zeros((nb, 4, 2))
-    np.add.at(ref_a, (pid[pick] // nb), pa_)
-    np.add.at(ref_b, (pid[pick] % nb), pb_)
-    got_a = ga.cpu().numpy()[rows]
-    got_b = gb.cpu().numpy()[cols]
-    for got_g, ref_g in ((got_a, ref_a[rows]), (got_b, ref_b[cols])):
-        err = np.linalg.norm((got_g - ref_g).reshape(len(ref_g), -1), axis=1)
-        scale = np.maximum(np.linalg.norm(ref_g.reshape(len(ref_g), -1), axis=1), 1e-6)
-        assert np.percentile(err / scale, 99) <= GRAD_TOL, np.sort(err / scale)[-5:]
+    ra, sa, rb, sb = _grad_reference(a, b, gs[pick], pid[pick] // nb, pid[pick] % nb,
+                                     np.arange(int(pick.sum())))
+    _assert_box_grads(_box_grads(ga)[rows], ra[rows], sa[rows], "rows")
+    _assert_box_grads(_box_grads(gb)[cols], rb[cols], sb[cols], "columns")
     _say(f"matrix beyond int32: {cnt} survivors, {len(hi)} past 2^31")
 
 
@@ -589,20 +773,14 @@ def test_scenes_beyond_int32(dg):
     g = torch.rand(total, device="cuda", generator=torch.Generator("cuda").manual_seed(6)) - 0.5
     ga, _, _, _ = dg.iou_matrix_backward(g, saved, seg, txy, self_pairs=True)
     dg.check_errors()
-    # pair (i, k) gives box i the gradient of IoU(i, k) weighted by
-    # g[i, k] + g[k, i]
-    tpid = s_ * ns * ns + (local % ns) * ns + local // ns
-    w = (g[torch.from_numpy(pid).cuda()] + g[torch.from_numpy(tpid).cuda()]).cpu().numpy()
+    # the saved entries hold both (i, k) and (k, i); every entry of a sampled
+    # box, weighted by its own upstream gradient, gives that box its role's
+    # gradient of the unordered pair (lower index first)
     boxes = rng.choice(np.unique(ia), 400, replace=False)
-    pick = np.isin(ia, boxes)
-    nx, xf = oracle.iou_pairs(xy[ia[pick]], xy[ib[pick]], threads=16)[1:3]
-    pa_, _, _, _ = oracle.iou_pairs_grad(xy[ia[pick]], xy[ib[pick]], w[pick].astype(np.float32),
-                                         nx, xf, threads=16)
-    ref_a = np.zeros((n, 4, 2))
-    np.add.at(ref_a, ia[pick], pa_)
-    got_a = ga.cpu().numpy()[boxes]
-    err = np.linalg.norm((got_a - ref_a[boxes]).reshape(len(boxes), -1), axis=1)
-    scale = np.maximum(np.linalg.norm(ref_a[boxes].reshape(len(boxes), -1), axis=1), 1e-6)
-    assert np.percentile(err / scale, 99) <= GRAD_TOL, np.sort(err / scale)[-5:]
+    pick = np.isin(ia, boxes) | np.isin(ib, boxes)
+    gs = g[torch.from_numpy(pid[pick]).cuda()].cpu().numpy()
+    ref, scale = _grad_reference(xy, xy, gs, ia[pick], ib[pick], np.arange(int(pick.sum())),
+                                 self_pairs=True)
+    _assert_box_grads(_box_grads(ga)[boxes], ref[boxes], scale[boxes], "scenes")
     _say(f"scenes beyond int32: {cnt} survivors, {int((pid >= 2 ** 31).sum())} past 2^31")
 

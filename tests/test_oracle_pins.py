@@ -542,12 +542,20 @@ def test_matrix_matches_pairs_and_self_diagonal(orc):
         blk = m[out_off[s]:out_off[s + 1]].reshape(n, n)
         assert np.all(np.diag(blk) == 1.0)
         r, c = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
-        ia, ib = (r.ravel() + off[s]), (c.ravel() + off[s])
+        # entry (r, c) is the unordered pair with the lower index first
+        ia = np.minimum(r, c).ravel() + off[s]
+        ib = np.maximum(r, c).ravel() + off[s]
         v, _, _ = orc.iou_index_pairs(ia, ib, xy, xy, a_z=(lo, hi), b_z=(lo, hi))
         v = v.reshape(n, n)
         np.fill_diagonal(v, 1.0)
         assert np.array_equal(v, blk)
-        assert np.max(np.abs(blk - blk.T)) <= 1e-14
+        assert np.array_equal(blk, blk.T)
+        # and each entry is the IoU of its two boxes in either order, up to rounding
+        w, _, _ = orc.iou_index_pairs(r.ravel() + off[s], c.ravel() + off[s], xy, xy,
+                                      a_z=(lo, hi), b_z=(lo, hi))
+        w = w.reshape(n, n)
+        np.fill_diagonal(w, 1.0)
+        assert np.max(np.abs(w - blk)) <= 1e-14
 
 
 def test_matrix_grad_is_sum_of_pair_grads(orc):
@@ -564,8 +572,9 @@ def test_matrix_grad_is_sum_of_pair_grads(orc):
         n = int(off[s + 1] - off[s])
         r, c = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
         sel = (r != c).ravel()
-        ia = (r.ravel() + off[s])[sel]
-        ib = (c.ravel() + off[s])[sel]
+        # entry (r, c) is the pair with the lower index as the first polygon
+        ia = (np.minimum(r, c).ravel() + off[s])[sel]
+        ib = (np.maximum(r, c).ravel() + off[s])[sel]
         gs = g[d["out_off"][s]:d["out_off"][s + 1]][sel]
         _, nx, xf = orc.iou_index_pairs(ia, ib, xy, xy, a_z=(lo, hi), b_z=(lo, hi))
         pa, pb, pz1, pz2 = orc.iou_pairs_grad(xy[ia], xy[ib], gs, nx, xf,
@@ -577,6 +586,139 @@ def test_matrix_grad_is_sum_of_pair_grads(orc):
     assert np.max(np.abs(ga - ref)) <= 1e-12
     assert np.max(np.abs(gaz - refz)) <= 1e-12
     assert np.abs(ga).max() > 0
+
+
+def _tie_scene(rng):
+    """A scene of 3D boxes full of exact contacts: integer axis-aligned boxes
+    whose edges are collinear or touch, exact duplicates, boxes on a common
+    ground plane (shared zlo) and shared tops, and a few rotated boxes."""
+    n_int = 14
+    x0 = rng.integers(0, 5, n_int).astype(np.float64)
+    y0 = rng.integers(0, 5, n_int).astype(np.float64)
+    w = rng.integers(1, 4, n_int).astype(np.float64)
+    h = rng.integers(1, 4, n_int).astype(np.float64)
+    quads = np.stack([np.stack([x0, y0], 1), np.stack([x0 + w, y0], 1),
+                      np.stack([x0 + w, y0 + h], 1), np.stack([x0, y0 + h], 1)], 1)
+    rot = synth.boxes_to_quads(rng.uniform(1, 4, 4), rng.uniform(1, 4, 4), rng.uniform(1, 3, 4),
+                               rng.uniform(1, 3, 4), rng.uniform(-np.pi, np.pi, 4))
+    xy = np.concatenate([quads.astype(np.float32), rot, quads[:3].astype(np.float32),
+                         rot[:1]], 0)
+    n = len(xy)
+    zlo = np.where(rng.uniform(size=n) < 0.6, 0.0, rng.integers(-1, 2, n)).astype(np.float32)
+    zhi = (zlo + rng.integers(1, 3, n)).astype(np.float32)
+    zhi[::5] = 2.0  # shared tops as well
+    zlo = np.minimum(zlo, zhi - 1.0).astype(np.float32)
+    return xy, zlo, zhi
+
+
+def test_self_pair_matrix_one_structure_per_pair(orc):
+    """Reading R8 pinned by what must hold for any consistent derivative: in a
+    self-pair matrix of tie-heavy 3D boxes (collinear and touching integer
+    edges, duplicates, shared ground planes and tops) the matrix is exactly
+    symmetric, and the summed gradient keeps the invariances of the 3D IoU:
+    zero net force under translation in x, y and z, zero torque about z, and
+    zero virial under scaling of the xy plane and of z.  Giving each row's
+    box the first-polygon gradient of its own ordered entry, weighted by both
+    entries' upstream gradients (so the two boxes of a pair take their
+    gradients from two different tie structures: the rule R8 replaces)
+    breaks them on the same boxes."""
+    rng = np.random.default_rng(97)
+    xy, lo, hi = _tie_scene(rng)
+    n = len(xy)
+    off = np.array([0, n], np.int64)
+    m, _ = orc.iou_matrix(xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    blk = m.reshape(n, n)
+    assert np.array_equal(blk, blk.T)
+    assert np.count_nonzero(blk) > 3 * n  # the contacts make many non-empty pairs
+    p = xy.astype(np.float64)
+
+    def residuals(gxy, gz):
+        fx, fy = gxy[..., 0].sum(), gxy[..., 1].sum()
+        fz = (gz[:, 0] + gz[:, 1]).sum()
+        torque = (p[..., 0] * gxy[..., 1] - p[..., 1] * gxy[..., 0]).sum()
+        virial = (p[..., 0] * gxy[..., 0] + p[..., 1] * gxy[..., 1]).sum()
+        zvir = (lo * gz[:, 0] + hi * gz[:, 1]).sum()
+        return np.abs([fx, fy, fz, torque, virial, zvir])
+
+    worst_ordered = 0.0
+    for t in range(6):
+        g = rng.uniform(-1, 1, n * n)
+        ga, _, gz, _ = orc.iou_matrix_grad(g, xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+        scale = np.abs(ga).sum() + np.abs(gz).sum()
+        assert scale > 0
+        assert residuals(ga, gz).max() <= 1e-12 * scale, residuals(ga, gz)
+        # the replaced rule: row i takes (g[i, k] + g[k, i]) times the first-
+        # polygon gradient of entry (i, k) evaluated in that order
+        r, c = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        sel = (r != c).ravel()
+        ia, ib = r.ravel()[sel], c.ravel()[sel]
+        w = (g.reshape(n, n) + g.reshape(n, n).T).ravel()[sel]
+        _, nx, xf = orc.iou_index_pairs(ia, ib, xy, xy, a_z=(lo, hi), b_z=(lo, hi))
+        pa, _, pz1, _ = orc.iou_pairs_grad(xy[ia], xy[ib], w, nx, xf,
+                                           a_z=(lo[ia], hi[ia]), b_z=(lo[ib], hi[ib]))
+        oa = np.zeros_like(ga)
+        oz = np.zeros_like(gz)
+        np.add.at(oa, ia, pa)
+        np.add.at(oz, ia, pz1)
+        worst_ordered = max(worst_ordered, residuals(oa, oz).max() / scale)
+    assert worst_ordered > 1e-3, worst_ordered
+
+
+def test_pair_margins_closed_forms(orc):
+    """The five degeneracy margins that select the parity set, on pairs whose
+    values are known in closed form (a mistake in any margin, such as a
+    dropped normalisation, segment instead of line distances, a wrong edge
+    index or the wrong polygon's area, changes at least one):
+      [0] smallest vertex distance to an edge line of the other polygon,
+          over the union's bounding-box diagonal L;
+      [1] smallest |sin| between two crossing edges;
+      [2] smallest normalised turn of either polygon (sin of the exterior
+          angle);
+      [3] smallest normalised cross product of consecutive intersection
+          vertices seen from their centroid;
+      [4] intersection area over the smaller polygon's area."""
+    sq = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], np.float64)
+    # A: unit square and the unit square moved by (0.3, 0.2): the nearest
+    # vertex / line distance is 0.2 (Q_0 above y = 0), L the diagonal of
+    # [0, 1.3] x [0, 1.2], crossings at right angles, the intersection the
+    # 0.7 x 0.8 rectangle whose corners are seen from its centre at the
+    # half-diagonal angle 2 atan(0.8 / 0.7)
+    pa, qa = sq, sq + [0.3, 0.2]
+    ang = 2 * math.atan2(0.4, 0.35)
+    want_a = [0.2 / math.hypot(1.3, 1.2), 1.0, 1.0, min(math.sin(ang), math.sin(math.pi - ang)),
+              0.7 * 0.8]
+    # B: squares of half-size 1 about one centre, the second turned by pi/4:
+    # the regular octagon between them; vertex / line distance sqrt(2) - 1,
+    # L = the diagonal of the [-sqrt 2, sqrt 2]^2 bounding box = 4, crossings
+    # at 45 degrees, octagon vertices 45 degrees apart, area 8 sqrt 2 - 8 of 4
+    r2 = math.sqrt(2.0)
+    pb = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], np.float64)
+    qb = np.array([[0, -r2], [r2, 0], [0, r2], [-r2, 0]])
+    want_b = [(r2 - 1) / 4, math.sin(math.pi / 4), 1.0, math.sin(math.pi / 4), (8 * r2 - 8) / 4]
+    # C: a regular hexagon of circumradius 1 inside a 10 x 10 square: every
+    # turn of the hexagon is sin(60 deg); no crossing; the intersection is
+    # the hexagon (ratio 1), its vertices 60 degrees apart.  The nearest
+    # vertex / line pair is not the hexagon against a side (4 away) but a
+    # square corner against the line of a hexagon edge whose normal points
+    # 30 degrees from the x axis: 5 (cos 30 - sin 30) - cos 30 away
+    t = np.arange(6) * math.pi / 3
+    ph = np.stack([np.cos(t), np.sin(t)], 1)
+    qh = np.array([[-5, -5], [5, -5], [5, 5], [-5, 5]], np.float64)
+    c30, s30 = math.cos(math.pi / 6), math.sin(math.pi / 6)
+    want_c = [(5 * (c30 - s30) - c30) / math.hypot(10, 10), 1.0, math.sin(math.pi / 3),
+              math.sin(math.pi / 3), 1.0]
+    # D: disjoint squares: no crossing, empty intersection (margins 3, 4 are 1)
+    pd, qd = sq, sq + [3.0, 0.5]
+    want_d = [0.5 / math.hypot(4, 1.5), 1.0, 1.0, 1.0, 1.0]
+    for p, q, want in ((pa, qa, want_a), (pb, qb, want_b), (ph, qh, want_c), (pd, qd, want_d)):
+        k = max(len(p), len(q), 4)
+        a = np.zeros((1, 8, 2), np.float32)
+        b = np.zeros((1, 8, 2), np.float32)
+        a[0, :len(p)] = p
+        b[0, :len(q)] = q
+        got = orc.pair_margins(a, b, np.array([len(p)], np.uint8), np.array([len(q)], np.uint8))[0]
+        # the inputs are rounded to fp32 (sqrt 2 and the hexagon)
+        assert np.allclose(got, want, rtol=2e-6, atol=1e-7), (got, want, k)
 
 
 # ------------------------------------------------- intersection and area primitives
