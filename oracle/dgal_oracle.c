@@ -35,8 +35,11 @@
  *   R1 flag encoding: P vertex i -> i; Q vertex j -> 0x10|j; crossing of P edge
  *      i with Q edge j -> 0x40|(i<<3)|j; unused slot -> 0xFF.  Edge i runs from
  *      vertex i to vertex (i+1) mod n.
- *   R2 vertex order: counter-clockwise by angle about the vertex centroid
- *      (atan2), ties by ascending code, rotated so the smallest code is first.
+ *   R2 vertex order: counter-clockwise along the boundary, starting at the
+ *      smallest code.  On distinct points this is the order by angle about
+ *      any interior point; where points coincide (contacts resolved by R3)
+ *      it is the boundary order of the moved pair, found by walking the
+ *      boundary from edge to edge (see intersect).
  *   R3 degeneracies: symbolic perturbation, Q translated by (eps, eps^2) with
  *      eps -> 0+.  An exactly-zero orientation takes the sign of the leading
  *      eps term (see side_of_q_edge / side_of_p_edge).
@@ -136,7 +139,8 @@ static int side_of_p_edge(point pi, point pi1, point q) {
 
 /* Sec. II-B `intersect`, Sec. III convex CCW polygon.  Returns the vertex
  * count m (0 for an empty intersection) or -1 if more than the capacity would
- * be produced (possible only for invalid, non-convex input). */
+ * be produced or the boundary walk does not close over the m vertices (both
+ * possible only for invalid, non-convex input). */
 static int intersect(const point *P, int n1, const point *Q, int n2,
                      polygon *out) {
   int sp[ORC_MAXV][ORC_MAXV]; /* sp[i][j]: side of P_i w.r.t. Q edge j */
@@ -185,37 +189,83 @@ static int intersect(const point *P, int n1, const point *Q, int n2,
   out->n = m;
   if (m == 0) return 0;
 
-  /* R2: counter-clockwise about the centroid; a stable insertion sort keeps
-   * the collection order (ascending code) among equal angles. */
-  point c = mkpt(0, 0);
+  /* R2: the boundary of P n Q walked counter-clockwise from the smallest
+   * code (the candidates were collected in ascending code, so that is the
+   * first one).  Each vertex leaves along one edge that runs inside the other
+   * polygon: a vertex of P (of Q) along its own edge; a crossing of P edge i
+   * with Q edge j along P edge i when that edge enters Q there (P_i outside
+   * the line of Q edge j), else along Q edge j (which then enters P).  The
+   * next vertex on an edge is its end vertex when that end is inside the
+   * other polygon, else the crossing where the edge leaves it (a convex
+   * polygon is left once).  The signs are those of the pair moved by the tie
+   * rule (R3), whose intersection has distinct vertices in a definite
+   * boundary order; this walk finds that order also where the unmoved points
+   * coincide, which no angle about a centre can tell apart. */
+  int order[ORC_MAXV * ORC_MAXV + 2 * ORC_MAXV];
+  int seen[ORC_MAXV * ORC_MAXV + 2 * ORC_MAXV];
+  for (int k = 0; k < m; ++k) seen[k] = 0;
+  int cur = 0;
   for (int k = 0; k < m; ++k) {
-    c.x += cand[k].x;
-    c.y += cand[k].y;
-  }
-  c.x /= m;
-  c.y /= m;
-  double ang[ORC_MAXV * ORC_MAXV + 2 * ORC_MAXV];
-  int idx[ORC_MAXV * ORC_MAXV + 2 * ORC_MAXV];
-  for (int k = 0; k < m; ++k) {
-    ang[k] = atan2(cand[k].y - c.y, cand[k].x - c.x);
-    idx[k] = k;
-  }
-  for (int k = 1; k < m; ++k) {
-    int t = idx[k];
-    int l = k - 1;
-    while (l >= 0 && ang[idx[l]] > ang[t]) {
-      idx[l + 1] = idx[l];
-      --l;
+    if (seen[cur]) return -1; /* a closed walk shorter than m: invalid input */
+    seen[cur] = 1;
+    order[k] = cur;
+    const int code = ccode[cur];
+    int along_p, e; /* the edge the boundary leaves on: P edge e or Q edge e */
+    if (code < 0x10) {
+      along_p = 1;
+      e = code;
+    } else if (code < 0x40) {
+      along_p = 0;
+      e = code & 0x0F;
+    } else {
+      const int i = (code >> 3) & 7, j = code & 7;
+      along_p = sp[i][j] < 0;
+      e = along_p ? i : j;
     }
-    idx[l + 1] = t;
+    int want = -1; /* code of the next vertex */
+    if (along_p) {
+      const int e1 = (e + 1) % n1;
+      int in = 1;
+      for (int j = 0; j < n2; ++j) in &= sp[e1][j] > 0;
+      if (in) {
+        want = e1;
+      } else {
+        for (int j = 0; j < n2; ++j) {
+          const int j1 = (j + 1) % n2;
+          const int leaves = sp[e][j] > 0 && sp[e1][j] < 0 && sq[j][e] != sq[j1][e];
+          if (leaves) {
+            if (want >= 0) return -1; /* left twice: not convex */
+            want = 0x40 | (e << 3) | j;
+          }
+        }
+      }
+    } else {
+      const int e1 = (e + 1) % n2;
+      int in = 1;
+      for (int i = 0; i < n1; ++i) in &= sq[e1][i] > 0;
+      if (in) {
+        want = 0x10 | e1;
+      } else {
+        for (int i = 0; i < n1; ++i) {
+          const int i1 = (i + 1) % n1;
+          const int leaves = sq[e][i] > 0 && sq[e1][i] < 0 && sp[i][e] != sp[i1][e];
+          if (leaves) {
+            if (want >= 0) return -1;
+            want = 0x40 | (i << 3) | e;
+          }
+        }
+      }
+    }
+    int next = -1;
+    for (int t = 0; t < m; ++t)
+      if (ccode[t] == want) next = t;
+    if (next < 0) return -1; /* the boundary leads to no collected vertex */
+    cur = next;
   }
-  int start = 0;
-  for (int k = 1; k < m; ++k)
-    if (ccode[idx[k]] < ccode[idx[start]]) start = k;
+  if (cur != 0) return -1; /* the walk must close on its first vertex */
   for (int k = 0; k < m; ++k) {
-    int s = idx[(start + k) % m];
-    out->v[k] = cand[s];
-    out->code[k] = ccode[s];
+    out->v[k] = cand[order[k]];
+    out->code[k] = ccode[order[k]];
   }
   return m;
 }

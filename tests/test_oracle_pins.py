@@ -251,7 +251,7 @@ def test_tie_rule_codes_are_the_moved_pairs(orc):
     touches, identical polygons): the oracle's vertex count and set of codes
     are those of the pair with b moved by (eps, eps^2) (eps = 2^-12, below
     every ratio of these small dyadic orientations), computed in exact
-    rationals.  The cyclic order of points that coincide is a convention."""
+    rationals (the order is pinned by the sequence test below)."""
     from fractions import Fraction
     eps = Fraction(1, 2 ** 12)
     sa, sb, _ = synth.degenerate_stress()
@@ -280,6 +280,115 @@ def test_tie_rule_codes_are_the_moved_pairs(orc):
             contacts += any(X.orient(Q[j], Q[(j + 1) % 4], v) == 0 for v in P for j in range(4))
             checked += 1
     assert checked == 2 * len(sa) + 400 and contacts > 100
+
+
+def _moved(q, eps):
+    return [(x + eps, y + eps * eps) for x, y in q]
+
+
+def _moved_sequence(P, Q, eps):
+    """Codes of the intersection of P with Q moved by (eps, eps^2), in the
+    counter-clockwise order of exact rational Sutherland-Hodgman clipping,
+    rotated to start at the smallest code (empty: [])."""
+    Qm = _moved(Q, eps)
+    poly = X.clip(P, Qm)
+    if len(poly) < 3:
+        return []
+    seq = []
+    for v in poly:
+        c = X.classify(P, Qm, v)
+        assert len(c) == 1, c  # the moved pair is generic: one name per point
+        seq.append(c.pop())
+    k = seq.index(min(seq))
+    return seq[k:] + seq[:k]
+
+
+def _contact_pairs(seed, n):
+    """Integer rectangles and diamonds on a small grid (exact contacts are
+    common), as pairs (a [n,4,2], b [n,4,2])."""
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for _ in range(2 * n):
+        x0, y0 = rng.integers(-3, 3, 2)
+        w, h = rng.integers(1, 4, 2)
+        if rng.integers(0, 2):
+            v = [(x0, y0), (x0 + w, y0), (x0 + w, y0 + h), (x0, y0 + h)]
+        else:
+            v = [(x0 + w, y0), (x0, y0 + w), (x0 - w, y0), (x0, y0 - w)]
+        shapes.append(v)
+    s = np.array(shapes, np.float32)
+    return s[:n], s[n:]
+
+
+def test_tie_rule_sequences_are_the_moved_pairs(orc):
+    """Reading R2 on exact contacts: the whole flag sequence, not only its set
+    of codes, is the counter-clockwise boundary of the pair moved by the tie
+    rule, taken from exact rational clipping of the moved pair (eps = 2^-12).
+    Where points coincide (a vertex on an edge, touching boxes, duplicates)
+    an order by angle about a centre cannot tell them apart; ordering such
+    ties by code reverses, for instance, the zero-area intersection of two
+    boxes that share part of an edge."""
+    eps = Fraction(1, 2 ** 12)
+    sa, sb, _ = synth.degenerate_stress()
+    ga, gb = _contact_pairs(27, 300)
+    checked = coincident = 0
+    for a, b in ((sa, sb), (sb, sa), (ga, gb), (gb, ga)):
+        _, nx, xf, bad = orc.iou_pairs(a, b)
+        assert bad == 0
+        for i in range(len(a)):
+            P, Q = X.fpoly(a[i]), X.fpoly(b[i])
+            want = _moved_sequence(P, Q, eps)
+            got = [int(c) for c in xf[i, :nx[i]]]
+            assert got == want, (i, [hex(c) for c in got], [hex(c) for c in want])
+            pts = [X.vertex_from_code(P, Q, c) for c in got]
+            coincident += len(set(pts)) < len(pts)
+            checked += 1
+    assert checked == 2 * len(sa) + 600 and coincident > 50, (checked, coincident)
+
+
+def _exact_iou(P, Q):
+    inter = X.clip(P, Q)
+    ai = X.area(inter) if len(inter) >= 3 else Fraction(0)
+    return ai / (X.area(P) + X.area(Q) - ai)
+
+
+def test_tie_rule_gradients_are_the_moved_pairs(orc):
+    """Reading R9 on exact contacts: the gradient the oracle takes from its
+    flags is the one-sided gradient in the direction of the tie rule, i.e.
+    the limit of the gradient of the moved pair.  Reference: exact rational
+    central differences of the exact IoU of the pair moved by eps = 2^-16,
+    with steps of 2^-44 (far below the eps^2 = 2^-32 separation of its
+    contacts, so the moved pair keeps its structure); the two differ by
+    O(eps).  Touching pairs (zero area, non-zero one-sided gradient) are
+    among them."""
+    eps = Fraction(1, 2 ** 16)
+    h = Fraction(1, 2 ** 44)
+    sa, sb, _ = synth.degenerate_stress()
+    ga, gb = _contact_pairs(28, 40)
+    a = np.concatenate([sa, ga])
+    b = np.concatenate([sb, gb])
+    g = np.ones(len(a))
+    _, nx, xf, _ = orc.iou_pairs(a, b)
+    oa, ob, _, _ = orc.iou_pairs_grad(a, b, g, nx, xf)
+    worst = 0.0
+    touching = 0
+    for i in range(len(a)):
+        P, Q = X.fpoly(a[i]), _moved(X.fpoly(b[i]), eps)
+        ref = np.zeros((2, 4, 2))
+        for side in range(2):
+            for k in range(4):
+                for d in range(2):
+                    def shifted(s):
+                        pp, qq = [list(v) for v in P], [list(v) for v in Q]
+                        (pp if side == 0 else qq)[k][d] += s
+                        return _exact_iou([tuple(v) for v in pp], [tuple(v) for v in qq])
+                    ref[side, k, d] = float((shifted(h) - shifted(-h)) / (2 * h))
+        got = np.stack([oa[i], ob[i]])
+        err = np.abs(got - ref).max()
+        worst = max(worst, err)
+        assert err <= 1e-3 * (1.0 + np.abs(ref).max()), (i, got, ref)
+        touching += nx[i] >= 3 and _exact_iou(X.fpoly(a[i]), X.fpoly(b[i])) == 0
+    assert touching >= 3, touching
 
 
 def test_identity_disjoint_nested(orc):
