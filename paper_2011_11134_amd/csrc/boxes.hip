@@ -66,7 +66,7 @@ template <bool Z3, bool SAVE>
 __global__ __launch_bounds__(kBoxBlock) void k_boxes_fwd(BoxesFwdArgs args) {
   constexpr int CAP = 8;
   __shared__ float2 s_pt[CAP * kBoxBlock];
-  __shared__ uint8_t s_cd[CAP * kBoxBlock];
+  __shared__ uint16_t s_cd[CAP * kBoxBlock];
   const int tid = threadIdx.x;
   const int dim = Z3 ? 7 : 5;
   for (int64_t i = (int64_t)blockIdx.x * kBoxBlock + tid; i < args.count;

@@ -15,12 +15,13 @@
 //      them in fp64 (exact for fp32 inputs) with the (eps, eps^2) tie rule;
 //   2. inside vertices (all signs positive) and edge crossings (both edges
 //      straddle each other's line) are appended, in ascending provenance code,
-//      to the lane's column of an LDS buffer (dynamic slot index);
-//   3. the points are ordered counter-clockwise by a rational monotone angle
-//      about their centroid (one reciprocal, no arctangent), measured as a
-//      fraction of a turn from the first (smallest-code) point; keys carry
-//      the slot index in their low bits, so a min/max network sorts plain
-//      words and the points are gathered back from LDS by slot;
+//      to the lane's column of an LDS buffer (dynamic slot index), each with
+//      the edge the intersection's boundary leaves it on and, per edge, the
+//      slot of the next point along it;
+//   3. the points are ordered counter-clockwise by walking that boundary from
+//      the smallest code (two bit-field reads a step, no angles, no sort);
+//      the signs are exact, so the order is the boundary of the pair moved by
+//      the tie rule also where points coincide;
 //   4. shoelace areas in a frame centred on P's first vertex, then IoU.
 // Backward, per pair: the intersection vertices are rebuilt from the codes
 // (no orientation test, no sort), the shoelace gradient is routed to the
@@ -29,6 +30,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace dgal {
 
@@ -124,37 +127,6 @@ __device__ __forceinline__ double orient64(float ax, float ay, float bx, float b
   return ux * vy - uy * vx;
 }
 
-// Sorting networks (Batcher odd-even merge) on positions 1..7 and 1..15 of
-// the key array; position 0 always holds the smallest-code vertex.
-#define DGAL_NET7(X)                                                                       \
-  X(0, 1) X(2, 3) X(4, 5) X(0, 2) X(1, 3) X(4, 6) X(1, 2) X(5, 6) X(0, 4) X(1, 5) X(2, 6) \
-  X(2, 4) X(3, 5) X(1, 2) X(3, 4) X(5, 6)
-#define DGAL_NET15(X)                                                                      \
-  X(0, 1) X(2, 3) X(4, 5) X(6, 7) X(8, 9) X(10, 11) X(12, 13) X(0, 2) X(1, 3) X(4, 6)     \
-  X(5, 7) X(8, 10) X(9, 11) X(12, 14) X(1, 2) X(5, 6) X(9, 10) X(13, 14) X(0, 4) X(1, 5)  \
-  X(2, 6) X(3, 7) X(8, 12) X(9, 13) X(10, 14) X(2, 4) X(3, 5) X(10, 12) X(11, 13) X(1, 2) \
-  X(3, 4) X(5, 6) X(9, 10) X(11, 12) X(13, 14) X(0, 8) X(1, 9) X(2, 10) X(3, 11) X(4, 12) \
-  X(5, 13) X(6, 14) X(4, 8) X(5, 9) X(6, 10) X(7, 11) X(2, 4) X(3, 5) X(6, 8) X(7, 9)     \
-  X(10, 12) X(11, 13) X(1, 2) X(3, 4) X(5, 6) X(7, 8) X(9, 10) X(11, 12) X(13, 14)
-
-template <int CAP>
-__device__ __forceinline__ void sort_keys(uint32_t (&key)[CAP]) {
-#define DGAL_CSWAP(A, B)                        \
-  {                                             \
-    uint32_t lo = min(key[1 + A], key[1 + B]);  \
-    uint32_t hi = max(key[1 + A], key[1 + B]);  \
-    key[1 + A] = lo;                            \
-    key[1 + B] = hi;                            \
-  }
-  if constexpr (CAP == 8) {
-    DGAL_NET7(DGAL_CSWAP)
-  } else {
-    static_assert(CAP == 16, "capacity 8 or 16");
-    DGAL_NET15(DGAL_CSWAP)
-  }
-#undef DGAL_CSWAP
-}
-
 // Result of one pair's forward.
 template <int K>
 struct PairResult {
@@ -174,14 +146,15 @@ constexpr int fwd_waves_per_simd() {
   return K == 8 ? 4 : 1;
 }
 
-// Forward of one pair.  s_pt / s_cd address this lane's column of a
-// [2K][BLOCK] LDS buffer (element stride BLOCK).  EMIT: the ordered
+// Forward of one pair.  s_pt / s_cd address this lane's column of
+// [2K][BLOCK] LDS buffers (element stride BLOCK): a point, and its code with,
+// in the high byte, the edge the intersection's boundary leaves it on.  EMIT: the ordered
 // intersection vertices are also returned in ov[0..2K) (absolute frame,
 // slots at and past the vertex count set to 0).
 template <int K, bool FIXED, int BLOCK, bool EMIT = false>
 __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Poly<K>& Q, int n2,
                                              float2* __restrict__ s_pt,
-                                             uint8_t* __restrict__ s_cd, PairResult<K>& res,
+                                             uint16_t* __restrict__ s_cd, PairResult<K>& res,
                                              float2* ov = nullptr) {
   constexpr int CAP = 2 * K;
   constexpr int NW = (K * K + 31) / 32;  // 32-bit words of a K x K sign table
@@ -315,23 +288,49 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
     res.a1 = 0.5f * s1;
     res.a2 = 0.5f * s2;
   }
+  // Points go to the lane's LDS column in ascending code (slot 0 holds the
+  // smallest).  For the counter-clockwise walk each point also records, in
+  // the high byte of its code entry, the edge the boundary leaves it on (P
+  // edge i as i, Q edge j as K + j), and each edge records, in its nibble of
+  // `nexw`, the slot of the next point on it: the edge's end when that end is
+  // inside the other polygon, else the crossing where the edge leaves it.
+  // Every nibble is written once for valid input; any mix of slots that
+  // invalid input ORs together still names a slot below CAP, so the walk
+  // stays in bounds.
+  using Nib = typename std::conditional<K == 4, uint32_t, uint64_t>::type;
+  Nib nexw = 0;
   int cnt = 0;
   // Appends a point; only invalid input can pass the capacity, and its
   // extra points then overwrite the last slot (the overflow is reported).
-  auto put = [&](bool in, float px, float py, uint32_t code) {
+  auto put = [&](bool in, float px, float py, uint32_t code, uint32_t leave, uint32_t reach) {
     const int s = min(cnt, CAP - 1);
     if (in) {
       s_pt[s * BLOCK] = make_float2(px, py);
-      s_cd[s * BLOCK] = (uint8_t)code;
+      s_cd[s * BLOCK] = (uint16_t)(code | (leave << 8));
     }
+    nexw |= in ? (Nib)s << (4 * reach) : (Nib)0;
     cnt += in;
   };
 #pragma unroll
-  for (int i = 0; i < K; ++i)
-    put((FIXED || i < n1) && (spr[i] & jmask) == jmask, lpx[i], lpy[i], (uint32_t)i);
+  for (int i = 0; i < K; ++i) {
+    const uint32_t ip = FIXED ? (uint32_t)((i + K - 1) % K) : (uint32_t)(i == 0 ? n1 - 1 : i - 1);
+    put((FIXED || i < n1) && (spr[i] & jmask) == jmask, lpx[i], lpy[i], (uint32_t)i, (uint32_t)i,
+        ip);
+  }
 #pragma unroll
-  for (int j = 0; j < K; ++j)
-    put((FIXED || j < n2) && ((qin >> j) & 1u), Q.x[j] - P.x[0], Q.y[j] - P.y[0], kCodeQ | j);
+  for (int j = 0; j < K; ++j) {
+    const uint32_t jp = FIXED ? (uint32_t)((j + K - 1) % K) : (uint32_t)(j == 0 ? n2 - 1 : j - 1);
+    put((FIXED || j < n2) && ((qin >> j) & 1u), Q.x[j] - P.x[0], Q.y[j] - P.y[0], kCodeQ | j,
+        (uint32_t)(K + j), (uint32_t)K + jp);
+  }
+  // A crossing of P edge i with Q edge j where P_i is left of Q edge j's line
+  // is where P edge i leaves Q (and Q edge j enters P, so the boundary goes on
+  // along Q edge j); otherwise P edge i enters Q there and Q edge j leaves P.
+  auto put_x = [&](bool in, float px, float py, int i, int j) {
+    const bool p_leaves = (spr[i] >> j) & 1u;
+    put(in, px, py, kCodeX | (uint32_t)(i << 3) | (uint32_t)j,
+        p_leaves ? (uint32_t)(K + j) : (uint32_t)i, p_leaves ? (uint32_t)i : (uint32_t)(K + j));
+  };
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     // P edge i straddles the line of Q edge j (rows i and i+1 of sp differ)
@@ -351,7 +350,7 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
         if ((FIXED || i < n1) && ((xm >> j) & 1u)) {
           const float o0 = oP[i][j], o1 = oP[inx][j];
           const float t = o0 * fast_rcp(o0 - o1);
-          put(true, fmaf(t, epx[i], lpx[i]), fmaf(t, epy[i], lpy[i]), kCodeX | (i << 3) | j);
+          put_x(true, fmaf(t, epx[i], lpx[i]), fmaf(t, epy[i], lpy[i]), i, j);
         }
       }
     } else {
@@ -390,7 +389,7 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
           o1 = (float)orient64(qx, qy, qnx, qny, P.x[inx], P.y[inx]);
         }
         const float t = o0 * fast_rcp(o0 - o1);
-        put(true, fmaf(t, ex, lx), fmaf(t, ey, ly), kCodeX | (uint32_t)(i << 3) | (uint32_t)j);
+        put_x(true, fmaf(t, ex, lx), fmaf(t, ey, ly), i, j);
       }
     }
   }
@@ -398,81 +397,58 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
   const int m = min(cnt, CAP);
   res.m = m;
 
-  // ---- 3. counter-clockwise order --------------------------------------
-  float x[CAP], y[CAP];
-  float cx = 0.f, cy = 0.f;
-#pragma unroll
-  for (int k = 0; k < CAP; ++k) {
-    const float2 v = s_pt[k * BLOCK];
-    x[k] = k < m ? v.x : 0.f;
-    y[k] = k < m ? v.y : 0.f;
-    cx += x[k];
-    cy += y[k];
-  }
-  const float inv_m = m > 0 ? fast_rcp((float)m) : 0.f;
-  cx *= inv_m;
-  cy *= inv_m;
-  // Turn of (dx, dy) about the centroid, in [0, 1) of a full turn measured
-  // from the first (smallest-code) point: 2 - sign(dy) (1 + dx / (|dx|+|dy|))
-  // is monotone in the polar angle over [0, 4); the scaled difference to the
-  // first point's value wraps with a fractional part.
-  auto quarter_turns = [](float dx, float dy) {
-    const float q = fmaf(dx, fast_rcp(fmaxf(fabsf(dx) + fabsf(dy), 1.17549435e-38f)), 1.f);
-    return copysignf(q, dy);  // 2 - this is the turn in quarters
-  };
-  const float c0 = -0.25f * quarter_turns(x[0] - cx, y[0] - cy);
-  uint32_t key[CAP];
-  key[0] = 0u;
-#pragma unroll
-  for (int k = 1; k < CAP; ++k) {
-    // fract(((2 - s_k) - (2 - s_0)) / 4) = fract(s_0/4 - s_k/4)
-    const float r = __builtin_amdgcn_fractf(fmaf(-0.25f, quarter_turns(x[k] - cx, y[k] - cy), -c0));
-    const uint32_t kb = k < m ? (__float_as_uint(r) & 0x7fffffffu) : 0x7f800000u;
-    key[k] = (kb & ~(uint32_t)(CAP - 1)) | (uint32_t)k;
-  }
-  sort_keys<CAP>(key);
-
-  // ---- 4. shoelace about the first vertex ------------------------------
+  // ---- 3 + 4. counter-clockwise walk from slot 0, shoelace about it ----
+  // Each step: the edge the current point leaves on, then the slot of the
+  // next point on that edge (both masked to their ranges, so that an entry
+  // that was never written, read when m = 0, still names a valid slot).  The
+  // signs are exact (certified, or fp64 with the tie rule), so the walk is
+  // the boundary of the pair moved by the tie rule, where points that
+  // coincide still have a definite order.
+  const float2 v0 = s_pt[0];
   float acc = 0.f;
   float px_prev = 0.f, py_prev = 0.f;
   uint32_t codes[K / 2];
 #pragma unroll
   for (int w = 0; w < K / 2; ++w) codes[w] = 0xffffffffu;
-  if (m > 0) codes[0] = 0xffffff00u | (uint32_t)s_cd[0];
+  uint32_t ent = s_cd[0];  // code | leave-edge << 8 of the current point
+  if (m > 0) codes[0] = 0xffffff00u | (ent & 0xffu);
   if (EMIT) {
 #pragma unroll
     for (int r = 0; r < CAP; ++r) ov[r] = make_float2(0.f, 0.f);
-    if (m > 0) ov[0] = make_float2(x[0] + P.x[0], y[0] + P.y[0]);
+    if (m > 0) ov[0] = make_float2(v0.x + P.x[0], v0.y + P.y[0]);
   }
+  uint32_t slot = 0;
 #pragma unroll
   for (int r = 1; r < CAP; ++r) {
     if constexpr (K == 4) {
-      // every slot is read (the key's low bits always name one of this
-      // lane's slots) and the ones at or past m are masked by selects, so
-      // that the rolling pair needs no register copies; a dead slot may hold
-      // anything and is never added in
+      // every step is taken (the walk only ever names this lane's slots) and
+      // the ones at or past m are masked by selects, so that the rolling pair
+      // needs no register copies; a dead slot may hold anything and is never
+      // added in
+      slot = (uint32_t)(nexw >> (4 * ((ent >> 8) & (uint32_t)(CAP - 1)))) & (uint32_t)(CAP - 1);
+      ent = s_cd[slot * BLOCK];
       const bool live = r < m;
-      const int slot = (int)(key[r] & (uint32_t)(CAP - 1));
       const float2 v = s_pt[slot * BLOCK];
-      const float vx = v.x - x[0], vy = v.y - y[0];
+      const float vx = v.x - v0.x, vy = v.y - v0.y;
       if (r >= 2) {
         const float term = px_prev * vy - py_prev * vx;
         acc += live ? term : 0.f;
       }
       px_prev = vx;
       py_prev = vy;
-      const uint32_t c = live ? (uint32_t)s_cd[slot * BLOCK] : 0xffu;
+      const uint32_t c = live ? (ent & 0xffu) : 0xffu;
       const int sh = (r & 3) * 8;
       codes[r >> 2] = (codes[r >> 2] & ~(0xffu << sh)) | (c << sh);
       if (EMIT) ov[r] = live ? make_float2(v.x + P.x[0], v.y + P.y[0]) : make_float2(0.f, 0.f);
     } else if (r < m) {
-      const int slot = (int)(key[r] & (uint32_t)(CAP - 1));
+      slot = (uint32_t)(nexw >> (4 * ((ent >> 8) & (uint32_t)(CAP - 1)))) & (uint32_t)(CAP - 1);
+      ent = s_cd[slot * BLOCK];
       const float2 v = s_pt[slot * BLOCK];
-      const float vx = v.x - x[0], vy = v.y - y[0];
+      const float vx = v.x - v0.x, vy = v.y - v0.y;
       if (r >= 2) acc += px_prev * vy - py_prev * vx;
       px_prev = vx;
       py_prev = vy;
-      const uint32_t c = s_cd[slot * BLOCK];
+      const uint32_t c = ent & 0xffu;
       const int sh = (r & 3) * 8;
       codes[r >> 2] = (codes[r >> 2] & ~(0xffu << sh)) | (c << sh);
       if (EMIT) ov[r] = make_float2(v.x + P.x[0], v.y + P.y[0]);

@@ -634,7 +634,7 @@ __global__ __launch_bounds__(kExactBlock)
 __attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_matrix_exact(ExactArgs m) {
   constexpr int CAP = 2 * K;
   __shared__ float2 s_pt[CAP * kExactBlock];
-  __shared__ uint8_t s_cd[CAP * kExactBlock];
+  __shared__ uint16_t s_cd[CAP * kExactBlock];
   const int tid = threadIdx.x;
   int64_t n = *m.count;
   n = n < m.capacity ? n : m.capacity;

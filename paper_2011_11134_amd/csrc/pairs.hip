@@ -18,7 +18,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_pairs_fwd(P
   constexpr int BLOCK = pairs_block<K>();
   constexpr int CAP = 2 * K;
   __shared__ float2 s_pt[CAP * BLOCK];
-  __shared__ uint8_t s_cd[CAP * BLOCK];
+  __shared__ uint16_t s_cd[CAP * BLOCK];
   const int tid = threadIdx.x;
   const int64_t n = args.a.count;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + tid; i < n; i += (int64_t)gridDim.x * BLOCK) {

@@ -1,11 +1,15 @@
 """Helpers for the GPU parity tests: run the HIP path through the binding and
 the FP64 oracle on the same seeded fp32 inputs, and compare.
 
-Parity bar: nx and xflags bit-exact on the generator-filtered (non-degenerate)
-set, and on every pair nx and the set of xflags codes equal; |IoU -
-IoU_oracle| <= 1e-5 on every pair; per-pair gradient relative
-error ||g - g_ref|| / max(||g_ref||, 1e-8) <= 1e-3 against the oracle's
-analytic gradient (on pairs whose structure both sides agree on).
+Parity bar: nx and xflags bit-exact on every pair (the signs that select the
+intersection's vertices and order its boundary are exact on both sides, so
+the sequences agree also on degenerate input); |IoU - IoU_oracle| <= 1e-5 on
+every pair; per-pair gradient relative error ||g - g_ref|| / max(||g_ref||,
+1e-8) <= 1e-3 against the oracle's analytic gradient on every pair whose
+gradient is well conditioned in fp32: crossing edges meet at |sin| >= 1e-3
+and the intersection is not a sliver (a non-empty intersection below 1e-4 of
+the smaller polygon's area, where fp32 vertices carry ~u L^2 / A of relative
+error).
 """
 import numpy as np
 import torch
@@ -23,6 +27,16 @@ def dev_t(x, dtype=None):
     if dtype is not None:
         t = t.to(dtype)
     return t.cuda()
+
+
+def conditioned_mask(margins):
+    """Pairs whose gradient fp32 can carry to 1e-3: no two crossing edges
+    meet at |sin| below 1e-3 (a crossing's chain rule carries 1/sin, so fp32
+    rounding reaches it as u/sin^2) and the intersection is empty or not a
+    sliver (margins [1] and [4] of the oracle's degeneracy margins).  The
+    structure and the IoU are compared on every pair regardless."""
+    m = np.asarray(margins)
+    return (m[:, 1] >= oracle.FILTER_SIN) & (m[:, 4] >= oracle.FILTER_SLIVER)
 
 
 def grad_rel_err(g, ref):
@@ -57,18 +71,13 @@ def compare_pairs(dg, a, b, a_nv=None, b_nv=None, a_z=None, b_z=None, grad=None,
     gpu = run_pairs(dg, a, b, a_nv, b_nv, a_z, b_z, grad)
     ref_iou, ref_nx, ref_xf, bad = oracle.iou_pairs(a, b, a_nv, b_nv, a_z, b_z, threads=threads)
     assert bad == 0
-    keep = oracle.filtered_mask(oracle.pair_margins(a, b, a_nv, b_nv, threads=threads))
+    margins = oracle.pair_margins(a, b, a_nv, b_nv, threads=threads)
+    keep = oracle.filtered_mask(margins)
     assert keep.mean() >= require_filtered_frac, keep.mean()
-    # integer state: bit-exact on the filtered set
-    assert np.array_equal(gpu["nx"][keep], ref_nx[keep]), np.nonzero(gpu["nx"][keep] != ref_nx[keep])
-    mism = np.nonzero(np.any(gpu["xflags"][keep] != ref_xf[keep], axis=1))[0]
-    assert mism.size == 0, (mism[:5], gpu["xflags"][keep][mism[:3]], ref_xf[keep][mism[:3]])
-    # every pair: the same count and the same set of codes, since the signs
-    # that select them are exact on both sides; only their order may differ
-    # where points (nearly) coincide, and the IoU check below covers it
+    # integer state: bit-exact on every pair
     assert np.array_equal(gpu["nx"], ref_nx), np.nonzero(gpu["nx"] != ref_nx)[0][:5]
-    diff = np.nonzero(np.any(np.sort(gpu["xflags"], axis=1) != np.sort(ref_xf, axis=1), axis=1))[0]
-    assert diff.size == 0, (diff[:5], gpu["xflags"][diff[:3]], ref_xf[diff[:3]])
+    mism = np.nonzero(np.any(gpu["xflags"] != ref_xf, axis=1))[0]
+    assert mism.size == 0, (mism[:5], gpu["xflags"][mism[:3]], ref_xf[mism[:3]])
     # IoU everywhere
     d = np.abs(gpu["iou"].astype(np.float64) - ref_iou)
     assert d.max() <= IOU_TOL, (d.max(), int(d.argmax()))
@@ -83,13 +92,14 @@ def compare_pairs(dg, a, b, a_nv=None, b_nv=None, a_z=None, b_z=None, grad=None,
         g_gpu = np.concatenate([p.reshape(n, -1) for p in parts_gpu], 1)
         g_ref = np.concatenate([p.reshape(n, -1) for p in parts_ref], 1)
         err = grad_rel_err(g_gpu, g_ref)
-        same = (gpu["nx"] == ref_nx) & np.all(gpu["xflags"] == ref_xf, axis=1)
+        cond = conditioned_mask(margins)
+        if cond.any():
+            assert err[cond].max() <= GRAD_TOL, (err[cond].max(),
+                                                 int(np.argmax(np.where(cond, err, 0))))
+            summary["max_grad_err"] = float(err[cond].max())
+        summary["max_grad_err_all"] = float(err.max())
         if keep.any():
-            assert err[keep].max() <= GRAD_TOL, (err[keep].max(),
-                                                 int(np.argmax(np.where(keep, err, 0))))
             summary["max_grad_err_filtered"] = float(err[keep].max())
-        if same.any():
-            summary["max_grad_err_same_structure"] = float(err[same].max())
         # the backward kernel on the oracle's own saved state, every pair
         ta, tb, tg, tan, tbn, taz, tbz = gpu["_tensors"]
         o_ga, o_gb, o_gaz, o_gbz = dg.iou_pairs_backward(ta, tb, tg, dev_t(ref_nx), dev_t(ref_xf),

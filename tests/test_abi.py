@@ -59,20 +59,3 @@ def test_binding_refuses_cpu_tensors(dgal):
     a = torch.zeros((4, 4, 2), dtype=torch.float32)
     with pytest.raises(ValueError, match="GPU tensor"):
         dgal.iou_pairs(a, a)
-
-
-def test_sorting_networks_sort_every_binary_input():
-    """0-1 principle: the comparator lists in geom.hpp sort all 2^n inputs."""
-    import itertools
-    src = open(os.path.join(ROOT, "paper_2011_11134_amd", "csrc", "geom.hpp")).read()
-    for name, n in (("DGAL_NET7", 7), ("DGAL_NET15", 15)):
-        # the macro body: its backslash-continued lines
-        body = re.search(r"#define %s\(X\)((?:.*\\\n)*.*)" % name, src).group(1)
-        pairs = [(int(a), int(b)) for a, b in re.findall(r"X\((\d+), (\d+)\)", body)]
-        assert all(a < b < n for a, b in pairs)
-        for bits in range(1 << n):
-            v = [(bits >> k) & 1 for k in range(n)]
-            for a, b in pairs:
-                if v[a] > v[b]:
-                    v[a], v[b] = v[b], v[a]
-            assert v == sorted(v), (name, bits)

@@ -6,7 +6,8 @@ import torch
 
 import oracle
 import synth
-from gpu_util import GRAD_TOL, IOU_TOL, compare_pairs, dev_t, grad_rel_err, run_pairs
+from gpu_util import (GRAD_TOL, IOU_TOL, compare_pairs, conditioned_mask, dev_t,
+                      grad_rel_err, run_pairs)
 
 pytestmark = pytest.mark.gpu
 
@@ -98,8 +99,8 @@ def test_3d_pairs(dg):
 
 def test_degenerate_stress(dg):
     """Exactly degenerate contacts: the fp64 fallback and the tie rule give the
-    oracle's vertex count, set of codes and IoU (the order of coinciding
-    points is not unique)."""
+    oracle's vertex count, flag sequence (the boundary order of the moved
+    pair, also where points coincide), IoU and one-sided gradient."""
     a, b, names = synth.degenerate_stress()
     g = np.ones(len(names), np.float32)
     gpu = run_pairs(dg, a, b, grad=g)
@@ -107,8 +108,14 @@ def test_degenerate_stress(dg):
     d = np.abs(gpu["iou"] - ref)
     assert d.max() <= IOU_TOL, [(names[i], gpu["iou"][i], ref[i]) for i in np.argsort(-d)[:3]]
     assert np.array_equal(gpu["nx"], nx), [(names[i], gpu["nx"][i], nx[i]) for i in range(len(nx))]
-    same = np.all(np.sort(gpu["xflags"], axis=1) == np.sort(xf, axis=1), axis=1)
+    same = np.all(gpu["xflags"] == xf, axis=1)
     assert same.all(), [(names[i], gpu["xflags"][i], xf[i]) for i in np.nonzero(~same)[0]]
+    # the one-sided gradient of the tie rule's structure (exact dyadic vertices)
+    ga, gb, _, _ = oracle.iou_pairs_grad(a, b, g, nx, xf)
+    err = grad_rel_err(np.concatenate([gpu["ga"].reshape(len(a), -1),
+                                       gpu["gb"].reshape(len(a), -1)], 1),
+                       np.concatenate([ga.reshape(len(a), -1), gb.reshape(len(a), -1)], 1))
+    assert err.max() <= GRAD_TOL, [(names[i], err[i]) for i in np.argsort(-err)[:3]]
     # swapped roles and translated copies (exact: dyadic shifts)
     for shift in (0.0, 1024.0, -3.5):
         gpu2 = run_pairs(dg, b + np.float32(shift), a + np.float32(shift))
@@ -117,7 +124,7 @@ def test_degenerate_stress(dg):
 
 def test_near_degenerate_fallback(dg):
     """Pairs within fp32 rounding of a vertex/edge contact: signs are decided in
-    fp64, so nx and the set of codes match the oracle exactly."""
+    fp64, so nx and the flag sequence match the oracle exactly."""
     d = synth.c1_pairs(n=4096, seed=51)
     a = d["a_xy"].copy()
     b = d["b_xy"].copy()
@@ -132,13 +139,13 @@ def test_near_degenerate_fallback(dg):
     ref, nx, xf, _ = oracle.iou_pairs(a, b)
     assert np.abs(gpu["iou"] - ref).max() <= IOU_TOL
     assert np.array_equal(gpu["nx"], nx)
-    assert np.array_equal(np.sort(gpu["xflags"], axis=1), np.sort(xf, axis=1))
+    assert np.array_equal(gpu["xflags"], xf)
 
 
 def test_grid_contacts(dg):
     """Integer rectangles and diamonds on a small grid: shared and collinear
-    edges, vertices on edges and corner touches on most pairs; count and set
-    of codes equal the oracle's on every pair, IoU on every pair."""
+    edges, vertices on edges and corner touches on most pairs; count and flag
+    sequence equal the oracle's on every pair, IoU on every pair."""
     rng = np.random.default_rng(2200)
     shapes = []
     for _ in range(40000):
@@ -159,8 +166,8 @@ def test_grid_contacts(dg):
 @pytest.mark.parametrize("sigma", [1e-6, 1e-7])
 def test_near_identical_boxes(dg, sigma):
     """b within about an ulp of a: nearly parallel edges that share ends, and
-    a filtered set that is nearly empty; IoU on every pair, count and codes
-    on every pair."""
+    a filtered set that is nearly empty; IoU, count and flag sequence on every
+    pair."""
     d = synth.c1_pairs(n=65536, seed=5000, center_sigma=sigma, yaw_sigma=sigma)
     _say(f"case: near-identical boxes sigma {sigma}")
     s = compare_pairs(dg, d["a_xy"], d["b_xy"], grad=d["grad"], require_filtered_frac=0.0)
@@ -202,12 +209,10 @@ def test_full_size_rectangles_sampled(dg):
     idx = np.concatenate([idx, np.arange(n - 100, n)])
     sub = {k: d[k][idx] for k in ("a_xy", "b_xy", "grad")}
     ref, nx, xf, _ = oracle.iou_pairs(sub["a_xy"], sub["b_xy"], threads=8)
-    keep = oracle.filtered_mask(oracle.pair_margins(sub["a_xy"], sub["b_xy"], threads=8))
+    keep = conditioned_mask(oracle.pair_margins(sub["a_xy"], sub["b_xy"], threads=8))
     assert np.abs(gpu["iou"][idx] - ref).max() <= IOU_TOL
-    assert np.array_equal(gpu["nx"][idx][keep], nx[keep])
-    assert np.array_equal(gpu["xflags"][idx][keep], xf[keep])
     assert np.array_equal(gpu["nx"][idx], nx)
-    assert np.array_equal(np.sort(gpu["xflags"][idx], axis=1), np.sort(xf, axis=1))
+    assert np.array_equal(gpu["xflags"][idx], xf)
     ga, gb, _, _ = oracle.iou_pairs_grad(sub["a_xy"], sub["b_xy"], sub["grad"], nx, xf, threads=8)
     err = grad_rel_err(np.concatenate([gpu["ga"][idx].reshape(len(idx), -1),
                                        gpu["gb"][idx].reshape(len(idx), -1)], 1),
@@ -229,13 +234,9 @@ def test_full_size_polygons_sampled(dg):
     idx = np.random.default_rng(1).choice(n, 30000, replace=False)
     sub = {k: d[k][idx] for k in ("a_xy", "b_xy", "grad", "a_nv", "b_nv")}
     ref, nx, xf, _ = oracle.iou_pairs(sub["a_xy"], sub["b_xy"], sub["a_nv"], sub["b_nv"], threads=8)
-    keep = oracle.filtered_mask(oracle.pair_margins(sub["a_xy"], sub["b_xy"], sub["a_nv"],
-                                                    sub["b_nv"], threads=8))
     assert np.abs(gpu["iou"][idx] - ref).max() <= IOU_TOL
-    assert np.array_equal(gpu["nx"][idx][keep], nx[keep])
-    assert np.array_equal(gpu["xflags"][idx][keep], xf[keep])
     assert np.array_equal(gpu["nx"][idx], nx)
-    assert np.array_equal(np.sort(gpu["xflags"][idx], axis=1), np.sort(xf, axis=1))
+    assert np.array_equal(gpu["xflags"][idx], xf)
 
 
 def test_deterministic(dg):
@@ -254,7 +255,7 @@ def test_autograd_function(dg):
     (iou * dev_t(d["grad"])).sum().backward()
     ref, nx, xf, _ = oracle.iou_pairs(d["a_xy"], d["b_xy"])
     ga, gb, _, _ = oracle.iou_pairs_grad(d["a_xy"], d["b_xy"], d["grad"], nx, xf)
-    keep = oracle.filtered_mask(oracle.pair_margins(d["a_xy"], d["b_xy"]))
+    keep = conditioned_mask(oracle.pair_margins(d["a_xy"], d["b_xy"]))
     err = grad_rel_err(np.concatenate([a.grad.cpu().numpy().reshape(2048, -1),
                                        b.grad.cpu().numpy().reshape(2048, -1)], 1),
                        np.concatenate([ga.reshape(2048, -1), gb.reshape(2048, -1)], 1))
@@ -401,8 +402,8 @@ def test_pairs_beyond_int32_elements(dg):
     assert bad == 0
     assert np.abs(iou[ti].cpu().numpy() - ref).max() <= IOU_TOL
     assert np.array_equal(nx[ti].cpu().numpy(), r_nx)
-    assert np.array_equal(np.sort(xf[ti].cpu().numpy(), axis=1), np.sort(r_xf, axis=1))
-    keep = oracle.filtered_mask(oracle.pair_margins(sa, sb, threads=16))
+    assert np.array_equal(xf[ti].cpu().numpy(), r_xf)
+    keep = conditioned_mask(oracle.pair_margins(sa, sb, threads=16))
     r_ga, r_gb = oracle.iou_pairs_grad(sa, sb, sg, r_nx, r_xf, threads=16)[:2]
     err = grad_rel_err(np.concatenate([ga[ti].cpu().numpy().reshape(len(idx), -1),
                                        gb[ti].cpu().numpy().reshape(len(idx), -1)], 1),
