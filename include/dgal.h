@@ -175,6 +175,32 @@ int dgal_iou_matrix(dgal_ctx *ctx, dgal_polys a, dgal_polys b,
                     float *iou, int64_t out_size, const dgal_saved *saved,
                     void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * forward of dgal_iou_matrix, with the same arguments less `saved`, whose
+ * work list, tile state and workspace live in a static device array of the
+ * library (DGAL_NOALLOC_SCRATCH_BYTES, held on each GPU the library runs on
+ * until the process ends; its address is taken once per device by
+ * dgal_create).  Nothing is allocated and nothing synchronises; the output is
+ * the same as dgal_iou_matrix's for the same input.  Limits: at most
+ * DGAL_NOALLOC_MAX_TILES tiles (ceil(rows / 8) x ceil(cols / 256) per block)
+ * and DGAL_NOALLOC_MAX_PAIRS pairs surviving the cull.  One block over the
+ * tile limit returns DGAL_ECAPACITY before anything is enqueued; segments
+ * (whose sizes are on the device) over either limit, and one block over the
+ * survivor limit, are reported by dgal_check as DGAL_ECAPACITY, with the IoU
+ * of the pairs past the limit not written.  All calls on one GPU share the
+ * array: calls that overlap on one GPU (two streams, two host threads) race,
+ * and the backward cannot follow this call (it keeps no state for the
+ * caller).  DGAL_EINVAL: as dgal_iou_matrix, without the conditions on saved.
+ * DGAL_EHIP: the context was not created on a device the scratch serves. */
+#define DGAL_NOALLOC_MAX_TILES 65536
+#define DGAL_NOALLOC_MAX_PAIRS 1048576
+#define DGAL_NOALLOC_SCRATCH_BYTES 44925440 /* ~42.8 MiB */
+int dgal_iou_matrix_noalloc(dgal_ctx *ctx, dgal_polys a, dgal_polys b,
+                            const int64_t *a_off, const int64_t *b_off,
+                            const int64_t *out_off, int32_t nseg, int32_t self_pairs,
+                            float *iou, int64_t out_size, void *stream);
+
 enum { DGAL_PAIRS = 0, DGAL_MATRIX = 1 };
 
 /* Sec. II-B `iou_grad`: gradient of sum(grad_iou * iou) with respect to the

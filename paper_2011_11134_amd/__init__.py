@@ -48,7 +48,7 @@ class Boxes(ctypes.Structure):
 
 
 EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
-           "dgal_iou_pairs", "dgal_iou_matrix", "dgal_iou_backward",
+           "dgal_iou_pairs", "dgal_iou_matrix", "dgal_iou_matrix_noalloc", "dgal_iou_backward",
            "dgal_intersect", "dgal_intersect_backward", "dgal_area", "dgal_area_backward",
            "dgal_iou_boxes", "dgal_iou_boxes_backward", "dgal_set_autotune",
            "dgal_autotune_report", "dgal_validate", "dgal_set_validate",
@@ -75,6 +75,9 @@ def _load():
     L.dgal_iou_matrix.argtypes = [_vp, Polys, Polys, _vp, _vp, _vp, i32, i32, _vp, i64,
                                   ctypes.POINTER(Saved), _vp]
     L.dgal_iou_matrix.restype = ctypes.c_int
+    L.dgal_iou_matrix_noalloc.argtypes = [_vp, Polys, Polys, _vp, _vp, _vp, i32, i32, _vp, i64,
+                                          _vp]
+    L.dgal_iou_matrix_noalloc.restype = ctypes.c_int
     L.dgal_iou_backward.argtypes = [_vp, i32, Polys, Polys, _vp, _vp, _vp, i32, i32, _vp, i64,
                                     _vp, _vp, ctypes.POINTER(Saved), _vp, _vp, _vp, _vp, _vp]
     L.dgal_iou_backward.restype = ctypes.c_int

@@ -168,6 +168,16 @@ int dgal_create(dgal_ctx** out, int hip_device) {
     delete c;
     return DGAL_EHIP;
   }
+  // the allocation-free matrix forward's static scratch: its address on this
+  // device, taken once per device (here, with the device current)
+  if (dgal::matrix_scratch_init(hip_device) != DGAL_OK) {
+    (void)hipFree(c->v.err);
+    (void)hipFree(c->v.prefix);
+    (void)hipFree(c->v.scan);
+    (void)hipFree(c->n_bad);
+    delete c;
+    return DGAL_EHIP;
+  }
   const char* dbg = getenv("DGAL_DEBUG_VALIDATE");
   c->validate = dbg != nullptr && strcmp(dbg, "1") == 0;
   *out = c;
@@ -328,6 +338,22 @@ int dgal_iou_matrix(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const int64_t* a_
     return dgal::matrix_forward(ctx->v, a, b, a_off, b_off, out_off, nseg, self_pairs, iou,
                                 out_size, saved, s, sh);
   });
+}
+
+int dgal_iou_matrix_noalloc(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
+                            const int64_t* b_off, const int64_t* out_off, int32_t nseg,
+                            int32_t self_pairs, float* iou, int64_t out_size, void* stream) {
+  if (ctx == nullptr) return DGAL_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (int st = debug_validate(ctx, s, a, dgal::same_polys(a, b) ? nullptr : &b)) return st;
+  // a shape the autotuner already chose for dgal_iou_matrix is reused; nothing
+  // is tuned here (tuning allocates events and records its choice)
+  const TuneKey key(kTuneMatrixFwd, reg_k(a.kmax, b.kmax), a.nv == nullptr && b.nv == nullptr,
+                    a.zlo != nullptr, a_off != nullptr);
+  const auto it = ctx->tuned.find(key);
+  const dgal::LaunchShape shape = it != ctx->tuned.end() ? it->second : dgal::LaunchShape();
+  return dgal::matrix_forward_noalloc(ctx->v, a, b, a_off, b_off, out_off, nseg, self_pairs, iou,
+                                      out_size, s, shape);
 }
 
 int dgal_intersect(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* out_xy, uint8_t* nx,

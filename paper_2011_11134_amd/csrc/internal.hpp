@@ -221,6 +221,16 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
                     float* grad_a_xy, float* grad_b_xy, float* grad_a_z, float* grad_b_z,
                     hipStream_t stream, const LaunchShape& shape = LaunchShape());
 
+// The allocation-free forward: dgal_iou_matrix with its work list, tile state
+// and workspace in the library's static device scratch (matrix.hip).
+// matrix_scratch_init takes the scratch's device address once per device
+// (that device current); the context does it at creation.
+int matrix_scratch_init(int device);
+int matrix_forward_noalloc(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
+                           const int64_t* b_off, const int64_t* out_off, int nseg,
+                           int self_pairs, float* iou, int64_t out_size, hipStream_t stream,
+                           const LaunchShape& shape = LaunchShape());
+
 // Launchers (return a hipError_t from the launch).
 hipError_t launch_pairs_fwd(const PairsFwdArgs& args, int K, bool fixed, bool z3, bool save,
                             hipStream_t stream, const LaunchShape& shape = LaunchShape());

@@ -27,6 +27,7 @@
 // gradient for the row's box, weighted by both entries' upstream gradients;
 // for two different sets the column gradients are added with global atomics.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -1084,6 +1085,85 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
     prof_end(ctx.prof, "k_matrix_bwd", stream);
   });
   return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
+}
+
+
+// ---- scratch of the allocation-free forward (dgal_iou_matrix_noalloc) ----
+// The work list, tile state, segment prefixes and scan totals that
+// dgal_iou_matrix takes from the caller's dgal_saved and the context live
+// here instead, in one static device array per GPU (allocated when the
+// library's code object is loaded on that GPU, held until the process ends).
+// Every call on a GPU shares its array: two such calls that overlap on one
+// GPU race.  Nothing in it must start at zero (the forward writes every
+// field it later reads, including the survivor count).
+constexpr int64_t kNaTiles = DGAL_NOALLOC_MAX_TILES;
+constexpr int64_t kNaPairs = DGAL_NOALLOC_MAX_PAIRS;
+constexpr int64_t kNaFlags = 16;  // codes per entry: kmax_a + kmax_b <= 16
+constexpr int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+constexpr int64_t kNaPrefix = 0;  // int64 [2][DGAL_MAX_SEGMENTS + 1]
+constexpr int64_t kNaScan = align256(kNaPrefix + 8 * 2 * (DGAL_MAX_SEGMENTS + 1));
+constexpr int64_t kNaCount = align256(kNaScan + 8 * kScanTotals);
+constexpr int64_t kNaTileStart = align256(kNaCount + 8);
+constexpr int64_t kNaTileCount = align256(kNaTileStart + 8 * kNaTiles);
+constexpr int64_t kNaTileMask = align256(kNaTileCount + 4 * kNaTiles);
+constexpr int64_t kNaPairId = align256(kNaTileMask + 8 * kMaskWords * kNaTiles);
+constexpr int64_t kNaNx = align256(kNaPairId + 8 * kNaPairs);
+constexpr int64_t kNaXflags = align256(kNaNx + kNaPairs);
+constexpr int64_t kNaBytes = align256(kNaXflags + kNaFlags * kNaPairs);
+static_assert(kNaBytes == DGAL_NOALLOC_SCRATCH_BYTES, "scratch size stated in dgal.h");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+constexpr int kNaDevices = 64;
+std::mutex na_mu;
+void* na_ptr[kNaDevices] = {};  // device address of `scratch` per GPU
+}  // namespace
+
+// Takes the device address of `scratch` on `device` (which must be current)
+// once; later calls for the same device return at once.
+int matrix_scratch_init(int device) {
+  if (device < 0 || device >= kNaDevices) return DGAL_EINVAL;
+  std::lock_guard<std::mutex> lock(na_mu);
+  if (na_ptr[device] != nullptr) return DGAL_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr)
+    return DGAL_EHIP;
+  na_ptr[device] = ptr;
+  return DGAL_OK;
+}
+
+int matrix_forward_noalloc(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
+                           const int64_t* b_off, const int64_t* out_off, int nseg,
+                           int self_pairs, float* iou, int64_t out_size, hipStream_t stream,
+                           const LaunchShape& shape) {
+  void* base_v = nullptr;
+  if (ctx.device >= 0 && ctx.device < kNaDevices) {
+    std::lock_guard<std::mutex> lock(na_mu);
+    base_v = na_ptr[ctx.device];
+  }
+  if (base_v == nullptr) return DGAL_EHIP;  // the context did not set this device up
+  // one block: its tile count is known here, and a block past the scratch's
+  // tiles is refused before anything is enqueued
+  if (a_off == nullptr && a.count > 0 && b.count > 0 &&
+      ceil_div(a.count, kTileRows) > kNaTiles / ceil_div(b.count, kTileCols))
+    return DGAL_ECAPACITY;
+  unsigned char* base = static_cast<unsigned char*>(base_v);
+  dgal_saved sv;
+  sv.pair_id = reinterpret_cast<int64_t*>(base + kNaPairId);
+  sv.nx = base + kNaNx;
+  sv.xflags = base + kNaXflags;
+  sv.capacity = kNaPairs;
+  sv.count = reinterpret_cast<int64_t*>(base + kNaCount);
+  sv.tile_start = reinterpret_cast<int64_t*>(base + kNaTileStart);
+  sv.tile_count = reinterpret_cast<int32_t*>(base + kNaTileCount);
+  sv.tile_capacity = kNaTiles;
+  sv.tile_mask = reinterpret_cast<uint64_t*>(base + kNaTileMask);
+  CtxView v = ctx;
+  v.prefix = reinterpret_cast<int64_t*>(base + kNaPrefix);
+  v.scan = reinterpret_cast<int64_t*>(base + kNaScan);
+  return matrix_forward(v, a, b, a_off, b_off, out_off, nseg, self_pairs, iou, out_size, &sv,
+                        stream, shape);
 }
 
 }  // namespace dgal
