@@ -731,6 +731,25 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
   __syncthreads();
   const bool segmented = m.seg.a_off != nullptr;
   const int64_t total = segmented ? m.seg.group_prefix[m.seg.nseg] : m.single_groups;
+  if (segmented) {
+    // rows that no row group writes are zeroed here: rows outside every
+    // segment, and the rows of a segment without row groups (rejected, or
+    // without columns); every other row is written once by its row group
+    const int64_t rowlen = (int64_t)m.a.kmax * 2;
+    auto zero_rows = [&](int64_t r0, int64_t r1, int64_t t, int64_t nt) {
+      r0 = max(r0, (int64_t)0);
+      r1 = min(r1, m.a.count);
+      for (int64_t i = r0 * rowlen + t; i < r1 * rowlen; i += nt) m.ga_xy[i] = 0.f;
+      if (Z3)
+        for (int64_t i = r0 * 2 + t; i < r1 * 2; i += nt) m.ga_z[i] = 0.f;
+    };
+    const int64_t gt = (int64_t)blockIdx.x * BLOCK + tid, gn = (int64_t)gridDim.x * BLOCK;
+    zero_rows(0, m.seg.a_off[0], gt, gn);
+    zero_rows(m.seg.a_off[m.seg.nseg], m.a.count, gt, gn);
+    for (int s = blockIdx.x; s < m.seg.nseg; s += gridDim.x)
+      if (m.seg.group_prefix[s + 1] == m.seg.group_prefix[s])
+        zero_rows(m.seg.a_off[s], m.seg.a_off[s + 1], tid, BLOCK);
+  }
 
   for (int64_t u = (int64_t)blockIdx.x * WAVES + wave; u < total; u += (int64_t)gridDim.x * WAVES) {
     const int s = segmented ? find_segment(m.seg.group_prefix, m.seg.nseg, u) : 0;
@@ -1032,9 +1051,14 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
   if (!dg.ok) return DGAL_EHIP;
   const int K = reg_k(a.kmax, b.kmax);
   const bool segmented = a_off != nullptr;
-  // rows outside every row group keep zeros; row groups overwrite their rows
-  zero(grad_a_xy, a.count * a.kmax * 2, stream, ctx.prof);
-  if (z3) zero(grad_a_z, a.count * 2, stream, ctx.prof);
+  // every row of a is written by its row group, or zeroed by the kernel when
+  // no row group holds it (segmented); without segments an empty b leaves no
+  // row group at all.  Columns of a second set take atomic adds: zeroed
+  // first.
+  if (!segmented && b.count == 0) {
+    zero(grad_a_xy, a.count * a.kmax * 2, stream, ctx.prof);
+    if (z3) zero(grad_a_z, a.count * 2, stream, ctx.prof);
+  }
   if (!self_pairs) {
     zero(grad_b_xy, b.count * b.kmax * 2, stream, ctx.prof);
     if (z3) zero(grad_b_z, b.count * 2, stream, ctx.prof);
