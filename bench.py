@@ -547,6 +547,65 @@ def _cpu_baseline_scenes(d, frac=0.1, seed=2011):
             "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
+def filter_stats(d, wl, step, sample=65536, seed=2012):
+    """Rejection rate of the degeneracy filter that defines the parity set (the
+    oracle's five margins: vertex-to-edge distance, crossing angle, polygon
+    turn, angular gap of the intersection's vertices, sliver ratio) on a
+    seeded sample of the workload's pairs; for the matrices, of the pairs
+    that survived the cull (every other pair is disjoint).  Host-side, after
+    the timed region."""
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(seed)
+    anv = bnv = None
+    if wl in ("c2", "c5"):
+        pid = step.saved.pair_id[:int(step.saved.count.item())].cpu().numpy()
+        pid = np.sort(rng.choice(pid, min(sample, len(pid)), replace=False))
+        if wl == "c2":
+            nb = len(d["b_xy"])
+            a, b = d["a_xy"][pid // nb], d["b_xy"][pid % nb]
+        else:
+            out_off, off = d["out_off"], d["off"]
+            s_ = np.searchsorted(out_off, pid, side="right") - 1
+            n = off[s_ + 1] - off[s_]
+            loc = pid - out_off[s_]
+            r, c = loc // n, loc % n
+            ia, ib = off[s_] + np.minimum(r, c), off[s_] + np.maximum(r, c)
+            a, b = d["a_xy"][ia], d["a_xy"][ib]
+        what = f"{len(pid)} sampled cull survivors"
+    else:
+        if wl == "c3b":
+            a_all, b_all = synth_corners(d["a_box"]), synth_corners(d["b_box"])
+        else:
+            a_all, b_all = d["a_xy"], d["b_xy"]
+        n = len(a_all)
+        idx = np.sort(rng.choice(n, min(sample, n), replace=False))
+        a, b = a_all[idx], b_all[idx]
+        if d.get("a_nv") is not None:
+            anv, bnv = d["a_nv"][idx], d["b_nv"][idx]
+        what = f"{len(idx)} sampled pairs"
+    threads = max(1, min(16, os.cpu_count() or 1))
+    if wl == "c4n":
+        m = oracle.simple_margins(a, b, anv, bnv, threads=threads)
+        keep = oracle.simple_filtered_mask(m)
+    else:
+        m = oracle.pair_margins(a, b, anv, bnv, threads=threads)
+        keep = oracle.filtered_mask(m)
+    out = {"sample": what, "rejected": round(float(1.0 - keep.mean()), 5)}
+    if "redrawn" in d:  # polygons the generator redrew (broken convexity after rounding)
+        out["generator_redrawn"] = int(d["redrawn"])
+    return out
+
+
+def synth_corners(box):
+    import numpy as np
+
+    import synth
+    b = np.asarray(box, np.float64)
+    return synth.boxes_to_quads(b[:, 0], b[:, 1], b[:, 2], b[:, 3], b[:, 4])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -658,6 +717,19 @@ def main():
     kernels = {k: {"ms_per_launch": round(per_launch[k], 4),
                    "launches_per_step": round(prof[k][0] / args.steps, 2)} for k in prof}
 
+    # path statistics of one forward (outside the timed region): the pairs the
+    # exact kernels evaluated and those whose signs took the fp64 path
+    path = None
+    if wl not in ("c4n",):
+        dg.set_path_stats(True)
+        dg.path_stats()
+        step.fwd(stream)
+        n_eval, n_fp64 = dg.path_stats()
+        dg.set_path_stats(False)
+        path = {"pairs_evaluated": n_eval, "fp64_signs": n_fp64,
+                "rate": round(n_fp64 / max(n_eval, 1), 6)}
+    filt = filter_stats(d, wl, step)
+
     if args.copy_calib_mib:
         src = torch.empty(args.copy_calib_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -697,6 +769,8 @@ def main():
         "kernels": kernels,
         "step_ms_events": round(step_ms_events, 4),
         "roofline": roof,
+        "fp64_fallback": path,
+        "filter": filt,
         "cpu_baseline": cpu,
         "plain": plain,
         "vs_plain": None if plain is None else round(value / plain["value"], 2),

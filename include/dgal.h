@@ -355,6 +355,17 @@ int dgal_validate_simple(dgal_ctx *ctx, dgal_polys p, uint8_t *status,
  * dgal_validate_simple instead.  DGAL_EINVAL: ctx NULL. */
 int dgal_set_validate(dgal_ctx *ctx, int32_t enable);
 
+/* Path statistics (off by default; the numerical-stability question the
+ * paper leaves open after Sec. II-C and in Sec. V).  While enabled, the
+ * forward kernels of dgal_iou_pairs, dgal_iou_matrix (its exact pass),
+ * dgal_intersect and dgal_iou_boxes count on the device the pairs they
+ * evaluate and those whose orientation signs fp32 could not certify and
+ * recomputed in fp64 (one pair of atomic adds per wavefront).
+ * dgal_path_stats synchronises `stream`, returns both counts and clears them.
+ * DGAL_EINVAL: ctx NULL (set), or ctx / an output NULL (read). */
+int dgal_set_path_stats(dgal_ctx *ctx, int32_t enable);
+int dgal_path_stats(dgal_ctx *ctx, int64_t *pairs, int64_t *fp64_pairs, void *stream);
+
 /* Launch-shape autotuning of the batched kernels (the grid of the pair
  * kernels, the persistent grids of the matrix kernels).  While enabled, the
  * first call of dgal_iou_pairs / dgal_iou_matrix / dgal_iou_backward on a new

@@ -53,7 +53,8 @@ EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
            "dgal_iou_boxes", "dgal_iou_boxes_backward", "dgal_set_autotune",
            "dgal_autotune_report", "dgal_validate", "dgal_set_validate",
            "dgal_iou_simple_pairs", "dgal_iou_simple_backward", "dgal_validate_simple",
-           "dgal_set_profiling", "dgal_profile_report")
+           "dgal_set_profiling", "dgal_profile_report", "dgal_set_path_stats",
+           "dgal_path_stats")
 
 
 def _load():
@@ -97,6 +98,10 @@ def _load():
     L.dgal_set_autotune.restype = ctypes.c_int
     L.dgal_autotune_report.argtypes = [_vp, ctypes.c_char_p, i64]
     L.dgal_autotune_report.restype = ctypes.c_int
+    L.dgal_set_path_stats.argtypes = [_vp, i32]
+    L.dgal_set_path_stats.restype = ctypes.c_int
+    L.dgal_path_stats.argtypes = [_vp, ctypes.POINTER(i64), ctypes.POINTER(i64), _vp]
+    L.dgal_path_stats.restype = ctypes.c_int
     L.dgal_set_profiling.argtypes = [_vp, i32]
     L.dgal_set_profiling.restype = ctypes.c_int
     L.dgal_profile_report.argtypes = [_vp, ctypes.c_char_p, i64]
@@ -587,6 +592,21 @@ def profile_report(device=None):
         name, launches, ms = line.split()
         out[name] = (int(launches), float(ms))
     return out
+
+
+def set_path_stats(enable=True, device=None):
+    """Counting, on the device, of the pairs the forward kernels evaluate and
+    of those whose orientation signs took the fp64 path."""
+    _ok(lib.dgal_set_path_stats(context(device), int(bool(enable))), "dgal_set_path_stats")
+
+
+def path_stats(device=None):
+    """(pairs evaluated, pairs with fp64 signs) since the last read; clears them."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    n, k = ctypes.c_int64(0), ctypes.c_int64(0)
+    _ok(lib.dgal_path_stats(context(dev), ctypes.byref(n), ctypes.byref(k),
+                            torch.cuda.current_stream(dev).cuda_stream), "dgal_path_stats")
+    return int(n.value), int(k.value)
 
 
 def check_errors(device=None):

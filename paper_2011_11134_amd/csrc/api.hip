@@ -22,6 +22,7 @@ struct dgal_ctx {
   bool tune = false;
   bool validate = false;         // check every input polygon before each call
   int64_t* n_bad = nullptr;      // device counter of the input check
+  unsigned long long* stats_dev = nullptr;  // path statistics (2 counters)
   std::map<TuneKey, dgal::LaunchShape> tuned;
 };
 
@@ -148,6 +149,7 @@ int dgal_create(dgal_ctx** out, int hip_device) {
   c->v.prefix = nullptr;
   c->v.scan = nullptr;
   c->v.prof = nullptr;
+  c->v.stats = nullptr;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
       cus <= 0)
@@ -160,7 +162,11 @@ int dgal_create(dgal_ctx** out, int hip_device) {
       hipMalloc(reinterpret_cast<void**>(&c->v.scan), sizeof(int64_t) * dgal::kScanTotals) !=
           hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c->n_bad), sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->stats_dev), 2 * sizeof(unsigned long long)) !=
+          hipSuccess ||
+      hipMemset(c->stats_dev, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
+    if (c->stats_dev) (void)hipFree(c->stats_dev);
     if (c->v.err) (void)hipFree(c->v.err);
     if (c->v.prefix) (void)hipFree(c->v.prefix);
     if (c->v.scan) (void)hipFree(c->v.scan);
@@ -175,6 +181,7 @@ int dgal_create(dgal_ctx** out, int hip_device) {
     (void)hipFree(c->v.prefix);
     (void)hipFree(c->v.scan);
     (void)hipFree(c->n_bad);
+    (void)hipFree(c->stats_dev);
     delete c;
     return DGAL_EHIP;
   }
@@ -193,6 +200,7 @@ void dgal_destroy(dgal_ctx* ctx) {
   if (ctx->v.prefix) (void)hipFree(ctx->v.prefix);
   if (ctx->v.scan) (void)hipFree(ctx->v.scan);
   if (ctx->n_bad) (void)hipFree(ctx->n_bad);
+  if (ctx->stats_dev) (void)hipFree(ctx->stats_dev);
   delete ctx;
 }
 
@@ -243,6 +251,7 @@ int dgal_iou_pairs(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* iou, uint8_
   args.cap = a.kmax + b.kmax;
   args.flags_vec = args.cap == 2 * K && aligned(xflags, (uintptr_t)(2 * K));
   args.err = ctx->v.err;
+  args.stats = ctx->v.stats;
   // the fixed-size kernels also assume vector-aligned rows of coordinates and codes
   const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
                      args.a.vec4 && args.b.vec4 && (nx == nullptr || args.flags_vec);
@@ -376,6 +385,7 @@ int dgal_intersect(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* out_xy, uin
   args.cap = a.kmax + b.kmax;
   args.rows_vec = args.cap == 2 * K && aligned(out_xy, 16) && aligned(xflags, (uintptr_t)(2 * K));
   args.err = ctx->v.err;
+  args.stats = ctx->v.stats;
   const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
                      args.a.vec4 && args.b.vec4 && args.rows_vec;
   const hipError_t e_ = [&] {
@@ -591,6 +601,27 @@ int dgal_set_profiling(dgal_ctx* ctx, int32_t enable) {
   return DGAL_OK;
 }
 
+int dgal_set_path_stats(dgal_ctx* ctx, int32_t enable) {
+  if (ctx == nullptr) return DGAL_EINVAL;
+  ctx->v.stats = enable ? ctx->stats_dev : nullptr;
+  return DGAL_OK;
+}
+
+int dgal_path_stats(dgal_ctx* ctx, int64_t* pairs, int64_t* fp64_pairs, void* stream) {
+  if (ctx == nullptr || pairs == nullptr || fp64_pairs == nullptr) return DGAL_EINVAL;
+  DeviceGuard g(ctx->v.device);
+  if (!g.ok) return DGAL_EHIP;
+  unsigned long long host[2] = {0ull, 0ull};
+  const unsigned long long zeros[2] = {0ull, 0ull};
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess ||
+      hipMemcpy(host, ctx->stats_dev, sizeof(host), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(ctx->stats_dev, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess)
+    return DGAL_EHIP;
+  *pairs = (int64_t)host[0];
+  *fp64_pairs = (int64_t)host[1];
+  return DGAL_OK;
+}
+
 int dgal_profile_report(dgal_ctx* ctx, char* buf, int64_t size) {
   if (ctx == nullptr || (buf == nullptr && size > 0) || size < 0) return DGAL_EINVAL;
   if (ctx->prof.err != hipSuccess) return DGAL_EHIP;
@@ -646,6 +677,7 @@ int dgal_iou_boxes(dgal_ctx* ctx, dgal_boxes a, dgal_boxes b, float* iou, uint8_
   args.nx = nx;
   args.xflags = xflags;
   args.err = ctx->v.err;
+  args.stats = ctx->v.stats;
   const hipError_t e_ = [&] {
     dgal::prof_begin(ctx->v.prof, static_cast<hipStream_t>(stream));
     const hipError_t r_ = dgal::launch_boxes_fwd(args, a.dim == 7, nx != nullptr,

@@ -79,6 +79,7 @@ __global__ __launch_bounds__(kBoxBlock) void k_boxes_fwd(BoxesFwdArgs args) {
     box_corners(fb, Q);
     PairResult<4> r;
     pair_forward<4, true, kBoxBlock>(P, 4, Q, 4, s_pt + tid, s_cd + tid, r);
+    count_path(args.stats, r.exact);
     float v;
     if (Z3) {
       const float za = ba[5], ha = ba[6], zb = bb[5], hb = bb[6];

@@ -133,8 +133,22 @@ struct PairResult {
   float inter, a1, a2;  // areas (intersection, P, Q)
   int m;                // intersection vertex count (clamped to 2K)
   bool overflow;        // more than 2K vertices (invalid input)
+  bool exact;           // the signs were recomputed in fp64 (fp32 could not certify them)
   uint32_t codes[K / 2];  // 2K provenance codes, 4 per word, 0xFF padded
 };
+
+// Path statistics of a wavefront's live lanes (stats: NULL when off, else two
+// device counters: pairs evaluated, pairs whose signs took the fp64 path),
+// one pair of atomic adds per wavefront.
+__device__ __forceinline__ void count_path(unsigned long long* stats, bool exact) {
+  if (stats == nullptr) return;  // uniform
+  const uint64_t live = __builtin_amdgcn_ballot_w64(true);
+  const uint64_t ex = __builtin_amdgcn_ballot_w64(exact);
+  if ((int)(__lane_id()) == __builtin_ctzll(live)) {
+    atomicAdd(stats, (unsigned long long)__popcll(live));
+    atomicAdd(stats + 1, (unsigned long long)__popcll(ex));
+  }
+}
 
 // Waves per SIMD that the LDS of a pair_forward kernel allows at K = 8
 // (144 bytes a lane against 160 KiB a CU); the register allocator is held
@@ -209,6 +223,7 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
     }
   }
   const bool exact = !(omin > kCertify * E * D);
+  res.exact = exact;
   if (exact) {
     // Exact signs in fp64; exact zeros take the sign of Q moved by (eps,
     // eps^2).  Rare, so it is written for few registers rather than speed:

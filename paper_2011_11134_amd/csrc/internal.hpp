@@ -29,6 +29,7 @@ struct PairsFwdArgs {
   int cap;        // a.kmax + b.kmax: bytes per xflags row
   bool flags_vec; // cap == 2K and rows aligned to cap bytes
   int* err;
+  unsigned long long* stats;  // path statistics (NULL: off)
 };
 
 struct PairsBwdArgs {
@@ -52,6 +53,7 @@ struct IntersectArgs {
   int cap;          // a.kmax + b.kmax
   bool rows_vec;    // cap == 2K, vertex rows 16-byte and flag rows cap-byte aligned
   int* err;
+  unsigned long long* stats;  // path statistics (NULL: off)
 };
 
 struct IntersectBwdArgs {
@@ -73,6 +75,7 @@ struct BoxesFwdArgs {
   uint8_t* nx;
   uint8_t* xflags;  // [count][8], 8-byte aligned
   int* err;
+  unsigned long long* stats;  // path statistics (NULL: off)
 };
 
 struct BoxesBwdArgs {
@@ -158,6 +161,7 @@ struct CtxView {
   int64_t* prefix;  // [2][DGAL_MAX_SEGMENTS + 1]: tile and row-group prefixes
   int64_t* scan;    // [kScanTotals]: per-chunk totals of the tile scan
   Profiler* prof;   // per-kernel timing, or NULL
+  unsigned long long* stats;  // path statistics: pairs evaluated, fp64 signs (NULL: off)
 };
 
 // Chunks of 4096 tiles the tile scan can combine (2^24 tiles per call).

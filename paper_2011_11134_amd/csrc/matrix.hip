@@ -590,6 +590,7 @@ struct ExactArgs {
   const int64_t* count;
   int cap;
   int* err;
+  unsigned long long* stats;  // path statistics (NULL: off)
 };
 
 __device__ __forceinline__ int64_t wave_first(int64_t v) {
@@ -658,6 +659,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_matrix_exac
     load_poly<K, FIXED>(m.b.xy, ib, m.b.kmax, m.b.vec4, n2, Q);
     PairResult<K> res;
     pair_forward<K, FIXED, kExactBlock>(P, n1, Q, n2, s_pt + tid, s_cd + tid, res);
+    count_path(m.stats, res.exact);
     float v;
     if (Z3) {
       v = iou_3d(res.inter, res.a1, res.a2, res.m, m.a.zlo[ia], m.a.zhi[ia], m.b.zlo[ib],
@@ -996,6 +998,7 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
   x.count = saved->count;
   x.cap = a.kmax + b.kmax;
   x.err = ctx.err;
+  x.stats = ctx.stats;
   int64_t cull_grid = (int64_t)ctx.cus * (shape.cull_mult > 0 ? shape.cull_mult : 16);
   if (!segmented) cull_grid = std::min(cull_grid, ceil_div(single_tiles, kCullBlock / 64));
   const int exact_grid = ctx.cus * (shape.exact_mult > 0 ? shape.exact_mult : 8);

@@ -29,6 +29,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_pairs_fwd(P
     load_poly<K, FIXED>(args.b.xy, i, args.b.kmax, args.b.vec4, n2, Q);
     PairResult<K> r;
     pair_forward<K, FIXED, BLOCK>(P, n1, Q, n2, s_pt + tid, s_cd + tid, r);
+    count_path(args.stats, r.exact);
     float v;
     if (Z3) {
       v = iou_3d(r.inter, r.a1, r.a2, r.m, args.a.zlo[i], args.a.zhi[i], args.b.zlo[i],

@@ -9,7 +9,8 @@
 // is cross(P_i, P_i+1) times the fraction of the edge inside Q, and that
 // fraction needs no sorting: it starts at 1 or 0 (P_i inside Q or not) and
 // each crossing at t_k changes the inside length by +-(1 - t_k) (+ where the
-// edge enters Q, - where it leaves).  Inclusion of P_0 in Q is one
+// edge enters Q, - where it leaves), a crossing near the edge's start being
+// written as +-1 -+ t_k so that short inside parts keep their precision.  Inclusion of P_0 in Q is one
 // crossing-number test; every later vertex follows by the parity of the
 // crossings on the edge before it.  Moving a vertex moves its two edges: the
 // area changes by the edges' outward normals (dy, -dx) weighted by the
@@ -131,30 +132,42 @@ __device__ __forceinline__ uint32_t vertex0_inclusion(const Poly<K>& P, int n1, 
 // Parity of the set bits of a byte.
 __device__ __forceinline__ uint32_t parity8(uint32_t v) { return __builtin_popcount(v & 0xffu) & 1u; }
 
-// Per-edge sums over the crossings: for P's edge i, L = sum s (1 - t) and
-// W1 = sum s (1 - t)^2 / 2 with s = +1 where the edge enters Q; the same for
-// Q's edges (M, V1) with the opposite sign (an edge of P entering Q is an
-// edge of Q leaving P at that point).  The integral of t over the inside
-// part is the inside length minus that of (1 - t), so it needs no sum.
+// Per-edge sums over the crossings.  Along P's edge i the inside fraction is
+// its start vertex's inclusion plus, per crossing at t with s = +1 where the
+// edge enters Q (-1 where it leaves), s (1 - t); the integrals of (1 - t) and
+// of t over the inside part add s (1 - t)^2 / 2 and s (1 - t^2) / 2.  Each
+// crossing is anchored at its nearer end of the edge: one at t < 1/2 puts s
+// into an integer base B (s / 2 into both integrals' bases) and contributes
+// -s t, -s t (2 - t) / 2 and -s t^2 / 2 instead, so that a short inside part
+// at either end keeps its relative precision (written as 1 - (1 - t) it
+// would lose u / t of it).  Per P edge: B, L (the fraction's terms), W1, W2
+// (the integrals' terms).  Q's edges take the same sums in their own
+// parameter s (the crossing's projection on the edge) with the opposite
+// sign (an edge of P entering Q is an edge of Q leaving P there), kept in
+// this lane's LDS column: (B', M, V1, V2) per edge of Q.
 //
 // Each edge of P walks the set bits of its crossing row (a wavefront takes
 // as many steps as its busiest lane's row has crossings); the crossed edge of
-// Q is read from this lane's LDS column (s_q: Q's vertices) and its sums are
-// kept there too (s_acc: (M, V1) per edge of Q).
+// Q is read from this lane's LDS column (s_q: Q's vertices).
 template <int K, bool GRAD, int BLOCK>
 __device__ __forceinline__ void crossing_sums(const Poly<K>& P, int n1, const Poly<K>& Q, int n2,
                                               const float (&epx)[K], const float (&epy)[K],
                                               const uint32_t (&xrow)[K], const uint32_t (&erow)[K],
                                               bool exact, float2* __restrict__ s_q,
-                                              float2* __restrict__ s_acc, float (&L)[K],
-                                              float (&W1)[K], float (&M)[K], float (&V1)[K]) {
+                                              float4* __restrict__ s_acc, float (&B)[K],
+                                              float (&L)[K], float (&W1)[K], float (&W2)[K],
+                                              float (&Bq)[K], float (&M)[K], float (&V1)[K],
+                                              float (&V2)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     s_q[k * BLOCK] = make_float2(Q.x[k], Q.y[k]);
-    s_acc[k * BLOCK] = make_float2(0.f, 0.f);
+    s_acc[k * BLOCK] = make_float4(0.f, 0.f, 0.f, 0.f);
+    B[k] = 0.f;
     L[k] = 0.f;
     W1[k] = 0.f;
+    W2[k] = 0.f;
   }
+  // Q's sums: .x base, .y fraction terms, .z / .w the integrals' terms
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     const int inx = next_idx<K, false>(i, n1);
@@ -180,28 +193,45 @@ __device__ __forceinline__ void crossing_sums(const Poly<K>& P, int n1, const Po
       // the edges meet at a shallow angle both parameters are uncertain
       // along the edges, and only a shared point keeps the two edges'
       // contributions consistent (an error of X along the boundary then
-      // changes the area in proportion to the angle only).
-      const float t = fminf(fmaxf(o0 * fast_rcp(o0 - o1), 0.f), 1.f);
+      // changes the area in proportion to the angle only).  t and 1 - t each
+      // come from their own quotient (o0 and -o1 over o0 - o1), s and 1 - s
+      // from X's offsets to both ends of Q's edge.
+      const float idn = fast_rcp(o0 - o1);
+      const float t = fminf(fmaxf(o0 * idn, 0.f), 1.f);
+      const float ut = fminf(fmaxf(-o1 * idn, 0.f), 1.f);
       const float rx = fmaf(t, epx[i], P.x[i] - q.x), ry = fmaf(t, epy[i], P.y[i] - q.y);
-      const float s =
-          fminf(fmaxf((rx * fx + ry * fy) * fast_rcp(fmaf(fx, fx, fy * fy)), 0.f), 1.f);
+      const float vx = fmaf(-t, epx[i], qn.x - P.x[i]), vy = fmaf(-t, epy[i], qn.y - P.y[i]);
+      const float ifn = fast_rcp(fmaf(fx, fx, fy * fy));
+      const float sq = fminf(fmaxf((rx * fx + ry * fy) * ifn, 0.f), 1.f);
+      const float us = fminf(fmaxf((vx * fx + vy * fy) * ifn, 0.f), 1.f);
       const float sg = ((er >> j) & 1u) ? 1.f : -1.f;
-      const float ut = 1.f - t, us = 1.f - s;
-      L[i] = fmaf(sg, ut, L[i]);
-      float2 a = s_acc[j * BLOCK];
-      a.x = fmaf(-sg, us, a.x);
+      const bool near_p = t < 0.5f;  // anchored at the edge's start
+      B[i] += near_p ? sg : 0.f;
+      float4 a = s_acc[j * BLOCK];
+      const bool near_q = sq < 0.5f;
+      a.x += near_q ? -sg : 0.f;
       if (GRAD) {
-        W1[i] = fmaf(0.5f * sg, ut * ut, W1[i]);
-        a.y = fmaf(-0.5f * sg, us * us, a.y);
+        // the fraction's term is the sum of the integrals' terms (int (1 - t)
+        // + int t over the inside part is its length): not kept apart
+        W1[i] = fmaf(0.5f * sg, near_p ? -t * (2.f - t) : ut * ut, W1[i]);
+        W2[i] = fmaf(0.5f * sg, near_p ? -t * t : ut * (1.f + t), W2[i]);
+        a.z = fmaf(-0.5f * sg, near_q ? -sq * (2.f - sq) : us * us, a.z);
+        a.w = fmaf(-0.5f * sg, near_q ? -sq * sq : us * (1.f + sq), a.w);
+      } else {
+        L[i] = fmaf(sg, near_p ? -t : ut, L[i]);
+        a.y = fmaf(-sg, near_q ? -sq : us, a.y);
       }
       s_acc[j * BLOCK] = a;
     }
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const float2 a = s_acc[k * BLOCK];
-    M[k] = a.x;
-    V1[k] = a.y;
+    const float4 a = s_acc[k * BLOCK];
+    Bq[k] = a.x;
+    V1[k] = a.z;
+    V2[k] = a.w;
+    M[k] = GRAD ? a.z + a.w : a.y;
+    if (GRAD) L[k] = W1[k] + W2[k];
   }
 }
 
@@ -263,7 +293,7 @@ __global__ __launch_bounds__(simple_block<K>())
 __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_fwd(SimpleFwdArgs args) {
   constexpr int BLOCK = simple_block<K>();
   __shared__ float2 s_q[K * BLOCK];
-  __shared__ float2 s_acc[K * BLOCK];
+  __shared__ float4 s_acc[K * BLOCK];
   const int tid = threadIdx.x;
   const int64_t n = args.a.count;
   for (int64_t p = (int64_t)blockIdx.x * BLOCK + tid; p < n; p += (int64_t)gridDim.x * BLOCK) {
@@ -291,17 +321,18 @@ __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_fwd(Simple
       sm |= (uint64_t)erow[i] << (8 * i);
     }
     const uint32_t inside = vertex0_inclusion<K>(P, n1, Q, n2, spr, sqr);
-    float L[K], M[K], W1[K], V1[K];
+    float B[K], L[K], W1[K], W2[K], Bq[K], M[K], V1[K], V2[K];
     crossing_sums<K, false, BLOCK>(P, n1, Q, n2, epx, epy, xrow, erow, exact, s_q + tid,
-                                   s_acc + tid, L, W1, M, V1);
+                                   s_acc + tid, B, L, W1, W2, Bq, M, V1, V2);
     float ep[K], eq[K], cp[K], cq[K];
     vertex_inclusion<K>(inside, xrow, ep, eq);
     edge_cross<K>(P, n1, Q, n2, cp, cq);
     float inter = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      inter = fmaf(cp[k], ep[k] + L[k], inter);
-      inter = fmaf(cq[k], eq[k] + M[k], inter);
+      // inside fractions: the integer part (inclusion and base) plus the terms
+      inter = fmaf(cp[k], (ep[k] + B[k]) + L[k], inter);
+      inter = fmaf(cq[k], (eq[k] + Bq[k]) + M[k], inter);
       a1 += cp[k];
       a2 += cq[k];
     }
@@ -323,7 +354,7 @@ __global__ __launch_bounds__(simple_block<K>())
 __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_bwd(SimpleBwdArgs args) {
   constexpr int BLOCK = simple_block<K>();
   __shared__ float2 s_q[K * BLOCK];
-  __shared__ float2 s_acc[K * BLOCK];
+  __shared__ float4 s_acc[K * BLOCK];
   const int tid = threadIdx.x;
   const int64_t n = args.a.count;
   for (int64_t p = (int64_t)blockIdx.x * BLOCK + tid; p < n; p += (int64_t)gridDim.x * BLOCK) {
@@ -345,17 +376,17 @@ __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_bwd(Simple
       xrow[i] = i < n1 ? (uint32_t)(xm >> (8 * i)) & jmask : 0u;
       erow[i] = (uint32_t)(sm >> (8 * i)) & jmask;
     }
-    float L[K], M[K], W1[K], V1[K];
+    float B[K], L[K], W1[K], W2[K], Bq[K], M[K], V1[K], V2[K];
     crossing_sums<K, true, BLOCK>(P, n1, Q, n2, epx, epy, xrow, erow, false, s_q + tid, s_acc + tid,
-                                  L, W1, M, V1);
+                                  B, L, W1, W2, Bq, M, V1, V2);
     float ep[K], eq[K], cp[K], cq[K];
     vertex_inclusion<K>(inside, xrow, ep, eq);
     edge_cross<K>(P, n1, Q, n2, cp, cq);
     float inter = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      inter = fmaf(cp[k], ep[k] + L[k], inter);
-      inter = fmaf(cq[k], eq[k] + M[k], inter);
+      inter = fmaf(cp[k], (ep[k] + B[k]) + L[k], inter);
+      inter = fmaf(cq[k], (eq[k] + Bq[k]) + M[k], inter);
       a1 += cp[k];
       a2 += cq[k];
     }
@@ -368,15 +399,15 @@ __attribute__((amdgpu_waves_per_eu(simple_waves<K>()))) void k_simple_bwd(Simple
     const float ru = live ? fast_rcp(u) : 0.f;
     const float g = args.grad[p];
     const float cI = g * (a1 + a2) * ru * ru, cA = -g * inter * ru * ru;
-    // inside-part weights of each edge: W1 = int (1 - t), W2 = int t =
-    // inside length - W1 (the same for Q's edges: V1, V2)
-    float W2[K], V2[K];
+    // inside-part weights of each edge: W1 = int (1 - t), W2 = int t over
+    // the inside part, each half the integer part plus its terms (the same
+    // for Q's edges: V1, V2)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      W1[k] = fmaf(0.5f, ep[k], W1[k]);
-      W2[k] = ep[k] + L[k] - W1[k];
-      V1[k] = fmaf(0.5f, eq[k], V1[k]);
-      V2[k] = eq[k] + M[k] - V1[k];
+      W1[k] = fmaf(0.5f, ep[k] + B[k], W1[k]);
+      W2[k] = fmaf(0.5f, ep[k] + B[k], W2[k]);
+      V1[k] = fmaf(0.5f, eq[k] + Bq[k], V1[k]);
+      V2[k] = fmaf(0.5f, eq[k] + Bq[k], V2[k]);
     }
     float* oa = args.ga_xy + p * (int64_t)args.a.kmax * 2;
     float* ob = args.gb_xy + p * (int64_t)args.b.kmax * 2;

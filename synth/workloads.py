@@ -147,9 +147,13 @@ def _strictly_convex32(xy, n, min_turn):
     return bool(np.all(cr > min_turn * nu))
 
 
-def random_convex(rng, n, kmin=3, kmax=8, min_turn=1e-3):
+def random_convex(rng, n, kmin=3, kmax=8, min_turn=0.0, stats=None):
     """n convex polygons [n, kmax, 2] fp32 (zero padded) and counts [n] u8.
-    A polygon whose rounded vertices turn by less than min_turn is redrawn."""
+    A polygon whose rounded vertices do not turn left by more than min_turn
+    (normalised) at every vertex is redrawn; by default only those that break
+    the convex, counter-clockwise input contract (Sec. III) after rounding,
+    so that near-degenerate polygons stay in the workload.  stats (a dict)
+    receives the number of redraws."""
     xy = np.zeros((n, kmax, 2), np.float32)
     nv = rng.integers(kmin, kmax + 1, n).astype(np.uint8)
     todo = np.arange(n)
@@ -172,6 +176,8 @@ def random_convex(rng, n, kmin=3, kmax=8, min_turn=1e-3):
         ok = np.array([_strictly_convex32(cand[r], int(k[r]), min_turn) for r in range(t)])
         xy[todo[ok]] = cand[ok]
         todo = todo[~ok]
+        if stats is not None:
+            stats["redrawn"] = stats.get("redrawn", 0) + int(todo.size)
     return xy, nv
 
 
@@ -217,10 +223,12 @@ def c4_simple(n=1 << 18, seed=None):
 
 def c4_polygons(n=1 << 18, seed=None):
     rng = _rng(3, seed)
-    a, anv = random_convex(rng, n)
-    b, bnv = random_convex(rng, n)
+    st = {}
+    a, anv = random_convex(rng, n, stats=st)
+    b, bnv = random_convex(rng, n, stats=st)
     g = rng.uniform(-1.0, 1.0, n).astype(np.float32)
-    return {"a_xy": a, "a_nv": anv, "b_xy": b, "b_nv": bnv, "grad": g, "kind": "pairs"}
+    return {"a_xy": a, "a_nv": anv, "b_xy": b, "b_nv": bnv, "grad": g, "kind": "pairs",
+            "redrawn": st.get("redrawn", 0)}
 
 
 def c5_scenes(scenes=64, nmin=50, nmax=2000, seed=None, with_grad=True):

@@ -410,3 +410,36 @@ def test_pairs_beyond_int32_elements(dg):
                        np.concatenate([r_ga.reshape(len(idx), -1), r_gb.reshape(len(idx), -1)], 1))
     assert keep.mean() > 0.9 and err[keep].max() <= GRAD_TOL
 
+
+
+def test_path_stats_count_the_fp64_path(dg):
+    """The device path statistics: every evaluated pair is counted once;
+    pairs with a vertex of b on (or an ulp off) an edge of a take the fp64
+    signs (fp32 cannot certify a near-zero orientation), generic pairs
+    rarely; the matrix's exact pass counts its saved survivors."""
+    d = synth.c1_pairs(n=4096, seed=51)
+    a, b = d["a_xy"].copy(), d["b_xy"].copy()
+    t = np.float32(0.37)
+    b[:, 2] = (a[:, 0] + t * (a[:, 1] - a[:, 0])).astype(np.float32)
+    b[1::2, 2] = np.nextafter(b[1::2, 2], np.float32(np.inf))
+    valid = np.array([oracle.polygon_valid(b[i].astype(np.float64)) for i in range(len(b))])
+    a, b = a[valid], b[valid]
+    dg.set_path_stats(True)
+    try:
+        assert dg.path_stats() == (0, 0)
+        dg.iou_pairs(dev_t(a), dev_t(b))
+        n, k = dg.path_stats()
+        assert n == len(a) and k >= 0.9 * n, (n, k)
+        g = synth.c3_pairs(n=65536, seed=52)
+        dg.iou_pairs(dev_t(g["a_xy"]), dev_t(g["b_xy"]))
+        n, k = dg.path_stats()
+        assert n == 65536 and k <= 0.05 * n, (n, k)
+        m = synth.c2_matrix(n=300, m=257, seed=3)
+        _, saved, _ = dg.iou_matrix(dev_t(m["a_xy"]), dev_t(m["b_xy"]), save=True)
+        n, k = dg.path_stats()
+        assert n == int(saved.count.item()) and 0 <= k <= n, (n, k)
+        _say(f"path stats: matrix {n} survivors, {k} with fp64 signs")
+    finally:
+        dg.set_path_stats(False)
+    dg.iou_pairs(dev_t(a), dev_t(b))
+    assert dg.path_stats() == (0, 0)
