@@ -307,8 +307,8 @@ class MatrixStep:
             self.hi = torch.from_numpy(d["a_zhi"]).cuda()
             self.pa, _ = dg.polys(self.a, None, (self.lo, self.hi))
             self.pb = self.pa
-            d_a, d_b, d_o, nseg, total, tiles = dg.segments(len(self.a), len(self.a), d["off"],
-                                                            self_pairs=True)
+            d_a, d_b, d_o, nseg, total, tiles, _ = dg.segments(len(self.a), len(self.a), d["off"],
+                                                               self_pairs=True)
             self.seg = (d_a, d_b, d_o, nseg)
             self.total = total
             self.saved = dg.SavedPairs(max(1 << 16, total // 16), 8, tiles, self.a.device)
@@ -357,6 +357,7 @@ class MatrixStep:
                                     self._p(d_o), nseg, self.self_pairs, self.iou.data_ptr(),
                                     self.total, dg.ctypes.byref(st_s), stream)
         assert st == 0, st
+        self.saved.tile_rows = st_s.tile_rows  # the tile shape used, for the backward
 
     def bwd(self, stream):
         dg = self.dg

@@ -63,7 +63,8 @@ enum {
   DGAL_OK = 0,
   DGAL_EINVAL = -1,    /* invalid argument (see each entry point) */
   DGAL_ECAPACITY = -2, /* deferred: an intersection or a saved-pair list overflowed */
-  DGAL_EHIP = -3       /* HIP runtime or launch error */
+  DGAL_EHIP = -3,      /* HIP runtime or launch error */
+  DGAL_EIO = -4        /* a file could not be read or written (tune cache) */
 };
 
 typedef struct dgal_ctx dgal_ctx;
@@ -108,21 +109,22 @@ int dgal_check(dgal_ctx *ctx, void *stream);
 int dgal_iou_pairs(dgal_ctx *ctx, dgal_polys a, dgal_polys b, float *iou,
                    uint8_t *nx, uint8_t *xflags, void *stream);
 
-/* Tiles of DGAL_TILE_ROWS rows x DGAL_TILE_COLS columns are the unit of work
- * of the matrix kernels. */
-#define DGAL_TILE_ROWS 8
-#define DGAL_TILE_COLS 256
+/* The matrix kernels work in tiles of DGAL_TILE_PAIRS pairs of one block:
+ * tile_rows rows x DGAL_TILE_PAIRS / tile_rows columns, with tile_rows 4, 8
+ * or 16 (512, 256 or 128 columns), chosen per call (dgal_saved.tile_rows). */
+#define DGAL_TILE_PAIRS 2048
+#define DGAL_TILE_ROWS_DEFAULT 8
 
 /* Work list and saved state of a matrix forward: one entry per pair that
  * survived the conservative cull (every other pair is disjoint: its IoU is 0
  * and its gradient zero), with the intersection's vertex count and provenance
  * codes (nx == 0 for a survivor whose intersection is empty), and a table that
  * gives each tile its contiguous range of entries.  Tiles are numbered segment
- * by segment, row-major over the segment's tile grid (ceil(rows / 8) x
- * ceil(cols / 256) tiles per segment with both sides non-empty).  All pointers
- * are device memory; the forward overwrites everything, including *count.
- * Entries are laid out tile by tile, in a fixed order. */
-#define DGAL_TILE_MASK_WORDS (DGAL_TILE_ROWS * DGAL_TILE_COLS / 64 + 2)
+ * by segment, row-major over the segment's tile grid (ceil(rows / tile_rows)
+ * x ceil(cols / tile_cols) tiles per segment with both sides non-empty).  All
+ * pointers are device memory; the forward overwrites everything, including
+ * *count.  Entries are laid out tile by tile, in a fixed order. */
+#define DGAL_TILE_MASK_WORDS (DGAL_TILE_PAIRS / 64 + 2)
 
 typedef struct {
   int64_t *pair_id;       /* [capacity] index into the flat iou output               */
@@ -136,9 +138,16 @@ typedef struct {
   int64_t tile_capacity;  /* >= number of tiles, else DGAL_ECAPACITY (deferred)       */
   uint64_t *tile_mask;    /* [tile_capacity][DGAL_TILE_MASK_WORDS] per tile, written by
                              the forward: words 0..31 the survivor bits (word
-                             c * DGAL_TILE_ROWS + r: row r, columns 64c .. 64c + 63
+                             c * tile_rows + r: row r, columns 64c .. 64c + 63
                              of the tile), word 32 the output index of the tile's
                              first element, word 33 its block's row length      */
+  int32_t tile_rows;      /* HOST field, in/out.  In: 4, 8 or 16 fixes the tile
+                             shape; 0 lets the forward choose it (the autotuned
+                             shape of this kind of call, else
+                             DGAL_TILE_ROWS_DEFAULT).  Out: the forward writes
+                             the rows it used, which the backward reads.  With 0,
+                             tile_capacity must hold the tiles of every shape
+                             (the largest of the three counts).                   */
 } dgal_saved;
 
 /* Most segments one matrix call may hold. */
@@ -160,7 +169,8 @@ typedef struct {
  *   iou           flat fp32 output; element indices are 64-bit, so an output
  *                 may hold more than 2^31 elements
  *   saved         REQUIRED: the forward's work list, also the state that
- *                 dgal_iou_backward needs (a forward-only caller may discard it).
+ *                 dgal_iou_backward needs (a forward-only caller may discard it);
+ *                 its tile_rows chooses the tile shape and returns the one used.
  * Offsets live on the device so that the call can be captured in a HIP graph;
  * the kernels check them (a block outside [0, out_size) or rows/columns
  * outside [0, count) is skipped and reported by dgal_check as DGAL_EINVAL).
@@ -168,11 +178,11 @@ typedef struct {
  * some but not all offsets NULL, nseg outside [1, DGAL_MAX_SEGMENTS] with
  * offsets, out_size < a.count * b.count without offsets, a block with 2^24 or
  * more columns, self_pairs with a and b differing, saved with a NULL field or
- * a negative capacity, saved NULL. */
+ * a negative capacity, saved NULL, saved->tile_rows not 0, 4, 8 or 16. */
 int dgal_iou_matrix(dgal_ctx *ctx, dgal_polys a, dgal_polys b,
                     const int64_t *a_off, const int64_t *b_off,
                     const int64_t *out_off, int32_t nseg, int32_t self_pairs,
-                    float *iou, int64_t out_size, const dgal_saved *saved,
+                    float *iou, int64_t out_size, dgal_saved *saved,
                     void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -183,7 +193,9 @@ int dgal_iou_matrix(dgal_ctx *ctx, dgal_polys a, dgal_polys b,
  * until the process ends; its address is taken once per device by
  * dgal_create).  Nothing is allocated and nothing synchronises; the output is
  * the same as dgal_iou_matrix's for the same input.  Limits: at most
- * DGAL_NOALLOC_MAX_TILES tiles (ceil(rows / 8) x ceil(cols / 256) per block)
+ * DGAL_NOALLOC_MAX_TILES tiles (ceil(rows / tile_rows) x ceil(cols /
+ * tile_cols) per block, in the shape dgal_iou_matrix would use: the one the
+ * autotuner chose for this kind of call, else DGAL_TILE_ROWS_DEFAULT rows)
  * and DGAL_NOALLOC_MAX_PAIRS pairs surviving the cull.  One block over the
  * tile limit returns DGAL_ECAPACITY before anything is enqueued; segments
  * (whose sizes are on the device) over either limit, and one block over the
@@ -224,8 +236,11 @@ enum { DGAL_PAIRS = 0, DGAL_MATRIX = 1 };
  * order, and so the low-order bits, may vary from run to run) and writes every
  * row once; with two different sets the column gradients are added with fp32
  * global atomics.
+ * The matrix mode reads the tile shape the forward recorded in
+ * saved->tile_rows.
  * DGAL_EINVAL: as the forward, plus a NULL required output or saved state, an
- * unknown mode, z outputs requested for 2D input. */
+ * unknown mode, z outputs requested for 2D input, saved->tile_rows not 4, 8
+ * or 16. */
 int dgal_iou_backward(dgal_ctx *ctx, int32_t mode, dgal_polys a, dgal_polys b,
                       const int64_t *a_off, const int64_t *b_off,
                       const int64_t *out_off, int32_t nseg, int32_t self_pairs,
@@ -366,23 +381,58 @@ int dgal_set_validate(dgal_ctx *ctx, int32_t enable);
 int dgal_set_path_stats(dgal_ctx *ctx, int32_t enable);
 int dgal_path_stats(dgal_ctx *ctx, int64_t *pairs, int64_t *fp64_pairs, void *stream);
 
-/* Launch-shape autotuning of the batched kernels (the grid of the pair
- * kernels, the persistent grids of the matrix kernels).  While enabled, the
- * first call of dgal_iou_pairs / dgal_iou_matrix / dgal_iou_backward on a new
- * kind of input (entry point, vertex capacity 4 or 8, fixed-size or counted
- * polygons, 2D or 3D, one block or segments) runs each candidate shape on
- * the caller's own buffers (one warm-up and three timed runs, HIP events on
- * the caller's stream) and keeps the fastest in the context for every later
- * call of that kind, enabled or not.  That first call synchronises the stream
- * (so it must not be captured in a graph) and creates two HIP events; its
- * outputs are those of its last run, which every shape computes alike.
- * Disabled by default: built-in shapes.  DGAL_EINVAL: ctx NULL. */
+/* Launch-shape autotuning of the batched kernels: the grid of the pair
+ * kernels; for the matrix forward, the tile shape (4, 8 or 16 rows, unless
+ * saved->tile_rows fixes it) and the persistent grids of its count and exact
+ * passes; the persistent grid of the matrix backward (Sec. II-C: kernels
+ * specialised per size).  Kinds of call are told apart by entry point, vertex
+ * capacity 4 or 8, fixed-size or counted polygons, 2D or 3D, one block or
+ * segments, and a size bucket (the bit lengths of the counts).  A call of a
+ * kind with no choice yet takes the process-wide store's (see
+ * dgal_tune_cache_load), else, while tuning is enabled, times each candidate
+ * on the caller's own buffers (two interleaved passes of one warm-up and
+ * three timed runs, HIP events on the caller's stream, the faster pass
+ * kept), drops any candidate that raises the sticky device error (a tile
+ * table too small for its shape), keeps the fastest (the built-in shape
+ * unless another beats it by more than 2%) in the context and in the store
+ * (and in the DGAL_TUNE_CACHE file, if set), and produces its outputs with
+ * one more run of it; later calls of that kind use the choice, enabled or
+ * not.  That first call synchronises the stream (so it
+ * must not be captured in a graph), creates two HIP events, and is skipped
+ * (built-in shapes) while the device error word holds an earlier call's
+ * error.  Disabled by default: built-in shapes.  DGAL_EINVAL: ctx NULL. */
 int dgal_set_autotune(dgal_ctx *ctx, int32_t enable);
 
-/* Writes one line per tuned kind into buf (NUL-terminated, truncated to
- * size) and returns the number of tuned kinds; DGAL_EINVAL for ctx NULL, a
- * negative size, or buf NULL with size > 0. */
+/* Writes one line per tuned kind of this context into buf ("<key>: grid=..
+ * cull=.. exact=.. bwd=.. rows=..", NUL-terminated, truncated to size) and
+ * returns the number of tuned kinds; DGAL_EINVAL for ctx NULL, a negative
+ * size, or buf NULL with size > 0. */
 int dgal_autotune_report(dgal_ctx *ctx, char *buf, int64_t size);
+
+/* The process-wide store of tuned launch shapes, shared by every context and
+ * keyed by "<gfx arch>/<kind>/K<4|8>/fixed<0|1>/z<0|1>/seg<0|1>/b<bucket>",
+ * and its JSON file:
+ *   {"format": "dgal-tune-cache", "version": 1, "entries": [{"key": "...",
+ *    "grid": G, "cull_mult": C, "exact_mult": E, "bwd_mult": B,
+ *    "tile_rows": R, "ms": T}, ...]}
+ * If DGAL_TUNE_CACHE names a file when the first context is created, it is
+ * loaded then, and rewritten (a temporary file renamed over it) after every
+ * tuning; a file that exists but does not load as a cache is never written.
+ * No GPU is needed for these four calls.
+ * dgal_tune_cache_load merges a file's entries (a file entry replaces one of
+ * the same key) and returns their number; DGAL_EIO if it cannot be read,
+ * DGAL_EINVAL if path is NULL or the file is not a cache or holds a value
+ * outside the launchable ranges (then nothing is merged).
+ * dgal_tune_cache_save writes the store: DGAL_OK, DGAL_EIO, DGAL_EINVAL
+ * (path NULL).  dgal_tune_cache_report writes one line per entry ("<key>
+ * grid=.. cull=.. exact=.. bwd=.. rows=.. ms=..") into buf (NUL-terminated,
+ * truncated to size) and returns the entry count (DGAL_EINVAL: a negative
+ * size, or buf NULL with size > 0).  dgal_tune_cache_clear empties the store
+ * (contexts keep the choices they already made). */
+int dgal_tune_cache_load(const char *path);
+int dgal_tune_cache_save(const char *path);
+int dgal_tune_cache_report(char *buf, int64_t size);
+int dgal_tune_cache_clear(void);
 
 /* Per-kernel timing, a measuring aid (off by default).  While enabled, every
  * kernel the library launches is bracketed by two HIP events on the caller's

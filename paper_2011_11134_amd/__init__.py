@@ -19,11 +19,13 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgal.so")
 
-DGAL_OK, DGAL_EINVAL, DGAL_ECAPACITY, DGAL_EHIP = 0, -1, -2, -3
+DGAL_OK, DGAL_EINVAL, DGAL_ECAPACITY, DGAL_EHIP, DGAL_EIO = 0, -1, -2, -3, -4
 DGAL_PAIRS, DGAL_MATRIX = 0, 1
 MAX_SEGMENTS = 4096
-TILE_ROWS, TILE_COLS = 8, 256
-TILE_MASK_WORDS = TILE_ROWS * TILE_COLS // 64 + 2  # survivor bits, tile origin, row length
+TILE_PAIRS = 2048                 # pairs per matrix tile: rows x (TILE_PAIRS // rows)
+TILE_ROWS_CHOICES = (4, 8, 16)    # tile shapes the matrix forward can use
+TILE_ROWS_DEFAULT = 8
+TILE_MASK_WORDS = TILE_PAIRS // 64 + 2  # survivor bits, tile origin, row length
 
 _vp = ctypes.c_void_p
 
@@ -39,7 +41,7 @@ class Saved(ctypes.Structure):
     _fields_ = [("pair_id", _vp), ("nx", _vp), ("xflags", _vp),
                 ("capacity", ctypes.c_int64), ("count", _vp),
                 ("tile_start", _vp), ("tile_count", _vp), ("tile_capacity", ctypes.c_int64),
-                ("tile_mask", _vp)]
+                ("tile_mask", _vp), ("tile_rows", ctypes.c_int32)]
 
 
 class Boxes(ctypes.Structure):
@@ -54,7 +56,8 @@ EXPORTS = ("dgal_create", "dgal_destroy", "dgal_status_string", "dgal_check",
            "dgal_autotune_report", "dgal_validate", "dgal_set_validate",
            "dgal_iou_simple_pairs", "dgal_iou_simple_backward", "dgal_validate_simple",
            "dgal_set_profiling", "dgal_profile_report", "dgal_set_path_stats",
-           "dgal_path_stats")
+           "dgal_path_stats", "dgal_tune_cache_load", "dgal_tune_cache_save",
+           "dgal_tune_cache_report", "dgal_tune_cache_clear")
 
 
 def _load():
@@ -98,6 +101,14 @@ def _load():
     L.dgal_set_autotune.restype = ctypes.c_int
     L.dgal_autotune_report.argtypes = [_vp, ctypes.c_char_p, i64]
     L.dgal_autotune_report.restype = ctypes.c_int
+    L.dgal_tune_cache_load.argtypes = [ctypes.c_char_p]
+    L.dgal_tune_cache_load.restype = ctypes.c_int
+    L.dgal_tune_cache_save.argtypes = [ctypes.c_char_p]
+    L.dgal_tune_cache_save.restype = ctypes.c_int
+    L.dgal_tune_cache_report.argtypes = [ctypes.c_char_p, i64]
+    L.dgal_tune_cache_report.restype = ctypes.c_int
+    L.dgal_tune_cache_clear.argtypes = []
+    L.dgal_tune_cache_clear.restype = ctypes.c_int
     L.dgal_set_path_stats.argtypes = [_vp, i32]
     L.dgal_set_path_stats.restype = ctypes.c_int
     L.dgal_path_stats.argtypes = [_vp, ctypes.POINTER(i64), ctypes.POINTER(i64), _vp]
@@ -347,7 +358,7 @@ class SavedPairs:
     """Device buffers of a dgal_saved work list (pairs that survived the cull
     of a matrix forward, with their nx / xflags) and its per-tile table."""
 
-    def __init__(self, capacity, cap, tiles, device):
+    def __init__(self, capacity, cap, tiles, device, tile_rows=0):
         self.pair_id = torch.empty(capacity, dtype=torch.int64, device=device)
         self.nx = torch.empty(capacity, dtype=torch.uint8, device=device)
         self.xflags = torch.empty((capacity, cap), dtype=torch.uint8, device=device)
@@ -359,16 +370,21 @@ class SavedPairs:
                                      device=device)
         self.capacity = capacity
         self.tiles = tiles
+        self.tiles_used = 0  # tiles of the last forward (set by iou_matrix)
+        # 0: the forward picks the tile shape (autotuned, else the default)
+        # and records it here for the backward
+        self.tile_rows = tile_rows
 
     def struct(self):
         return Saved(_ptr(self.pair_id), _ptr(self.nx), _ptr(self.xflags), self.capacity,
                      _ptr(self.count), _ptr(self.tile_start), _ptr(self.tile_count), self.tiles,
-                     _ptr(self.tile_mask))
+                     _ptr(self.tile_mask), self.tile_rows)
 
 
 def segments(n_a, n_b, a_off, b_off=None, self_pairs=False, device=None):
     """Device segment table for iou_matrix: (a_off, b_off, out_off, nseg,
-    total output size, tile count).  Build it before a HIP-graph capture and pass it as
+    total output size, tile capacity (the most tiles over the tile shapes),
+    {tile rows: tile count}).  Build it before a HIP-graph capture and pass it as
     `seg=` (the table itself needs host-to-device copies)."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
     return _segments(n_a, n_b, a_off, b_off, self_pairs, dev)
@@ -377,8 +393,9 @@ def segments(n_a, n_b, a_off, b_off=None, self_pairs=False, device=None):
 def _segments(n_a, n_b, a_off, b_off, self_pairs, dev):
     """Device offsets (a_off, b_off, out_off) and total output size."""
     if a_off is None:
-        tiles = (-(-n_a // TILE_ROWS)) * (-(-n_b // TILE_COLS)) if n_a and n_b else 0
-        return None, None, None, 0, n_a * n_b, tiles
+        by = {r: ((-(-n_a // r)) * (-(-n_b // (TILE_PAIRS // r))) if n_a and n_b else 0)
+              for r in TILE_ROWS_CHOICES}
+        return None, None, None, 0, n_a * n_b, max(by.values()), by
     a_off = torch.as_tensor(a_off, dtype=torch.int64)
     b_off = a_off if (self_pairs or b_off is None) else torch.as_tensor(b_off, dtype=torch.int64)
     a_cpu, b_cpu = a_off.cpu(), b_off.cpu()
@@ -390,10 +407,11 @@ def _segments(n_a, n_b, a_off, b_off, self_pairs, dev):
         raise ValueError(f"1..{MAX_SEGMENTS} segments supported, got {nseg}")
     na = a_cpu[1:] - a_cpu[:-1]
     nb = b_cpu[1:] - b_cpu[:-1]
-    tiles = int(torch.where(sizes > 0, ((na + TILE_ROWS - 1) // TILE_ROWS) *
-                            ((nb + TILE_COLS - 1) // TILE_COLS), 0).sum())
+    by = {r: int(torch.where(sizes > 0, ((na + r - 1) // r) *
+                             ((nb + TILE_PAIRS // r - 1) // (TILE_PAIRS // r)), 0).sum())
+          for r in TILE_ROWS_CHOICES}
     return (a_off.to(dev).contiguous(), b_off.to(dev).contiguous(), out_off.to(dev).contiguous(),
-            nseg, total, tiles)
+            nseg, total, max(by.values()), by)
 
 
 def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=None, b_off=None,
@@ -419,7 +437,7 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
     dev = a_xy.device
     if seg is None:
         seg = _segments(a_xy.shape[0], b_xy.shape[0], a_off, b_off, self_pairs, dev)
-    d_a, d_b, d_o, nseg, total, tiles = seg
+    d_a, d_b, d_o, nseg, total, tiles, tiles_by = seg
     iou = torch.empty(total, dtype=torch.float32, device=dev)
     given = saved
     sized = capacity is not None or given is not None
@@ -437,6 +455,8 @@ def iou_matrix(a_xy, b_xy=None, a_nv=None, b_nv=None, a_z=None, b_z=None, a_off=
                                 int(bool(self_pairs)), _ptr(iou), total, ctypes.byref(st),
                                 _stream(a_xy)),
             "dgal_iou_matrix")
+        sv.tile_rows = st.tile_rows  # the shape the forward used, for the backward
+        sv.tiles_used = tiles_by[sv.tile_rows]
         return sv
 
     if check:
@@ -564,6 +584,38 @@ def set_autotune(enable=True, device=None):
     the next call of each kind times its candidate grids once (synchronising)
     and keeps the fastest."""
     _ok(lib.dgal_set_autotune(context(device), int(bool(enable))), "dgal_set_autotune")
+
+
+def tune_cache_load(path):
+    """Merges a tune-cache JSON file into the process-wide store of tuned
+    launch shapes; returns the number of entries read."""
+    n = lib.dgal_tune_cache_load(os.fsencode(path))
+    if n < 0:
+        raise DgalError(n, "dgal_tune_cache_load")
+    return n
+
+
+def tune_cache_save(path):
+    """Writes the process-wide store of tuned launch shapes to a JSON file."""
+    _ok(lib.dgal_tune_cache_save(os.fsencode(path)), "dgal_tune_cache_save")
+
+
+def tune_cache_report():
+    """The store's entries, one line each (key, shape, timed milliseconds)."""
+    need = 1 << 16
+    while True:
+        buf = ctypes.create_string_buffer(need)
+        n = lib.dgal_tune_cache_report(buf, need)
+        if n < 0:
+            raise DgalError(n, "dgal_tune_cache_report")
+        text = buf.value.decode()
+        if text.count("\n") >= n or need >= 1 << 26:
+            return text
+        need *= 4
+
+
+def tune_cache_clear():
+    lib.dgal_tune_cache_clear()
 
 
 def autotune_report(device=None):

@@ -1,6 +1,7 @@
 """Builds the HIP library (gfx950) into paper_2011_11134_amd/libdgal.so.
 
-Every source under csrc/ is compiled with hipcc for gfx950 only.  Packed fp32
+Every source under csrc/ is compiled with hipcc for gfx950 only (tune_cache.cpp
+is host code).  Packed fp32
 instructions are disabled (-packed-fp32-ops) for all device code.
 """
 import os
@@ -13,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgal.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "pairs.hip", "matrix.hip", "prims.hip", "boxes.hip", "validate.hip", "simple.hip"]
+SOURCES = ["api.hip", "pairs.hip", "matrix.hip", "prims.hip", "boxes.hip", "validate.hip", "simple.hip",
+           "tune_cache.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -6,14 +6,26 @@
 
 #include <map>
 #include <new>
-#include <tuple>
+#include <string>
 #include <vector>
 
 #include "internal.hpp"
 
-// A kind of call: (entry point, register capacity K, fixed size, 3D,
-// segmented) -> the launch shape the autotuner chose for it.
-using TuneKey = std::tuple<int, int, int, int, int>;
+// A kind of call the autotuner tells apart: the entry point, register
+// capacity K, fixed size, 3D, segmented (or saving, for the pair forward) and
+// a size bucket (bit lengths of the counts).  Its text form, prefixed with
+// the GPU architecture, keys the process-wide store and the cache file.
+struct TuneKey {
+  int kind, K, fixed, z3, seg;
+  std::string bucket;
+  std::string text(const std::string& arch) const {
+    static const char* names[] = {"pairs_fwd", "pairs_bwd", "matrix_fwd", "matrix_bwd"};
+    char b[160];
+    snprintf(b, sizeof(b), "%s/%s/K%d/fixed%d/z%d/seg%d/b%s", arch.c_str(), names[kind], K, fixed,
+             z3, seg, bucket.c_str());
+    return b;
+  }
+};
 enum { kTunePairsFwd, kTunePairsBwd, kTuneMatrixFwd, kTuneMatrixBwd };
 
 struct dgal_ctx {
@@ -23,7 +35,8 @@ struct dgal_ctx {
   bool validate = false;         // check every input polygon before each call
   int64_t* n_bad = nullptr;      // device counter of the input check
   unsigned long long* stats_dev = nullptr;  // path statistics (2 counters)
-  std::map<TuneKey, dgal::LaunchShape> tuned;
+  std::string arch;              // e.g. "gfx950"
+  std::map<std::string, dgal::LaunchShape> tuned;  // by TuneKey::text
 };
 
 namespace {
@@ -36,42 +49,112 @@ using dgal::valid_polys;
 
 int status_of(hipError_t e) { return e == hipSuccess ? DGAL_OK : DGAL_EHIP; }
 
-// Runs launch(shape) with the shape tuned for `key`; while tuning is enabled
-// and the kind is new, first times every candidate (one warm-up and three
-// timed runs each, HIP events on the caller's stream) and keeps the fastest.
-// The outputs are those of the last run: every shape computes the same values.
-template <class F>
+int bits_of(int64_t v) {
+  int b = 0;
+  while (v > 0) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+std::string bucket_of(int64_t x, int64_t y = -1) {
+  return y < 0 ? std::to_string(bits_of(x)) : std::to_string(bits_of(x)) + "." + std::to_string(bits_of(y));
+}
+
+// Sticky device error word: read (after the stream's work) and cleared.
+int read_err(dgal_ctx* ctx, hipStream_t stream, int* out) {
+  if (hipStreamSynchronize(stream) != hipSuccess ||
+      hipMemcpy(out, ctx->v.err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return DGAL_EHIP;
+  if (*out != 0 && hipMemset(ctx->v.err, 0, sizeof(int)) != hipSuccess) return DGAL_EHIP;
+  return DGAL_OK;
+}
+
+// Runs launch(shape) with the shape tuned for `key`: the context's choice,
+// else the process-wide store's (loaded from the cache file, or tuned by
+// another context), else, while tuning is enabled, the fastest candidate.
+// Every candidate is timed in two interleaved passes (each: one warm-up run,
+// then three runs between HIP events on the caller's stream), keeping its
+// faster pass; a candidate that raises the device error word (a table too
+// small for its tile shape, say) is dropped and the word cleared.  The first
+// candidate is the built-in shape, which another must beat by more than 2%
+// to be chosen (run-to-run noise is about that size).  The choice is kept in
+// the context and the store (and written to the cache file, if one is set),
+// and the call's outputs come from one more run of it.  Tuning is skipped
+// while the error word already holds an error.  `fix` (optional) overrides
+// fields of every shape the call launches.
+template <class F, class G>
 int run_tuned(dgal_ctx* ctx, const TuneKey& key, const std::vector<dgal::LaunchShape>& cands,
-              hipStream_t stream, F launch) {
-  auto it = ctx->tuned.find(key);
-  if (it != ctx->tuned.end()) return launch(it->second);
-  if (!ctx->tune) return launch(dgal::LaunchShape());
+              hipStream_t stream, F launch, G fix) {
+  auto go = [&](dgal::LaunchShape sh) { return launch(fix(sh)); };
+  const std::string text = key.text(ctx->arch);
+  auto it = ctx->tuned.find(text);
+  if (it != ctx->tuned.end()) return go(it->second);
+  dgal::LaunchShape stored;
+  if (dgal::tune_store_get(text, &stored) && dgal::shape_valid(stored)) {
+    ctx->tuned[text] = stored;
+    return go(stored);
+  }
+  if (!ctx->tune) return go(dgal::LaunchShape());
+  int pending = 0;
+  if (int st = read_err(ctx, stream, &pending)) return st;
+  if (pending != 0) {  // an earlier call's error: put it back, tune another time
+    if (hipMemcpy(ctx->v.err, &pending, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+      return DGAL_EHIP;
+    return go(dgal::LaunchShape());
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
     return DGAL_EHIP;
   }
-  int best = -1, st = DGAL_OK;
-  float best_ms = 0.f;
-  for (size_t c = 0; c < cands.size() && st == DGAL_OK; ++c) {
-    st = launch(cands[c]);
-    if (st != DGAL_OK) break;
-    if (hipEventRecord(e0, stream) != hipSuccess) st = DGAL_EHIP;
-    for (int r = 0; r < 3 && st == DGAL_OK; ++r) st = launch(cands[c]);
-    float ms = 0.f;
-    if (st == DGAL_OK && (hipEventRecord(e1, stream) != hipSuccess ||
-                          hipEventSynchronize(e1) != hipSuccess ||
-                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-      st = DGAL_EHIP;
-    if (st == DGAL_OK && (best < 0 || ms < best_ms)) {
-      best = (int)c;
-      best_ms = ms;
+  int st = DGAL_OK;
+  std::vector<float> best_of(cands.size(), -1.f);  // < 0: failed or not timed
+  std::vector<char> failed(cands.size(), 0);
+  for (int pass = 0; pass < 2 && st == DGAL_OK; ++pass) {
+    for (size_t c = 0; c < cands.size() && st == DGAL_OK; ++c) {
+      if (failed[c]) continue;
+      st = go(cands[c]);
+      if (st != DGAL_OK) break;
+      if (hipEventRecord(e0, stream) != hipSuccess) st = DGAL_EHIP;
+      for (int r = 0; r < 3 && st == DGAL_OK; ++r) st = go(cands[c]);
+      float ms = 0.f;
+      if (st == DGAL_OK && (hipEventRecord(e1, stream) != hipSuccess ||
+                            hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = DGAL_EHIP;
+      int err = 0;
+      if (st == DGAL_OK) st = read_err(ctx, stream, &err);
+      if (st != DGAL_OK) break;
+      if (err != 0) {
+        failed[c] = 1;
+        best_of[c] = -1.f;
+      } else if (best_of[c] < 0.f || ms < best_of[c]) {
+        best_of[c] = ms;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st == DGAL_OK && best >= 0) ctx->tuned[key] = cands[best];
-  return st;
+  if (st != DGAL_OK) return st;
+  int best = -1;
+  for (size_t c = 0; c < cands.size(); ++c)
+    if (best_of[c] >= 0.f && (best < 0 || best_of[c] < best_of[best])) best = (int)c;
+  if (best < 0) return go(dgal::LaunchShape());  // every candidate failed: its error stands
+  if (best != 0 && best_of[0] >= 0.f && best_of[best] > 0.98f * best_of[0]) best = 0;
+  const float best_ms = best_of[best];
+  const dgal::LaunchShape chosen = fix(cands[best]);
+  ctx->tuned[text] = chosen;
+  dgal::tune_store_put(text, chosen, best_ms / 3.0);
+  if (const char* path = dgal::tune_cache_path()) (void)dgal::tune_store_save(path);
+  return go(chosen);
+}
+
+template <class F>
+int run_tuned(dgal_ctx* ctx, const TuneKey& key, const std::vector<dgal::LaunchShape>& cands,
+              hipStream_t stream, F launch) {
+  return run_tuned(ctx, key, cands, stream, launch, [](dgal::LaunchShape sh) { return sh; });
 }
 
 std::vector<dgal::LaunchShape> pair_grids(int cus) {
@@ -84,26 +167,44 @@ std::vector<dgal::LaunchShape> pair_grids(int cus) {
   return v;
 }
 
-std::vector<dgal::LaunchShape> matrix_fwd_shapes() {
+// Tile rows (unless the caller fixed them) x persistent grids of the count
+// and exact passes.
+std::vector<dgal::LaunchShape> matrix_fwd_shapes(int fixed_rows) {
   std::vector<dgal::LaunchShape> v;
-  for (int c : {8, 16, 32})
-    for (int e : {4, 8, 16}) {
-      dgal::LaunchShape s;
-      s.cull_mult = c;
-      s.exact_mult = e;
-      v.push_back(s);
-    }
+  for (int r : {8, 4, 16}) {  // the built-in shape (8, 16, 8) first
+    if (fixed_rows != 0 && r != fixed_rows) continue;
+    for (int c : {16, 8, 32})
+      for (int e : {8, 4, 16}) {
+        dgal::LaunchShape s;
+        s.tile_rows = r;
+        s.cull_mult = c;
+        s.exact_mult = e;
+        v.push_back(s);
+      }
+  }
   return v;
 }
 
 std::vector<dgal::LaunchShape> matrix_bwd_shapes() {
   std::vector<dgal::LaunchShape> v;
-  for (int b : {4, 8, 16}) {
+  for (int b : {8, 4, 16}) {  // the built-in multiplier first
     dgal::LaunchShape s;
     s.bwd_mult = b;
     v.push_back(s);
   }
   return v;
+}
+
+TuneKey matrix_key(int kind, const dgal_polys& a, const dgal_polys& b, const int64_t* a_off,
+                   int nseg) {
+  TuneKey k;
+  k.kind = kind;
+  k.K = reg_k(a.kmax, b.kmax);
+  k.fixed = a.nv == nullptr && b.nv == nullptr;
+  k.z3 = a.zlo != nullptr;
+  k.seg = a_off != nullptr;
+  k.bucket = bucket_of(a.count, a_off != nullptr ? (int64_t)nseg : b.count);
+  return k;
 }
 
 // With input checking on (dgal_set_validate, or DGAL_DEBUG_VALIDATE=1 in the
@@ -187,6 +288,14 @@ int dgal_create(dgal_ctx** out, int hip_device) {
   }
   const char* dbg = getenv("DGAL_DEBUG_VALIDATE");
   c->validate = dbg != nullptr && strcmp(dbg, "1") == 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
+    c->arch.assign(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+    const size_t colon = c->arch.find(':');  // "gfx950:sramecc+:xnack-" -> "gfx950"
+    if (colon != std::string::npos) c->arch.resize(colon);
+  }
+  if (c->arch.empty()) c->arch = "unknown";
+  (void)dgal::tune_cache_path();  // DGAL_TUNE_CACHE: loaded once per process
   *out = c;
   return DGAL_OK;
 }
@@ -210,6 +319,7 @@ const char* dgal_status_string(int status) {
     case DGAL_EINVAL: return "DGAL_EINVAL: invalid argument";
     case DGAL_ECAPACITY: return "DGAL_ECAPACITY: capacity exceeded";
     case DGAL_EHIP: return "DGAL_EHIP: HIP runtime error";
+    case DGAL_EIO: return "DGAL_EIO: file could not be read or written";
     default: return "unknown dgal status";
   }
 }
@@ -257,7 +367,8 @@ int dgal_iou_pairs(dgal_ctx* ctx, dgal_polys a, dgal_polys b, float* iou, uint8_
                      args.a.vec4 && args.b.vec4 && (nx == nullptr || args.flags_vec);
   const bool z3 = a.zlo != nullptr, save = nx != nullptr;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return run_tuned(ctx, TuneKey(kTunePairsFwd, K, fixed, z3, save), pair_grids(ctx->v.cus), s,
+  const TuneKey key{kTunePairsFwd, K, fixed, z3, save, bucket_of(a.count)};
+  return run_tuned(ctx, key, pair_grids(ctx->v.cus), s,
                    [&](const dgal::LaunchShape& sh) {
                      dgal::prof_begin(ctx->v.prof, s);
                      const hipError_t e = dgal::launch_pairs_fwd(args, K, fixed, z3, save, s, sh);
@@ -313,7 +424,8 @@ int dgal_iou_backward(dgal_ctx* ctx, int32_t mode, dgal_polys a, dgal_polys b,
     const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
                        args.a.vec4 && args.b.vec4 && args.flags_vec;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run_tuned(ctx, TuneKey(kTunePairsBwd, K, fixed, z3, 0), pair_grids(ctx->v.cus), s,
+    const TuneKey key{kTunePairsBwd, K, fixed, z3, 0, bucket_of(a.count)};
+    return run_tuned(ctx, key, pair_grids(ctx->v.cus), s,
                      [&](const dgal::LaunchShape& sh) {
                        dgal::prof_begin(ctx->v.prof, s);
                        const hipError_t e = dgal::launch_pairs_bwd(args, K, fixed, z3, s, sh);
@@ -323,8 +435,7 @@ int dgal_iou_backward(dgal_ctx* ctx, int32_t mode, dgal_polys a, dgal_polys b,
   }
   if (mode == DGAL_MATRIX) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const TuneKey key(kTuneMatrixBwd, reg_k(a.kmax, b.kmax), a.nv == nullptr && b.nv == nullptr,
-                      z3, a_off != nullptr);
+    const TuneKey key = matrix_key(kTuneMatrixBwd, a, b, a_off, nseg);
     return run_tuned(ctx, key, matrix_bwd_shapes(), s, [&](const dgal::LaunchShape& sh) {
       return dgal::matrix_backward(ctx->v, a, b, a_off, b_off, out_off, nseg, self_pairs,
                                    grad_iou, out_size, saved, grad_a_xy, grad_b_xy, grad_a_z,
@@ -336,17 +447,25 @@ int dgal_iou_backward(dgal_ctx* ctx, int32_t mode, dgal_polys a, dgal_polys b,
 
 int dgal_iou_matrix(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
                     const int64_t* b_off, const int64_t* out_off, int32_t nseg,
-                    int32_t self_pairs, float* iou, int64_t out_size, const dgal_saved* saved,
+                    int32_t self_pairs, float* iou, int64_t out_size, dgal_saved* saved,
                     void* stream) {
-  if (ctx == nullptr) return DGAL_EINVAL;
+  if (ctx == nullptr || saved == nullptr) return DGAL_EINVAL;
+  // the caller's tile rows, if fixed, hold for every shape the call launches
+  const int rows = saved->tile_rows;
+  if (rows != 0 && rows != 4 && rows != 8 && rows != 16) return DGAL_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (int st = debug_validate(ctx, s, a, dgal::same_polys(a, b) ? nullptr : &b)) return st;
-  const TuneKey key(kTuneMatrixFwd, reg_k(a.kmax, b.kmax), a.nv == nullptr && b.nv == nullptr,
-                    a.zlo != nullptr, a_off != nullptr);
-  return run_tuned(ctx, key, matrix_fwd_shapes(), s, [&](const dgal::LaunchShape& sh) {
-    return dgal::matrix_forward(ctx->v, a, b, a_off, b_off, out_off, nseg, self_pairs, iou,
-                                out_size, saved, s, sh);
-  });
+  const TuneKey key = matrix_key(kTuneMatrixFwd, a, b, a_off, nseg);
+  return run_tuned(
+      ctx, key, matrix_fwd_shapes(rows), s,
+      [&](const dgal::LaunchShape& sh) {
+        return dgal::matrix_forward(ctx->v, a, b, a_off, b_off, out_off, nseg, self_pairs, iou,
+                                    out_size, saved, s, sh);
+      },
+      [&](dgal::LaunchShape sh) {
+        sh.tile_rows = rows != 0 ? rows : (sh.tile_rows != 0 ? sh.tile_rows : DGAL_TILE_ROWS_DEFAULT);
+        return sh;
+      });
 }
 
 int dgal_iou_matrix_noalloc(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
@@ -355,12 +474,14 @@ int dgal_iou_matrix_noalloc(dgal_ctx* ctx, dgal_polys a, dgal_polys b, const int
   if (ctx == nullptr) return DGAL_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (int st = debug_validate(ctx, s, a, dgal::same_polys(a, b) ? nullptr : &b)) return st;
-  // a shape the autotuner already chose for dgal_iou_matrix is reused; nothing
-  // is tuned here (tuning allocates events and records its choice)
-  const TuneKey key(kTuneMatrixFwd, reg_k(a.kmax, b.kmax), a.nv == nullptr && b.nv == nullptr,
-                    a.zlo != nullptr, a_off != nullptr);
+  // a shape the autotuner already chose for dgal_iou_matrix (in this context,
+  // or in the process-wide store) is reused; nothing is tuned here (tuning
+  // allocates events and records its choice)
+  const std::string key = matrix_key(kTuneMatrixFwd, a, b, a_off, nseg).text(ctx->arch);
+  dgal::LaunchShape shape;
   const auto it = ctx->tuned.find(key);
-  const dgal::LaunchShape shape = it != ctx->tuned.end() ? it->second : dgal::LaunchShape();
+  if (it != ctx->tuned.end()) shape = it->second;
+  else if (!dgal::tune_store_get(key, &shape) || !dgal::shape_valid(shape)) shape = dgal::LaunchShape();
   return dgal::matrix_forward_noalloc(ctx->v, a, b, a_off, b_off, out_off, nseg, self_pairs, iou,
                                       out_size, s, shape);
 }
@@ -641,24 +762,40 @@ int dgal_profile_report(dgal_ctx* ctx, char* buf, int64_t size) {
 
 int dgal_autotune_report(dgal_ctx* ctx, char* buf, int64_t size) {
   if (ctx == nullptr || (buf == nullptr && size > 0) || size < 0) return DGAL_EINVAL;
-  static const char* names[] = {"pairs_fwd", "pairs_bwd", "matrix_fwd", "matrix_bwd"};
   int64_t used = 0;
   if (size > 0) buf[0] = '\0';
   for (const auto& kv : ctx->tuned) {
-    const TuneKey& k = kv.first;
     const dgal::LaunchShape& sh = kv.second;
-    char line[160];
-    const int n = snprintf(line, sizeof(line),
-                           "%s K=%d fixed=%d z3=%d seg/save=%d: grid=%lld cull=%d exact=%d bwd=%d\n",
-                           names[std::get<0>(k)], std::get<1>(k), std::get<2>(k), std::get<3>(k),
-                           std::get<4>(k), (long long)sh.grid, sh.cull_mult, sh.exact_mult,
-                           sh.bwd_mult);
+    char line[320];
+    const int n = snprintf(line, sizeof(line), "%s: grid=%lld cull=%d exact=%d bwd=%d rows=%d\n",
+                           kv.first.c_str(), (long long)sh.grid, sh.cull_mult, sh.exact_mult,
+                           sh.bwd_mult, sh.tile_rows);
     if (n > 0 && used + n < size) {
       memcpy(buf + used, line, (size_t)n + 1);
       used += n;
     }
   }
   return (int)ctx->tuned.size();
+}
+
+int dgal_tune_cache_load(const char* path) {
+  if (path == nullptr || path[0] == '\0') return DGAL_EINVAL;
+  return dgal::tune_store_load(path);
+}
+
+int dgal_tune_cache_save(const char* path) {
+  if (path == nullptr || path[0] == '\0') return DGAL_EINVAL;
+  return dgal::tune_store_save(path);
+}
+
+int dgal_tune_cache_report(char* buf, int64_t size) {
+  if ((buf == nullptr && size > 0) || size < 0) return DGAL_EINVAL;
+  return dgal::tune_store_report(buf, size);
+}
+
+int dgal_tune_cache_clear(void) {
+  dgal::tune_store_clear();
+  return DGAL_OK;
 }
 
 int dgal_iou_boxes(dgal_ctx* ctx, dgal_boxes a, dgal_boxes b, float* iou, uint8_t* nx,

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/dgal.h"
+#include "tune_cache.hpp"
 
 namespace dgal {
 
@@ -109,14 +110,6 @@ struct SimpleBwdArgs {
   float* gb_xy;
 };
 
-// Grid shapes of one call, chosen by the autotuner (0 = built-in default).
-// grid: workgroups of a grid-stride elementwise kernel (0 => one lane per
-// item); the matrix multipliers scale the persistent grids by the CU count.
-struct LaunchShape {
-  int64_t grid = 0;
-  int cull_mult = 0, exact_mult = 0, bwd_mult = 0;
-};
-
 // Per-kernel timing of a context (dgal_set_profiling): each launch is
 // bracketed by two events on its stream and waited for, and its duration is
 // added to its kernel's total.  Names are string literals.
@@ -217,7 +210,7 @@ struct DeviceGuard {
 
 int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
                    const int64_t* b_off, const int64_t* out_off, int nseg, int self_pairs,
-                   float* iou, int64_t out_size, const dgal_saved* saved, hipStream_t stream,
+                   float* iou, int64_t out_size, dgal_saved* saved, hipStream_t stream,
                    const LaunchShape& shape = LaunchShape());
 int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
                     const int64_t* b_off, const int64_t* out_off, int nseg, int self_pairs,

@@ -4,8 +4,10 @@
 //
 // The forward is split by register pressure into lean cull kernels and one
 // dense exact kernel, with no shared counter anywhere:
-//   k_matrix_cull -- one wavefront per tile of kTileRows rows x kTileCols
-//     columns of one segment.  The rows' axis-aligned bounds (and z-extents)
+//   k_matrix_cull -- one wavefront per tile of R rows x 2048 / R columns of
+//     one segment (R = 4, 8 or 16, chosen per call: the autotuner weighs
+//     longer contiguous output rows against more column-bound loads per
+//     pair).  The rows' axis-aligned bounds (and z-extents)
 //     sit in scalar registers; each lane bounds its column boxes 64 at a
 //     time, tests them against the rows, writes every pair's initial value
 //     (0, or the self diagonal's 1) straight to the output row segments
@@ -20,7 +22,8 @@
 // A persistent grid walks the tiles of all segments (a prefix sum of tiles per
 // segment computed on the device by k_seg_prep, so everything is
 // graph-capturable).  The backward (k_matrix_bwd) gives one wavefront a row
-// group: its tiles' entries are one contiguous range of the work list; the row
+// group of 8 rows, whatever the tile shape: the entries of the tile rows
+// that cover it are one contiguous range of the work list; the row
 // gradients are summed in LDS and every row is written once.  Self pairs need
 // nothing else: entries (i, k) and (k, i) are one unordered pair evaluated with
 // the lower index first, so the row role of either entry is that pair's
@@ -36,13 +39,18 @@
 
 namespace dgal {
 
-constexpr int kTileRows = DGAL_TILE_ROWS;
-constexpr int kTileCols = DGAL_TILE_COLS;
+constexpr int kTilePairs = DGAL_TILE_PAIRS;
+constexpr int kGroupRows = 8;     // rows of a backward row group
 constexpr int kCullBlock = 256;   // four independent wavefronts
 constexpr int kScanBlock = 1024;
 constexpr int kExactBlock = 256;
 constexpr int kMaxSeg = DGAL_MAX_SEGMENTS;
-static_assert(kTileCols == 256, "four 64-column chunks per tile");
+static_assert(kTilePairs == 2048, "32 words of survivor bits per tile");
+
+// log2 of a supported tile row count (4, 8, 16), or -1.
+inline int tile_rows_log2(int rows) {
+  return rows == 4 ? 2 : (rows == 8 ? 3 : (rows == 16 ? 4 : -1));
+}
 
 struct Segment {
   int64_t a0, b0, na, nb, out0;
@@ -58,6 +66,7 @@ struct SegArgs {
   int self_pairs;
   const int64_t* tile_prefix;   // [nseg+1] (segmented), from k_seg_prep
   const int64_t* group_prefix;  // [nseg+1] row groups (segmented), from k_seg_prep
+  int rows_log2;                // tiles of 2^rows_log2 rows x 2^(11 - rows_log2) columns
 };
 
 __device__ __forceinline__ Segment load_segment(const SegArgs& a, int s) {
@@ -89,11 +98,16 @@ __device__ __forceinline__ Segment load_segment(const SegArgs& a, int s) {
   return g;
 }
 
+// Backward row groups, tile rows and tile columns of a segment.
 __device__ __forceinline__ int64_t groups_of(const Segment& g) {
-  return (g.na > 0 && g.nb > 0) ? (g.na + kTileRows - 1) / kTileRows : 0;
+  return (g.na > 0 && g.nb > 0) ? (g.na + kGroupRows - 1) / kGroupRows : 0;
 }
-__device__ __forceinline__ int64_t col_tiles_of(const Segment& g) {
-  return (g.nb + kTileCols - 1) / kTileCols;
+__device__ __forceinline__ int64_t tile_rows_of(const Segment& g, int rl) {
+  return (g.na > 0 && g.nb > 0) ? (g.na + (1 << rl) - 1) >> rl : 0;
+}
+__device__ __forceinline__ int64_t col_tiles_of(const Segment& g, int rl) {
+  const int cl = 11 - rl;
+  return (g.nb + (1 << cl) - 1) >> cl;
 }
 
 // Tile and row-group prefixes over segments (one workgroup).  Rejected
@@ -112,7 +126,7 @@ __global__ __launch_bounds__(256) void k_seg_prep(SegArgs a, int* err, int64_t* 
       continue;
     }
     sg += groups_of(g);
-    st += groups_of(g) * col_tiles_of(g);
+    st += tile_rows_of(g, a.rows_log2) * col_tiles_of(g, a.rows_log2);
   }
   part_t[tid] = st;
   part_g[tid] = sg;
@@ -134,7 +148,7 @@ __global__ __launch_bounds__(256) void k_seg_prep(SegArgs a, int* err, int64_t* 
     const Segment g = load_segment(a, s);
     if (g.ok) {
       rg += groups_of(g);
-      rt += groups_of(g) * col_tiles_of(g);
+      rt += tile_rows_of(g, a.rows_log2) * col_tiles_of(g, a.rows_log2);
     }
     tile_prefix[s + 1] = rt;
     group_prefix[s + 1] = rg;
@@ -201,7 +215,7 @@ struct CullArgs {
   int* err;
 };
 
-constexpr int kBitWords = kTileRows * (kTileCols / 64);  // survivor bits of a tile
+constexpr int kBitWords = kTilePairs / 64;  // survivor bits of a tile
 constexpr int kMaskWords = DGAL_TILE_MASK_WORDS;            // + tile origin + row length
 static_assert(kMaskWords == kBitWords + 2 && kMaskWords <= 64, "mask words");
 
@@ -231,10 +245,12 @@ __device__ __forceinline__ Segment tile_segment(const SegArgs& a, int s) {
 __device__ __forceinline__ uint32_t gap_bits(float hi, float lo) {
   return __float_as_uint(hi - lo);
 }
+
 template <int N, class F, int... I>
 __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
   (f(std::integral_constant<int, I>()), ...);
 }
+// f(0), f(1), ..., f(N - 1) with compile-time arguments.
 template <int N, class F>
 __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl<N>(f, std::make_integer_sequence<int, N>());
@@ -243,6 +259,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 // v_writelane: `val` (wave-uniform) into lane L (a constant) of `old`.
 template <int L>
 __device__ __forceinline__ uint32_t write_lane(uint32_t old, uint32_t val) {
+  static_assert(L >= 0 && L < 64, "lane");
   asm("v_writelane_b32 %0, %1, %2" : "+v"(old) : "s"(val), "n"(L));
   return old;
 }
@@ -258,7 +275,10 @@ __device__ __forceinline__ float below(float v) {
 // Walks a contiguous range of tiles: the segment is searched once, then
 // followed tile by tile (row-major within a segment, segments in order), so
 // that a tile costs no search and no division.
+template <int R>
 struct TileCursor {
+  static constexpr int C = kTilePairs / R;
+  static constexpr int RL = R == 4 ? 2 : (R == 8 ? 3 : 4);
   int s;
   int64_t seg_end;  // first tile past segment s
   Segment g;
@@ -266,7 +286,7 @@ struct TileCursor {
 
   __device__ void load(const SegArgs& seg, bool segmented) {
     g = tile_segment(seg, s);
-    nct = col_tiles_of(g);
+    nct = col_tiles_of(g, RL);
     seg_end = segmented ? seg.tile_prefix[s + 1] : (int64_t)0x7fffffffffffffff;
   }
   __device__ void seek(const SegArgs& seg, bool segmented, int64_t u) {
@@ -293,8 +313,8 @@ struct TileCursor {
       }
     }
   }
-  __device__ int64_t r0() const { return tr * kTileRows; }
-  __device__ int64_t cb() const { return tc * kTileCols; }
+  __device__ int64_t r0() const { return tr * R; }
+  __device__ int64_t cb() const { return tc * C; }
 };
 
 // The contiguous range of tiles of wavefront `wid` out of `nw`.
@@ -316,9 +336,11 @@ __device__ __forceinline__ void wave_tiles(int64_t total, int64_t wid, int64_t n
 // with overlapping open z extents (a closed test against upper ends lowered
 // by one ulp) survive; invalid columns and rows, and empty z extents, carry
 // x1 = -inf.
-template <int K, bool FIXED, bool Z3>
+template <int K, bool FIXED, bool Z3, int R>
 __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
   constexpr int WAVES = kCullBlock / 64;
+  constexpr int C = kTilePairs / R;
+  static_assert(R == 4 || R == 8 || R == 16, "tile rows");
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool segmented = m.seg.a_off != nullptr;
@@ -326,13 +348,13 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
 
   int64_t u0, u1;
   wave_tiles(total, (int64_t)blockIdx.x * WAVES + wave, (int64_t)gridDim.x * WAVES, u0, u1);
-  TileCursor cur;
+  TileCursor<R> cur;
   if (u0 < u1) cur.seek(m.seg, segmented, u0);
   for (int64_t u = u0; u < u1; cur.next(m.seg, segmented, u), ++u) {
     const Segment& g = cur.g;
     const int64_t r0 = cur.r0(), cb = cur.cb();
-    const int nr = (int)min((int64_t)kTileRows, g.na - r0);
-    const int64_t ce = min(g.nb, cb + kTileCols);
+    const int nr = (int)min((int64_t)R, g.na - r0);
+    const int64_t ce = min(g.nb, cb + C);
     float* out_rows = m.iou + g.out0 + r0 * g.nb;
 
     // row bounds: lane j < nr bounds row j, then every lane holds all of them
@@ -340,9 +362,9 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
     if (lane < nr) rl = box_bounds<K, FIXED, Z3>(m.a, g.a0 + r0 + lane);
     if (lane >= nr || (Z3 && !(rl.hi > rl.lo))) rl.x1 = -__builtin_inff();
     if (Z3) rl.hi = below(rl.hi);
-    Bounds rb[kTileRows];
+    Bounds rb[R];
 #pragma unroll
-    for (int j = 0; j < kTileRows; ++j) {
+    for (int j = 0; j < R; ++j) {
       rb[j].x0 = lane_bcast(rl.x0, j);
       rb[j].y0 = lane_bcast(rl.y0, j);
       rb[j].x1 = lane_bcast(rl.x1, j);
@@ -350,15 +372,15 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
       rb[j].lo = lane_bcast(rl.lo, j);
       rb[j].hi = lane_bcast(rl.hi, j);
     }
-    uint32_t n = 0;         // survivors so far (uniform; at most kTileRows * kTileCols)
+    uint32_t n = 0;         // survivors so far (uniform; at most kTilePairs)
     uint32_t mlo = 0u, mhi = 0u;  // lane w < kBitWords: mask word w of the tile
     // the next 64 column boxes are loaded while the current ones are tested
     Bounds nxt = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
     if (cb + lane < ce) nxt = box_bounds<K, FIXED, Z3>(m.b, g.b0 + cb + lane);
-#pragma unroll
-    for (int ci = 0; ci < kTileCols / 64; ++ci) {
+    static_for<C / 64>([&](auto cic) {
+      constexpr int ci = decltype(cic)::value;
       const int64_t c0 = cb + ci * 64;
-      if (c0 >= ce) break;
+      if (c0 >= ce) return;  // uniform; so are the later chunks
       const bool valid = c0 + lane < ce;
       Bounds cbx = nxt;
       if (c0 + 64 + lane < ce) nxt = box_bounds<K, FIXED, Z3>(m.b, g.b0 + c0 + 64 + lane);
@@ -366,10 +388,10 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
       if (Z3) cbx.hi = below(cbx.hi);
       // the self diagonal crosses this chunk at lane r0 + j - c0
       const int64_t dd = r0 - c0;
-      const bool dchunk = m.seg.self_pairs && dd > -kTileRows && dd < 64;
-      uint64_t mk[kTileRows];
+      const bool dchunk = m.seg.self_pairs && dd > -R && dd < 64;
+      uint64_t mk[R];
 #pragma unroll
-      for (int j = 0; j < kTileRows; ++j) {
+      for (int j = 0; j < R; ++j) {
         uint32_t bits = gap_bits(rb[j].x1, cbx.x0) | gap_bits(cbx.x1, rb[j].x0) |
                         gap_bits(rb[j].y1, cbx.y0) | gap_bits(cbx.y1, rb[j].y0);
         if (Z3) bits |= gap_bits(rb[j].hi, cbx.lo) | gap_bits(cbx.hi, rb[j].lo);
@@ -378,33 +400,26 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
       if (dchunk) {  // rare: the chunk holds part of the diagonal
         const int d = (int)dd;
 #pragma unroll
-        for (int j = 0; j < kTileRows; ++j)
+        for (int j = 0; j < R; ++j)
           if (d + j >= 0 && d + j < 64) mk[j] &= ~(1ull << (d + j));
       }
-      // word ci * kTileRows + j of the tile goes to that lane
-      auto put = [&](auto jc) {
-        constexpr int J = decltype(jc)::value;
-        mlo = write_lane<J>(mlo, (uint32_t)mk[J % kTileRows]);
-        mhi = write_lane<J>(mhi, (uint32_t)(mk[J % kTileRows] >> 32));
-        n += (uint32_t)__popcll(mk[J % kTileRows]);
-      };
-      static_for<kTileRows>([&](auto j) {
-        constexpr int J = decltype(j)::value;
-        if (ci == 0) put(std::integral_constant<int, 0 * kTileRows + J>());
-        if (ci == 1) put(std::integral_constant<int, 1 * kTileRows + J>());
-        if (ci == 2) put(std::integral_constant<int, 2 * kTileRows + J>());
-        if (ci == 3) put(std::integral_constant<int, 3 * kTileRows + J>());
+      // word ci * R + j of the tile goes to that lane
+      static_for<R>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        mlo = write_lane<ci * R + j>(mlo, (uint32_t)mk[j]);
+        mhi = write_lane<ci * R + j>(mhi, (uint32_t)(mk[j] >> 32));
+        n += (uint32_t)__popcll(mk[j]);
       });
-    }
+    });
     // the tile's output rows, each one contiguous run of up to 256 values (0,
     // or 1 where a self block's diagonal crosses); the exact kernel later
     // overwrites the survivors
     const int64_t dg = m.seg.self_pairs ? r0 - cb : INT64_MIN / 2;  // diagonal column of row 0
     for (int j = 0; j < nr; ++j) {
       float* row = out_rows + (int64_t)j * g.nb + cb;
-      const bool drow = dg + j >= 0 && dg + j < kTileCols;  // uniform
+      const bool drow = dg + j >= 0 && dg + j < C;  // uniform
 #pragma unroll
-      for (int ci = 0; ci < kTileCols / 64; ++ci) {
+      for (int ci = 0; ci < C / 64; ++ci) {
         const int col = ci * 64 + lane;
         if (cb + col < ce) row[col] = (drow && col == dg + j) ? 1.f : 0.f;
       }
@@ -468,7 +483,8 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_fill(CullArgs m) {
       if (lane >= d) incl += o;
     }
     int64_t slot = start + (incl - cnt);
-    const int j = lane % kTileRows, c = lane / kTileRows;
+    const int rl = m.seg.rows_log2;
+    const int j = lane & ((1 << rl) - 1), c = lane >> rl;
     const int64_t first = origin + (int64_t)j * nb + c * 64;
     uint64_t w = bits;
     while (w != 0ull) {
@@ -720,7 +736,7 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
   // up to 64 lanes adding into the same 8 rows' words (serialised LDS
   // atomics); four copies cut that by four and are summed at the end.
   constexpr int COPIES = 4;
-  constexpr int ACC = kTileRows * ROW;
+  constexpr int ACC = kGroupRows * ROW;
   __shared__ float s_acc[WAVES][COPIES * ACC];
   __shared__ float2 s_v[CAP * BLOCK];
   __shared__ float2 s_g[CAP * BLOCK];
@@ -758,14 +774,18 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
     const int64_t tr = segmented ? u - m.seg.group_prefix[s] : u;  // row group in the segment
     const Segment g = load_segment(m.seg, s);
     if (!g.ok) continue;
-    const int64_t r0 = tr * kTileRows;
-    const int nr = (int)min((int64_t)kTileRows, g.na - r0);
-    const int64_t nct = col_tiles_of(g);
-    const int64_t t0 = (segmented ? m.seg.tile_prefix[s] : 0) + tr * nct;
+    const int64_t r0 = tr * kGroupRows;
+    const int nr = (int)min((int64_t)kGroupRows, g.na - r0);
+    // the tile rows that cover the group (several when tiles are shorter
+    // than the group, part of one when taller: entries of its other rows are
+    // skipped below); their tiles are consecutive, so are their entries
+    const int rlog = m.seg.rows_log2;
+    const int64_t nct = col_tiles_of(g, rlog);
+    const int64_t tbase = segmented ? m.seg.tile_prefix[s] : 0;
+    const int64_t t0 = tbase + (r0 >> rlog) * nct;
+    const int64_t t1 = tbase + (((r0 + nr - 1) >> rlog) + 1) * nct - 1;
     for (int i = lane; i < COPIES * ACC; i += 64) acc_w[i] = 0.f;
     wave_sync();
-    // the row group's tiles are consecutive, so are their entries
-    const int64_t t1 = t0 + nct - 1;
     const bool have = t1 < m.tile_capacity;
     const int64_t e_begin = have ? m.tile_start[t0] : 0;
     const int64_t e_end = have ? m.tile_start[t1] + m.tile_count[t1] : 0;
@@ -942,6 +962,7 @@ int check_shapes(dgal_polys a, dgal_polys b, const int64_t* a_off, const int64_t
   sa.self_pairs = self_pairs;
   sa.tile_prefix = nullptr;
   sa.group_prefix = nullptr;
+  sa.rows_log2 = 3;
   return DGAL_OK;
 }
 
@@ -951,12 +972,18 @@ int64_t ceil_div(int64_t x, int64_t y) { return (x + y - 1) / y; }
 
 int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t* a_off,
                    const int64_t* b_off, const int64_t* out_off, int nseg, int self_pairs,
-                   float* iou, int64_t out_size, const dgal_saved* saved, hipStream_t stream,
+                   float* iou, int64_t out_size, dgal_saved* saved, hipStream_t stream,
                    const LaunchShape& shape) {
   SegArgs sa;
   const int st = check_shapes(a, b, a_off, b_off, out_off, nseg, self_pairs, out_size, saved, sa);
   if (st != DGAL_OK) return st;
   if (out_size > 0 && iou == nullptr) return DGAL_EINVAL;
+  // the tile shape: the launch shape's, else the caller's, else the default
+  const int R = shape.tile_rows > 0 ? shape.tile_rows
+                : (saved->tile_rows > 0 ? saved->tile_rows : DGAL_TILE_ROWS_DEFAULT);
+  sa.rows_log2 = tile_rows_log2(R);
+  if (sa.rows_log2 < 0) return DGAL_EINVAL;
+  saved->tile_rows = R;
   DeviceGuard dg(ctx.device);
   if (!dg.ok) return DGAL_EHIP;
   const int K = reg_k(a.kmax, b.kmax);
@@ -971,7 +998,7 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
     prof_end(ctx.prof, "k_seg_prep", stream);
   } else {
     if (a.count == 0 || b.count == 0) return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
-    single_tiles = ceil_div(a.count, kTileRows) * ceil_div(b.count, kTileCols);
+    single_tiles = ceil_div(a.count, R) * ceil_div(b.count, kTilePairs / R);
   }
   CullArgs c;
   c.seg = sa;
@@ -1008,8 +1035,10 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
     constexpr int KK = decltype(k)::value;
     constexpr bool FX = decltype(fx)::value, ZZ = decltype(z)::value;
     prof_begin(ctx.prof, stream);
-    hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ>), dim3((unsigned)cull_grid),
-                       dim3(kCullBlock), 0, stream, c);
+    const dim3 cg((unsigned)cull_grid), cb(kCullBlock);
+    if (R == 4) hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ, 4>), cg, cb, 0, stream, c);
+    else if (R == 16) hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ, 16>), cg, cb, 0, stream, c);
+    else hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ, 8>), cg, cb, 0, stream, c);
     prof_end(ctx.prof, "k_matrix_cull", stream);
     const int64_t chunks = std::max<int64_t>(1, ceil_div(saved->tile_capacity, kScanChunk));
     prof_begin(ctx.prof, stream);
@@ -1050,6 +1079,8 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
     return DGAL_EINVAL;
   if (z3 != (grad_a_z != nullptr)) return DGAL_EINVAL;
   if (!self_pairs && z3 != (grad_b_z != nullptr)) return DGAL_EINVAL;
+  sa.rows_log2 = tile_rows_log2(saved->tile_rows);  // the shape the forward recorded
+  if (sa.rows_log2 < 0) return DGAL_EINVAL;
   DeviceGuard dg(ctx.device);
   if (!dg.ok) return DGAL_EHIP;
   const int K = reg_k(a.kmax, b.kmax);
@@ -1077,7 +1108,7 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
     prof_end(ctx.prof, "k_seg_prep", stream);
   } else {
     if (a.count == 0 || b.count == 0) return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
-    single_groups = ceil_div(a.count, kTileRows);
+    single_groups = ceil_div(a.count, kGroupRows);
   }
   BwdArgs m;
   m.seg = sa;
@@ -1172,8 +1203,10 @@ int matrix_forward_noalloc(const CtxView& ctx, dgal_polys a, dgal_polys b, const
   if (base_v == nullptr) return DGAL_EHIP;  // the context did not set this device up
   // one block: its tile count is known here, and a block past the scratch's
   // tiles is refused before anything is enqueued
+  const int R = shape.tile_rows > 0 ? shape.tile_rows : DGAL_TILE_ROWS_DEFAULT;
+  if (tile_rows_log2(R) < 0) return DGAL_EINVAL;
   if (a_off == nullptr && a.count > 0 && b.count > 0 &&
-      ceil_div(a.count, kTileRows) > kNaTiles / ceil_div(b.count, kTileCols))
+      ceil_div(a.count, R) > kNaTiles / ceil_div(b.count, kTilePairs / R))
     return DGAL_ECAPACITY;
   unsigned char* base = static_cast<unsigned char*>(base_v);
   dgal_saved sv;
@@ -1186,6 +1219,7 @@ int matrix_forward_noalloc(const CtxView& ctx, dgal_polys a, dgal_polys b, const
   sv.tile_count = reinterpret_cast<int32_t*>(base + kNaTileCount);
   sv.tile_capacity = kNaTiles;
   sv.tile_mask = reinterpret_cast<uint64_t*>(base + kNaTileMask);
+  sv.tile_rows = R;
   CtxView v = ctx;
   v.prefix = reinterpret_cast<int64_t*>(base + kNaPrefix);
   v.scan = reinterpret_cast<int64_t*>(base + kNaScan);

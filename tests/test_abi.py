@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(dgal):
 
 
 def test_status_strings(dgal):
-    for st in (0, -1, -2, -3):
+    for st in (0, -1, -2, -3, -4):
         assert dgal.lib.dgal_status_string(st).startswith(b"DGAL_")
     assert b"unknown" in dgal.lib.dgal_status_string(7)
 

@@ -1,5 +1,8 @@
 """Launch-shape autotuning: tuned calls compute exactly what the built-in
-shapes compute, and every kind of call used is recorded once."""
+shapes compute, every kind of call used is recorded once, and the choices
+persist through the tune cache into a fresh context."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -53,3 +56,54 @@ def test_autotuned_calls_match_builtin_shapes(dg):
     for r, t, a in zip(ref_s, tuned_s, again_s):
         assert np.allclose(r, t, rtol=1e-5, atol=1e-6) and np.allclose(r, a, rtol=1e-5, atol=1e-6)
     dg.check_errors()
+
+
+def test_tuned_shapes_persist_into_a_fresh_context(dg, tmp_path):
+    """A tuned matrix forward (tile shape included) is saved to a cache file,
+    loaded back into the process-wide store, and taken by a context created
+    afterwards without tuning; its outputs equal the built-in shape's."""
+    print("case: tune cache, scenes 5", flush=True)
+    ds = synth.c5_scenes(scenes=5, nmin=40, nmax=900, seed=131)
+    xy = dev_t(ds["a_xy"])
+    z = (dev_t(ds["a_zlo"]), dev_t(ds["a_zhi"]))
+    ref, _, _ = dg.iou_matrix(xy, a_z=z, a_off=ds["off"], self_pairs=True)
+    dg.set_autotune(True)
+    try:
+        tuned, saved, _ = dg.iou_matrix(xy, a_z=z, a_off=ds["off"], self_pairs=True, save=True)
+    finally:
+        dg.set_autotune(False)
+    assert saved.tile_rows in dg.TILE_ROWS_CHOICES
+    assert torch.equal(ref, tuned)
+    _, text = dg.autotune_report()
+    line = [ln for ln in text.splitlines() if "matrix_fwd" in ln and "seg1" in ln
+            and f"/b{len(ds['a_xy']).bit_length()}.{(5).bit_length()}:" in ln]
+    assert len(line) == 1, text
+    assert f"rows={saved.tile_rows}" in line[0]
+    key = line[0].split(":")[0]
+    path = tmp_path / "tune.json"
+    dg.tune_cache_save(str(path))
+    dg.tune_cache_clear()
+    assert dg.tune_cache_load(str(path)) >= 1
+    assert key in dg.tune_cache_report()
+    # a fresh context, tuning off: the forward takes the stored shape
+    ctx = ctypes.c_void_p()
+    assert dg.lib.dgal_create(ctypes.byref(ctx), torch.cuda.current_device()) == dg.DGAL_OK
+    try:
+        pa, _ = dg.polys(xy, None, z)
+        seg = dg.segments(len(ds["a_xy"]), len(ds["a_xy"]), ds["off"], self_pairs=True)
+        sv = dg.SavedPairs(1 << 20, 8, seg[5], xy.device)
+        st = sv.struct()
+        out = torch.full((seg[4],), -1.0, device="cuda")
+        rc = dg.lib.dgal_iou_matrix(ctx, pa, pa, seg[0].data_ptr(), seg[1].data_ptr(),
+                                    seg[2].data_ptr(), seg[3], 1, out.data_ptr(), seg[4],
+                                    ctypes.byref(st), torch.cuda.current_stream().cuda_stream)
+        assert rc == dg.DGAL_OK
+        assert dg.lib.dgal_check(ctx, torch.cuda.current_stream().cuda_stream) == dg.DGAL_OK
+        assert st.tile_rows == saved.tile_rows
+        buf = ctypes.create_string_buffer(1 << 14)
+        assert dg.lib.dgal_autotune_report(ctx, buf, len(buf)) == 1
+        assert buf.value.decode().split(":")[0] == key
+        assert torch.equal(out, ref)
+    finally:
+        torch.cuda.synchronize()
+        dg.lib.dgal_destroy(ctx)

@@ -31,7 +31,7 @@ def _crowd(xy, factor):
 
 def _saved_entries(saved):
     """(pair_id, nx) of the work-list entries, tile by tile, and the table."""
-    nt = saved.tiles
+    nt = saved.tiles_used
     st = saved.tile_start[:nt].cpu().numpy()
     sc = saved.tile_count[:nt].cpu().numpy()
     pid_all = saved.pair_id.cpu().numpy()
@@ -150,7 +150,8 @@ def test_matrix_small_dense_overlap(dg):
     assert np.abs(got - ref).max() <= IOU_TOL
     # work list: every cull survivor once, with the oracle's vertex counts; the
     # entries with nx > 0 are exactly the pairs with a non-empty intersection;
-    # tile t covers rows 8 (t // ct) .. +7 and columns 256 (t % ct) .. +255
+    # tile t covers rows R (t // ct) .. +R-1 and columns C (t % ct) .. +C-1 (R
+    # rows and C = 2048 / R columns per tile, the shape the forward used)
     pid, snx, st, sc = _saved_entries(saved)
     cnt = int((snx > 0).sum())
     assert len(np.unique(pid)) == len(pid) == int(saved.count.item())
@@ -162,13 +163,15 @@ def test_matrix_small_dense_overlap(dg):
     ent = np.concatenate([np.arange(a0, a0 + c0) for a0, c0 in zip(st, sc)])
     sxf = saved.xflags.cpu().numpy()[ent]
     assert np.array_equal(sxf, xf_all[pid])
-    ct = (257 + 255) // 256
-    assert saved.tiles == ((300 + 7) // 8) * ct
-    for t in range(saved.tiles):
+    R = saved.tile_rows
+    C = dg.TILE_PAIRS // R
+    ct = (257 + C - 1) // C
+    assert saved.tiles_used == ((300 + R - 1) // R) * ct
+    for t in range(saved.tiles_used):
         ent = saved.pair_id[st[t]:st[t] + sc[t]].cpu().numpy()
         rows, cols = ent // 257, ent % 257
-        assert np.all((rows >= 8 * (t // ct)) & (rows < 8 * (t // ct) + 8))
-        assert np.all((cols >= 256 * (t % ct)) & (cols < 256 * (t % ct) + 256))
+        assert np.all((rows >= R * (t // ct)) & (rows < R * (t // ct) + R))
+        assert np.all((cols >= C * (t % ct)) & (cols < C * (t % ct) + C))
     _say(f"small matrix: {cnt} non-empty of {300 * 257}")
 
 
@@ -306,6 +309,69 @@ def test_segmented_two_sets(dg):
     assert np.abs(rb - om_b.reshape(len(b), -1)).max() <= 1e-12 * (1 + np.abs(om_b).max())
     _assert_box_grads(_box_grads(ga), ra, sa, "rows")
     _assert_box_grads(_box_grads(gb), rb, sb, "columns")
+
+
+def _shape_run(dg, rows, a, b, anv=None, bnv=None, z=None, off=None, self_pairs=False,
+               g=None):
+    """Forward (+ backward with g) with the tile shape fixed to `rows` rows."""
+    ta = dev_t(a)
+    tb = ta if self_pairs else dev_t(b)
+    tz = None if z is None else (dev_t(z[0]), dev_t(z[1]))
+    tanv = None if anv is None else dev_t(anv)
+    tbnv = tanv if self_pairs else (None if bnv is None else dev_t(bnv))
+    seg = dg.segments(len(a), len(a) if self_pairs else len(b), off, self_pairs=self_pairs)
+    sv = dg.SavedPairs(1 << 20, a.shape[1] + (a if self_pairs else b).shape[1], seg[5],
+                       ta.device, tile_rows=rows)
+    iou, saved, seg4 = dg.iou_matrix(ta, None if self_pairs else tb, tanv,
+                                     None if self_pairs else tbnv, tz, None, off,
+                                     self_pairs=self_pairs, save=True, seg=seg, saved=sv)
+    dg.check_errors()
+    assert saved.tile_rows == rows
+    pid, snx, _, _ = _saved_entries(saved)
+    grads = None
+    if g is not None:
+        if self_pairs:
+            ga, _, gz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg4, ta, None, tanv, None,
+                                                  tz, None, self_pairs=True)
+            grads = (_box_grads(ga, gz),)
+        else:
+            ga, gb, _, _ = dg.iou_matrix_backward(dev_t(g), saved, seg4, ta, tb, tanv, tbnv)
+            grads = (_box_grads(ga), _box_grads(gb))
+    return iou.cpu().numpy().reshape(-1), np.sort(pid), grads
+
+
+@pytest.mark.parametrize("rows", [4, 16])
+def test_tile_shapes_agree(dg, rows):
+    """A tile shape other than the default computes the same IoU bit for bit
+    and the same survivor set as 8-row tiles, and its backward meets the
+    gradient bar against the oracle: a ragged two-set block of counted
+    polygons, and ragged 3D self-pair scenes (the diagonal crosses tiles
+    differently in every shape)."""
+    _say(f"case: tile rows {rows}, polygon block 333 x 517 and 7 scenes")
+    d = synth.c4_polygons(n=600, seed=15)
+    a, anv, b, bnv = d["a_xy"][:333], d["a_nv"][:333], d["b_xy"][:517], d["b_nv"][:517]
+    g = np.random.default_rng(16).uniform(-1, 1, 333 * 517).astype(np.float32)
+    ref = _shape_run(dg, 8, a, b, anv, bnv)
+    got = _shape_run(dg, rows, a, b, anv, bnv, g=g)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    om, _ = oracle.iou_matrix(a, b, anv, bnv)
+    assert np.abs(got[0] - om).max() <= IOU_TOL
+    ia, ib, fl = _aabb_candidates(a, b)
+    ra, sa, rb, sb = _grad_reference(a, b, g, ia, ib, fl, anv, bnv)
+    _assert_box_grads(got[2][0], ra, sa, "rows")
+    _assert_box_grads(got[2][1], rb, sb, "columns")
+
+    xy, lo, hi, off, out_off = _scenes(7, 3, 600, 17, 0.12)
+    gs = np.random.default_rng(18).uniform(-1, 1, int(out_off[-1])).astype(np.float32)
+    ref = _shape_run(dg, 8, xy, None, z=(lo, hi), off=off, self_pairs=True)
+    got = _shape_run(dg, rows, xy, None, z=(lo, hi), off=off, self_pairs=True, g=gs)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    om, _ = oracle.iou_matrix(xy, a_z=(lo, hi), a_off=off, self_pairs=True)
+    assert np.abs(got[0] - om).max() <= IOU_TOL
+    ia, ib, fl = _aabb_candidates(xy, xy, off, off, True)
+    rg, sg = _grad_reference(xy, xy, gs, ia, ib, fl, a_z=(lo, hi), b_z=(lo, hi), self_pairs=True)
+    e = _assert_box_grads(got[2][0], rg, sg, "scenes")
+    _say(f"tile rows {rows}: {len(got[1])} scene survivors, max rel err {e:.2e}")
 
 
 def test_scenes_full_size(dg):
@@ -683,8 +749,8 @@ def test_matrix_beyond_int32(dg):
     iou = iou.reshape(-1)  # flat, as the saved pair ids index it
     cnt = int(saved.count.item())
     assert 0 < cnt <= saved.capacity
-    st = saved.tile_start[:saved.tiles].cpu().numpy()
-    sc = saved.tile_count[:saved.tiles].cpu().numpy().astype(np.int64)
+    st = saved.tile_start[:saved.tiles_used].cpu().numpy()
+    sc = saved.tile_count[:saved.tiles_used].cpu().numpy().astype(np.int64)
     ent = np.repeat(st, sc) + (np.arange(int(sc.sum())) - np.repeat(np.cumsum(sc) - sc, sc))
     pid = saved.pair_id.cpu().numpy()[ent]
     assert len(pid) == cnt and len(np.unique(pid)) == cnt
@@ -748,8 +814,8 @@ def test_scenes_beyond_int32(dg):
                                     capacity=1 << 22)
     dg.check_errors()
     cnt = int(saved.count.item())
-    st = saved.tile_start[:saved.tiles].cpu().numpy()
-    sc = saved.tile_count[:saved.tiles].cpu().numpy().astype(np.int64)
+    st = saved.tile_start[:saved.tiles_used].cpu().numpy()
+    sc = saved.tile_count[:saved.tiles_used].cpu().numpy().astype(np.int64)
     ent = np.repeat(st, sc) + (np.arange(int(sc.sum())) - np.repeat(np.cumsum(sc) - sc, sc))
     pid = saved.pair_id.cpu().numpy()[ent]
     assert len(pid) == cnt and len(np.unique(pid)) == cnt

@@ -33,7 +33,7 @@ def _both(dg, a, b, a_off, self_pairs, a_z=None):
     pa, _ = dg.polys(a, None, a_z)
     pb, _ = dg.polys(b, None, a_z if self_pairs else None)
     seg = dg.segments(a.shape[0], b.shape[0], a_off, None, self_pairs=self_pairs)
-    d_a, d_b, d_o, nseg, total, tiles = seg
+    d_a, d_b, d_o, nseg, total, tiles, _ = seg
     ptr = lambda t: None if t is None else t.data_ptr()
     stream = torch.cuda.current_stream().cuda_stream
     ctx = dg.context(dev)
