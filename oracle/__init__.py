@@ -27,9 +27,12 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        # DGAL_ORACLE_LIB: another build of the same sources (the sanitizer
+        # build of the CPU tests); else the regular one, built on first use
+        path = os.environ.get("DGAL_ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        L = ctypes.CDLL(path)
         i64, i32 = ctypes.c_int64, ctypes.c_int
         L.oracle_polygon_valid.argtypes = [_f64p, i32]
         L.oracle_polygon_valid.restype = i32
