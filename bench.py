@@ -725,10 +725,10 @@ def main():
         dg.set_path_stats(True)
         dg.path_stats()
         step.fwd(stream)
-        n_eval, n_fp64 = dg.path_stats()
+        n_eval, n_fp64, n_thin = dg.path_stats()
         dg.set_path_stats(False)
         path = {"pairs_evaluated": n_eval, "fp64_signs": n_fp64,
-                "rate": round(n_fp64 / max(n_eval, 1), 6)}
+                "rate": round(n_fp64 / max(n_eval, 1), 6), "fp64_areas": n_thin}
     filt = filter_stats(d, wl, step)
 
     if args.copy_calib_mib:

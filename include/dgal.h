@@ -374,12 +374,16 @@ int dgal_set_validate(dgal_ctx *ctx, int32_t enable);
  * paper leaves open after Sec. II-C and in Sec. V).  While enabled, the
  * forward kernels of dgal_iou_pairs, dgal_iou_matrix (its exact pass),
  * dgal_intersect and dgal_iou_boxes count on the device the pairs they
- * evaluate and those whose orientation signs fp32 could not certify and
- * recomputed in fp64 (one pair of atomic adds per wavefront).
- * dgal_path_stats synchronises `stream`, returns both counts and clears them.
+ * evaluate, those whose orientation signs fp32 could not certify and
+ * recomputed in fp64, and those whose areas were rebuilt in fp64 (thin
+ * pairs: the pair's largest coordinate in the frame at its first polygon's
+ * vertex 0, squared, above 32 times the union; dgal_intersect rebuilds
+ * none), with one set of atomic adds per wavefront.  dgal_path_stats
+ * synchronises `stream`, returns the three counts and clears them.
  * DGAL_EINVAL: ctx NULL (set), or ctx / an output NULL (read). */
 int dgal_set_path_stats(dgal_ctx *ctx, int32_t enable);
-int dgal_path_stats(dgal_ctx *ctx, int64_t *pairs, int64_t *fp64_pairs, void *stream);
+int dgal_path_stats(dgal_ctx *ctx, int64_t *pairs, int64_t *fp64_pairs, int64_t *thin_pairs,
+                    void *stream);
 
 /* Launch-shape autotuning of the batched kernels: the grid of the pair
  * kernels; for the matrix forward, the tile shape (4, 8 or 16 rows, unless

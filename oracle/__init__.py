@@ -262,13 +262,16 @@ FILTER_DELTA = 1e-4      # vertex/edge margin
 FILTER_SIN = 1e-3        # crossing angle
 FILTER_TURN = 1e-3       # polygon strict convexity
 FILTER_GAP = 1e-4        # angular gap between ordered intersection vertices
-FILTER_SLIVER = 1e-4     # intersection area / smaller polygon area, if non-empty
+FILTER_SLIVER = 1e-4     # intersection area / smaller polygon area (simple polygons only)
 
 
 def filtered_mask(margins):
+    """Pairs away from degeneracy by margins [0]..[3]; margin [4], the
+    sliver ratio, is reported but no longer selects (thin intersections are
+    computed to the bars by the library's fp64 rebuild)."""
     m = np.asarray(margins)
     return ((m[:, 0] >= FILTER_DELTA) & (m[:, 1] >= FILTER_SIN) & (m[:, 2] >= FILTER_TURN)
-            & (m[:, 3] >= FILTER_GAP) & (m[:, 4] >= FILTER_SLIVER))
+            & (m[:, 3] >= FILTER_GAP))
 
 
 def polygon_valid(xy):

@@ -111,7 +111,8 @@ def _load():
     L.dgal_tune_cache_clear.restype = ctypes.c_int
     L.dgal_set_path_stats.argtypes = [_vp, i32]
     L.dgal_set_path_stats.restype = ctypes.c_int
-    L.dgal_path_stats.argtypes = [_vp, ctypes.POINTER(i64), ctypes.POINTER(i64), _vp]
+    L.dgal_path_stats.argtypes = [_vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                  ctypes.POINTER(i64), _vp]
     L.dgal_path_stats.restype = ctypes.c_int
     L.dgal_set_profiling.argtypes = [_vp, i32]
     L.dgal_set_profiling.restype = ctypes.c_int
@@ -647,18 +648,20 @@ def profile_report(device=None):
 
 
 def set_path_stats(enable=True, device=None):
-    """Counting, on the device, of the pairs the forward kernels evaluate and
-    of those whose orientation signs took the fp64 path."""
+    """Counting, on the device, of the pairs the forward kernels evaluate, of
+    those whose orientation signs took the fp64 path, and of those whose
+    areas were rebuilt in fp64 (thin pairs)."""
     _ok(lib.dgal_set_path_stats(context(device), int(bool(enable))), "dgal_set_path_stats")
 
 
 def path_stats(device=None):
-    """(pairs evaluated, pairs with fp64 signs) since the last read; clears them."""
+    """(pairs evaluated, pairs with fp64 signs, pairs with fp64 areas) since
+    the last read; clears them."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
-    n, k = ctypes.c_int64(0), ctypes.c_int64(0)
-    _ok(lib.dgal_path_stats(context(dev), ctypes.byref(n), ctypes.byref(k),
+    n, k, t = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _ok(lib.dgal_path_stats(context(dev), ctypes.byref(n), ctypes.byref(k), ctypes.byref(t),
                             torch.cuda.current_stream(dev).cuda_stream), "dgal_path_stats")
-    return int(n.value), int(k.value)
+    return int(n.value), int(k.value), int(t.value)
 
 
 def check_errors(device=None):

@@ -34,7 +34,7 @@ struct dgal_ctx {
   bool tune = false;
   bool validate = false;         // check every input polygon before each call
   int64_t* n_bad = nullptr;      // device counter of the input check
-  unsigned long long* stats_dev = nullptr;  // path statistics (2 counters)
+  unsigned long long* stats_dev = nullptr;  // path statistics (3 counters)
   std::string arch;              // e.g. "gfx950"
   std::map<std::string, dgal::LaunchShape> tuned;  // by TuneKey::text
 };
@@ -263,9 +263,9 @@ int dgal_create(dgal_ctx** out, int hip_device) {
       hipMalloc(reinterpret_cast<void**>(&c->v.scan), sizeof(int64_t) * dgal::kScanTotals) !=
           hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c->n_bad), sizeof(int64_t)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->stats_dev), 2 * sizeof(unsigned long long)) !=
+      hipMalloc(reinterpret_cast<void**>(&c->stats_dev), 3 * sizeof(unsigned long long)) !=
           hipSuccess ||
-      hipMemset(c->stats_dev, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->stats_dev, 0, 3 * sizeof(unsigned long long)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     if (c->stats_dev) (void)hipFree(c->stats_dev);
     if (c->v.err) (void)hipFree(c->v.err);
@@ -728,18 +728,21 @@ int dgal_set_path_stats(dgal_ctx* ctx, int32_t enable) {
   return DGAL_OK;
 }
 
-int dgal_path_stats(dgal_ctx* ctx, int64_t* pairs, int64_t* fp64_pairs, void* stream) {
-  if (ctx == nullptr || pairs == nullptr || fp64_pairs == nullptr) return DGAL_EINVAL;
+int dgal_path_stats(dgal_ctx* ctx, int64_t* pairs, int64_t* fp64_pairs, int64_t* thin_pairs,
+                    void* stream) {
+  if (ctx == nullptr || pairs == nullptr || fp64_pairs == nullptr || thin_pairs == nullptr)
+    return DGAL_EINVAL;
   DeviceGuard g(ctx->v.device);
   if (!g.ok) return DGAL_EHIP;
-  unsigned long long host[2] = {0ull, 0ull};
-  const unsigned long long zeros[2] = {0ull, 0ull};
+  unsigned long long host[3] = {0ull, 0ull, 0ull};
+  const unsigned long long zeros[3] = {0ull, 0ull, 0ull};
   if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess ||
       hipMemcpy(host, ctx->stats_dev, sizeof(host), hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(ctx->stats_dev, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess)
     return DGAL_EHIP;
   *pairs = (int64_t)host[0];
   *fp64_pairs = (int64_t)host[1];
+  *thin_pairs = (int64_t)host[2];
   return DGAL_OK;
 }
 

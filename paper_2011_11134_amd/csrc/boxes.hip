@@ -79,20 +79,32 @@ __global__ __launch_bounds__(kBoxBlock) void k_boxes_fwd(BoxesFwdArgs args) {
     box_corners(fb, Q);
     PairResult<4> r;
     pair_forward<4, true, kBoxBlock>(P, 4, Q, 4, s_pt + tid, s_cd + tid, r);
-    count_path(args.stats, r.exact);
-    float v;
+    count_path(args.stats, r.exact, r.thin);
+    float zl1 = 0.f, zh1 = 0.f, zl2 = 0.f, zh2 = 0.f;
     if (Z3) {
-      const float za = ba[5], ha = ba[6], zb = bb[5], hb = bb[6];
-      v = iou_3d(r.inter, r.a1, r.a2, r.m, za - 0.5f * ha, za + 0.5f * ha, zb - 0.5f * hb,
-                 zb + 0.5f * hb);
-    } else {
-      v = iou_2d(r.inter, r.a1, r.a2, r.m);
+      zl1 = ba[5] - 0.5f * ba[6];
+      zh1 = ba[5] + 0.5f * ba[6];
+      zl2 = bb[5] - 0.5f * bb[6];
+      zh2 = bb[5] + 0.5f * bb[6];
     }
-    args.iou[i] = v;
+    args.iou[i] = Z3 ? iou_3d(r.inter, r.a1, r.a2, r.m, zl1, zh1, zl2, zh2)
+                     : iou_2d(r.inter, r.a1, r.a2, r.m);
     if (r.overflow) atomicOr(args.err, kErrCapacity);
     if (SAVE) {
       args.nx[i] = (uint8_t)r.m;
       *reinterpret_cast<uint2*>(args.xflags + i * CAP) = make_uint2(r.codes[0], r.codes[1]);
+    }
+    // rare: the areas again in fp64, from the corners formed again, and the
+    // IoU written again
+    if (r.thin) {
+      const int64_t i2 = opaque(i);
+      box_corners(box_frame(args.a + i2 * dim), P);
+      box_corners(box_frame(args.b + i2 * dim), Q);
+      stage_pair<4, kBoxBlock>(s_pt + tid, P, Q);
+      float inter, a1, a2;
+      thin_areas64<4, true, kBoxBlock>(r.m, r.codes, 4, 4, s_pt + tid, inter, a1, a2);
+      args.iou[i] = Z3 ? iou_3d(inter, a1, a2, r.m, zl1, zh1, zl2, zh2)
+                       : iou_2d(inter, a1, a2, r.m);
     }
   }
 }
@@ -125,9 +137,17 @@ __global__ __launch_bounds__(kBoxBlock) void k_boxes_bwd(BoxesBwdArgs args) {
       hi2 = bb[5] + 0.5f * bb[6];
     }
     float2 gP[4], gQ[4], gz1, gz2;
-    pair_backward<4, true, Z3, kBoxBlock>(P, 4, Q, 4, args.grad[i], (int)args.nx[i], codes, lo1,
-                                          hi1, lo2, hi2, s_v + tid, s_g + tid, s_tab, gP, gQ,
-                                          gz1, gz2);
+    bool thin;
+    const float gi = args.grad[i];
+    const int nxi = (int)args.nx[i];
+    pair_backward<4, true, Z3, kBoxBlock, true>(P, 4, Q, 4, gi, nxi, codes, lo1, hi1, lo2, hi2,
+                                                s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2,
+                                                thin);
+    if (thin) {  // rare: the gradient again in fp64, from the same fp32 corners
+      stage_pair<4, kBoxBlock>(s_v + tid, P, Q);
+      pair_backward64<4, true, Z3, kBoxBlock>(4, 4, gi, nxi, codes, lo1, hi1, lo2, hi2,
+                                              s_v + tid, s_g + tid, gP, gQ, gz1, gz2);
+    }
     float gpa[5], gpb[5];
     box_param_grad(fa, gP, gpa);
     box_param_grad(fb, gQ, gpb);

@@ -22,11 +22,16 @@
 //      the smallest code (two bit-field reads a step, no angles, no sort);
 //      the signs are exact, so the order is the boundary of the pair moved by
 //      the tie rule also where points coincide;
-//   4. shoelace areas in a frame centred on P's first vertex, then IoU.
+//   4. shoelace areas in a frame centred on P's first vertex, then IoU;
+//   5. thin pairs (the largest coordinate F of the pair in that frame large
+//      against the union: F^2 > kThinUnion * max(A1, A2)) take their areas
+//      again in fp64 from the polygons and the (exact) codes (thin_areas64).
 // Backward, per pair: the intersection vertices are rebuilt from the codes
 // (no orientation test, no sort), the shoelace gradient is routed to the
 // polygon vertices by code, crossings through the chain rule of the
-// two-line meeting point.
+// two-line meeting point; thin pairs (and, for elementwise pairs, tiny
+// intersections: F^2 > kThinInter * I) take the whole gradient again in fp64
+// (pair_backward64).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -46,6 +51,24 @@ constexpr uint32_t kCodeX = 0x40u;
 // (|ex*dy| + |ey*dx|) <= 8 * 2^-24 * E * D; the factor 2 on top covers the
 // rounding of E, D and of the bound itself.
 constexpr float kCertify = 16.0f * 5.9604644775390625e-08f;
+
+// Bounds of the fp64 rebuild.  Rounding in fp32 moves the areas by about
+// u F P (u = 2^-24, F the pair's largest coordinate in the frame at P_0, P a
+// perimeter, at most about 2 pi F), i.e. the IoU by about u F^2 / U.  Measured
+// on thin rotated rectangles (widths 1e-3..1e-2, lengths 1..3): about 4e-8 of
+// IoU error per unit of F^2 / U.  The test is taken as soon as the polygons'
+// areas are known, against the lower bound max(A1, A2) of the union: lanes
+// with F^2 > kThinUnion * max(A1, A2) (so every lane with F^2 / U above 32,
+// 1.3e-6 of IoU error) recompute their areas in fp64.  On the benchmark
+// workloads F^2 / max(A1, A2) stays below 6 (rectangles), 12 (scenes) and
+// 130 (3..8-gons: 4e-4 of the pairs above the bound).
+constexpr float kThinUnion = 32.f;
+// A gradient's rebuilt vertices are off by about u F against an
+// intersection of extent about sqrt(I): relative error about u F / sqrt(I).
+// Elementwise pairs with F^2 > kThinInter * I (about 2.5e-4 at the bound with
+// the constant a needle-shaped intersection measured) take the gradient in
+// fp64.
+constexpr float kThinInter = 1048576.f;  // 2^20
 
 template <int K>
 struct Poly {
@@ -130,6 +153,7 @@ __device__ __forceinline__ double orient64(float ax, float ay, float bx, float b
 // Result of one pair's forward.
 template <int K>
 struct PairResult {
+  bool thin;  // the areas need the fp64 rebuild (thin_areas64)
   float inter, a1, a2;  // areas (intersection, P, Q)
   int m;                // intersection vertex count (clamped to 2K)
   bool overflow;        // more than 2K vertices (invalid input)
@@ -137,17 +161,27 @@ struct PairResult {
   uint32_t codes[K / 2];  // 2K provenance codes, 4 per word, 0xFF padded
 };
 
-// Path statistics of a wavefront's live lanes (stats: NULL when off, else two
-// device counters: pairs evaluated, pairs whose signs took the fp64 path),
-// one pair of atomic adds per wavefront.
-__device__ __forceinline__ void count_path(unsigned long long* stats, bool exact) {
+// Path statistics of a wavefront's live lanes (stats: NULL when off, else
+// three device counters: pairs evaluated, pairs whose signs took the fp64
+// path, pairs whose areas took the fp64 rebuild), one set of atomic adds per
+// wavefront.
+__device__ __forceinline__ void count_path(unsigned long long* stats, bool exact, bool thin) {
   if (stats == nullptr) return;  // uniform
   const uint64_t live = __builtin_amdgcn_ballot_w64(true);
   const uint64_t ex = __builtin_amdgcn_ballot_w64(exact);
+  const uint64_t th = __builtin_amdgcn_ballot_w64(thin);
   if ((int)(__lane_id()) == __builtin_ctzll(live)) {
     atomicAdd(stats, (unsigned long long)__popcll(live));
     atomicAdd(stats + 1, (unsigned long long)__popcll(ex));
+    atomicAdd(stats + 2, (unsigned long long)__popcll(th));
   }
+}
+
+// An index the compiler cannot see through, so that a reload from it is not
+// merged with an earlier load (which would keep those registers live).
+__device__ __forceinline__ int64_t opaque(int64_t i) {
+  asm volatile("" : "+v"(i));
+  return i;
 }
 
 // Waves per SIMD that the LDS of a pair_forward kernel allows at K = 8
@@ -302,6 +336,16 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
     }
     res.a1 = 0.5f * s1;
     res.a2 = 0.5f * s2;
+  }
+  // step 5's test, decided here: F, the pair's largest coordinate in this
+  // frame, is bounded by max(|P_k - P_0|, D) (each Q_j - P_0 is one of the
+  // differences D bounds), which is at most 2 F
+  bool thin_pre;
+  {
+    float F = D;
+#pragma unroll
+    for (int k = 1; k < K; ++k) F = fmaxf(F, fmaxf(fabsf(lpx[k]), fabsf(lpy[k])));
+    thin_pre = F * F > kThinUnion * fmaxf(res.a1, res.a2);
   }
   // Points go to the lane's LDS column in ascending code (slot 0 holds the
   // smallest).  For the counter-clockwise walk each point also records, in
@@ -472,7 +516,7 @@ __device__ __forceinline__ void pair_forward(const Poly<K>& P, int n1, const Pol
   res.inter = m >= 3 ? 0.5f * acc : 0.f;
 #pragma unroll
   for (int w = 0; w < K / 2; ++w) res.codes[w] = codes[w];
-
+  res.thin = m >= 3 && thin_pre;
 }
 
 // IoU from the areas (2D), with the conventions: empty intersection or a
@@ -490,6 +534,16 @@ __device__ __forceinline__ float iou_3d(float inter, float a1, float a2, int m, 
   const float v = inter * hz;
   const float u = a1 * (hi1 - lo1) + a2 * (hi2 - lo2) - v;
   return (m > 0 && u > 0.f) ? v * fast_rcp(u) : 0.f;
+}
+
+// IoU of a pair from its areas, 2D, or 3D with z extents [lo, hi] read at
+// indices ia / ib.
+template <bool Z3>
+__device__ __forceinline__ float pair_iou(float inter, float a1, float a2, int m,
+                                          const float* zlo_a, const float* zhi_a, int64_t ia,
+                                          const float* zlo_b, const float* zhi_b, int64_t ib) {
+  if (Z3) return iou_3d(inter, a1, a2, m, zlo_a[ia], zhi_a[ia], zlo_b[ib], zhi_b[ib]);
+  return iou_2d(inter, a1, a2, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -641,13 +695,17 @@ __device__ __forceinline__ float2 rebuild_slot(uint32_t c, uint32_t n1S, uint32_
   return slot_vertex(sg.oa, sg.ob, sg.oc, sg.od, s_v, sg.t, sg.idn);
 }
 
-template <int K, bool FIXED, bool Z3, int BLOCK>
+// `thin` (out): the lane's gradient needs the fp64 rebuild (pair_backward64):
+// thin polygons (F^2 > kThinUnion * max(A1, A2)) and, with TINY, tiny
+// intersections (F^2 > kThinInter * I).
+template <int K, bool FIXED, bool Z3, int BLOCK, bool TINY = false>
 __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Poly<K>& Q, int n2,
                                               float g, int nx, const uint32_t (&codes)[K / 2],
                                               float lo1, float hi1, float lo2, float hi2,
                                               float2* __restrict__ s_v, float2* __restrict__ s_g,
                                               const uint2* __restrict__ s_tab, float2 (&gP)[K],
-                                              float2 (&gQ)[K], float2& gz1, float2& gz2) {
+                                              float2 (&gQ)[K], float2& gz1, float2& gz2,
+                                              bool& thin) {
   constexpr int CAP = 2 * K;
   if (FIXED) {
     n1 = K;
@@ -655,12 +713,14 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   }
   const float ox = P.x[0], oy = P.y[0];
   float lpx[K], lpy[K], lqx[K], lqy[K];
+  float F = 0.f;  // the pair's largest coordinate in the frame at P_0
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     lpx[k] = P.x[k] - ox;
     lpy[k] = P.y[k] - oy;
     lqx[k] = Q.x[k] - ox;
     lqy[k] = Q.y[k] - oy;
+    F = fmaxf(fmaxf(F, fmaxf(fabsf(lpx[k]), fabsf(lpy[k]))), fmaxf(fabsf(lqx[k]), fabsf(lqy[k])));
     s_v[k * BLOCK] = make_float2(lpx[k], lpy[k]);
     s_v[(K + k) * BLOCK] = make_float2(lqx[k], lqy[k]);
     s_g[k * BLOCK] = make_float2(0.f, 0.f);
@@ -675,6 +735,8 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
       s2 += (lqx[k] - lqx[0]) * (lqy[k + 1] - lqy[0]) - (lqy[k] - lqy[0]) * (lqx[k + 1] - lqx[0]);
   }
   const float a1 = 0.5f * s1, a2 = 0.5f * s2;
+  const float F2 = F * F;
+  const bool thin_pre = F2 > kThinUnion * fmaxf(a1, a2);
 
   // ---- one pass: rebuild r + 1, route r (padding codes name valid slots;
   // vertices past nx are never used)
@@ -737,6 +799,7 @@ __device__ __forceinline__ void pair_backward(const Poly<K>& P, int n1, const Po
   if (m > 0) route_slot(X1.y - last.y, last.x - X1.x, g0.t, g0.idn, g0.oa, g0.ob, g0.oc, g0.od,
                         s_v, s_g);
   const float inter = m >= 3 ? 0.5f * acc : 0.f;
+  thin = m >= 3 && (thin_pre || (TINY && F2 > kThinInter * inter));
 
   // scalar factors (zero where the IoU is constant: empty, non-positive union)
   float gI = 0.f, gA1 = 0.f, gA2 = 0.f;
@@ -887,6 +950,249 @@ __device__ __forceinline__ void poly_area_grad(const Poly<K>& P, int n, float g,
       }
     }
     gv[k] = (FIXED || k < n) ? make_float2(h * (pny - ppy), h * (ppx - pnx)) : make_float2(0.f, 0.f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fp64 rebuild of ill-conditioned pairs (thin polygons, tiny intersections).
+// The pair's polygons are staged, as their fp32 values, in the lane's column
+// of a [2K][BLOCK] float2 LDS buffer: P in slots 0..K-1, Q in K..2K-1.  Every
+// difference of two fp32 values and every product of two such differences is
+// exact in fp64, so the rebuilt vertices carry one rounding each; the codes
+// (exact on both sides) fix the structure.  Rare lanes: runtime loops, few
+// registers.
+
+// The ordered codes as values the compiler cannot trace back to their
+// array: the selects of code_of then stay selects between registers (a
+// select between two loads from one array would become a load at a dynamic
+// index, which puts the array, and the struct around it, in scratch memory).
+template <int K>
+struct Codes {
+  uint32_t w[K / 2];
+  __device__ __forceinline__ explicit Codes(const uint32_t (&codes)[K / 2]) {
+#pragma unroll
+    for (int k = 0; k < K / 2; ++k) {
+      w[k] = codes[k];
+      asm volatile("" : "+v"(w[k]));
+    }
+  }
+};
+
+// Code r of the ordered list (a dynamic index: shifts of 64-bit words).
+template <int K>
+__device__ __forceinline__ uint32_t code_of(const Codes<K>& c, int r) {
+  const uint64_t lo = (uint64_t)c.w[0] | ((uint64_t)c.w[1] << 32);
+  if constexpr (K == 4) {
+    return (uint32_t)(lo >> (8 * (r & 7))) & 0xffu;
+  } else {
+    const uint64_t hi = (uint64_t)c.w[2] | ((uint64_t)c.w[3] << 32);
+    return (uint32_t)((r < 8 ? lo : hi) >> (8 * (r & 7))) & 0xffu;
+  }
+}
+
+// Intersection vertex of code c relative to (ox, oy): a polygon vertex, or
+// the crossing X = A + t (B - A), t = cross(C - A, D - C) / cross(B - A,
+// D - C), with its slots and t, 1 / den kept for the chain rule.
+struct Vert64 {
+  double x, y, t, idn;
+  int ia, ib, ic, id;
+};
+
+template <int K, bool FIXED, int BLOCK>
+__device__ __forceinline__ Vert64 vertex64(uint32_t c, int n1, int n2,
+                                           const float2* __restrict__ col, double ox, double oy) {
+  Vert64 v;
+  code_slots<K, FIXED>(c, n1, n2, v.ia, v.ib, v.ic, v.id);
+  const float2 a = col[v.ia * BLOCK], b = col[v.ib * BLOCK];
+  const float2 cc = col[v.ic * BLOCK], d = col[v.id * BLOCK];
+  const double ex = (double)b.x - (double)a.x, ey = (double)b.y - (double)a.y;
+  const double fx = (double)d.x - (double)cc.x, fy = (double)d.y - (double)cc.y;
+  const double wx = (double)cc.x - (double)a.x, wy = (double)cc.y - (double)a.y;
+  const double den = ex * fy - ey * fx;
+  v.idn = den != 0.0 ? 1.0 / den : 0.0;
+  v.t = (wx * fy - wy * fx) * v.idn;
+  v.x = ((double)a.x - ox) + v.t * ex;
+  v.y = ((double)a.y - oy) + v.t * ey;
+  return v;
+}
+
+// Area of the polygon in slots 0..n-1 of a column (about its vertex 0).
+template <int BLOCK>
+__device__ __forceinline__ double area64(const float2* __restrict__ col, int n) {
+  const double x0 = col[0].x, y0 = col[0].y;
+  double s = 0.0;
+  for (int k = 1; k + 1 < n; ++k) {
+    const float2 u = col[k * BLOCK], w = col[(k + 1) * BLOCK];
+    s += ((double)u.x - x0) * ((double)w.y - y0) - ((double)u.y - y0) * ((double)w.x - x0);
+  }
+  return 0.5 * s;
+}
+
+// Step 5 of the forward: the intersection's and the polygons' areas in fp64,
+// each rounded once.
+template <int K, bool FIXED, int BLOCK>
+__device__ __forceinline__ void thin_areas64(int m, const uint32_t (&codes)[K / 2], int n1, int n2,
+                                             const float2* __restrict__ col, float& inter,
+                                             float& a1, float& a2) {
+  if (FIXED) {
+    n1 = K;
+    n2 = K;
+  }
+  const Codes<K> cw(codes);
+  const double ox = col[0].x, oy = col[0].y;
+  double acc = 0.0, x0 = 0.0, y0 = 0.0, xp = 0.0, yp = 0.0;
+  for (int r = 0; r < m; ++r) {
+    const Vert64 v = vertex64<K, FIXED, BLOCK>(code_of<K>(cw, r), n1, n2, col, ox, oy);
+    if (r == 0) {
+      x0 = v.x;
+      y0 = v.y;
+    } else if (r >= 2) {
+      acc += (xp - x0) * (v.y - y0) - (yp - y0) * (v.x - x0);
+    }
+    xp = v.x;
+    yp = v.y;
+  }
+  inter = m >= 3 ? (float)(0.5 * acc) : 0.f;
+  a1 = (float)area64<BLOCK>(col, n1);
+  a2 = (float)area64<BLOCK>(col + K * BLOCK, n2);
+}
+
+// Chain rule of one vertex for d(2I)/dX = (Gx, Gy), as route_slot, in fp64,
+// added into the column's fp32 accumulators (each receives a few terms
+// computed in fp64; their sum's rounding is relative to the gradient).
+template <int BLOCK>
+__device__ __forceinline__ void route64(double Gx, double Gy, const Vert64& v,
+                                        const float2* __restrict__ col, float2* __restrict__ acc) {
+  auto add = [&](int s, double x, double y) {
+    float2 t = acc[s * BLOCK];
+    t.x = (float)((double)t.x + x);
+    t.y = (float)((double)t.y + y);
+    acc[s * BLOCK] = t;
+  };
+  if (v.ia == v.ib) {  // a polygon vertex: its own slot takes the gradient
+    add(v.ia, Gx, Gy);
+    return;
+  }
+  const float2 a = col[v.ia * BLOCK], b = col[v.ib * BLOCK];
+  const float2 cc = col[v.ic * BLOCK], d = col[v.id * BLOCK];
+  const double ex = (double)b.x - (double)a.x, ey = (double)b.y - (double)a.y;
+  const double fx = (double)d.x - (double)cc.x, fy = (double)d.y - (double)cc.y;
+  const double wx = (double)cc.x - (double)a.x, wy = (double)cc.y - (double)a.y;
+  const double gt = Gx * ex + Gy * ey;
+  const double gN = gt * v.idn;
+  const double gD = -gN * v.t;
+  const double gex = v.t * Gx + gD * fy, gey = v.t * Gy - gD * fx;
+  const double gfx = -gN * wy - gD * ey, gfy = gN * wx + gD * ex;
+  const double gwx = gN * fy, gwy = -gN * fx;
+  add(v.ib, gex, gey);
+  add(v.ic, gwx - gfx, gwy - gfy);
+  add(v.id, gfx, gfy);
+  add(v.ia, Gx - gex - gwx, Gy - gey - gwy);
+}
+
+// The backward of pair_backward, in fp64 (polygons staged in s_v as above;
+// s_g is overwritten): the same outputs, for the lanes it flags `thin`.
+template <int K, bool FIXED, bool Z3, int BLOCK>
+__device__ __forceinline__ void pair_backward64(int n1, int n2, float g, int nx,
+                                                const uint32_t (&codes)[K / 2], float lo1,
+                                                float hi1, float lo2, float hi2,
+                                                const float2* __restrict__ s_v,
+                                                float2* __restrict__ s_g, float2 (&gP)[K],
+                                                float2 (&gQ)[K], float2& gz1, float2& gz2) {
+  constexpr int CAP = 2 * K;
+  if (FIXED) {
+    n1 = K;
+    n2 = K;
+  }
+  const int m = min(nx, CAP);
+  const Codes<K> cw(codes);
+#pragma unroll
+  for (int k = 0; k < CAP; ++k) s_g[k * BLOCK] = make_float2(0.f, 0.f);
+  const double ox = s_v[0].x, oy = s_v[0].y;
+  // one pass with a rolling window: d(2I)/dX_r = (y_r+1 - y_r-1, x_r-1 - x_r+1)
+  double acc = 0.0;
+  if (m >= 3) {
+    const Vert64 first = vertex64<K, FIXED, BLOCK>(code_of<K>(cw, 0), n1, n2, s_v, ox, oy);
+    const Vert64 last = vertex64<K, FIXED, BLOCK>(code_of<K>(cw, m - 1), n1, n2, s_v, ox, oy);
+    double px = last.x, py = last.y;
+    Vert64 cur = first;
+    for (int r = 0; r < m; ++r) {
+      const Vert64 nxt =
+          r + 1 < m ? vertex64<K, FIXED, BLOCK>(code_of<K>(cw, r + 1), n1, n2, s_v, ox, oy)
+                    : first;
+      route64<BLOCK>(nxt.y - py, px - nxt.x, cur, s_v, s_g);
+      acc += (cur.x - first.x) * (nxt.y - first.y) - (cur.y - first.y) * (nxt.x - first.x);
+      px = cur.x;
+      py = cur.y;
+      cur = nxt;
+    }
+  }
+  const double inter = m >= 3 ? 0.5 * acc : 0.0;
+  const double a1 = area64<BLOCK>(s_v, n1), a2 = area64<BLOCK>(s_v + K * BLOCK, n2);
+
+  // scalar factors, as in pair_backward
+  double gI = 0.0, gA1 = 0.0, gA2 = 0.0;
+  double z1x = 0.0, z1y = 0.0, z2x = 0.0, z2y = 0.0;
+  if (!Z3) {
+    const double u = a1 + a2 - inter;
+    if (m >= 3 && u > 0.0) {
+      const double giu2 = (double)g / (u * u);
+      gI = giu2 * (a1 + a2);
+      gA1 = -giu2 * inter;
+      gA2 = gA1;
+    }
+  } else {
+    const double h1 = (double)hi1 - lo1, h2 = (double)hi2 - lo2;
+    const double hz = (double)fminf(hi1, hi2) - (double)fmaxf(lo1, lo2);
+    const double v = inter * hz, v1 = a1 * h1, v2 = a2 * h2, u = v1 + v2 - v;
+    if (m >= 3 && hz > 0.0 && u > 0.0) {
+      const double giu2 = (double)g / (u * u);
+      const double gV = giu2 * (v1 + v2), gV1 = -giu2 * v;
+      gI = gV * hz;
+      const double ghz = gV * inter;
+      gA1 = gV1 * h1;
+      gA2 = gV1 * h2;
+      const double gh1 = gV1 * a1, gh2 = gV1 * a2;
+      z1x = -gh1;
+      z1y = gh1;
+      z2x = -gh2;
+      z2y = gh2;
+      if (hi1 <= hi2) z1y += ghz; else z2y += ghz;
+      if (lo1 >= lo2) z1x -= ghz; else z2x -= ghz;
+    }
+  }
+  gz1 = make_float2((float)z1x, (float)z1y);
+  gz2 = make_float2((float)z2x, (float)z2y);
+
+  // read back: dL/dv = gI / 2 * (routed terms) + gA / 2 * (y+ - y-, x- - x+)
+  const double hI = 0.5 * gI, h1a = 0.5 * gA1, h2a = 0.5 * gA2;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int kn1 = next_idx<K, FIXED>(k, n1), kp1 = k == 0 ? n1 - 1 : k - 1;
+    const int kn2 = next_idx<K, FIXED>(k, n2), kp2 = k == 0 ? n2 - 1 : k - 1;
+    const float2 pn = s_v[kn1 * BLOCK], pp = s_v[kp1 * BLOCK];
+    const float2 qn = s_v[(K + kn2) * BLOCK], qp = s_v[(K + kp2) * BLOCK];
+    const float2 tp = s_g[k * BLOCK], tq = s_g[(K + k) * BLOCK];
+    gP[k] = (FIXED || k < n1)
+                ? make_float2((float)(hI * tp.x + h1a * ((double)pn.y - (double)pp.y)),
+                              (float)(hI * tp.y + h1a * ((double)pp.x - (double)pn.x)))
+                : make_float2(0.f, 0.f);
+    gQ[k] = (FIXED || k < n2)
+                ? make_float2((float)(hI * tq.x + h2a * ((double)qn.y - (double)qp.y)),
+                              (float)(hI * tq.y + h2a * ((double)qp.x - (double)qn.x)))
+                : make_float2(0.f, 0.f);
+  }
+}
+
+// Stages a pair's polygons (fp32 values) into a lane column for the fp64
+// rebuild: P in slots 0..K-1, Q in K..2K-1.
+template <int K, int BLOCK>
+__device__ __forceinline__ void stage_pair(float2* __restrict__ col, const Poly<K>& P,
+                                           const Poly<K>& Q) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    col[k * BLOCK] = make_float2(P.x[k], P.y[k]);
+    col[(K + k) * BLOCK] = make_float2(Q.x[k], Q.y[k]);
   }
 }
 

@@ -154,7 +154,7 @@ struct CtxView {
   int64_t* prefix;  // [2][DGAL_MAX_SEGMENTS + 1]: tile and row-group prefixes
   int64_t* scan;    // [kScanTotals]: per-chunk totals of the tile scan
   Profiler* prof;   // per-kernel timing, or NULL
-  unsigned long long* stats;  // path statistics: pairs evaluated, fp64 signs (NULL: off)
+  unsigned long long* stats;  // path statistics: pairs evaluated, fp64 signs, fp64 areas (NULL: off)
 };
 
 // Chunks of 4096 tiles the tile scan can combine (2^24 tiles per call).

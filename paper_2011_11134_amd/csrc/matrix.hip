@@ -675,21 +675,25 @@ __attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_matrix_exac
     load_poly<K, FIXED>(m.b.xy, ib, m.b.kmax, m.b.vec4, n2, Q);
     PairResult<K> res;
     pair_forward<K, FIXED, kExactBlock>(P, n1, Q, n2, s_pt + tid, s_cd + tid, res);
-    count_path(m.stats, res.exact);
-    float v;
-    if (Z3) {
-      v = iou_3d(res.inter, res.a1, res.a2, res.m, m.a.zlo[ia], m.a.zhi[ia], m.b.zlo[ib],
-                 m.b.zhi[ib]);
-    } else {
-      v = iou_2d(res.inter, res.a1, res.a2, res.m);
-    }
-    m.iou[pid] = v;
+    count_path(m.stats, res.exact, res.thin);
+    m.iou[pid] = pair_iou<Z3>(res.inter, res.a1, res.a2, res.m, m.a.zlo, m.a.zhi, ia, m.b.zlo,
+                              m.b.zhi, ib);
     if (res.overflow) atomicOr(m.err, kErrCapacity);
     m.s_nx[e] = (uint8_t)res.m;
     uint8_t* row = m.s_flags + e * (int64_t)m.cap;
 #pragma unroll
     for (int b = 0; b < CAP; ++b)
       if (b < m.cap) row[b] = (uint8_t)(res.codes[b >> 2] >> ((b & 3) * 8));
+    // rare: the areas again in fp64, from the polygons reloaded, and the IoU
+    // written again
+    if (res.thin) {
+      load_poly<K, FIXED>(m.a.xy, opaque(ia), m.a.kmax, m.a.vec4, n1, P);
+      load_poly<K, FIXED>(m.b.xy, opaque(ib), m.b.kmax, m.b.vec4, n2, Q);
+      stage_pair<K, kExactBlock>(s_pt + tid, P, Q);
+      float inter, a1, a2;
+      thin_areas64<K, FIXED, kExactBlock>(res.m, res.codes, n1, n2, s_pt + tid, inter, a1, a2);
+      m.iou[pid] = pair_iou<Z3>(inter, a1, a2, res.m, m.a.zlo, m.a.zhi, ia, m.b.zlo, m.b.zhi, ib);
+    }
   }
 }
 
@@ -853,8 +857,16 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
           hi2 = m.b.zhi[ib];
         }
         float2 gP[K], gQ[K], gz1, gz2;
+        bool thin;
         pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
-                                           s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2);
+                                           s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2, thin);
+        if (thin) {  // rare: the gradient again in fp64, from the polygons reloaded
+          load_poly<K, FIXED>(m.a.xy, opaque(ia), m.a.kmax, m.a.vec4, n1, P);
+          load_poly<K, FIXED>(m.b.xy, opaque(ib), m.b.kmax, m.b.vec4, n2, Q);
+          stage_pair<K, BLOCK>(s_v + tid, P, Q);
+          pair_backward64<K, FIXED, Z3, BLOCK>(n1, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
+                                               s_v + tid, s_g + tid, gP, gQ, gz1, gz2);
+        }
         float* acc = acc_w + (lane >> 4) * ACC + rl * ROW;
         const int nr_own = swapped ? n2 : n1;  // the row box's vertex count
 #pragma unroll

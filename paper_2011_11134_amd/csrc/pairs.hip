@@ -29,15 +29,9 @@ __attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_pairs_fwd(P
     load_poly<K, FIXED>(args.b.xy, i, args.b.kmax, args.b.vec4, n2, Q);
     PairResult<K> r;
     pair_forward<K, FIXED, BLOCK>(P, n1, Q, n2, s_pt + tid, s_cd + tid, r);
-    count_path(args.stats, r.exact);
-    float v;
-    if (Z3) {
-      v = iou_3d(r.inter, r.a1, r.a2, r.m, args.a.zlo[i], args.a.zhi[i], args.b.zlo[i],
-                 args.b.zhi[i]);
-    } else {
-      v = iou_2d(r.inter, r.a1, r.a2, r.m);
-    }
-    args.iou[i] = v;
+    count_path(args.stats, r.exact, r.thin);
+    args.iou[i] = pair_iou<Z3>(r.inter, r.a1, r.a2, r.m, args.a.zlo, args.a.zhi, i, args.b.zlo,
+                               args.b.zhi, i);
     if (r.overflow) atomicOr(args.err, kErrCapacity);
     if (SAVE) {
       args.nx[i] = (uint8_t)r.m;
@@ -54,6 +48,18 @@ __attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_pairs_fwd(P
           if (k < args.cap) row[k] = (uint8_t)(r.codes[k >> 2] >> ((k & 3) * 8));
         }
       }
+    }
+    // rare: the areas again in fp64, from the polygons reloaded, and the IoU
+    // written again (last, so that nothing of it is live on the common path)
+    if (r.thin) {
+      const int64_t i2 = opaque(i);
+      load_poly<K, FIXED>(args.a.xy, i2, args.a.kmax, args.a.vec4, n1, P);
+      load_poly<K, FIXED>(args.b.xy, i2, args.b.kmax, args.b.vec4, n2, Q);
+      stage_pair<K, BLOCK>(s_pt + tid, P, Q);
+      float inter, a1, a2;
+      thin_areas64<K, FIXED, BLOCK>(r.m, r.codes, n1, n2, s_pt + tid, inter, a1, a2);
+      args.iou[i] = pair_iou<Z3>(inter, a1, a2, r.m, args.a.zlo, args.a.zhi, i, args.b.zlo,
+                                 args.b.zhi, i);
     }
   }
 }
@@ -108,8 +114,19 @@ __global__ __launch_bounds__(pairs_block<K>()) void k_pairs_bwd(PairsBwdArgs arg
       hi2 = args.b.zhi[i];
     }
     float2 gP[K], gQ[K], gz1, gz2;
-    pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, args.grad[i], (int)args.nx[i], codes, lo1, hi1,
-                                       lo2, hi2, s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2);
+    bool thin;
+    const float gi = args.grad[i];
+    const int nxi = (int)args.nx[i];
+    pair_backward<K, FIXED, Z3, BLOCK, true>(P, n1, Q, n2, gi, nxi, codes, lo1, hi1, lo2, hi2,
+                                             s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2, thin);
+    if (thin) {  // rare: the gradient again in fp64, from the polygons reloaded
+      const int64_t i2 = opaque(i);
+      load_poly<K, FIXED>(args.a.xy, i2, args.a.kmax, args.a.vec4, n1, P);
+      load_poly<K, FIXED>(args.b.xy, i2, args.b.kmax, args.b.vec4, n2, Q);
+      stage_pair<K, BLOCK>(s_v + tid, P, Q);
+      pair_backward64<K, FIXED, Z3, BLOCK>(n1, n2, gi, nxi, codes, lo1, hi1, lo2, hi2, s_v + tid,
+                                           s_g + tid, gP, gQ, gz1, gz2);
+    }
     float* oa = args.ga_xy + i * (int64_t)args.a.kmax * 2;
     float* ob = args.gb_xy + i * (int64_t)args.b.kmax * 2;
     if (FIXED || args.a.vec4) {

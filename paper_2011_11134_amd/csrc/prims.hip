@@ -32,7 +32,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_intersect_f
     PairResult<K> r;
     float2 ov[CAP];
     pair_forward<K, FIXED, BLOCK, true>(P, n1, Q, n2, s_pt + tid, s_cd + tid, r, ov);
-    count_path(args.stats, r.exact);
+    count_path(args.stats, r.exact, false);  // vertices only: no areas to rebuild
     if (r.overflow) atomicOr(args.err, kErrCapacity);
     args.nx[i] = (uint8_t)r.m;
     uint8_t* row = args.xflags + i * (int64_t)args.cap;

@@ -47,7 +47,7 @@ static void null_context(void) {
   dgal_boxes bx;
   memset(&bx, 0, sizeof(bx));
   bx.dim = 5;
-  int64_t a = 0, b = 0;
+  int64_t a = 0, b = 0, t = 0;
   char buf[64];
   CHECK(dgal_iou_pairs(NULL, p, p, NULL, NULL, NULL, NULL) == DGAL_EINVAL);
   CHECK(dgal_iou_matrix(NULL, p, p, NULL, NULL, NULL, 0, 0, NULL, 0, &s, NULL) == DGAL_EINVAL);
@@ -76,7 +76,7 @@ static void null_context(void) {
   CHECK(dgal_set_profiling(NULL, 1) == DGAL_EINVAL);
   CHECK(dgal_profile_report(NULL, buf, sizeof(buf)) == DGAL_EINVAL);
   CHECK(dgal_set_path_stats(NULL, 1) == DGAL_EINVAL);
-  CHECK(dgal_path_stats(NULL, &a, &b, NULL) == DGAL_EINVAL);
+  CHECK(dgal_path_stats(NULL, &a, &b, &t, NULL) == DGAL_EINVAL);
   CHECK(dgal_check(NULL, NULL) == DGAL_EINVAL);
   dgal_destroy(NULL);
   CHECK(dgal_create(NULL, 0) == DGAL_EINVAL);

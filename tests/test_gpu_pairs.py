@@ -23,6 +23,70 @@ def _say(msg):
     print(msg, flush=True)
 
 
+def _thin_boxes(n, seed):
+    """Thin rotated rectangles (widths 1e-3..1e-2, lengths 1..3) against a copy
+    moved by up to 2e-3 and turned by about 0.05 rad: unions of 1e-3..1e-1
+    against coordinates of about 1, so fp32 areas carry ~u F^2 / U of IoU
+    error (above 1e-5 for most pairs without the fp64 rebuild)."""
+    rng = np.random.default_rng(seed)
+    w, l = rng.uniform(1e-3, 1e-2, n), rng.uniform(1, 3, n)
+    cx, cy, yaw = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(-np.pi, np.pi, n)
+    a = synth.boxes_to_quads(cx, cy, w, l, yaw)
+    b = synth.boxes_to_quads(cx + rng.uniform(-2e-3, 2e-3, n), cy + rng.uniform(-2e-3, 2e-3, n),
+                             w * rng.uniform(0.5, 2, n), l, yaw + rng.normal(0, 0.05, n))
+    return a, b
+
+
+def _needles(n, seed):
+    """Thin triangles (apex angles 1e-3..1e-1 rad, length 1..2) whose apex
+    pokes 1e-4..1e-2 deep into a convex 3..8-gon: intersections of area
+    ~1e-11..1e-5 against coordinates of about 1, the pairs whose fp32
+    gradient carries ~u F / sqrt(I) of relative error."""
+    rng = np.random.default_rng(seed)
+    d = synth.c4_polygons(n=n, seed=seed)
+    a, anv = d["a_xy"], d["a_nv"]
+    b = np.zeros((n, 3, 2), np.float32)
+    for i in range(n):
+        k = int(anv[i])
+        e = int(rng.integers(k))
+        p0, p1 = a[i, e].astype(np.float64), a[i, (e + 1) % k].astype(np.float64)
+        t = rng.uniform(0.2, 0.8)
+        foot = p0 + t * (p1 - p0)
+        out = np.array([p1[1] - p0[1], p0[0] - p1[0]])  # outward normal of a CCW edge
+        out /= np.linalg.norm(out)
+        ang = rng.uniform(-0.6, 0.6)                    # the needle's tilt off the normal
+        dirn = np.array([out[0] * np.cos(ang) - out[1] * np.sin(ang),
+                         out[0] * np.sin(ang) + out[1] * np.cos(ang)])
+        apex = foot - dirn * rng.uniform(1e-4, 1e-2)
+        length, half = rng.uniform(1, 2), 0.5 * rng.uniform(1e-3, 1e-1)
+        side = np.array([-dirn[1], dirn[0]])
+        base = apex + dirn * length
+        b[i] = [apex, base - side * length * np.tan(half), base + side * length * np.tan(half)]
+    return a, anv, b
+
+
+def test_thin_rectangles(dg):
+    """Thin polygons: every pair's IoU within 1e-5 (the areas are rebuilt in
+    fp64 where F^2 / U is large), the gradient on every pair whose crossings
+    meet at |sin| >= 1e-3."""
+    _say("case: thin rectangles 65536 pairs")
+    a, b = _thin_boxes(65536, seed=61)
+    g = np.random.default_rng(62).uniform(-1, 1, len(a)).astype(np.float32)
+    s = compare_pairs(dg, a, b, grad=g, require_filtered_frac=0.0)
+    _say(str(s))
+
+
+def test_tiny_intersections(dg):
+    """Needle triangles poking into polygons: no sliver filter; the gradient
+    of every pair (crossings at |sin| >= 1e-3) within 1e-3, tiny
+    intersections taking the fp64 backward."""
+    _say("case: needles 8192 pairs")
+    a, anv, b = _needles(8192, seed=63)
+    g = np.random.default_rng(64).uniform(-1, 1, len(a)).astype(np.float32)
+    s = compare_pairs(dg, a, b, a_nv=anv, grad=g, require_filtered_frac=0.0)
+    _say(str(s))
+
+
 def test_rectangles_c1(dg):
     _say("case: c1 rectangles 1024 pairs")
     d = synth.c1_pairs()
@@ -426,20 +490,25 @@ def test_path_stats_count_the_fp64_path(dg):
     a, b = a[valid], b[valid]
     dg.set_path_stats(True)
     try:
-        assert dg.path_stats() == (0, 0)
+        assert dg.path_stats() == (0, 0, 0)
         dg.iou_pairs(dev_t(a), dev_t(b))
-        n, k = dg.path_stats()
-        assert n == len(a) and k >= 0.9 * n, (n, k)
+        n, k, t = dg.path_stats()
+        assert n == len(a) and k >= 0.9 * n and t == 0, (n, k, t)
         g = synth.c3_pairs(n=65536, seed=52)
         dg.iou_pairs(dev_t(g["a_xy"]), dev_t(g["b_xy"]))
-        n, k = dg.path_stats()
-        assert n == 65536 and k <= 0.05 * n, (n, k)
+        n, k, t = dg.path_stats()
+        assert n == 65536 and k <= 0.05 * n and t == 0, (n, k, t)
         m = synth.c2_matrix(n=300, m=257, seed=3)
         _, saved, _ = dg.iou_matrix(dev_t(m["a_xy"]), dev_t(m["b_xy"]), save=True)
-        n, k = dg.path_stats()
-        assert n == int(saved.count.item()) and 0 <= k <= n, (n, k)
+        n, k, t = dg.path_stats()
+        assert n == int(saved.count.item()) and 0 <= k <= n and t == 0, (n, k, t)
         _say(f"path stats: matrix {n} survivors, {k} with fp64 signs")
+        # thin rectangles: every overlapping pair rebuilds its areas
+        ta, tb = _thin_boxes(2048, seed=53)
+        iou, nx, _ = dg.iou_pairs(dev_t(ta), dev_t(tb))
+        n, k, t = dg.path_stats()
+        assert n == 2048 and t == int((nx.cpu().numpy() >= 3).sum()), (n, t)
     finally:
         dg.set_path_stats(False)
     dg.iou_pairs(dev_t(a), dev_t(b))
-    assert dg.path_stats() == (0, 0)
+    assert dg.path_stats() == (0, 0, 0)

@@ -23,8 +23,10 @@ def test_plain_form_matches_oracle(wl):
     iou = iou_pairs_plain(a, b, anv, bnv)
     iou.backward(torch.from_numpy(d["grad"]).cuda())
     ref, nx, xf, _ = oracle.iou_pairs(d["a_xy"], d["b_xy"], d.get("a_nv"), d.get("b_nv"), threads=8)
-    keep = oracle.filtered_mask(oracle.pair_margins(d["a_xy"], d["b_xy"], d.get("a_nv"),
-                                                    d.get("b_nv"), threads=8))
+    marg = oracle.pair_margins(d["a_xy"], d["b_xy"], d.get("a_nv"), d.get("b_nv"), threads=8)
+    # the plain form is fp32 throughout (no fp64 rebuild): sliver intersections,
+    # whose fp32 gradient carries ~u F / sqrt(I), stay out of its gradient bar
+    keep = oracle.filtered_mask(marg) & (marg[:, 4] >= oracle.FILTER_SLIVER)
     assert np.abs(iou.detach().cpu().numpy() - ref).max() <= IOU_TOL
     ga, gb, _, _ = oracle.iou_pairs_grad(d["a_xy"], d["b_xy"], d["grad"], nx, xf, d.get("a_nv"),
                                          d.get("b_nv"), threads=8)
