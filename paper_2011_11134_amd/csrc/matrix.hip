@@ -13,8 +13,8 @@
 //     (0, or the self diagonal's 1) straight to the output row segments
 //     (coalesced), and records the tile's survivor mask and count.
 //   k_scan_totals, k_scan_apply -- exclusive prefix of the tile counts in two
-//     parallel passes, so the work list is laid out tile by tile,
-//     deterministically.
+//     parallel passes (k_scan_small: in one workgroup, for at most 8192
+//     tiles), so the work list is laid out tile by tile, deterministically.
 //   k_matrix_fill -- reads the masks; survivors go to their tile's range.
 //   k_matrix_exact -- one lane per survivor with every lane busy: the exact
 //     pair forward, the IoU written to its place in the output, nx / xflags
@@ -595,6 +595,60 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int64_t* tile_p
   }
 }
 
+// The same exclusive prefix in one workgroup, for tile tables of at most
+// kScanSmall entries (a call's tile capacity bounds its tile count): one
+// coalesced round of loads into LDS (a tile holds at most 2048 survivors, so
+// its count fits 16 bits and a prefix over 8192 tiles 32 bits), the scan of
+// each thread's run of 8 tiles, and one coalesced round of stores: one
+// launch in place of the two passes.
+constexpr int64_t kScanSmall = 8 * kScanBlock;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_small(const int64_t* tile_prefix, int nseg,
+                                                           int64_t single_tiles,
+                                                           int64_t tile_capacity,
+                                                           int64_t* tile_start,
+                                                           int32_t* tile_count, int64_t* count,
+                                                           int64_t capacity, int* err) {
+  constexpr int PER = kScanSmall / kScanBlock;
+  __shared__ uint16_t s_cnt[kScanSmall];
+  __shared__ int32_t s_pre[kScanSmall];
+  __shared__ int64_t s_w[kScanBlock / 64];
+  const int t = threadIdx.x;
+  const int64_t nt = scan_tiles(tile_prefix, nseg, single_tiles, tile_capacity);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = k * kScanBlock + t;
+    s_cnt[i] = i < nt ? (uint16_t)tile_count[i] : (uint16_t)0;
+  }
+  __syncthreads();
+  int64_t v = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) v += s_cnt[t * PER + k];
+  const int64_t incl = block_inclusive_scan(v, s_w);
+  int32_t run = (int32_t)(incl - v);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    s_pre[t * PER + k] = run;
+    run += s_cnt[t * PER + k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = k * kScanBlock + t;
+    if (i < nt) {
+      const int64_t start = s_pre[i], c = s_cnt[i];
+      tile_start[i] = start;
+      int64_t room = capacity - start;
+      room = room < 0 ? 0 : (room > c ? c : room);
+      tile_count[i] = (int32_t)room;
+    }
+  }
+  if (t == kScanBlock - 1) {
+    *count = incl;
+    if (incl > capacity) atomicOr(err, kErrCapacity);
+  }
+}
+
 struct ExactArgs {
   SegArgs seg;
   PolyArgs a, b;
@@ -1052,18 +1106,26 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
     else if (R == 16) hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ, 16>), cg, cb, 0, stream, c);
     else hipLaunchKernelGGL((k_matrix_cull<KK, FX, ZZ, 8>), cg, cb, 0, stream, c);
     prof_end(ctx.prof, "k_matrix_cull", stream);
-    const int64_t chunks = std::max<int64_t>(1, ceil_div(saved->tile_capacity, kScanChunk));
-    prof_begin(ctx.prof, stream);
-    hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)chunks), dim3(kScanBlock), 0, stream,
-                       sa.tile_prefix, sa.nseg, single_tiles, saved->tile_capacity,
-                       saved->tile_count, ctx.scan);
-    prof_end(ctx.prof, "k_scan_totals", stream);
-    prof_begin(ctx.prof, stream);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)chunks), dim3(kScanBlock), 0, stream,
-                       sa.tile_prefix, sa.nseg, single_tiles, saved->tile_capacity, ctx.scan,
-                       saved->tile_start, saved->tile_count, saved->count, saved->capacity,
-                       ctx.err);
-    prof_end(ctx.prof, "k_scan_apply", stream);
+    if (saved->tile_capacity <= kScanSmall) {  // few tiles: one launch
+      prof_begin(ctx.prof, stream);
+      hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanBlock), 0, stream, sa.tile_prefix,
+                         sa.nseg, single_tiles, saved->tile_capacity, saved->tile_start,
+                         saved->tile_count, saved->count, saved->capacity, ctx.err);
+      prof_end(ctx.prof, "k_scan_small", stream);
+    } else {
+      const int64_t chunks = std::max<int64_t>(1, ceil_div(saved->tile_capacity, kScanChunk));
+      prof_begin(ctx.prof, stream);
+      hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)chunks), dim3(kScanBlock), 0, stream,
+                         sa.tile_prefix, sa.nseg, single_tiles, saved->tile_capacity,
+                         saved->tile_count, ctx.scan);
+      prof_end(ctx.prof, "k_scan_totals", stream);
+      prof_begin(ctx.prof, stream);
+      hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)chunks), dim3(kScanBlock), 0, stream,
+                         sa.tile_prefix, sa.nseg, single_tiles, saved->tile_capacity, ctx.scan,
+                         saved->tile_start, saved->tile_count, saved->count, saved->capacity,
+                         ctx.err);
+      prof_end(ctx.prof, "k_scan_apply", stream);
+    }
     // the fill walks ~8 resident waves per SIMD, each over a contiguous range of tiles
     prof_begin(ctx.prof, stream);
     hipLaunchKernelGGL(k_matrix_fill, dim3((unsigned)std::max<int64_t>(1, (int64_t)ctx.cus * 8)),
