@@ -395,7 +395,9 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
         uint32_t bits = gap_bits(rb[j].x1, cbx.x0) | gap_bits(cbx.x1, rb[j].x0) |
                         gap_bits(rb[j].y1, cbx.y0) | gap_bits(cbx.y1, rb[j].y0);
         if (Z3) bits |= gap_bits(rb[j].hi, cbx.lo) | gap_bits(cbx.hi, rb[j].lo);
-        mk[j] = __ballot((int32_t)bits >= 0);
+        // rows and columns past the block never survive, whatever the
+        // infinities of the other side's bounds make of the test
+        mk[j] = j < nr ? __ballot(valid && (int32_t)bits >= 0) : 0ull;
       }
       if (dchunk) {  // rare: the chunk holds part of the diagonal
         const int d = (int)dd;
