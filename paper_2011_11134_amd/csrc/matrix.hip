@@ -165,6 +165,25 @@ __device__ __forceinline__ int find_segment(const int64_t* prefix, int nseg, int
   return lo;
 }
 
+// The same search by a whole wavefront, for a wave-uniform v: each round
+// loads up to 64 evenly spaced entries of the remaining range (one a lane)
+// and keeps the span from the last one not past v, so up to 64 segments take
+// one round of loads and up to 4096 two (the scalar search above takes a
+// dependent load per halving).
+__device__ __forceinline__ int wave_find_segment(const int64_t* prefix, int nseg, int64_t v) {
+  const int lane = threadIdx.x & 63;
+  int lo = 0, hi = nseg;  // the answer lies in [lo, hi)
+  while (hi - lo > 1) {
+    const int step = (hi - lo + 63) >> 6;
+    const int i = lo + lane * step;
+    const uint64_t m = __ballot(i < hi && prefix[i] <= v);
+    const int k = m != 0ull ? 63 - __clzll(m) : 0;
+    lo += k * step;
+    hi = min(hi, lo + step);
+  }
+  return lo;
+}
+
 // Axis-aligned bounds and z-extent of one box (padded slots repeat vertex 0,
 // so the bounds over all K slots are the polygon's).
 struct Bounds {
@@ -290,7 +309,7 @@ struct TileCursor {
     seg_end = segmented ? seg.tile_prefix[s + 1] : (int64_t)0x7fffffffffffffff;
   }
   __device__ void seek(const SegArgs& seg, bool segmented, int64_t u) {
-    s = segmented ? find_segment(seg.tile_prefix, seg.nseg, u) : 0;
+    s = segmented ? wave_find_segment(seg.tile_prefix, seg.nseg, u) : 0;
     load(seg, segmented);
     const int64_t lu = segmented ? u - seg.tile_prefix[s] : u;
     tr = lu / nct;
@@ -692,7 +711,7 @@ __device__ __forceinline__ bool locate(const SegArgs& sa, int64_t pid, Segment& 
   int s = 0;
   if (sa.a_off != nullptr) {
     const int64_t pid0 = wave_first(pid);
-    const int s0 = find_segment(sa.out_off, sa.nseg, pid0);
+    const int s0 = wave_find_segment(sa.out_off, sa.nseg, pid0);
     const bool inside = pid >= sa.out_off[s0] && pid < sa.out_off[s0 + 1];
     s = inside ? s0 : find_segment(sa.out_off, sa.nseg, pid);
   }
@@ -830,7 +849,7 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
   }
 
   for (int64_t u = (int64_t)blockIdx.x * WAVES + wave; u < total; u += (int64_t)gridDim.x * WAVES) {
-    const int s = segmented ? find_segment(m.seg.group_prefix, m.seg.nseg, u) : 0;
+    const int s = segmented ? wave_find_segment(m.seg.group_prefix, m.seg.nseg, u) : 0;
     const int64_t tr = segmented ? u - m.seg.group_prefix[s] : u;  // row group in the segment
     const Segment g = load_segment(m.seg, s);
     if (!g.ok) continue;
