@@ -650,6 +650,22 @@ def main():
     dg.check_errors()
     tuned = dg.autotune_report()[1].strip().splitlines()
 
+    # path statistics of one forward (before the timed region, so that a
+    # profile's last steps are the timed ones and the per-kernel timing): the
+    # pairs the exact kernels evaluated and those whose signs took the fp64
+    # path
+    path = None
+    if wl not in ("c4n",):
+        dg.set_path_stats(True)
+        dg.path_stats()
+        step.fwd(stream)
+        n_eval, n_fp64, n_thin = dg.path_stats()
+        dg.set_path_stats(False)
+        path = {"pairs_evaluated": n_eval, "fp64_signs": n_fp64,
+                "rate": round(n_fp64 / max(n_eval, 1), 6), "fp64_areas": n_thin}
+    torch.cuda.synchronize()
+    dg.check_errors()
+
     # The step is captured once into a HIP graph (the library allocates
     # nothing per call and needs no host synchronisation) and replayed;
     # --eager launches the calls one by one instead.
@@ -718,17 +734,6 @@ def main():
     kernels = {k: {"ms_per_launch": round(per_launch[k], 4),
                    "launches_per_step": round(prof[k][0] / args.steps, 2)} for k in prof}
 
-    # path statistics of one forward (outside the timed region): the pairs the
-    # exact kernels evaluated and those whose signs took the fp64 path
-    path = None
-    if wl not in ("c4n",):
-        dg.set_path_stats(True)
-        dg.path_stats()
-        step.fwd(stream)
-        n_eval, n_fp64, n_thin = dg.path_stats()
-        dg.set_path_stats(False)
-        path = {"pairs_evaluated": n_eval, "fp64_signs": n_fp64,
-                "rate": round(n_fp64 / max(n_eval, 1), 6), "fp64_areas": n_thin}
     filt = filter_stats(d, wl, step)
 
     if args.copy_calib_mib:
