@@ -148,6 +148,12 @@ typedef struct {
                              the rows it used, which the backward reads.  With 0,
                              tile_capacity must hold the tiles of every shape
                              (the largest of the three counts).                   */
+  int64_t *seg_prefix;    /* [2][DGAL_MAX_SEGMENTS + 1] or NULL (segmented calls):
+                             the forward writes its segments' tile and row-group
+                             prefixes here (else into the context's workspace),
+                             and a backward given them does not recompute them
+                             (they hold for the offsets and tile shape of the
+                             forward that wrote them).                           */
 } dgal_saved;
 
 /* Most segments one matrix call may hold. */

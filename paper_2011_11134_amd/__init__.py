@@ -41,7 +41,7 @@ class Saved(ctypes.Structure):
     _fields_ = [("pair_id", _vp), ("nx", _vp), ("xflags", _vp),
                 ("capacity", ctypes.c_int64), ("count", _vp),
                 ("tile_start", _vp), ("tile_count", _vp), ("tile_capacity", ctypes.c_int64),
-                ("tile_mask", _vp), ("tile_rows", ctypes.c_int32)]
+                ("tile_mask", _vp), ("tile_rows", ctypes.c_int32), ("seg_prefix", _vp)]
 
 
 class Boxes(ctypes.Structure):
@@ -369,6 +369,8 @@ class SavedPairs:
         self.tile_count = torch.empty(max(tiles, 1), dtype=torch.int32, device=device)
         self.tile_mask = torch.empty((max(tiles, 1), TILE_MASK_WORDS), dtype=torch.int64,
                                      device=device)
+        # the segments' prefixes, written by the forward and reused by the backward
+        self.seg_prefix = torch.empty(2 * (MAX_SEGMENTS + 1), dtype=torch.int64, device=device)
         self.capacity = capacity
         self.tiles = tiles
         self.tiles_used = 0  # tiles of the last forward (set by iou_matrix)
@@ -379,7 +381,7 @@ class SavedPairs:
     def struct(self):
         return Saved(_ptr(self.pair_id), _ptr(self.nx), _ptr(self.xflags), self.capacity,
                      _ptr(self.count), _ptr(self.tile_start), _ptr(self.tile_count), self.tiles,
-                     _ptr(self.tile_mask), self.tile_rows)
+                     _ptr(self.tile_mask), self.tile_rows, _ptr(self.seg_prefix))
 
 
 def segments(n_a, n_b, a_off, b_off=None, self_pairs=False, device=None):

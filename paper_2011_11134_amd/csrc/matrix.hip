@@ -1077,11 +1077,13 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
   const bool segmented = a_off != nullptr;
   int64_t single_tiles = 0;
   if (segmented) {
-    sa.tile_prefix = ctx.prefix;
-    sa.group_prefix = ctx.prefix + (kMaxSeg + 1);
+    // in the caller's saved state when it has room, for the backward
+    int64_t* pre = saved->seg_prefix != nullptr ? saved->seg_prefix : ctx.prefix;
+    sa.tile_prefix = pre;
+    sa.group_prefix = pre + (kMaxSeg + 1);
     prof_begin(ctx.prof, stream);
-    hipLaunchKernelGGL(k_seg_prep, dim3(1), dim3(256), 0, stream, sa, ctx.err, ctx.prefix,
-                       ctx.prefix + (kMaxSeg + 1));
+    hipLaunchKernelGGL(k_seg_prep, dim3(1), dim3(256), 0, stream, sa, ctx.err, pre,
+                       pre + (kMaxSeg + 1));
     prof_end(ctx.prof, "k_seg_prep", stream);
   } else {
     if (a.count == 0 || b.count == 0) return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
@@ -1194,13 +1196,18 @@ int matrix_backward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_
   }
   int64_t single_groups = 0;
   if (segmented) {
-    // recomputed: another matrix call may have used the workspace since the forward
-    sa.tile_prefix = ctx.prefix;
-    sa.group_prefix = ctx.prefix + (kMaxSeg + 1);
-    prof_begin(ctx.prof, stream);
-    hipLaunchKernelGGL(k_seg_prep, dim3(1), dim3(256), 0, stream, sa, ctx.err, ctx.prefix,
-                       ctx.prefix + (kMaxSeg + 1));
-    prof_end(ctx.prof, "k_seg_prep", stream);
+    if (saved->seg_prefix != nullptr) {  // the forward's, kept with its work list
+      sa.tile_prefix = saved->seg_prefix;
+      sa.group_prefix = saved->seg_prefix + (kMaxSeg + 1);
+    } else {
+      // recomputed: another matrix call may have used the workspace since the forward
+      sa.tile_prefix = ctx.prefix;
+      sa.group_prefix = ctx.prefix + (kMaxSeg + 1);
+      prof_begin(ctx.prof, stream);
+      hipLaunchKernelGGL(k_seg_prep, dim3(1), dim3(256), 0, stream, sa, ctx.err, ctx.prefix,
+                         ctx.prefix + (kMaxSeg + 1));
+      prof_end(ctx.prof, "k_seg_prep", stream);
+    }
   } else {
     if (a.count == 0 || b.count == 0) return hipGetLastError() == hipSuccess ? DGAL_OK : DGAL_EHIP;
     single_groups = ceil_div(a.count, kGroupRows);
@@ -1315,6 +1322,7 @@ int matrix_forward_noalloc(const CtxView& ctx, dgal_polys a, dgal_polys b, const
   sv.tile_capacity = kNaTiles;
   sv.tile_mask = reinterpret_cast<uint64_t*>(base + kNaTileMask);
   sv.tile_rows = R;
+  sv.seg_prefix = nullptr;  // the scratch's own prefixes
   CtxView v = ctx;
   v.prefix = reinterpret_cast<int64_t*>(base + kNaPrefix);
   v.scan = reinterpret_cast<int64_t*>(base + kNaScan);
