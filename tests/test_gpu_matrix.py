@@ -580,7 +580,10 @@ def test_graph_replay_matches_eager(dg):
         torch.cuda.synchronize()
         assert torch.equal(iou_g, iou_e), rep
         assert int(saved_g.count.item()) == int(saved_e.count.item())
-        assert torch.equal(saved_g.tile_count, saved_e.tile_count)
+        # the tiles of the shape used (the table has room for every shape's)
+        assert saved_g.tiles_used == saved_e.tiles_used
+        nt = saved_e.tiles_used
+        assert torch.equal(saved_g.tile_count[:nt], saved_e.tile_count[:nt])
         assert torch.allclose(ga_g, ga_e, atol=1e-5, rtol=1e-5), rep
         assert torch.allclose(gaz_g, gaz_e, atol=1e-5, rtol=1e-5), rep
         del junk
