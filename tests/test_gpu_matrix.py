@@ -618,6 +618,42 @@ def test_invalid_segments_are_rejected(dg):
                                   0) == dg.DGAL_EINVAL  # out too small
 
 
+@pytest.mark.parametrize("rows", [4, 8, 16])
+def test_cull_keeps_nothing_past_the_block(dg, rows):
+    """Rows and columns past a block (its last tiles are ragged) never
+    survive the count pass, whatever infinite bounds the other side has: a
+    column box reaching x = -inf meets the padded rows of the last tile row,
+    and a row box reaching x = -inf the padded columns of the last tile
+    column, in a pair test whose difference with the padding's -inf bound is
+    NaN.  The finite boxes are placed so that no pair overlaps at all: the
+    work list is empty and the output all 0."""
+    na, nb = 13, 300  # 13 % rows != 0 and 300 % (2048 / rows) != 0: padded rows and columns
+    rng = np.random.default_rng(81)
+
+    def boxes(n, x_lo, x_hi, y_lo, y_hi):
+        return synth.boxes_to_quads(rng.uniform(x_lo, x_hi, n), rng.uniform(y_lo, y_hi, n),
+                                    np.full(n, 1.0), np.full(n, 2.0), rng.uniform(-np.pi, np.pi, n))
+
+    # x in [-inf, 1], y in [-2, 2]: a padded row or column (bounds 0 .. -1, x1
+    # = -inf) passes the test against it unless the padding is excluded
+    star = np.array([[-np.inf, -2.0], [1.0, -2.0], [1.0, 2.0], [-np.inf, 2.0]], np.float32)
+    for side in ("column", "row"):
+        _say(f"case: infinite {side} bound, {na} x {nb}, tile rows {rows}")
+        a = boxes(na, 100.0, 200.0, -50.0, 50.0)  # rows: far right of the star
+        b = boxes(nb, -300.0, -200.0, 10.0, 20.0)  # columns: left of it, above y = 2
+        if side == "column":
+            b[5] = star
+        else:
+            a[2] = star
+        seg = dg.segments(na, nb, None)
+        sv = dg.SavedPairs(1 << 12, 8, seg[5], torch.device("cuda"), tile_rows=rows)
+        iou, saved, _ = dg.iou_matrix(dev_t(a), dev_t(b), save=True, seg=seg, saved=sv)
+        dg.check_errors()
+        assert saved.tile_rows == rows
+        assert int(saved.count.item()) == 0, side
+        assert not iou.cpu().numpy().any(), side
+
+
 def test_saved_capacity_overflow_is_reported(dg):
     d = synth.c2_matrix(n=100, m=100, seed=15)
     a = _crowd(d["a_xy"], 0.02)
