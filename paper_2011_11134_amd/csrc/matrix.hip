@@ -369,6 +369,10 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
   wave_tiles(total, (int64_t)blockIdx.x * WAVES + wave, (int64_t)gridDim.x * WAVES, u0, u1);
   TileCursor<R> cur;
   if (u0 < u1) cur.seek(m.seg, segmented, u0);
+  // the rows' bounds, in scalar registers, kept while the tiles of a range
+  // stay in one tile row (the usual case: a range is a few tiles)
+  Bounds rb[R];
+  int64_t rows_of = -1;  // first row (in a) whose bounds rb holds
   for (int64_t u = u0; u < u1; cur.next(m.seg, segmented, u), ++u) {
     const Segment& g = cur.g;
     const int64_t r0 = cur.r0(), cb = cur.cb();
@@ -376,20 +380,22 @@ __global__ __launch_bounds__(kCullBlock) void k_matrix_cull(CullArgs m) {
     const int64_t ce = min(g.nb, cb + C);
     float* out_rows = m.iou + g.out0 + r0 * g.nb;
 
-    // row bounds: lane j < nr bounds row j, then every lane holds all of them
-    Bounds rl = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
-    if (lane < nr) rl = box_bounds<K, FIXED, Z3>(m.a, g.a0 + r0 + lane);
-    if (lane >= nr || (Z3 && !(rl.hi > rl.lo))) rl.x1 = -__builtin_inff();
-    if (Z3) rl.hi = below(rl.hi);
-    Bounds rb[R];
+    if (g.a0 + r0 != rows_of) {  // uniform
+      // row bounds: lane j < nr bounds row j, then every lane holds all of them
+      rows_of = g.a0 + r0;
+      Bounds rl = {0.f, 0.f, -1.f, -1.f, 0.f, 0.f};
+      if (lane < nr) rl = box_bounds<K, FIXED, Z3>(m.a, g.a0 + r0 + lane);
+      if (lane >= nr || (Z3 && !(rl.hi > rl.lo))) rl.x1 = -__builtin_inff();
+      if (Z3) rl.hi = below(rl.hi);
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      rb[j].x0 = lane_bcast(rl.x0, j);
-      rb[j].y0 = lane_bcast(rl.y0, j);
-      rb[j].x1 = lane_bcast(rl.x1, j);
-      rb[j].y1 = lane_bcast(rl.y1, j);
-      rb[j].lo = lane_bcast(rl.lo, j);
-      rb[j].hi = lane_bcast(rl.hi, j);
+      for (int j = 0; j < R; ++j) {
+        rb[j].x0 = lane_bcast(rl.x0, j);
+        rb[j].y0 = lane_bcast(rl.y0, j);
+        rb[j].x1 = lane_bcast(rl.x1, j);
+        rb[j].y1 = lane_bcast(rl.y1, j);
+        rb[j].lo = lane_bcast(rl.lo, j);
+        rb[j].hi = lane_bcast(rl.hi, j);
+      }
     }
     uint32_t n = 0;         // survivors so far (uniform; at most kTilePairs)
     uint32_t mlo = 0u, mhi = 0u;  // lane w < kBitWords: mask word w of the tile
