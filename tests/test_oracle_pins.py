@@ -391,6 +391,68 @@ def test_tie_rule_gradients_are_the_moved_pairs(orc):
     assert touching >= 3, touching
 
 
+def _exact_iou3(P, Q, z1, z2):
+    """Exact 3D IoU: BEV intersection area times the z-overlap, over the
+    union volume."""
+    inter = X.clip(P, Q)
+    ai = X.area(inter) if len(inter) >= 3 else Fraction(0)
+    hz = max(Fraction(0), min(z1[1], z2[1]) - max(z1[0], z2[0]))
+    v = ai * hz
+    return v / (X.area(P) * (z1[1] - z1[0]) + X.area(Q) * (z2[1] - z2[0]) - v)
+
+
+def test_z_tie_gradients_are_the_moved_pairs(orc):
+    """Reading R9 on z-extent ties (boxes on a common ground plane, equal
+    tops, equal extents): the oracle gives the overlap's derivative to the
+    first box's end, which is the gradient of the pair with the second box's
+    ends moved outward by eps (lower end down, upper end up), so that the
+    first box's ends bind the overlap.  Reference: exact rational central
+    differences (steps 2^-40) of the exact 3D IoU of the moved pair (eps =
+    2^-20), on axis-aligned rectangles with dyadic corners (exact areas);
+    the two differ by O(eps).  A plain one-sided difference of the tied pair
+    would pick a side per end; this one fixes which."""
+    eps = Fraction(1, 2 ** 20)
+    h = Fraction(1, 2 ** 40)
+    rng = np.random.default_rng(91)
+    zsets = [((0.5, 2.0), (0.5, 1.5)),    # common lower end
+             ((0.5, 2.0), (0.25, 2.0)),   # common upper end
+             ((0.5, 1.75), (0.5, 1.75)),  # equal extents
+             ((-1.0, 0.5), (-1.0, 2.5))]
+    rows = []
+    for zi, (z1, z2) in enumerate(zsets):
+        for k in range(5):
+            x0, y0 = (rng.integers(-8, 8, 2) / 4.0)
+            w, l = rng.integers(4, 12, 2) / 4.0
+            dx, dy = rng.integers(1, 6, 2) / 8.0  # partial BEV overlap, no BEV ties
+            a = [(x0, y0), (x0 + w, y0), (x0 + w, y0 + l), (x0, y0 + l)]
+            b = [(x0 + dx, y0 + dy), (x0 + dx + w, y0 + dy), (x0 + dx + w, y0 + dy + l),
+                 (x0 + dx, y0 + dy + l)]
+            rows.append((a, b, z1, z2))
+    a = np.array([r[0] for r in rows], np.float32)
+    b = np.array([r[1] for r in rows], np.float32)
+    za = tuple(np.array([r[2][i] for r in rows], np.float32) for i in range(2))
+    zb = tuple(np.array([r[3][i] for r in rows], np.float32) for i in range(2))
+    g = np.ones(len(rows))
+    iou, nx, xf, _ = orc.iou_pairs(a, b, a_z=za, b_z=zb)
+    _, _, gaz, gbz = orc.iou_pairs_grad(a, b, g, nx, xf, a_z=za, b_z=zb)
+    for i, (pa, pb, z1, z2) in enumerate(rows):
+        P, Q = [tuple(map(Fraction, v)) for v in pa], [tuple(map(Fraction, v)) for v in pb]
+        f1 = [Fraction(z1[0]), Fraction(z1[1])]
+        f2 = [Fraction(z2[0]) - eps, Fraction(z2[1]) + eps]  # the second box moved outward
+        assert abs(iou[i] - float(_exact_iou3(P, Q, [Fraction(v) for v in z1],
+                                              [Fraction(v) for v in z2]))) <= 1e-12
+        ref = np.zeros((2, 2))
+        for side, zz in ((0, f1), (1, f2)):
+            for e in range(2):
+                def shifted(s):
+                    za_, zb_ = list(f1), list(f2)
+                    (za_ if side == 0 else zb_)[e] += s
+                    return _exact_iou3(P, Q, za_, zb_)
+                ref[side, e] = float((shifted(h) - shifted(-h)) / (2 * h))
+        got = np.stack([gaz[i], gbz[i]])
+        assert np.abs(got - ref).max() <= 1e-4 * (1.0 + np.abs(ref).max()), (i, got, ref)
+
+
 def test_identity_disjoint_nested(orc):
     d = synth.c4_polygons(n=300, seed=21)
     a, anv = d["a_xy"], d["a_nv"]
