@@ -712,16 +712,26 @@ __device__ __forceinline__ void divmod(int64_t v, int64_t d, int64_t& q, int64_t
 // work list is in output order, so the entries of one wavefront mostly share
 // a segment: it is searched once for the wavefront's first entry, and a lane
 // outside that segment searches for itself.
-__device__ __forceinline__ bool locate(const SegArgs& sa, int64_t pid, Segment& g, int64_t& r,
-                                       int64_t& c) {
-  int s = 0;
-  if (sa.a_off != nullptr) {
+// The segment a wavefront last located, and its block of the output
+// [lo, hi) (empty until the first search; wave-uniform).
+struct SegCache {
+  Segment g;
+  int64_t lo = 0, hi = 0;
+};
+
+__device__ __forceinline__ bool locate(const SegArgs& sa, int64_t pid, SegCache& sc, Segment& g,
+                                       int64_t& r, int64_t& c) {
+  if (sa.a_off == nullptr) {
+    g = load_segment(sa, 0);
+  } else {
     const int64_t pid0 = wave_first(pid);
-    const int s0 = wave_find_segment(sa.out_off, sa.nseg, pid0);
-    const bool inside = pid >= sa.out_off[s0] && pid < sa.out_off[s0 + 1];
-    s = inside ? s0 : find_segment(sa.out_off, sa.nseg, pid);
+    if (!(pid0 >= sc.lo && pid0 < sc.hi)) {  // uniform: a wavefront's entries mostly stay in one
+      sc.g = load_segment(sa, wave_find_segment(sa.out_off, sa.nseg, pid0));
+      sc.lo = sc.g.out0;
+      sc.hi = sc.g.ok ? sc.g.out0 + sc.g.na * sc.g.nb : sc.g.out0;
+    }
+    g = (pid >= sc.lo && pid < sc.hi) ? sc.g : load_segment(sa, find_segment(sa.out_off, sa.nseg, pid));
   }
-  g = load_segment(sa, s);
   const int64_t local = pid - g.out0;
   if (!g.ok || g.nb <= 0 || local < 0) return false;
   divmod(local, g.nb, r, c);
@@ -730,19 +740,25 @@ __device__ __forceinline__ bool locate(const SegArgs& sa, int64_t pid, Segment& 
 
 template <int K, bool FIXED, bool Z3>
 __global__ __launch_bounds__(kExactBlock)
-__attribute__((amdgpu_waves_per_eu(fwd_waves_per_simd<K>()))) void k_matrix_exact(ExactArgs m) {
+__attribute__((amdgpu_waves_per_eu(4))) void k_matrix_exact(ExactArgs m) {
   constexpr int CAP = 2 * K;
   __shared__ float2 s_pt[CAP * kExactBlock];
   __shared__ uint16_t s_cd[CAP * kExactBlock];
   const int tid = threadIdx.x;
   int64_t n = *m.count;
   n = n < m.capacity ? n : m.capacity;
-  for (int64_t e = (int64_t)blockIdx.x * kExactBlock + tid; e < n;
-       e += (int64_t)gridDim.x * kExactBlock) {
+  // each wavefront a contiguous range of entries, 64 at a time: consecutive
+  // entries mostly share a segment, which is then searched once
+  const int64_t wid = ((int64_t)blockIdx.x * kExactBlock + tid) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * kExactBlock) >> 6;
+  const int64_t per = (((n + nw - 1) / nw) + 63) & ~(int64_t)63;
+  const int64_t e_end = min(n, wid * per + per);
+  SegCache sc;
+  for (int64_t e = wid * per + (tid & 63); e < e_end; e += 64) {
     const int64_t pid = m.pair_id[e];
     Segment g;
     int64_t r = 0, c = 0;
-    if (!locate(m.seg, pid, g, r, c)) continue;  // not written by the cull on these shapes
+    if (!locate(m.seg, pid, sc, g, r, c)) continue;  // not written by the cull on these shapes
     int64_t ia = g.a0 + r, ib = g.b0 + c;
     if (m.seg.self_pairs && r > c) {  // one unordered pair: the lower index is P
       const int64_t t = ia;
