@@ -501,11 +501,12 @@ def _cpu_model():
 
 def _cpu_baseline_scenes(d, frac=0.1, seed=2011):
     """The oracle's per-scene self-pair matrix, forward + analytic backward,
-    on a seeded sample of 10% of the scenes (every pair of each sampled
-    scene), run on one thread and on the host's cores (the sampled scenes in
-    parallel, one per thread; ctypes releases the GIL), at least 3 runs each,
-    median; pairs/s scales linearly to the whole workload (each pair costs the
-    same on average, independent of its scene)."""
+    on a seeded sample of the scenes (10% of them, or one per host thread up
+    to 16 if that is more; every pair of each sampled scene), run on one
+    thread and on the host's cores (the sampled scenes in parallel, one per
+    thread; ctypes releases the GIL), at least 3 runs each, median; pairs/s
+    scales linearly to the whole workload (each pair costs the same on
+    average, independent of its scene)."""
     import numpy as np
 
     import oracle
@@ -513,8 +514,9 @@ def _cpu_baseline_scenes(d, frac=0.1, seed=2011):
     off, xy, lo, hi, g = d["off"], d["a_xy"], d["a_zlo"], d["a_zhi"], d["grad"]
     out_off = d["out_off"]
     nsc = len(off) - 1
-    pick = np.sort(np.random.default_rng(seed).choice(nsc, max(1, round(frac * nsc)),
-                                                      replace=False))
+    host = max(1, min(os.cpu_count() or 1, 16))
+    pick = np.sort(np.random.default_rng(seed).choice(
+        nsc, min(nsc, max(1, round(frac * nsc), host)), replace=False))
     jobs = []
     for s in pick:
         o0, o1 = int(off[s]), int(off[s + 1])
@@ -531,7 +533,7 @@ def _cpu_baseline_scenes(d, frac=0.1, seed=2011):
         for j in jobs:
             one(j)
 
-    threads = max(1, min(len(jobs), os.cpu_count() or 1, 16))
+    threads = max(1, min(len(jobs), host))
 
     def parallel():
         with ThreadPoolExecutor(max_workers=threads) as ex:
@@ -540,7 +542,7 @@ def _cpu_baseline_scenes(d, frac=0.1, seed=2011):
     t1, r1 = _timed_runs(serial, min_s=0.0)
     tn, rn = _timed_runs(parallel, min_s=0.0)
     return {"value": round(pairs / tn, 1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": (f"seeded 10% of the scenes ({len(pick)} of {nsc}: {pairs} self pairs), "
+            "sample": (f"seeded {len(pick)} of the {nsc} scenes ({pairs} self pairs), "
                        f"forward + backward, one scene per thread, x {rn} runs, median "
                        f"{tn:.3f} s per run; scales to the whole workload by pairs"),
             "value_1_thread": round(pairs / t1, 1),
