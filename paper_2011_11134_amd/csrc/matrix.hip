@@ -754,8 +754,14 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_matrix_exact(ExactArgs m) {
   const int64_t per = (((n + nw - 1) / nw) + 63) & ~(int64_t)63;
   const int64_t e_end = min(n, wid * per + per);
   SegCache sc;
+  // 4-slot pairs: the next step's ids are loaded while this step's pairs are
+  // evaluated (the 8-slot kernel has no registers to spare for them)
+  constexpr bool PREFETCH = K == 4;
+  int64_t pid_next = 0;
+  if (PREFETCH && wid * per + (tid & 63) < e_end) pid_next = m.pair_id[wid * per + (tid & 63)];
   for (int64_t e = wid * per + (tid & 63); e < e_end; e += 64) {
-    const int64_t pid = m.pair_id[e];
+    const int64_t pid = PREFETCH ? pid_next : m.pair_id[e];
+    if (PREFETCH && e + 64 < e_end) pid_next = m.pair_id[e + 64];
     Segment g;
     int64_t r = 0, c = 0;
     if (!locate(m.seg, pid, sc, g, r, c)) continue;  // not written by the cull on these shapes
