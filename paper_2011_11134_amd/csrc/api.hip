@@ -78,8 +78,9 @@ int read_err(dgal_ctx* ctx, hipStream_t stream, int* out) {
 // then three runs between HIP events on the caller's stream), keeping its
 // faster pass; a candidate that raises the device error word (a table too
 // small for its tile shape, say) is dropped and the word cleared.  The first
-// candidate is the built-in shape, which another must beat by more than 2%
-// to be chosen (run-to-run noise is about that size).  The choice is kept in
+// candidate is the built-in shape; the fastest other one is timed against it
+// three more times, alternately, and must beat it there by more than 2% to be
+// chosen (run-to-run noise is about that size).  The choice is kept in
 // the context and the store (and written to the cache file, if one is set),
 // and the call's outputs come from one more run of it.  Tuning is skipped
 // while the error word already holds an error.  `fix` (optional) overrides
@@ -135,12 +136,35 @@ int run_tuned(dgal_ctx* ctx, const TuneKey& key, const std::vector<dgal::LaunchS
       }
     }
   }
+  int best = -1;
+  if (st == DGAL_OK)
+    for (size_t c = 0; c < cands.size(); ++c)
+      if (best_of[c] >= 0.f && (best < 0 || best_of[c] < best_of[best])) best = (int)c;
+  // The minimum over many noisy timings favours a lucky draw: a challenger
+  // is timed again against the built-in shape, alternately, and the verdict
+  // rests on these fresh timings alone.
+  if (st == DGAL_OK && best > 0 && best_of[0] >= 0.f) {
+    float again[2] = {-1.f, -1.f};
+    for (int round = 0; round < 3 && st == DGAL_OK; ++round)
+      for (int k = 0; k < 2 && st == DGAL_OK; ++k) {
+        const size_t c = k == 0 ? 0 : (size_t)best;
+        if (hipEventRecord(e0, stream) != hipSuccess) st = DGAL_EHIP;
+        for (int r = 0; r < 3 && st == DGAL_OK; ++r) st = go(cands[c]);
+        float ms = 0.f;
+        if (st == DGAL_OK && (hipEventRecord(e1, stream) != hipSuccess ||
+                              hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          st = DGAL_EHIP;
+        if (st == DGAL_OK && (again[k] < 0.f || ms < again[k])) again[k] = ms;
+      }
+    if (st == DGAL_OK) {
+      best_of[0] = again[0];
+      best_of[best] = again[1];
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != DGAL_OK) return st;
-  int best = -1;
-  for (size_t c = 0; c < cands.size(); ++c)
-    if (best_of[c] >= 0.f && (best < 0 || best_of[c] < best_of[best])) best = (int)c;
   if (best < 0) return go(dgal::LaunchShape());  // every candidate failed: its error stands
   if (best != 0 && best_of[0] >= 0.f && best_of[best] > 0.98f * best_of[0]) best = 0;
   const float best_ms = best_of[best];
@@ -168,12 +192,14 @@ std::vector<dgal::LaunchShape> pair_grids(int cus) {
 }
 
 // Tile rows (unless the caller fixed them) x persistent grids of the count
-// and exact passes.
+// and exact passes.  16-row tiles are tried only when the caller fixed them:
+// the backward's 8-row groups scan each 16-row tile row's entries twice (c5
+// backward 71 -> 85 us), a cost the forward's timing cannot see.
 std::vector<dgal::LaunchShape> matrix_fwd_shapes(int fixed_rows) {
   std::vector<dgal::LaunchShape> v;
-  for (int r : {8, 4, 16}) {  // the built-in shape (8, 16, 8) first
-    if (fixed_rows != 0 && r != fixed_rows) continue;
-    for (int c : {16, 8, 32})
+  for (int r : {8, 4, 16}) {  // the built-in shape (8, 32, 8) first
+    if (fixed_rows != 0 ? r != fixed_rows : r == 16) continue;
+    for (int c : {32, 16, 64})
       for (int e : {8, 4, 16}) {
         dgal::LaunchShape s;
         s.tile_rows = r;

@@ -1143,7 +1143,9 @@ int matrix_forward(const CtxView& ctx, dgal_polys a, dgal_polys b, const int64_t
   x.cap = a.kmax + b.kmax;
   x.err = ctx.err;
   x.stats = ctx.stats;
-  int64_t cull_grid = (int64_t)ctx.cus * (shape.cull_mult > 0 ? shape.cull_mult : 16);
+  // 32 workgroups per CU by default: ranges of one or two tiles a wavefront
+  // (c5: 110 us at 32, 48 or 64, 116 us at 16); a single block is capped below
+  int64_t cull_grid = (int64_t)ctx.cus * (shape.cull_mult > 0 ? shape.cull_mult : 32);
   if (!segmented) cull_grid = std::min(cull_grid, ceil_div(single_tiles, kCullBlock / 64));
   const int exact_grid = ctx.cus * (shape.exact_mult > 0 ? shape.exact_mult : 8);
   const bool fixed = a.nv == nullptr && b.nv == nullptr && a.kmax == K && b.kmax == K &&
