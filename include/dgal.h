@@ -238,10 +238,11 @@ enum { DGAL_PAIRS = 0, DGAL_MATRIX = 1 };
  * Outputs (overwritten; padded vertex slots are written 0):
  *   grad_a_xy [a.count][a.kmax][2], grad_b_xy [b.count][b.kmax][2] fp32
  *   grad_a_z, grad_b_z [count][2] fp32 = (d/dzlo, d/dzhi); NULL for 2D.
- * The matrix mode sums each row's gradient over its tiles in LDS (their
- * order, and so the low-order bits, may vary from run to run) and writes every
- * row once; with two different sets the column gradients are added with fp32
- * global atomics.
+ * The matrix mode sums each row's gradient in a fixed order (its entries in
+ * work-list order) and writes every row once, so rows (and every self-pair
+ * gradient) are the same bits from run to run; with two different sets the
+ * column gradients are added with fp32 global atomics (their order, and so
+ * the low-order bits, may vary).
  * The matrix mode reads the tile shape the forward recorded in
  * saved->tile_rows.
  * DGAL_EINVAL: as the forward, plus a NULL required output or saved state, an

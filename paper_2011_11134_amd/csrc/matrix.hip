@@ -23,8 +23,10 @@
 // segment computed on the device by k_seg_prep, so everything is
 // graph-capturable).  The backward (k_matrix_bwd) gives one wavefront a row
 // group of 8 rows, whatever the tile shape: the entries of the tile rows
-// that cover it are one contiguous range of the work list; the row
-// gradients are summed in LDS and every row is written once.  Self pairs need
+// that cover it are one contiguous range of the work list; each step's row
+// gradients are summed without atomics (sorted by row in LDS, each lane
+// adding up one (row, vertex) run in a fixed order) and every row is written
+// once.  Self pairs need
 // nothing else: entries (i, k) and (k, i) are one unordered pair evaluated with
 // the lower index first, so the row role of either entry is that pair's
 // gradient for the row's box, weighted by both entries' upstream gradients;
@@ -832,35 +834,93 @@ constexpr int bwd_block() {
   return K == 8 ? 128 : 256;
 }
 
+// Sums one step's row gradients (64 entries, each one row's H value pairs:
+// a vertex's x and y, or the z-extent's two ends) per (row, pair) into the
+// lanes' accumulators without atomics (LDS float atomic adds measured slow
+// here: 10 a lane per step cost the c5 backward ~15 us).  The lanes' pairs go
+// to the wavefront's own LDS columns ordered by row (the row's offset, then
+// the lane's rank among that row's lanes); lane c then adds up the run of
+// combination c = (row c / H, pair c % H), and c + 64, ..., in lane order: a
+// fixed order, so the sums are the same from run to run.  rl < 0: the lane
+// holds nothing.  Called by all 64 lanes.
+template <int H, int BLOCK>
+__device__ __forceinline__ void step_row_sums(int rl, const float2 (&gv)[H], float2* stage,
+                                              float2 (&acc)[(kGroupRows * H + 63) / 64]) {
+  constexpr int NACC = (kGroupRows * H + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  int pos = 0, base = 0, most = 0;
+  int off[kGroupRows], cnt[kGroupRows];
+#pragma unroll
+  for (int r = 0; r < kGroupRows; ++r) {
+    const uint64_t mr = __ballot(rl == r);
+    const int c = __popcll(mr);
+    if (rl == r)
+      pos = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mr >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mr, 0u));
+    off[r] = base;
+    cnt[r] = c;
+    base += c;
+    most = max(most, c);
+  }
+  if (base == 0) return;  // uniform: nothing in this step
+  if (rl >= 0) {
+#pragma unroll
+    for (int h = 0; h < H; ++h) stage[h * BLOCK + pos] = gv[h];
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < NACC; ++j) {
+    const int c = lane + 64 * j;
+    const int r = c / H, h = c - r * H;
+    int o = 0, n = 0;  // the run of row r (none past the last row)
+#pragma unroll
+    for (int rr = 0; rr < kGroupRows; ++rr) {
+      if (r == rr) {
+        o = off[rr];
+        n = cnt[rr];
+      }
+    }
+    const float2* run = stage + h * BLOCK + o;
+    float sx = 0.f, sy = 0.f;
+    for (int i = 0; i < most; ++i) {
+      if (i < n) {
+        const float2 v = run[i];
+        sx += v.x;
+        sy += v.y;
+      }
+    }
+    acc[j].x += sx;
+    acc[j].y += sy;
+  }
+  wave_sync();  // the columns are the pair kernels' staging again
+}
+
 template <int K, bool FIXED, bool Z3>
-__global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
+__global__ __launch_bounds__(bwd_block<K>())
+__attribute__((amdgpu_waves_per_eu(K == 4 ? 4 : 2))) void k_matrix_bwd(BwdArgs m) {
   constexpr int BLOCK = bwd_block<K>();
   constexpr int WAVES = BLOCK / 64;
   constexpr int CAP = 2 * K;
-  constexpr int ROW = 2 * K + 2;  // accumulated floats per row: xy slots, then (zlo, zhi)
-  // Each quarter of the wavefront adds into its own copy of the row sums:
-  // the entries of a row group come from few rows, so one copy would see
-  // up to 64 lanes adding into the same 8 rows' words (serialised LDS
-  // atomics); four copies cut that by four and are summed at the end.
-  constexpr int COPIES = 4;
-  constexpr int ACC = kGroupRows * ROW;
-  __shared__ float s_acc[WAVES][COPIES * ACC];
+  constexpr int H = K + (Z3 ? 1 : 0);  // a row's value pairs: vertices, then (zlo, zhi)
+  constexpr int NACC = (kGroupRows * H + 63) / 64;
+  static_assert(H <= CAP, "a step's row values fit the staging columns");
   __shared__ float2 s_v[CAP * BLOCK];
   __shared__ float2 s_g[CAP * BLOCK];
   __shared__ uint2 s_tab[256];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the row-group walk is scalar
-  float* acc_w = s_acc[wave];
+  float2* stage = s_v + wave * 64;  // this wavefront's columns of the staging
   fill_code_table<K, FIXED, BLOCK>(s_tab);
   __syncthreads();
   const bool segmented = m.seg.a_off != nullptr;
   const int64_t total = segmented ? m.seg.group_prefix[m.seg.nseg] : m.single_groups;
+  const int kx = m.a.kmax;
   if (segmented) {
     // rows that no row group writes are zeroed here: rows outside every
     // segment, and the rows of a segment without row groups (rejected, or
     // without columns); every other row is written once by its row group
-    const int64_t rowlen = (int64_t)m.a.kmax * 2;
+    const int64_t rowlen = (int64_t)kx * 2;
     auto zero_rows = [&](int64_t r0, int64_t r1, int64_t t, int64_t nt) {
       r0 = max(r0, (int64_t)0);
       r1 = min(r1, m.a.count);
@@ -891,129 +951,133 @@ __global__ __launch_bounds__(bwd_block<K>()) void k_matrix_bwd(BwdArgs m) {
     const int64_t tbase = segmented ? m.seg.tile_prefix[s] : 0;
     const int64_t t0 = tbase + (r0 >> rlog) * nct;
     const int64_t t1 = tbase + (((r0 + nr - 1) >> rlog) + 1) * nct - 1;
-    for (int i = lane; i < COPIES * ACC; i += 64) acc_w[i] = 0.f;
-    wave_sync();
     const bool have = t1 < m.tile_capacity;
     const int64_t e_begin = have ? m.tile_start[t0] : 0;
     const int64_t e_end = have ? m.tile_start[t1] + m.tile_count[t1] : 0;
-    {
-      for (int64_t e = e_begin + lane; e < e_end; e += 64) {
-        if (e < 0 || e >= m.capacity) continue;
-        const int nx = m.s_nx[e];
-        if (nx == 0) continue;  // empty intersection: zero gradient
-        const int64_t pid = m.pair_id[e];
-        const int64_t local = pid - g.out0;
-        if (local < 0 || g.nb <= 0) continue;
-        int64_t rg, col;  // row and column within the segment
-        divmod(local, g.nb, rg, col);
-        const int rl = (int)(rg - r0);
-        if (rl < 0 || rl >= nr) continue;
-        int64_t ia = g.a0 + rg, ib = g.b0 + col;
-        // self pairs: an entry below the diagonal was evaluated with the
-        // column's box as P (the lower index), so the row's box is Q there
-        const bool swapped = m.seg.self_pairs && rg > col;
-        if (swapped) {
-          const int64_t t = ia;
-          ia = ib;
-          ib = t;
-        }
-        const int n1 = FIXED ? K : poly_count(m.a.nv, ia, m.a.kmax);
-        const int n2 = FIXED ? K : poly_count(m.b.nv, ib, m.b.kmax);
-        Poly<K> P, Q;
-        load_poly<K, FIXED>(m.a.xy, ia, m.a.kmax, m.a.vec4, n1, P);
-        load_poly<K, FIXED>(m.b.xy, ib, m.b.kmax, m.b.vec4, n2, Q);
-        uint32_t codes[K / 2];
-        const uint8_t* row = m.s_flags + e * (int64_t)m.cap;
-        if (m.flags_vec) {
-          if constexpr (K == 4) {
-            const uint2 w = *reinterpret_cast<const uint2*>(row);
-            codes[0] = w.x;
-            codes[1] = w.y;
-          } else {
-            const uint4 w = *reinterpret_cast<const uint4*>(row);
-            codes[0] = w.x;
-            codes[1] = w.y;
-            codes[2] = w.z;
-            codes[3] = w.w;
-          }
+    float2 acc[NACC];
+#pragma unroll
+    for (int j = 0; j < NACC; ++j) acc[j] = make_float2(0.f, 0.f);
+    // one entry: its row in the group and the row box's gradient in gv
+    // (every slot written), or -1 (gv untouched)
+    auto entry = [&](int64_t e, float2 (&gv)[H]) -> int {
+      if (e < 0 || e >= e_end || e >= m.capacity) return -1;
+      const int nx = m.s_nx[e];
+      if (nx == 0) return -1;  // empty intersection: zero gradient
+      const int64_t pid = m.pair_id[e];
+      const int64_t local = pid - g.out0;
+      if (local < 0 || g.nb <= 0) return -1;
+      int64_t rg, col;  // row and column within the segment
+      divmod(local, g.nb, rg, col);
+      const int rl = (int)(rg - r0);
+      if (rl < 0 || rl >= nr) return -1;
+      int64_t ia = g.a0 + rg, ib = g.b0 + col;
+      // self pairs: an entry below the diagonal was evaluated with the
+      // column's box as P (the lower index), so the row's box is Q there
+      const bool swapped = m.seg.self_pairs && rg > col;
+      if (swapped) {
+        const int64_t t = ia;
+        ia = ib;
+        ib = t;
+      }
+      const int n1 = FIXED ? K : poly_count(m.a.nv, ia, m.a.kmax);
+      const int n2 = FIXED ? K : poly_count(m.b.nv, ib, m.b.kmax);
+      Poly<K> P, Q;
+      load_poly<K, FIXED>(m.a.xy, ia, m.a.kmax, m.a.vec4, n1, P);
+      load_poly<K, FIXED>(m.b.xy, ib, m.b.kmax, m.b.vec4, n2, Q);
+      uint32_t codes[K / 2];
+      const uint8_t* row = m.s_flags + e * (int64_t)m.cap;
+      if (m.flags_vec) {
+        if constexpr (K == 4) {
+          const uint2 w = *reinterpret_cast<const uint2*>(row);
+          codes[0] = w.x;
+          codes[1] = w.y;
         } else {
+          const uint4 w = *reinterpret_cast<const uint4*>(row);
+          codes[0] = w.x;
+          codes[1] = w.y;
+          codes[2] = w.z;
+          codes[3] = w.w;
+        }
+      } else {
 #pragma unroll
-          for (int w = 0; w < K / 2; ++w) codes[w] = 0xffffffffu;
+        for (int w = 0; w < K / 2; ++w) codes[w] = 0xffffffffu;
 #pragma unroll
-          for (int k = 0; k < CAP; ++k) {
-            if (k < m.cap) {
-              const uint32_t cc = row[k];
-              codes[k >> 2] = (codes[k >> 2] & ~(0xffu << ((k & 3) * 8))) | (cc << ((k & 3) * 8));
-            }
+        for (int k = 0; k < CAP; ++k) {
+          if (k < m.cap) {
+            const uint32_t cc = row[k];
+            codes[k >> 2] = (codes[k >> 2] & ~(0xffu << ((k & 3) * 8))) | (cc << ((k & 3) * 8));
           }
         }
-        // self pairs: entries (i, k) and (k, i) are one unordered pair with
-        // one structure, so the row's box takes its role's gradient of that
-        // pair weighted by both entries' upstream gradients
-        float gw = m.grad[pid];
-        if (m.seg.self_pairs) gw += m.grad[g.out0 + col * g.nb + rg];
-        float lo1 = 0.f, hi1 = 0.f, lo2 = 0.f, hi2 = 0.f;
-        if (Z3) {
-          lo1 = m.a.zlo[ia];
-          hi1 = m.a.zhi[ia];
-          lo2 = m.b.zlo[ib];
-          hi2 = m.b.zhi[ib];
-        }
-        float2 gP[K], gQ[K], gz1, gz2;
-        bool thin;
-        pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
-                                           s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2, thin);
-        if (thin) {  // rare: the gradient again in fp64, from the polygons reloaded
-          load_poly<K, FIXED>(m.a.xy, opaque(ia), m.a.kmax, m.a.vec4, n1, P);
-          load_poly<K, FIXED>(m.b.xy, opaque(ib), m.b.kmax, m.b.vec4, n2, Q);
-          stage_pair<K, BLOCK>(s_v + tid, P, Q);
-          pair_backward64<K, FIXED, Z3, BLOCK>(n1, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
-                                               s_v + tid, s_g + tid, gP, gQ, gz1, gz2);
-        }
-        float* acc = acc_w + (lane >> 4) * ACC + rl * ROW;
-        const int nr_own = swapped ? n2 : n1;  // the row box's vertex count
+      }
+      // self pairs: entries (i, k) and (k, i) are one unordered pair with
+      // one structure, so the row's box takes its role's gradient of that
+      // pair weighted by both entries' upstream gradients
+      float gw = m.grad[pid];
+      if (m.seg.self_pairs) gw += m.grad[g.out0 + col * g.nb + rg];
+      float lo1 = 0.f, hi1 = 0.f, lo2 = 0.f, hi2 = 0.f;
+      if (Z3) {
+        lo1 = m.a.zlo[ia];
+        hi1 = m.a.zhi[ia];
+        lo2 = m.b.zlo[ib];
+        hi2 = m.b.zhi[ib];
+      }
+      float2 gP[K], gQ[K], gz1, gz2;
+      bool thin;
+      pair_backward<K, FIXED, Z3, BLOCK>(P, n1, Q, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
+                                         s_v + tid, s_g + tid, s_tab, gP, gQ, gz1, gz2, thin);
+      if (thin) {  // rare: the gradient again in fp64, from the polygons reloaded
+        load_poly<K, FIXED>(m.a.xy, opaque(ia), m.a.kmax, m.a.vec4, n1, P);
+        load_poly<K, FIXED>(m.b.xy, opaque(ib), m.b.kmax, m.b.vec4, n2, Q);
+        stage_pair<K, BLOCK>(s_v + tid, P, Q);
+        pair_backward64<K, FIXED, Z3, BLOCK>(n1, n2, gw, nx, codes, lo1, hi1, lo2, hi2,
+                                             s_v + tid, s_g + tid, gP, gQ, gz1, gz2);
+      }
+      const int nr_own = swapped ? n2 : n1;  // the row box's vertex count
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const bool own = FIXED || k < nr_own;  // padded slots: 0
+        gv[k] = own ? (swapped ? gQ[k] : gP[k]) : make_float2(0.f, 0.f);
+      }
+      if constexpr (Z3) gv[K] = swapped ? gz2 : gz1;
+      if (!m.seg.self_pairs) {
+        float* ob = m.gb_xy + ib * (int64_t)m.b.kmax * 2;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          if (FIXED || k < nr_own) {
-            atomicAdd(acc + 2 * k, swapped ? gQ[k].x : gP[k].x);
-            atomicAdd(acc + 2 * k + 1, swapped ? gQ[k].y : gP[k].y);
+          if ((FIXED || k < n2) && k < m.b.kmax) {
+            unsafeAtomicAdd(ob + 2 * k, gQ[k].x);
+            unsafeAtomicAdd(ob + 2 * k + 1, gQ[k].y);
           }
         }
         if (Z3) {
-          atomicAdd(acc + 2 * K, swapped ? gz2.x : gz1.x);
-          atomicAdd(acc + 2 * K + 1, swapped ? gz2.y : gz1.y);
-        }
-        if (!m.seg.self_pairs) {
-          float* ob = m.gb_xy + ib * (int64_t)m.b.kmax * 2;
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            if ((FIXED || k < n2) && k < m.b.kmax) {
-              unsafeAtomicAdd(ob + 2 * k, gQ[k].x);
-              unsafeAtomicAdd(ob + 2 * k + 1, gQ[k].y);
-            }
-          }
-          if (Z3) {
-            unsafeAtomicAdd(m.gb_z + 2 * ib, gz2.x);
-            unsafeAtomicAdd(m.gb_z + 2 * ib + 1, gz2.y);
-          }
+          unsafeAtomicAdd(m.gb_z + 2 * ib, gz2.x);
+          unsafeAtomicAdd(m.gb_z + 2 * ib + 1, gz2.y);
         }
       }
+      return rl;
+    };
+    for (int64_t e0 = e_begin; e0 < e_end; e0 += 64) {  // uniform: every lane sums
+      float2 gv[H];  // read only where rl >= 0
+      const int rl = entry(e0 + lane, gv);
+      step_row_sums<H, BLOCK>(rl, gv, stage, acc);
     }
-    wave_sync();
     // each row of a belongs to exactly one row group: plain stores
-    for (int i = lane; i < nr * ROW; i += 64) {
-      const int rl = i / ROW, k = i - rl * ROW;
-      const int64_t ia = g.a0 + r0 + rl;
-      float v = acc_w[i];
 #pragma unroll
-      for (int c = 1; c < COPIES; ++c) v += acc_w[c * ACC + i];
-      if (k < 2 * K) {
-        if (k < 2 * m.a.kmax) m.ga_xy[ia * (int64_t)m.a.kmax * 2 + k] = v;
-      } else if (Z3) {
-        m.ga_z[ia * 2 + (k - 2 * K)] = v;
+    for (int j = 0; j < NACC; ++j) {
+      const int c = lane + 64 * j;
+      const int r = c / H, h = c - r * H;
+      if (r < nr) {
+        const int64_t ia = g.a0 + r0 + r;
+        if (h < K) {
+          if (h < kx) {
+            m.ga_xy[(ia * kx + h) * 2] = acc[j].x;
+            m.ga_xy[(ia * kx + h) * 2 + 1] = acc[j].y;
+          }
+        } else if (Z3) {
+          m.ga_z[ia * 2] = acc[j].x;
+          m.ga_z[ia * 2 + 1] = acc[j].y;
+        }
       }
     }
-    wave_sync();
   }
 }
 
