@@ -961,31 +961,11 @@ __attribute__((amdgpu_waves_per_eu(K == 4 ? 4 : 2))) void k_matrix_bwd(BwdArgs m
     // (every slot written), or -1 (gv untouched)
     auto entry = [&](int64_t e, float2 (&gv)[H]) -> int {
       if (e < 0 || e >= e_end || e >= m.capacity) return -1;
+      // the entry's saved state in one round of loads (none waits for another)
       const int nx = m.s_nx[e];
-      if (nx == 0) return -1;  // empty intersection: zero gradient
       const int64_t pid = m.pair_id[e];
-      const int64_t local = pid - g.out0;
-      if (local < 0 || g.nb <= 0) return -1;
-      int64_t rg, col;  // row and column within the segment
-      divmod(local, g.nb, rg, col);
-      const int rl = (int)(rg - r0);
-      if (rl < 0 || rl >= nr) return -1;
-      int64_t ia = g.a0 + rg, ib = g.b0 + col;
-      // self pairs: an entry below the diagonal was evaluated with the
-      // column's box as P (the lower index), so the row's box is Q there
-      const bool swapped = m.seg.self_pairs && rg > col;
-      if (swapped) {
-        const int64_t t = ia;
-        ia = ib;
-        ib = t;
-      }
-      const int n1 = FIXED ? K : poly_count(m.a.nv, ia, m.a.kmax);
-      const int n2 = FIXED ? K : poly_count(m.b.nv, ib, m.b.kmax);
-      Poly<K> P, Q;
-      load_poly<K, FIXED>(m.a.xy, ia, m.a.kmax, m.a.vec4, n1, P);
-      load_poly<K, FIXED>(m.b.xy, ib, m.b.kmax, m.b.vec4, n2, Q);
-      uint32_t codes[K / 2];
       const uint8_t* row = m.s_flags + e * (int64_t)m.cap;
+      uint32_t codes[K / 2];
       if (m.flags_vec) {
         if constexpr (K == 4) {
           const uint2 w = *reinterpret_cast<const uint2*>(row);
@@ -1009,6 +989,27 @@ __attribute__((amdgpu_waves_per_eu(K == 4 ? 4 : 2))) void k_matrix_bwd(BwdArgs m
           }
         }
       }
+      if (nx == 0) return -1;  // empty intersection: zero gradient
+      const int64_t local = pid - g.out0;
+      if (local < 0 || g.nb <= 0) return -1;
+      int64_t rg, col;  // row and column within the segment
+      divmod(local, g.nb, rg, col);
+      const int rl = (int)(rg - r0);
+      if (rl < 0 || rl >= nr) return -1;
+      int64_t ia = g.a0 + rg, ib = g.b0 + col;
+      // self pairs: an entry below the diagonal was evaluated with the
+      // column's box as P (the lower index), so the row's box is Q there
+      const bool swapped = m.seg.self_pairs && rg > col;
+      if (swapped) {
+        const int64_t t = ia;
+        ia = ib;
+        ib = t;
+      }
+      const int n1 = FIXED ? K : poly_count(m.a.nv, ia, m.a.kmax);
+      const int n2 = FIXED ? K : poly_count(m.b.nv, ib, m.b.kmax);
+      Poly<K> P, Q;
+      load_poly<K, FIXED>(m.a.xy, ia, m.a.kmax, m.a.vec4, n1, P);
+      load_poly<K, FIXED>(m.b.xy, ib, m.b.kmax, m.b.vec4, n2, Q);
       // self pairs: entries (i, k) and (k, i) are one unordered pair with
       // one structure, so the row's box takes its role's gradient of that
       // pair weighted by both entries' upstream gradients
