@@ -405,7 +405,7 @@ int dgal_path_stats(dgal_ctx *ctx, int64_t *pairs, int64_t *fp64_pairs, int64_t 
  * three timed runs, HIP events on the caller's stream, the faster pass
  * kept), drops any candidate that raises the sticky device error (a tile
  * table too small for its shape), keeps the fastest (the built-in shape
- * unless another beats it by more than 2%) in the context and in the store
+ * unless another beats it by more than 5%) in the context and in the store
  * (and in the DGAL_TUNE_CACHE file, if set), and produces its outputs with
  * one more run of it; later calls of that kind use the choice, enabled or
  * not.  That first call synchronises the stream (so it
