@@ -1,5 +1,6 @@
 """GPU parity of the IoU-matrix path (LDS tiles, cull, survivor compaction,
-persistent segment schedule, saved non-empty pairs, atomic backward) and of
+persistent segment schedule, saved non-empty pairs, a backward that sums rows
+without atomics and adds a second set's columns with global atomics) and of
 per-scene 3D self-pairs, against the FP64 oracle."""
 import numpy as np
 import pytest
@@ -278,6 +279,59 @@ def test_scenes_small_forward_backward(dg):
     ga2, _, gaz2, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, txy, a_z=(tlo, thi),
                                              self_pairs=True)
     assert torch.equal(ga2, ga) and torch.equal(gaz2, gaz)
+
+
+@pytest.mark.parametrize("two_sets", [False, True])
+def test_extruded_polygons_3d(dg, two_sets):
+    """3D IoU of extruded convex 3..8-gons (counted vertices with z-extents:
+    the 8-slot 3D kernels, whose backward sums nine value pairs per row, so
+    a row group's 72 (row, pair) sums take a second round of lanes), as
+    ragged per-scene self pairs (a one-box scene included) or ragged two-set
+    segments: IoU on every pair and gradients against the oracle."""
+    d = synth.c4_polygons(n=700, seed=15)
+    rng = np.random.default_rng(19)
+    xy, nv = d["a_xy"][:700], d["a_nv"][:700]
+    lo = rng.uniform(-2.0, 1.0, 700).astype(np.float32)
+    hi = (lo + rng.uniform(0.5, 2.0, 700)).astype(np.float32)
+    if two_sets:
+        a, anv, az = xy[:350], nv[:350], (lo[:350], hi[:350])
+        b, bnv, bz = xy[350:], nv[350:], (lo[350:], hi[350:])
+        a_off = np.array([0, 120, 120, 300, 350], np.int64)
+        b_off = np.array([0, 60, 200, 201, 350], np.int64)
+        _say(f"case: extruded polygons, two sets, segments {a_off.tolist()} / {b_off.tolist()}")
+        iou, saved, seg = dg.iou_matrix(dev_t(a), dev_t(b), dev_t(anv), dev_t(bnv),
+                                        (dev_t(az[0]), dev_t(az[1])),
+                                        (dev_t(bz[0]), dev_t(bz[1])), a_off, b_off, save=True)
+        ref, _ = oracle.iou_matrix(a, b, anv, bnv, az, bz, a_off, b_off)
+    else:
+        off = np.array([0, 150, 151, 400, 700], np.int64)
+        _say(f"case: extruded polygons, self pairs, scenes {off.tolist()}")
+        a, anv, az = xy, nv, (lo, hi)
+        iou, saved, seg = dg.iou_matrix(dev_t(a), None, dev_t(anv), None,
+                                        (dev_t(lo), dev_t(hi)), None, off, self_pairs=True,
+                                        save=True)
+        ref, _ = oracle.iou_matrix(a, a_nv=anv, a_z=az, a_off=off, self_pairs=True)
+    dg.check_errors()
+    assert np.abs(iou.cpu().numpy() - ref).max() <= IOU_TOL
+    g = rng.uniform(-1, 1, ref.shape[0]).astype(np.float32)
+    if two_sets:
+        ga, gb, gaz, gbz = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(a), dev_t(b),
+                                                  dev_t(anv), dev_t(bnv),
+                                                  (dev_t(az[0]), dev_t(az[1])),
+                                                  (dev_t(bz[0]), dev_t(bz[1])))
+        ia, ib, fl = _aabb_candidates(a, b, a_off, b_off)
+        ra, sa, rb, sb = _grad_reference(a, b, g, ia, ib, fl, anv, bnv, az, bz)
+        _assert_box_grads(_box_grads(ga, gaz), ra, sa, "rows")
+        e = _assert_box_grads(_box_grads(gb, gbz), rb, sb, "columns")
+    else:
+        ga, _, gaz, _ = dg.iou_matrix_backward(dev_t(g), saved, seg, dev_t(a), None, dev_t(anv),
+                                               None, (dev_t(lo), dev_t(hi)), None,
+                                               self_pairs=True)
+        ia, ib, fl = _aabb_candidates(a, a, off, off, True)
+        rr, sc = _grad_reference(a, a, g, ia, ib, fl, anv, anv, az, az, self_pairs=True)
+        e = _assert_box_grads(_box_grads(ga, gaz), rr, sc, "scenes")
+    _say(f"extruded polygons ({'two sets' if two_sets else 'self pairs'}): "
+         f"{int(saved.count.item())} saved pairs, max rel err {e:.2e}")
 
 
 def test_scenes_with_empty_and_single_box_segments(dg):
