@@ -161,6 +161,44 @@ def test_3d_pairs(dg):
     _say(str(s))
 
 
+def test_zero_height_boxes(dg):
+    """Reading R5 on the GPU: flat 3D boxes (zlo == zhi) that overlap in BEV
+    have a union volume of zero, so their IoU is exactly 0 and their gradient
+    all zero, as in the oracle (no NaN from 0 / 0).  In a self-pair matrix of
+    flat boxes every element off the diagonal is 0 (the diagonal keeps R15's
+    exact 1) and the gradient is zero."""
+    d = synth.c1_pairs(n=4096, seed=61)
+    a, b = d["a_xy"], d["b_xy"]
+    z = np.random.default_rng(62).uniform(-2, 1, 4096).astype(np.float32)
+    zz = (z, z)
+    tz = (dev_t(z), dev_t(z))
+    iou, nx, xf = dg.iou_pairs(dev_t(a), dev_t(b), a_z=tz, b_z=tz)
+    ref, rnx, _, _ = oracle.iou_pairs(a, b, a_z=zz, b_z=zz, threads=8)
+    assert (ref == 0.0).all()
+    assert (iou.cpu().numpy() == 0.0).all()
+    assert int((rnx > 0).sum()) > 1000  # many pairs reach the zero-union branch
+    g = torch.ones(4096, device="cuda")
+    ga, gb, gaz, gbz = dg.iou_pairs_backward(dev_t(a), dev_t(b), g, nx, xf, a_z=tz, b_z=tz)
+    for t in (ga, gb, gaz, gbz):
+        assert torch.isfinite(t).all() and not t.any()
+    off = np.array([0, 700, 701, 2048], np.int64)
+    xy = a[:2048]
+    mz = (dev_t(z[:2048]), dev_t(z[:2048]))
+    out, saved, seg = dg.iou_matrix(dev_t(xy), a_z=mz, a_off=off, self_pairs=True, save=True)
+    dg.check_errors()
+    flat = out.cpu().numpy()
+    diag = np.zeros(flat.shape[0], bool)
+    o = 0
+    for s in range(len(off) - 1):
+        n = int(off[s + 1] - off[s])
+        diag[o + np.arange(n) * (n + 1)] = True
+        o += n * n
+    assert (flat[diag] == 1.0).all() and (flat[~diag] == 0.0).all()
+    gm = torch.ones(flat.shape[0], device="cuda")
+    ga, _, gaz, _ = dg.iou_matrix_backward(gm, saved, seg, dev_t(xy), a_z=mz, self_pairs=True)
+    assert not ga.any() and not gaz.any()
+
+
 def test_degenerate_stress(dg):
     """Exactly degenerate contacts: the fp64 fallback and the tie rule give the
     oracle's vertex count, flag sequence (the boundary order of the moved

@@ -453,6 +453,47 @@ def test_z_tie_gradients_are_the_moved_pairs(orc):
         assert np.abs(got - ref).max() <= 1e-4 * (1.0 + np.abs(ref).max()), (i, got, ref)
 
 
+def test_zero_union_volume(orc):
+    """Reading R5 (a union of measure zero gives IoU 0 and gradient 0) on the
+    valid input that reaches it: flat 3D boxes (zlo == zhi) whose BEV
+    rectangles overlap, where the quotient would be 0 / 0.  The same boxes
+    with a positive height give the exact 3D IoU (identical boxes: 1, the
+    closed form) and finite gradients; flat, they give exactly 0 and an
+    all-zero gradient, never NaN.  A guard dropped from either the forward
+    or the backward shows up here as NaN."""
+    rng = np.random.default_rng(57)
+    rows = []
+    for k in range(10):
+        x0, y0 = rng.integers(-8, 8, 2) / 4.0
+        w, l = rng.integers(4, 12, 2) / 4.0
+        dx, dy = (rng.integers(1, 6, 2) / 8.0) if k % 2 else (0.0, 0.0)  # odd: partial overlap
+        a = [(x0, y0), (x0 + w, y0), (x0 + w, y0 + l), (x0, y0 + l)]
+        b = [(x0 + dx, y0 + dy), (x0 + dx + w, y0 + dy), (x0 + dx + w, y0 + dy + l),
+             (x0 + dx, y0 + dy + l)]
+        rows.append((a, b))
+    a = np.array([r[0] for r in rows], np.float32)
+    b = np.array([r[1] for r in rows], np.float32)
+    z0 = (rng.integers(-4, 4, len(rows)) / 4.0).astype(np.float32)
+    same = np.arange(len(rows)) % 2 == 0
+    for height in (0.0, 0.5, 2.0):
+        z = (z0, (z0 + np.float32(height)).astype(np.float32))
+        iou, nx, xf, _ = orc.iou_pairs(a, b, a_z=z, b_z=z)
+        ga, gb, gaz, gbz = orc.iou_pairs_grad(a, b, np.ones(len(rows)), nx, xf, a_z=z, b_z=z)
+        assert (nx >= 3).all()  # every BEV intersection is non-empty
+        grads = np.concatenate([ga.ravel(), gb.ravel(), gaz.ravel(), gbz.ravel()])
+        assert np.isfinite(iou).all() and np.isfinite(grads).all(), height
+        if height == 0.0:
+            assert (iou == 0.0).all() and (grads == 0.0).all()
+            continue
+        assert np.abs(iou[same] - 1.0).max() <= 1e-12
+        for i in np.nonzero(~same)[0]:
+            P = [tuple(map(Fraction, v)) for v in rows[i][0]]
+            Q = [tuple(map(Fraction, v)) for v in rows[i][1]]
+            zz = [Fraction(float(z[0][i])), Fraction(float(z[1][i]))]
+            assert abs(iou[i] - float(_exact_iou3(P, Q, zz, zz))) <= 1e-12
+        assert np.abs(grads).max() > 0
+
+
 def test_identity_disjoint_nested(orc):
     d = synth.c4_polygons(n=300, seed=21)
     a, anv = d["a_xy"], d["a_nv"]
