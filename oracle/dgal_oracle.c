@@ -43,12 +43,15 @@
  *   R3 degeneracies: symbolic perturbation, Q translated by (eps, eps^2) with
  *      eps -> 0+.  An exactly-zero orientation takes the sign of the leading
  *      eps term (see side_of_q_edge / side_of_p_edge).
- *   R4 empty intersection or a non-positive union: IoU = 0, gradient 0.
- *   R5 capacity of an intersection: n1 + n2.
- *   R6 3D IoU: BEV intersection area times z-overlap over the union volume.
- *   R7 gradient at a change of combinatorial type: the one-sided gradient of
+ *   R4 empty intersection: IoU = 0, gradient 0.
+ *   R5 a non-positive union (reached by flat 3D boxes): IoU = 0, gradient 0.
+ *   R6 capacity of an intersection: n1 + n2.
+ *   R9 gradient at a change of combinatorial type: the one-sided gradient of
  *      the structure recorded in the flags.
- *   R8 self-pair matrices (one set against itself, as in the per-scene 3D
+ *   R12 3D IoU: BEV intersection area times z-overlap over the union volume.
+ *   R15 self-pair matrices: the diagonal is exactly 1 (the IoU of a polygon
+ *      with itself), with zero gradient.
+ *   R25 self-pair matrices (one set against itself, as in the per-scene 3D
  *      IoU of Sec. IV-A): entries (r, c) and (c, r) hold the IoU of one
  *      unordered pair, evaluated once with the lower-indexed polygon as P and
  *      the higher-indexed one as Q (the polygon the tie rule R3 moves, and the
@@ -63,7 +66,7 @@
 #include <string.h>
 
 #define ORC_MAXV 8             /* most vertices of an input polygon */
-#define ORC_CAP (2 * ORC_MAXV) /* most vertices of an intersection (R5) */
+#define ORC_CAP (2 * ORC_MAXV) /* most vertices of an intersection (R6) */
 
 typedef struct { double x, y; } point;
 typedef struct { double v[3]; } hvec;     /* homogeneous 3-vector */
@@ -286,7 +289,7 @@ static point vertex_from_code(const point *P, int n1, const point *Q, int n2,
   return edge_meet(P[i], P[(i + 1) % n1], Q[j], Q[(j + 1) % n2]);
 }
 
-/* R6: z-overlap of two extents. */
+/* R12: z-overlap of two extents. */
 static double z_overlap(double lo1, double hi1, double lo2, double hi2) {
   double top = hi1 < hi2 ? hi1 : hi2;
   double bot = lo1 > lo2 ? lo1 : lo2;
@@ -856,7 +859,7 @@ int64_t oracle_iou_index_pairs(int64_t lo, int64_t hi, const int64_t *ia,
  * columns b[b_off[s]..b_off[s+1]) fill the row-major block that starts at
  * out_off[s].  self_pairs != 0 means b is a (same offsets) and the diagonal
  * of each block is 1 (the IoU of a polygon with itself); entry (r, c) is then
- * the pair evaluated with the lower index first (R8). */
+ * the pair evaluated with the lower index first (R25). */
 void oracle_iou_matrix(int nseg, const int64_t *a_off, const int64_t *b_off,
                        const int64_t *out_off, int self_pairs, const float *a_xy,
                        const uint8_t *a_nv, int ka, const float *a_zlo,
@@ -873,7 +876,7 @@ void oracle_iou_matrix(int nseg, const int64_t *a_off, const int64_t *b_off,
           *o = 1.0;
           continue;
         }
-        if (self_pairs && r > c) { /* R8: the unordered pair, lower index first */
+        if (self_pairs && r > c) { /* R25: the unordered pair, lower index first */
           int64_t t = ia;
           ia = ib;
           ib = t;
@@ -887,7 +890,7 @@ void oracle_iou_matrix(int nseg, const int64_t *a_off, const int64_t *b_off,
 /* Gradient of sum g * IoU over a segmented matrix (layout as above).  Rows
  * accumulate into ga, columns into gb (into ga as well when self_pairs, whose
  * diagonal is the constant 1 and contributes nothing; entry (r, c) with r > c
- * is the pair (c, r) of R8, so its P gradient goes to box c and its Q
+ * is the pair (c, r) of R25, so its P gradient goes to box c and its Q
  * gradient to box r).  Outputs are overwritten.  ga_z/gb_z may be NULL for
  * 2D. */
 void oracle_iou_matrix_grad(int nseg, const int64_t *a_off, const int64_t *b_off,
@@ -915,7 +918,7 @@ void oracle_iou_matrix_grad(int nseg, const int64_t *a_off, const int64_t *b_off
       for (int64_t c = 0; c < nb; ++c) {
         if (self_pairs && r == c) continue;
         int64_t ia = a_off[s] + r, ib = b_off[s] + c;
-        if (self_pairs && r > c) { /* R8 */
+        if (self_pairs && r > c) { /* R25 */
           int64_t t = ia;
           ia = ib;
           ib = t;

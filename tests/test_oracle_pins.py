@@ -824,7 +824,7 @@ def _tie_scene(rng):
 
 
 def test_self_pair_matrix_one_structure_per_pair(orc):
-    """Reading R8 pinned by what must hold for any consistent derivative: in a
+    """Reading R25 pinned by what must hold for any consistent derivative: in a
     self-pair matrix of tie-heavy 3D boxes (collinear and touching integer
     edges, duplicates, shared ground planes and tops) the matrix is exactly
     symmetric, and the summed gradient keeps the invariances of the 3D IoU:
@@ -832,7 +832,7 @@ def test_self_pair_matrix_one_structure_per_pair(orc):
     zero virial under scaling of the xy plane and of z.  Giving each row's
     box the first-polygon gradient of its own ordered entry, weighted by both
     entries' upstream gradients (so the two boxes of a pair take their
-    gradients from two different tie structures: the rule R8 replaces)
+    gradients from two different tie structures: the rule R25 replaces)
     breaks them on the same boxes."""
     rng = np.random.default_rng(97)
     xy, lo, hi = _tie_scene(rng)
